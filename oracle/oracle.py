@@ -1,0 +1,363 @@
+"""CPU oracle for the block-sparse quadtree multiply -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's
+``cpu_baseline`` leg may import this module.  The GPU library never uses it,
+and the two share no code.
+
+The oracle computes the plain definitions that the paper's recursive
+sparse-quadtree algorithms reach (no quadtree here):
+
+* Sparse quadtree semantics (paper Sec. 2 and Sec. 2.1): a matrix is zero, a
+  leaf, or four quadrants; a nil chunk is a zero submatrix and a task with a
+  nil input yields nil.  At leaf-block granularity the product pattern is
+  therefore the boolean product of the block patterns,
+  ``P_C = {(I,J) : exists K, (I,K) in P_A and (K,J) in P_B}``, and
+  ``C_IJ = sum_K A_IK B_KJ`` over exactly those K.
+* Truncation (paper Sec. 2.2, block-level variant): a block is dropped iff its
+  FP64 Frobenius norm is strictly below the tolerance (NaN norms are kept).
+* Matrix-matrix multiplication (paper Sec. 2.2): regular multiply; its masked
+  adjoints dA = (dC B^T) restricted to P_A and dB = (A^T dC) restricted to P_B.
+* Flop counts: element level ``2 * sum_k r(k) c(k)`` (the convention that
+  reproduces the paper's Table 1) and block level ``2 * sum m_I k_K n_J`` over
+  the nonzero leaf products with logical (unpadded) sizes.
+
+Readings of points the paper leaves open are listed with each function.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qbsm_oracle.c")
+_LIB = os.path.join(_HERE, "_qbsm_oracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part with gcc (FP64, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-shared", "-fPIC", "-std=c99", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        i64, i32, p = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        lib.oracle_block_fnorm.argtypes = [i64, i32, p, p]
+        lib.oracle_block_fnorm.restype = None
+        lib.oracle_segmented_products.argtypes = [i32, i64, p, p, p, p, p,
+                                                  ctypes.c_int, ctypes.c_int, p]
+        lib.oracle_segmented_products.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# --------------------------------------------------------------------------
+# Block norms and truncation
+# --------------------------------------------------------------------------
+
+def block_fnorms(vals: np.ndarray, bs: int) -> np.ndarray:
+    """FP64 Frobenius norm of each block (column-major summation order)."""
+    vals = np.ascontiguousarray(vals, dtype=np.float64).reshape(-1, bs * bs)
+    out = np.empty(vals.shape[0], dtype=np.float64)
+    if vals.shape[0]:
+        _load().oracle_block_fnorm(vals.shape[0], bs, _ptr(vals), _ptr(out))
+    return out
+
+
+def keep_mask(vals: np.ndarray, bs: int, tol: float) -> np.ndarray:
+    """Blocks kept by truncation: not (norm < tol).  Equality and NaN keep.
+
+    Reading: the paper names truncation with error control (Sec. 2.2) without
+    a formula; the block-level rule here drops iff ||X||_F < tol in FP64.
+    """
+    if tol <= 0.0:
+        return np.ones(vals.shape[0], dtype=bool)
+    return ~(block_fnorms(vals, bs) < tol)
+
+
+def borderline(vals: np.ndarray, bs: int, tol: float, rel: float = 1e-9) -> np.ndarray:
+    """Blocks whose squared norm lies within ``rel`` of tol^2 (order-sensitive)."""
+    if tol <= 0.0:
+        return np.zeros(vals.shape[0], dtype=bool)
+    n = block_fnorms(vals, bs)
+    return np.abs(n * n / (tol * tol) - 1.0) < rel
+
+
+@dataclass
+class OMatrix:
+    """Oracle-side block matrix: canonical row-major pattern + FP64 blocks."""
+
+    nrows: int
+    ncols: int
+    bs: int
+    brow: np.ndarray  # int64
+    bcol: np.ndarray  # int64
+    vals: np.ndarray  # float64 [nblk, bs*bs], column-major blocks
+
+    @property
+    def nblk(self):
+        return int(self.brow.shape[0])
+
+
+def canonical(nrows, ncols, bs, brow, bcol, vals, drop_tol=0.0) -> OMatrix:
+    """Sort blocks row-major, apply truncation, reject duplicates / out-of-range."""
+    brow = np.asarray(brow, dtype=np.int64)
+    bcol = np.asarray(bcol, dtype=np.int64)
+    vals = np.asarray(vals, dtype=np.float64).reshape(-1, bs * bs)
+    nbr, nbc = -(-nrows // bs), -(-ncols // bs)
+    if brow.size and (brow.min() < 0 or bcol.min() < 0 or brow.max() >= nbr or bcol.max() >= nbc):
+        raise ValueError("block index out of range")
+    order = np.lexsort((bcol, brow))
+    brow, bcol, vals = brow[order], bcol[order], vals[order]
+    if brow.size > 1 and np.any((np.diff(brow) == 0) & (np.diff(bcol) == 0)):
+        raise ValueError("duplicate block")
+    keep = keep_mask(vals, bs, drop_tol)
+    return OMatrix(nrows, ncols, bs, brow[keep], bcol[keep], np.ascontiguousarray(vals[keep]))
+
+
+def from_workload(m, drop_tol=0.0) -> OMatrix:
+    return canonical(m.nrows, m.ncols, m.bs, m.brow, m.bcol, m.vals, drop_tol)
+
+
+# --------------------------------------------------------------------------
+# Symbolic part: product triples and the C pattern
+# --------------------------------------------------------------------------
+
+def _row_index(brow: np.ndarray, nrows_blk: int) -> np.ndarray:
+    """Row pointer of a row-major sorted pattern."""
+    return np.searchsorted(brow, np.arange(nrows_blk + 1), side="left")
+
+
+def product_triples(a: OMatrix, b: OMatrix, trans_a=False, trans_b=False):
+    """All nonzero leaf products of op(A) op(B), canonical (I, J, K) order.
+
+    Returns (I, J, K, ia, ib): ``ia``/``ib`` index the stored blocks of A/B.
+    Plain definition: for every stored block (I,K) of op(A) and every stored
+    block (K,J) of op(B), the triple (I,K,J) is a product.
+    """
+    # logical coordinates of op(X)
+    ai, ak = (a.bcol, a.brow) if trans_a else (a.brow, a.bcol)
+    bk, bj = (b.bcol, b.brow) if trans_b else (b.brow, b.bcol)
+    # index B's blocks by their K (block row of op(B))
+    order_b = np.lexsort((bj, bk))
+    bk_s, bj_s = bk[order_b], bj[order_b]
+    nk = int(max(ak.max(initial=-1), bk.max(initial=-1)) + 1)
+    ptr = np.searchsorted(bk_s, np.arange(nk + 1), side="left")
+    cnt = (ptr[ak + 1] - ptr[ak]) if ak.size else np.zeros(0, dtype=np.int64)
+    total = int(cnt.sum())
+    ia = np.repeat(np.arange(a.nblk, dtype=np.int64), cnt)
+    start = np.repeat(ptr[ak] if ak.size else np.zeros(0, np.int64), cnt)
+    off = np.arange(total, dtype=np.int64) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    ib = order_b[start + off]
+    I, K, J = ai[ia], ak[ia], bj[ib]
+    o = np.lexsort((K, J, I))
+    return I[o], J[o], K[o], ia[o], ib[o]
+
+
+def c_pattern_from_triples(I, J):
+    """Unique (I, J) of the triples in row-major order, with segment offsets."""
+    if I.size == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros(1, np.int64)
+    new = np.ones(I.size, dtype=bool)
+    new[1:] = (I[1:] != I[:-1]) | (J[1:] != J[:-1])
+    starts = np.nonzero(new)[0]
+    seg = np.append(starts, I.size).astype(np.int64)
+    return I[starts], J[starts], seg
+
+
+def boolean_pattern_product(a: OMatrix, b: OMatrix):
+    """C pattern as the boolean matrix product of the block masks (pin)."""
+    nbi, nbk = -(-a.nrows // a.bs), -(-a.ncols // a.bs)
+    nbj = -(-b.ncols // b.bs)
+    ma = np.zeros((nbi, nbk), dtype=np.int64)
+    mb = np.zeros((nbk, nbj), dtype=np.int64)
+    ma[a.brow, a.bcol] = 1
+    mb[b.brow, b.bcol] = 1
+    prod = ma @ mb
+    ii, jj = np.nonzero(prod)
+    return ii.astype(np.int64), jj.astype(np.int64), prod[ii, jj]
+
+
+# --------------------------------------------------------------------------
+# Numeric part
+# --------------------------------------------------------------------------
+
+@dataclass
+class OProduct:
+    brow: np.ndarray
+    bcol: np.ndarray
+    vals: np.ndarray
+    I: np.ndarray
+    J: np.ndarray
+    K: np.ndarray
+    seg: np.ndarray
+
+
+def _segmented(bs, seg, lidx, ridx, L, R, transL, transR):
+    nout = seg.size - 1
+    out = np.empty((nout, bs * bs), dtype=np.float64)
+    if nout:
+        seg = np.ascontiguousarray(seg, dtype=np.int64)
+        lidx = np.ascontiguousarray(lidx, dtype=np.int64)
+        ridx = np.ascontiguousarray(ridx, dtype=np.int64)
+        L = np.ascontiguousarray(L, dtype=np.float64)
+        R = np.ascontiguousarray(R, dtype=np.float64)
+        _load().oracle_segmented_products(bs, nout, _ptr(seg), _ptr(lidx), _ptr(ridx),
+                                          _ptr(L), _ptr(R), int(transL), int(transR), _ptr(out))
+    return out
+
+
+def multiply(a: OMatrix, b: OMatrix, trans_a=False, trans_b=False) -> OProduct:
+    """C = op(A) op(B): structural pattern (no numerical dropping) + FP64 values.
+
+    Readings: C keeps every structurally nonzero block even when its value is
+    numerically zero (truncation is a separate operation, paper Sec. 2.2);
+    each C block sums its leaf products with K ascending.
+    """
+    if a.bs != b.bs:
+        raise ValueError("leaf sizes differ")
+    I, J, K, ia, ib = product_triples(a, b, trans_a, trans_b)
+    ci, cj, seg = c_pattern_from_triples(I, J)
+    vals = _segmented(a.bs, seg, ia, ib, a.vals, b.vals, trans_a, trans_b)
+    return OProduct(ci, cj, vals, I, J, K, seg)
+
+
+def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j) -> np.ndarray:
+    """Values of selected C blocks only (for sampling very large products).
+
+    A selected (I, J) with no product gets a zero block.
+    """
+    sample_i = np.asarray(sample_i, dtype=np.int64)
+    sample_j = np.asarray(sample_j, dtype=np.int64)
+    bs = a.bs
+    # rows of A needed, columns of B needed
+    segs = [0]
+    lid, rid = [], []
+    a_rowptr = _row_index(a.brow, -(-a.nrows // bs))
+    bt_order = np.lexsort((b.brow, b.bcol))  # B sorted by column, then row
+    b_col = b.bcol[bt_order]
+    b_colptr = np.searchsorted(b_col, np.arange(-(-b.ncols // bs) + 1), side="left")
+    for i, j in zip(sample_i.tolist(), sample_j.tolist()):
+        ra = np.arange(a_rowptr[i], a_rowptr[i + 1])
+        cb = bt_order[b_colptr[j]:b_colptr[j + 1]]
+        ks_a = a.bcol[ra]
+        ks_b = b.brow[cb]
+        common, xa, xb = np.intersect1d(ks_a, ks_b, assume_unique=True, return_indices=True)
+        lid.append(ra[xa])
+        rid.append(cb[xb])
+        segs.append(segs[-1] + common.size)
+    seg = np.asarray(segs, dtype=np.int64)
+    lidx = np.concatenate(lid) if lid else np.zeros(0, np.int64)
+    ridx = np.concatenate(rid) if rid else np.zeros(0, np.int64)
+    return _segmented(bs, seg, lidx, ridx, a.vals, b.vals, False, False)
+
+
+def _restrict(prod: OProduct, mask: OMatrix) -> np.ndarray:
+    """Values of ``prod`` on the blocks of ``mask`` (zero where no product)."""
+    bs = mask.bs
+    out = np.zeros((mask.nblk, bs * bs), dtype=np.float64)
+    if prod.brow.size == 0 or mask.nblk == 0:
+        return out
+    nbc = int(max(mask.bcol.max(), prod.bcol.max()) + 1)
+    key_p = prod.brow * nbc + prod.bcol
+    key_m = mask.brow * nbc + mask.bcol
+    pos = np.searchsorted(key_p, key_m)
+    pos = np.minimum(pos, key_p.size - 1)
+    hit = key_p[pos] == key_m
+    out[hit] = prod.vals[pos[hit]]
+    return out
+
+
+def backward(a: OMatrix, b: OMatrix, dc: OMatrix):
+    """Masked adjoints of C = A B.
+
+    dA = (dC B^T) restricted to A's pattern; dB = (A^T dC) restricted to B's
+    pattern.  Each block sums over the free index ascending (J for dA, I for
+    dB).  Blocks of the mask with no contributing product are zero.
+    """
+    pa = multiply(dc, b, trans_a=False, trans_b=True)   # (I,K) = sum_J dC_IJ B_KJ^T
+    pb = multiply(a, dc, trans_a=True, trans_b=False)   # (K,J) = sum_I A_IK^T dC_IJ
+    return _restrict(pa, a), _restrict(pb, b)
+
+
+# --------------------------------------------------------------------------
+# Flop counts
+# --------------------------------------------------------------------------
+
+def element_flops(col_counts_a: np.ndarray, row_counts_b: np.ndarray) -> int:
+    """2 * sum_k r(k) c(k): r(k) nonzeros in column k of A, c(k) in row k of B.
+
+    This is the element-level count of scalar multiply-adds (two flops each)
+    that the paper's Table 1 reports for A*A.
+    """
+    r = np.asarray(col_counts_a, dtype=np.int64)
+    c = np.asarray(row_counts_b, dtype=np.int64)
+    return int(2 * np.sum(r * c, dtype=np.int64))
+
+
+def block_flops(I, J, K, m_rows: int, k_dim: int, n_cols: int, bs: int) -> int:
+    """2 * sum over leaf products of m_I * k_K * n_J with logical sizes."""
+    def ext(idx, n):
+        idx = np.asarray(idx, dtype=np.int64)
+        return np.minimum(bs, n - idx * bs)
+    return int(2 * np.sum(ext(I, m_rows) * ext(K, k_dim) * ext(J, n_cols), dtype=np.int64))
+
+
+# --------------------------------------------------------------------------
+# Precision-mode input roundings (used to isolate accumulation error)
+# --------------------------------------------------------------------------
+
+def round_to_f32(x: np.ndarray) -> np.ndarray:
+    """Round-to-nearest-even to binary32 (returned as float64)."""
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_to_bf16(x: np.ndarray) -> np.ndarray:
+    """Round-to-nearest-even of an FP64 value straight to bfloat16 (no double rounding).
+
+    bfloat16: 8 significant bits, the binary32 exponent range (normal
+    exponents -126..127, subnormal quantum 2^-133), overflow to infinity.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    out = np.array(x, copy=True)
+    fin = np.isfinite(x)
+    ax = np.abs(x)
+    normal = fin & (ax >= 2.0 ** -126)
+    m, e = np.frexp(x[normal])               # x = m * 2^e, 0.5 <= |m| < 1
+    out[normal] = np.ldexp(np.rint(m * 256.0) / 256.0, e)   # 8 significant bits
+    sub = fin & ~normal
+    out[sub] = np.rint(x[sub] * 2.0 ** 133) * 2.0 ** -133
+    big = np.isfinite(out) & (np.abs(out) >= 2.0 ** 128)
+    out[big] = np.sign(out[big]) * np.inf
+    return out
+
+
+def split_bf16(x: np.ndarray):
+    """hi = bf16(x), lo = bf16(x - hi) with x - hi formed in FP64 (exact)."""
+    hi = round_to_bf16(x)
+    lo = round_to_bf16(np.asarray(x, dtype=np.float64) - hi)
+    return hi, lo
+
+
+def rel_fro(x: np.ndarray, ref: np.ndarray) -> float:
+    """Relative Frobenius error ||x - ref|| / ||ref||."""
+    num = np.linalg.norm((np.asarray(x) - np.asarray(ref)).ravel())
+    den = np.linalg.norm(np.asarray(ref).ravel())
+    return float(num / den) if den > 0 else float(num)

@@ -1,0 +1,380 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Every check here is independent of the GPU library: textbook dense GEMM,
+brute-force enumeration, algebraic identities, the paper's printed Table 1,
+and closed-form counts of the banded workloads.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+from oracle import oracle as O  # noqa: E402
+from paper_2011_11762_amd import workloads as W  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def om(m, tol=0.0):
+    return O.from_workload(m, tol)
+
+
+def dense_of(nrows, ncols, bs, brow, bcol, vals):
+    nbr, nbc = -(-nrows // bs), -(-ncols // bs)
+    out = np.zeros((nbr * bs, nbc * bs))
+    for t in range(len(brow)):
+        i, j = int(brow[t]), int(bcol[t])
+        out[i * bs:(i + 1) * bs, j * bs:(j + 1) * bs] = np.asarray(vals[t]).reshape(bs, bs).T
+    return out[:nrows, :ncols]
+
+
+def transpose_matrix(a: O.OMatrix) -> O.OMatrix:
+    bs = a.bs
+    v = a.vals.reshape(-1, bs, bs).transpose(0, 2, 1).reshape(-1, bs * bs)
+    return O.canonical(a.ncols, a.nrows, bs, a.bcol, a.brow, v)
+
+
+# ---------------------------------------------------------------- dense GEMM
+@pytest.mark.parametrize("m,k,n,bs,p,seed", [
+    (64, 64, 64, 16, 0.5, 10),
+    (100, 70, 90, 16, 0.4, 11),      # ragged in every dimension
+    (130, 257, 33, 32, 0.6, 12),     # ragged, rectangular
+    (48, 48, 48, 8, 1.0, 13),        # fully dense
+    (300, 300, 300, 64, 0.3, 14),
+])
+def test_dense_gemm(m, k, n, bs, p, seed):
+    a, b = W.small_random(m, k, n, bs, p, seed)
+    A, B = om(a), om(b)
+    C = O.multiply(A, B)
+    got = dense_of(m, n, bs, C.brow, C.bcol, C.vals)
+    ref = a.to_dense() @ b.to_dense()
+    scale = np.abs(a.to_dense()) @ np.abs(b.to_dense())
+    assert np.all(np.abs(got - ref) <= 4 * k * 2.0 ** -53 * scale + 1e-300)
+    # padding of edge blocks stays zero
+    full = np.zeros((C.brow.size, bs, bs))
+    full[:] = C.vals.reshape(-1, bs, bs)
+    for t in range(C.brow.size):
+        mr = min(bs, m - C.brow[t] * bs)
+        nc = min(bs, n - C.bcol[t] * bs)
+        assert np.all(full[t, nc:, :] == 0) and np.all(full[t, :, mr:] == 0)
+
+
+def test_all_nil_operands():
+    a, b = W.small_random(64, 64, 64, 16, 0.5, 3)
+    A, B = om(a), om(b)
+    Z = O.canonical(64, 64, 16, [], [], np.zeros((0, 256)))
+    for x, y in ((Z, B), (A, Z), (Z, Z)):
+        C = O.multiply(x, y)
+        assert C.brow.size == 0 and C.vals.shape == (0, 256)
+
+
+# ------------------------------------------------------- products / pattern
+def brute_triples(A, B):
+    sa = {(int(i), int(k)) for i, k in zip(A.brow, A.bcol)}
+    sb = {(int(k), int(j)) for k, j in zip(B.brow, B.bcol)}
+    nbi, nbk, nbj = -(-A.nrows // A.bs), -(-A.ncols // A.bs), -(-B.ncols // B.bs)
+    out = []
+    for i in range(nbi):
+        for j in range(nbj):
+            for k in range(nbk):
+                if (i, k) in sa and (k, j) in sb:
+                    out.append((i, j, k))
+    return out
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_products_brute_force(seed):
+    a, b = W.small_random(160, 120, 200, 8, 0.2, seed)
+    A, B = om(a), om(b)
+    I, J, K, ia, ib = O.product_triples(A, B)
+    assert list(zip(I.tolist(), J.tolist(), K.tolist())) == brute_triples(A, B)
+    # indices point at the right stored blocks
+    assert np.array_equal(A.brow[ia], I) and np.array_equal(A.bcol[ia], K)
+    assert np.array_equal(B.brow[ib], K) and np.array_equal(B.bcol[ib], J)
+
+
+def check_pattern(A, B):
+    I, J, K, _, _ = O.product_triples(A, B)
+    ci, cj, seg = O.c_pattern_from_triples(I, J)
+    bi, bj, cnt = O.boolean_pattern_product(A, B)
+    assert np.array_equal(ci, bi) and np.array_equal(cj, bj)
+    assert np.array_equal(np.diff(seg), cnt)
+    return ci.size, I.size
+
+
+def test_pattern_config1_closed_form():
+    c = W.config1()
+    A, B = om(c["A"]), om(c["B"])
+    assert (A.nblk, B.nblk) == (556, 556)
+    nc, npr = check_pattern(A, B)
+    assert (nc, npr) == (1016, 4884)
+
+
+def test_pattern_config5_closed_form():
+    c = W.config5()
+    A, B = om(c["A"]), om(c["B"])
+    assert A.nblk == 3286
+    nc, npr = check_pattern(A, B)
+    assert (nc, npr) == (6244, 42354)
+    dc = om(c["dC"])
+    C = O.multiply(A, B)
+    assert np.array_equal(dc.brow, C.brow) and np.array_equal(dc.bcol, C.bcol)
+
+
+def test_pattern_config3():
+    c = W.config3()
+    A, B = om(c["A"]), om(c["B"])
+    nc, npr = check_pattern(A, B)
+    assert 2400 < A.nblk < 2850 and 2400 < B.nblk < 2850
+    assert npr >= nc > 0
+
+
+@pytest.mark.slow
+def test_pattern_config2_after_drop():
+    c = W.config2()
+    A = om(c["A"], c["drop_tol"])
+    assert not np.any(O.borderline(c["A"].vals, 64, c["drop_tol"]))
+    assert 0.97 * 65536 < A.nblk < 0.99 * 65536
+    nc, npr = check_pattern(A, A)
+    assert nc == 65536
+
+
+def test_pattern_config4_small_members():
+    specs = [s for s in W.config4_members() if s["n"] <= 3000][:4]
+    assert specs
+    for s in specs:
+        mem = W.config4_member(s)
+        A, B = om(mem["A"], mem["drop_tol"]), om(mem["B"], mem["drop_tol"])
+        check_pattern(A, B)
+
+
+# --------------------------------------------------------------- identities
+def identity_matrix(n, bs):
+    nb = -(-n // bs)
+    vals = np.zeros((nb, bs * bs))
+    for t in range(nb):
+        d = min(bs, n - t * bs)
+        for e in range(d):
+            vals[t, e + e * bs] = 1.0
+    return O.canonical(n, n, bs, np.arange(nb), np.arange(nb), vals)
+
+
+def test_identity_bit_exact():
+    a, _ = W.small_random(120, 90, 10, 16, 0.5, 7)
+    A = om(a)
+    for C in (O.multiply(A, identity_matrix(90, 16)), O.multiply(identity_matrix(120, 16), A)):
+        assert np.array_equal(C.brow, A.brow) and np.array_equal(C.bcol, A.bcol)
+        assert np.array_equal(C.vals, A.vals)
+
+
+def test_transpose_bit_exact():
+    a, b = W.small_random(100, 140, 75, 16, 0.5, 8)
+    A, B = om(a), om(b)
+    C = O.multiply(A, B)
+    Ct = transpose_matrix(O.canonical(100, 75, 16, C.brow, C.bcol, C.vals))
+    D = O.multiply(transpose_matrix(B), transpose_matrix(A))
+    assert np.array_equal(D.brow, Ct.brow) and np.array_equal(D.bcol, Ct.bcol)
+    assert np.array_equal(D.vals, Ct.vals)
+    # the same through the oracle's transposed-operand path
+    E = O.multiply(B, A, trans_a=True, trans_b=True)
+    assert np.array_equal(E.vals, Ct.vals)
+
+
+def test_associativity_distributivity():
+    rng = np.random.default_rng(9)
+    bs = 16
+    a = W.random_blocks(96, bs, 0.4, rng, ncols=80)
+    b = W.random_blocks(80, bs, 0.4, rng, ncols=112)
+    c = W.random_blocks(112, bs, 0.4, rng, ncols=64)
+    b2 = W.random_blocks(80, bs, 0.4, rng, ncols=112)
+    A, B, Cm, B2 = om(a), om(b), om(c), om(b2)
+
+    def mat(p, nr, nc):
+        return O.canonical(nr, nc, bs, p.brow, p.bcol, p.vals)
+
+    AB = mat(O.multiply(A, B), 96, 112)
+    BC = mat(O.multiply(B, Cm), 80, 64)
+    L, R = O.multiply(AB, Cm), O.multiply(A, BC)
+    bi, bj, _ = O.boolean_pattern_product(mat(O.multiply(A, B), 96, 112), Cm)
+    assert np.array_equal(L.brow, R.brow) and np.array_equal(L.bcol, R.bcol)
+    assert np.array_equal(L.brow, bi) and np.array_equal(L.bcol, bj)
+    absd = lambda m: np.abs(m.to_dense()) if hasattr(m, "to_dense") else None  # noqa: E731
+    scale = np.abs(a.to_dense()) @ np.abs(b.to_dense()) @ np.abs(c.to_dense())
+    gam = 2 * (80 + 112) * 2.0 ** -53
+    diff = dense_of(96, 64, bs, L.brow, L.bcol, L.vals) - dense_of(96, 64, bs, R.brow, R.bcol, R.vals)
+    assert np.all(np.abs(diff) <= gam * scale)
+    # A (B + B2) = A B + A B2 on the union pattern
+    dsum = b.to_dense() + b2.to_dense()
+    bsum_blocks = np.unique(np.concatenate([B.brow * 1000 + B.bcol, B2.brow * 1000 + B2.bcol]))
+    bi_, bj_ = bsum_blocks // 1000, bsum_blocks % 1000
+    vals = np.stack([dsum[i * bs:(i + 1) * bs, j * bs:(j + 1) * bs].T.ravel() for i, j in zip(bi_, bj_)])
+    S = O.canonical(80, 112, bs, bi_, bj_, vals)
+    lhs = O.multiply(A, S)
+    lhs_d = dense_of(96, 112, bs, lhs.brow, lhs.bcol, lhs.vals)
+    r1, r2 = O.multiply(A, B), O.multiply(A, B2)
+    rhs_d = dense_of(96, 112, bs, r1.brow, r1.bcol, r1.vals) + dense_of(96, 112, bs, r2.brow, r2.bcol, r2.vals)
+    sc = np.abs(a.to_dense()) @ (np.abs(b.to_dense()) + np.abs(b2.to_dense()))
+    assert np.all(np.abs(lhs_d - rhs_d) <= 2 * 80 * 2.0 ** -53 * sc * 2)
+    _ = absd
+
+
+# ----------------------------------------------------------------- flops
+def interval_union_len(ivs):
+    ivs = sorted(ivs)
+    tot, cur_lo, cur_hi = 0, None, None
+    for lo, hi in ivs:
+        if cur_hi is None or lo > cur_hi + 1:
+            if cur_hi is not None:
+                tot += cur_hi - cur_lo + 1
+            cur_lo, cur_hi = lo, hi
+        else:
+            cur_hi = max(cur_hi, hi)
+    if cur_hi is not None:
+        tot += cur_hi - cur_lo + 1
+    return tot
+
+
+def column_counts_banded(n, h, block=0):
+    """Nonzeros per column of band(h) plus an optional dense upper-left block,
+    from the pattern's definition as a union of row intervals per column."""
+    k = np.arange(n, dtype=np.int64)
+    band = np.minimum(k + h, n - 1) - np.maximum(k - h, 0) + 1
+    if block:
+        for kk in range(block):
+            band[kk] = interval_union_len([(max(0, kk - h), min(n - 1, kk + h)), (0, block - 1)])
+    return band
+
+
+def test_table1_flops_reproduced():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "table1_tflop.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 7
+    for n_s, band_s, blk_s, gb_s in rows:
+        n, blk = int(n_s), int(blk_s)
+        r = column_counts_banded(n, 3000)
+        assert f"{O.element_flops(r, r) / 1e12:.4g}" == band_s
+        r2 = column_counts_banded(n, 3000, block=blk)
+        assert f"{O.element_flops(r2, r2) / 1e12:.4g}" == gb_s
+
+
+def test_block_flops_brute_force():
+    a, b = W.small_random(70, 45, 52, 16, 0.6, 5)
+    A, B = om(a), om(b)
+    I, J, K, _, _ = O.product_triples(A, B)
+    got = O.block_flops(I, J, K, 70, 45, 52, 16)
+    cnt = 0
+    for i, j, k in zip(I, J, K):
+        for r in range(i * 16, min(70, (i + 1) * 16)):
+            for c in range(j * 16, min(52, (j + 1) * 16)):
+                cnt += min(45, (k + 1) * 16) - k * 16
+    assert got == 2 * cnt
+    # fully dense blocks, divisible sizes: block count == element count
+    rng = np.random.default_rng(0)
+    d = W.random_blocks(64, 16, 1.0, rng)
+    D = om(d)
+    I, J, K, _, _ = O.product_triples(D, D)
+    dense = d.to_dense() != 0
+    assert O.block_flops(I, J, K, 64, 64, 64, 16) == O.element_flops(dense.sum(0), dense.sum(1))
+
+
+# --------------------------------------------------------------- backward
+def test_backward_finite_differences_and_adjoint():
+    rng = np.random.default_rng(21)
+    bs = 8
+    a = W.random_blocks(40, bs, 0.5, rng, ncols=48)
+    b = W.random_blocks(48, bs, 0.5, rng, ncols=32)
+    A, B = om(a), om(b)
+    C = O.multiply(A, B)
+    dcv = rng.uniform(-1, 1, size=C.vals.shape)
+    dC = O.canonical(40, 32, bs, C.brow, C.bcol, dcv)
+    dA, dB = O.backward(A, B, dC)
+
+    def loss(Am, Bm):
+        P = O.multiply(Am, Bm)
+        return float(np.sum(P.vals * dcv))
+
+    for _ in range(12):
+        t = int(rng.integers(A.nblk))
+        e = int(rng.integers(bs * bs))
+        Ap, Am_ = O.OMatrix(**{**A.__dict__, "vals": A.vals.copy()}), O.OMatrix(**{**A.__dict__, "vals": A.vals.copy()})
+        Ap.vals[t, e] += 1.0
+        Am_.vals[t, e] -= 1.0
+        fd = (loss(Ap, B) - loss(Am_, B)) / 2.0
+        assert abs(fd - dA[t, e]) <= 1e-12 * (1 + abs(fd))
+        t = int(rng.integers(B.nblk))
+        Bp, Bm_ = O.OMatrix(**{**B.__dict__, "vals": B.vals.copy()}), O.OMatrix(**{**B.__dict__, "vals": B.vals.copy()})
+        Bp.vals[t, e] += 1.0
+        Bm_.vals[t, e] -= 1.0
+        fd = (loss(A, Bp) - loss(A, Bm_)) / 2.0
+        assert abs(fd - dB[t, e]) <= 1e-12 * (1 + abs(fd))
+    l0 = float(np.sum(C.vals * dcv))
+    assert abs(np.sum(dA * A.vals) - l0) <= 1e-12 * (1 + abs(l0))
+    assert abs(np.sum(dB * B.vals) - l0) <= 1e-12 * (1 + abs(l0))
+    # against dense autograd-free formulas
+    Dd, Bd, Ad = dense_of(40, 32, bs, C.brow, C.bcol, dcv), b.to_dense(), a.to_dense()
+    gA, gB = Dd @ Bd.T, Ad.T @ Dd
+    got_a = dense_of(40, 48, bs, A.brow, A.bcol, dA)
+    got_b = dense_of(48, 32, bs, B.brow, B.bcol, dB)
+    ma = dense_of(40, 48, bs, A.brow, A.bcol, np.ones_like(A.vals)) != 0
+    mb = dense_of(48, 32, bs, B.brow, B.bcol, np.ones_like(B.vals)) != 0
+    assert np.allclose(got_a, np.where(ma, gA, 0), rtol=0, atol=1e-13)
+    assert np.allclose(got_b, np.where(mb, gB, 0), rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------- norms / drop rule
+def test_block_norms_and_drop_rule():
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal((50, 64))
+    n = O.block_fnorms(v, 8)
+    ref = np.linalg.norm(v, axis=1)
+    assert np.allclose(n, ref, rtol=4e-16 * 64, atol=0)
+    blk = np.zeros((4, 4))
+    blk[0, 0] = 0.5
+    vals = np.stack([blk.ravel(), blk.ravel() * (1 - 2.0 ** -52), np.full(16, np.nan), np.zeros(16)])
+    keep = O.keep_mask(vals, 4, 0.5)
+    assert keep.tolist() == [True, False, True, False]
+    assert O.keep_mask(vals, 4, 0.0).all()
+
+
+# ------------------------------------------------------ precision roundings
+def test_bf16_rounding():
+    import torch
+    x = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -40, -(1 + 2 ** -8),
+                  3.0e38, 3.4e38, 2.0 ** -130, -2.0 ** -133 * 1.5, 0.0, np.inf, -np.inf])
+    got = O.round_to_bf16(x)
+    exp = [1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -1.0, 3.0e38, np.inf, 2.0 ** -130, -2.0 ** -132, 0.0,
+           np.inf, -np.inf]
+    assert np.allclose(got[[0, 1, 2, 3, 4, 7, 8, 9]], np.array(exp)[[0, 1, 2, 3, 4, 7, 8, 9]], rtol=0, atol=0)
+    assert abs(got[5] - 3.0e38) / 3.0e38 < 2 ** -8 and np.isinf(got[6]) and np.isinf(got[10])
+    assert np.isnan(O.round_to_bf16(np.array([np.nan]))[0])
+    # values exactly representable in binary32: torch's binary32 -> bfloat16 RNE
+    rng = np.random.default_rng(0)
+    f = (rng.standard_normal(100000) * np.exp(rng.uniform(-30, 30, 100000))).astype(np.float32)
+    ref = torch.from_numpy(f).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(O.round_to_bf16(f.astype(np.float64)), ref)
+    # split: hi + lo carries ~16 bits
+    xd = rng.uniform(-1, 1, 100000)
+    hi, lo = O.split_bf16(xd)
+    assert np.array_equal(O.round_to_bf16(hi), hi) and np.array_equal(O.round_to_bf16(lo), lo)
+    assert np.all(np.abs(xd - hi - lo) <= 2.0 ** -16 * np.abs(xd) + 1e-300)
+
+
+def test_canonical_rejects_bad_input():
+    v = np.zeros((2, 4))
+    with pytest.raises(ValueError):
+        O.canonical(4, 4, 2, [0, 0], [1, 1], v)
+    with pytest.raises(ValueError):
+        O.canonical(4, 4, 2, [0, 2], [0, 0], v)
+
+
+def test_multiply_blocks_matches_full():
+    a, b = W.small_random(200, 160, 180, 16, 0.3, 17)
+    A, B = om(a), om(b)
+    C = O.multiply(A, B)
+    pick = np.arange(0, C.brow.size, 3)
+    got = O.multiply_blocks(A, B, C.brow[pick], C.bcol[pick])
+    assert np.array_equal(got, C.vals[pick])
