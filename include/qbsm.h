@@ -1,0 +1,232 @@
+/*
+ * qbsm -- block-sparse quadtree matrix multiply on AMD MI355X (gfx950).
+ *
+ * C ABI of libqbsm.so.  Plain pointers and sizes only.
+ *
+ * Method (Rubensson, Rudberg, Kruchinina, Artemov, "The Chunks and Tasks
+ * Matrix Library 2.0"):
+ *   - Sec. 2: a matrix is a sparse quadtree -- identically zero, a small leaf
+ *     matrix, or four quadrants that are themselves sparse quadtrees; matrix
+ *     operations are recursive algorithms over the nonzero branches.
+ *   - Sec. 2.1: a non-leaf node refers to its four children; a nil child is an
+ *     identically zero quadrant.  Each task handles one quadtree level and a
+ *     task with a nil input does no work (this is how sparsity is exploited).
+ *     The dense leaf type stores elements column-wise.
+ *   - Sec. 2.2: construction from index/value vectors, extraction, regular
+ *     matrix-matrix multiplication, truncation of small parts.
+ *
+ * Conventions for every call
+ *   - All array arguments are DEVICE pointers unless stated otherwise; scalar
+ *     results are written through HOST pointers.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every launch of a call goes to that stream.  Calls that report sizes
+ *     (set_blocks, multiply_symbolic) synchronise the stream before returning.
+ *   - A leaf block is bs x bs, column-major (element (r,c) at r + c*bs).
+ *     Edge blocks of a matrix whose size is not a multiple of bs are padded;
+ *     the library zeroes the padding of every block it stores or writes.
+ *   - Block coordinates (I,J) are 0-based.  Matrices may be rectangular; the
+ *     block grid side is limited to 65536 (quadtree depth <= 16).
+ *   - Every call returns a qbsm_status; nothing is thrown or aborted across
+ *     the ABI.  qbsm_last_error() gives a per-thread text for the last
+ *     failure.  NaN/Inf values propagate per IEEE 754.
+ *   - Handles are not thread safe: do not use one handle from two threads at
+ *     once, and keep a plan's matrices alive (and their patterns unchanged)
+ *     for the plan's lifetime.
+ *   - Device memory comes from the allocator set by qbsm_set_allocator
+ *     (default: hipMallocAsync / hipFreeAsync on the call's stream).
+ */
+#ifndef QBSM_H
+#define QBSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QBSM_OK = 0,
+    QBSM_ERR_ARG = 1,         /* null pointer, negative size, bad enum value        */
+    QBSM_ERR_SHAPE = 2,       /* inner dimensions / leaf sizes do not agree         */
+    QBSM_ERR_PATTERN = 3,     /* duplicate or out-of-range block coordinates        */
+    QBSM_ERR_OOM = 4,         /* the allocator returned NULL                        */
+    QBSM_ERR_HIP = 5,         /* a HIP runtime call failed                          */
+    QBSM_ERR_UNSUPPORTED = 6, /* size or option outside what the library handles    */
+    QBSM_ERR_STATE = 7        /* handle not ready (e.g. matrix without blocks)      */
+} qbsm_status;
+
+/* Arithmetic of the leaf products.  Operands are stored by the library in
+ * the mode's format, products accumulate on the GPU's matrix cores (MFMA):
+ *   QBSM_F64    FP64 operands, FP64 accumulation, FP64 result.
+ *   QBSM_F32    operands rounded to binary32 (RNE), FP32 accumulation, FP32 result.
+ *   QBSM_BF16   operands rounded to bfloat16 (RNE, straight from FP64), FP32
+ *               accumulation, FP32 result.
+ *   QBSM_BF16X3 split precision: x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
+ *               a*b ~ hi_a*hi_b + hi_a*lo_b + lo_a*hi_b, FP32 accumulation,
+ *               FP32 result. */
+typedef enum {
+    QBSM_F64 = 0,
+    QBSM_F32 = 1,
+    QBSM_BF16 = 2,
+    QBSM_BF16X3 = 3
+} qbsm_mode;
+
+typedef struct qbsm_matrix_ *qbsm_matrix;
+typedef struct qbsm_plan_ *qbsm_plan;
+typedef struct qbsm_batch_ *qbsm_batch;
+
+/* Device allocator hooks.  alloc(bytes, stream, ctx) returns device memory
+ * usable on `stream` or NULL; release(ptr, stream, ctx) returns it.  Passing
+ * two NULL functions restores the default.  Not thread safe w.r.t. calls in
+ * flight. */
+typedef void *(*qbsm_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*qbsm_release_fn)(void *ptr, void *stream, void *ctx);
+qbsm_status qbsm_set_allocator(qbsm_alloc_fn alloc, qbsm_release_fn release, void *ctx);
+
+const char *qbsm_status_string(qbsm_status st);
+const char *qbsm_last_error(void);
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t qbsm_version(void);
+
+/* ---------------------------------------------------------------- matrices */
+
+/* An empty (identically zero) nrows x ncols matrix with leaf size bs
+ * (Sec. 2: the zero quadtree).  bs must be 32, 64 or 128.  The handle owns
+ * all memory it later allocates. */
+qbsm_status qbsm_matrix_create(int64_t nrows, int64_t ncols, int32_t bs, qbsm_matrix *out);
+qbsm_status qbsm_matrix_destroy(qbsm_matrix m);
+
+/* Construction from leaf blocks (Sec. 2.2, assignment from index and value
+ * vectors, at leaf-block granularity) followed by block truncation.
+ *   brow, bcol : int32[nblk] block coordinates (device), any order.
+ *   vals       : double[nblk * bs * bs] (device), block t at t*bs*bs, column-major.
+ *   drop_tol   : 0 keeps every block; otherwise block t is dropped iff its
+ *                FP64 Frobenius norm is < drop_tol (equality and NaN keep) --
+ *                the truncation operation of Sec. 2.2 at block granularity.
+ *   nkept      : host out, number of stored blocks after truncation.
+ * The values are copied (the caller keeps ownership of its buffers); padding
+ * beyond the logical size is stored as zero.  Replaces any previous content.
+ * Errors: QBSM_ERR_PATTERN for a coordinate outside the block grid or a
+ * repeated (I,J) (checked on the device before anything is stored; the
+ * matrix is left unchanged). */
+qbsm_status qbsm_matrix_set_blocks(qbsm_matrix m, int64_t nblk, const int32_t *brow,
+                                   const int32_t *bcol, const double *vals, double drop_tol,
+                                   void *stream, int64_t *nkept);
+
+/* Shape and stored-block count (host outs; any may be NULL). */
+qbsm_status qbsm_matrix_info(qbsm_matrix m, int64_t *nrows, int64_t *ncols, int32_t *bs,
+                             int64_t *nblk);
+
+/* Extraction (Sec. 2.2), at leaf-block granularity: the stored pattern in
+ * canonical row-major (I, J) order into device int32[nblk] arrays. */
+qbsm_status qbsm_matrix_get_pattern(qbsm_matrix m, int32_t *brow, int32_t *bcol, void *stream);
+
+/* Values of the stored blocks, same canonical order, as FP64 column-major
+ * blocks into device double[nblk * bs * bs].  Results of an FP32 mode are
+ * widened exactly. */
+qbsm_status qbsm_matrix_get_values(qbsm_matrix m, double *vals, void *stream);
+
+/* ---------------------------------------------------------------- multiply */
+
+/* Options of the symbolic phase.  unit: side, in elements, of the C quadtree
+ * node that one GPU workgroup owns (the depth where the recursion hands over
+ * to a dense kernel); 0 picks the default (128).  Must be bs * 2^s with s in
+ * 0..2 and a value in {64, 128}. */
+typedef struct {
+    int32_t unit;
+    int32_t reserved[7];
+} qbsm_plan_opts;
+
+/* Symbolic phase of C = A * B (Sec. 2 and 2.1: the recursive multiply over
+ * nonzero quadtree branches; a pair with a nil operand is pruned).
+ * Walks the two quadtrees level by level from the root, keeping only node
+ * pairs whose both operands are non-nil, and records the nonzero leaf-pair
+ * products and the block pattern of C.  Integer work, deterministic.
+ *   A : m x k, B : k x n, equal leaf sizes.  A and B may be the same handle.
+ *   opts may be NULL.  Host outs nblk_C (blocks of C) and nprod (nonzero
+ *   leaf products) may be NULL.
+ * Errors: QBSM_ERR_SHAPE for k mismatch or different bs; QBSM_ERR_STATE if
+ * a matrix has never been given blocks (an empty set_blocks is fine). */
+qbsm_status qbsm_multiply_symbolic(qbsm_matrix A, qbsm_matrix B, const qbsm_plan_opts *opts,
+                                   void *stream, qbsm_plan *plan, int64_t *nblk_C,
+                                   int64_t *nprod);
+
+/* Generalised symbolic phase: out = op(L) * op(R) restricted to the block
+ * pattern of `mask` (mask may be NULL for no restriction); op transposes
+ * when the flag is nonzero.  With a mask, the output has exactly the mask's
+ * pattern and blocks without any product are zero.  Used for the masked
+ * adjoints of the multiply; same errors as qbsm_multiply_symbolic. */
+qbsm_status qbsm_multiply_symbolic_ex(qbsm_matrix L, int32_t trans_l, qbsm_matrix R,
+                                      int32_t trans_r, qbsm_matrix mask,
+                                      const qbsm_plan_opts *opts, void *stream, qbsm_plan *plan,
+                                      int64_t *nblk_out, int64_t *nprod);
+
+/* Plan facts (host outs, any may be NULL): output blocks, nonzero leaf
+ * products, block-level flops 2*sum(m_I k_K n_J) over the products with
+ * logical sizes, the work unit side, the number of work units (C quadtree
+ * nodes at the unit level) and of node pairs at that level. */
+qbsm_status qbsm_plan_info(qbsm_plan p, int64_t *nblk_out, int64_t *nprod, int64_t *flops,
+                           int32_t *unit, int64_t *nunits, int64_t *npairs);
+
+/* The nonzero leaf products in canonical (I, J, K) order (row-major output
+ * block, then contraction index ascending), as device int32[nprod] arrays.
+ * Coordinates are those of op(L) (I,K) and op(R) (K,J). */
+qbsm_status qbsm_plan_get_products(qbsm_plan p, int32_t *I, int32_t *K, int32_t *J,
+                                   void *stream);
+
+qbsm_status qbsm_plan_destroy(qbsm_plan p);
+
+/* Numeric phase: leaf-block products on the matrix cores with a segmented,
+ * atomic-free accumulation -- every output block is owned by one workgroup,
+ * which sums its products with the contraction index ascending and writes
+ * the block once.  `out` receives the plan's output pattern and values
+ * (result storage FP64 for QBSM_F64, FP32 otherwise); its shape must be
+ * rows(op(L)) x cols(op(R)) with the same bs.  Does not synchronise.
+ * The operands' current values are used (they may change between calls as
+ * long as their patterns do not). */
+qbsm_status qbsm_multiply_numeric(qbsm_plan p, qbsm_mode mode, qbsm_matrix out, void *stream);
+
+/* Masked backward of C = A * B for an upstream gradient dC given on C's
+ * pattern (dC may hold any subset of C's blocks):
+ *   dA = (dC * B^T) restricted to A's pattern,
+ *   dB = (A^T * dC) restricted to B's pattern.
+ * dA / dB receive A's / B's pattern (either may be NULL to skip it).
+ * Runs two masked symbolic walks and two numeric phases on `stream`. */
+qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC, qbsm_mode mode,
+                                   const qbsm_plan_opts *opts, qbsm_matrix dA, qbsm_matrix dB,
+                                   void *stream);
+
+/* ----------------------------------------------------------------- batched */
+
+/* Batched numeric phase over n independent plans: one persistent kernel
+ * launch serves every output work unit of every member, units ordered
+ * longest-processing-time first and pulled from a device work counter.
+ * qbsm_batch_create validates, allocates the outputs and operand packs and
+ * builds the work list (synchronises).  All plans must use the same work
+ * unit side.  outs[i] receives plans[i]'s result. */
+qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode,
+                              qbsm_matrix *outs, void *stream, qbsm_batch *batch);
+/* Launch-only part (operand packing + the persistent kernel); no allocation
+ * and no synchronisation, so it may be captured into a HIP graph. */
+qbsm_status qbsm_batch_run(qbsm_batch batch, void *stream);
+/* Captures qbsm_batch_run into a HIP graph on first use, then replays it. */
+qbsm_status qbsm_batch_run_graph(qbsm_batch batch, void *stream);
+/* Persistent workgroups per compute unit (default 0 = chosen by the library). */
+qbsm_status qbsm_batch_set_occupancy(qbsm_batch batch, int32_t wg_per_cu);
+qbsm_status qbsm_batch_destroy(qbsm_batch batch);
+
+/* ----------------------------------------------------------------- tuning */
+
+/* Times the numeric phase of C = A * B for every valid unit side (symbolic
+ * + numeric, `reps` timed repetitions after one warm-up) and reports the
+ * fastest.  times_ms (host, may be NULL) receives 2 entries in the order
+ * unit = 64, 128 (negative when not applicable to the leaf size). */
+qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps,
+                               void *stream, int32_t *best_unit, double *times_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QBSM_H */

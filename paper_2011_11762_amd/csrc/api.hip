@@ -1,0 +1,425 @@
+// The C ABI of libqbsm: argument checks, error mapping, handle lifetimes,
+// batched launches with HIP graph replay, and the unit-size autotuner.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+
+struct qbsm_matrix_ {
+    qbsm::Matrix m;
+};
+struct qbsm_plan_ {
+    std::unique_ptr<qbsm::Plan> p;
+};
+struct qbsm_batch_ {
+    qbsm::Batch b;
+};
+
+namespace qbsm {
+
+K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
+int k5_occupancy(qbsm_mode mode, int unit);
+
+namespace {
+thread_local std::string g_last_error;
+
+Allocator g_alloc;
+}  // namespace
+
+Allocator &allocator() { return g_alloc; }
+
+void *dalloc(size_t bytes, hipStream_t s) {
+    if (!bytes) return nullptr;
+    void *p = nullptr;
+    if (g_alloc.alloc) {
+        p = g_alloc.alloc(bytes, (void *)s, g_alloc.ctx);
+    } else {
+        hipError_t e = hipMallocAsync(&p, bytes, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+        }
+    }
+    if (!p) throw Error(QBSM_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    return p;
+}
+
+void dfree(void *p, hipStream_t s) {
+    if (!p) return;
+    if (g_alloc.release)
+        g_alloc.release(p, (void *)s, g_alloc.ctx);
+    else
+        (void)hipFreeAsync(p, s);
+}
+
+int device_cu_count() {
+    int dev = 0;
+    QB_HIP(hipGetDevice(&dev));
+    int n = 0;
+    QB_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    return n;
+}
+
+}  // namespace qbsm
+
+using namespace qbsm;
+
+namespace {
+
+template <class F>
+qbsm_status guard(F &&f) {
+    try {
+        f();
+        return QBSM_OK;
+    } catch (const Error &e) {
+        g_last_error = e.what();
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return QBSM_ERR_OOM;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return QBSM_ERR_HIP;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return QBSM_ERR_HIP;
+    }
+}
+
+hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+bool valid_mode(qbsm_mode m) { return m == QBSM_F64 || m == QBSM_F32 || m == QBSM_BF16 || m == QBSM_BF16X3; }
+
+}  // namespace
+
+extern "C" {
+
+qbsm_status qbsm_set_allocator(qbsm_alloc_fn alloc, qbsm_release_fn release, void *ctx) {
+    return guard([&] {
+        QB_CHECK((alloc == nullptr) == (release == nullptr), QBSM_ERR_ARG, "set both hooks or neither");
+        g_alloc.alloc = alloc;
+        g_alloc.release = release;
+        g_alloc.ctx = ctx;
+    });
+}
+
+const char *qbsm_status_string(qbsm_status st) {
+    switch (st) {
+        case QBSM_OK: return "ok";
+        case QBSM_ERR_ARG: return "invalid argument";
+        case QBSM_ERR_SHAPE: return "shape mismatch";
+        case QBSM_ERR_PATTERN: return "invalid block pattern";
+        case QBSM_ERR_OOM: return "out of device memory";
+        case QBSM_ERR_HIP: return "HIP runtime error";
+        case QBSM_ERR_UNSUPPORTED: return "unsupported";
+        case QBSM_ERR_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+const char *qbsm_last_error(void) { return g_last_error.c_str(); }
+
+int32_t qbsm_version(void) { return 10000; }
+
+qbsm_status qbsm_matrix_create(int64_t nrows, int64_t ncols, int32_t bs, qbsm_matrix *out) {
+    return guard([&] {
+        QB_CHECK(out, QBSM_ERR_ARG, "null output handle");
+        QB_CHECK(nrows >= 0 && ncols >= 0, QBSM_ERR_ARG, "negative size");
+        QB_CHECK(bs == 32 || bs == 64 || bs == 128, QBSM_ERR_UNSUPPORTED, "leaf size must be 32, 64 or 128");
+        const int64_t nbr = (nrows + bs - 1) / bs, nbc = (ncols + bs - 1) / bs;
+        QB_CHECK(nbr <= 65536 && nbc <= 65536, QBSM_ERR_UNSUPPORTED, "block grid side above 65536");
+        auto h = std::make_unique<qbsm_matrix_>();
+        h->m.nrows = nrows;
+        h->m.ncols = ncols;
+        h->m.bs = bs;
+        h->m.nbr = nbr;
+        h->m.nbc = nbc;
+        *out = h.release();
+    });
+}
+
+qbsm_status qbsm_matrix_destroy(qbsm_matrix m) {
+    return guard([&] { delete m; });
+}
+
+qbsm_status qbsm_matrix_set_blocks(qbsm_matrix m, int64_t nblk, const int32_t *brow, const int32_t *bcol,
+                                   const double *vals, double drop_tol, void *stream, int64_t *nkept) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        const int64_t k = matrix_set_blocks(m->m, nblk, brow, bcol, vals, drop_tol, as_stream(stream));
+        if (nkept) *nkept = k;
+    });
+}
+
+qbsm_status qbsm_matrix_info(qbsm_matrix m, int64_t *nrows, int64_t *ncols, int32_t *bs, int64_t *nblk) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        if (nrows) *nrows = m->m.nrows;
+        if (ncols) *ncols = m->m.ncols;
+        if (bs) *bs = m->m.bs;
+        if (nblk) *nblk = m->m.nblk;
+    });
+}
+
+qbsm_status qbsm_matrix_get_pattern(qbsm_matrix m, int32_t *brow, int32_t *bcol, void *stream) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        QB_CHECK(m->m.nblk == 0 || (brow && bcol), QBSM_ERR_ARG, "null output arrays");
+        matrix_get_pattern(m->m, brow, bcol, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_matrix_get_values(qbsm_matrix m, double *vals, void *stream) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        QB_CHECK(m->m.nblk == 0 || vals, QBSM_ERR_ARG, "null output array");
+        matrix_get_values(m->m, vals, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_multiply_symbolic_ex(qbsm_matrix L, int32_t trans_l, qbsm_matrix R, int32_t trans_r,
+                                      qbsm_matrix mask, const qbsm_plan_opts *opts, void *stream,
+                                      qbsm_plan *plan, int64_t *nblk_out, int64_t *nprod) {
+    return guard([&] {
+        QB_CHECK(L && R && plan, QBSM_ERR_ARG, "null argument");
+        const int unit = opts ? opts->unit : 0;
+        auto p = plan_build(&L->m, trans_l ? 1 : 0, &R->m, trans_r ? 1 : 0, mask ? &mask->m : nullptr, unit,
+                            as_stream(stream));
+        if (nblk_out) *nblk_out = p->nout;
+        if (nprod) *nprod = p->nprod;
+        auto h = std::make_unique<qbsm_plan_>();
+        h->p = std::move(p);
+        *plan = h.release();
+    });
+}
+
+qbsm_status qbsm_multiply_symbolic(qbsm_matrix A, qbsm_matrix B, const qbsm_plan_opts *opts, void *stream,
+                                   qbsm_plan *plan, int64_t *nblk_C, int64_t *nprod) {
+    return qbsm_multiply_symbolic_ex(A, 0, B, 0, nullptr, opts, stream, plan, nblk_C, nprod);
+}
+
+qbsm_status qbsm_plan_info(qbsm_plan p, int64_t *nblk_out, int64_t *nprod, int64_t *flops, int32_t *unit,
+                           int64_t *nunits, int64_t *npairs) {
+    return guard([&] {
+        QB_CHECK(p && p->p, QBSM_ERR_ARG, "null plan");
+        if (nblk_out) *nblk_out = p->p->nout;
+        if (nprod) *nprod = p->p->nprod;
+        if (flops) *flops = p->p->flops;
+        if (unit) *unit = p->p->unit;
+        if (nunits) *nunits = p->p->nunits;
+        if (npairs) *npairs = p->p->npairs;
+    });
+}
+
+qbsm_status qbsm_plan_get_products(qbsm_plan p, int32_t *I, int32_t *K, int32_t *J, void *stream) {
+    return guard([&] {
+        QB_CHECK(p && p->p, QBSM_ERR_ARG, "null plan");
+        QB_CHECK(p->p->nprod == 0 || (I && K && J), QBSM_ERR_ARG, "null output arrays");
+        plan_get_products(*p->p, I, K, J, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_plan_destroy(qbsm_plan p) {
+    return guard([&] { delete p; });
+}
+
+qbsm_status qbsm_multiply_numeric(qbsm_plan p, qbsm_mode mode, qbsm_matrix out, void *stream) {
+    return guard([&] {
+        QB_CHECK(p && p->p && out, QBSM_ERR_ARG, "null argument");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        numeric_prepare_output(*p->p, mode, out->m, as_stream(stream));
+        numeric_launch(*p->p, mode, out->m, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC, qbsm_mode mode,
+                                   const qbsm_plan_opts *opts, qbsm_matrix dA, qbsm_matrix dB, void *stream) {
+    return guard([&] {
+        QB_CHECK(A && B && dC, QBSM_ERR_ARG, "null argument");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        QB_CHECK(dC->m.nrows == A->m.nrows && dC->m.ncols == B->m.ncols, QBSM_ERR_SHAPE,
+                 "dC shape differs from A*B");
+        const int unit = opts ? opts->unit : 0;
+        hipStream_t s = as_stream(stream);
+        if (dA) {
+            // dA = (dC * B^T) restricted to A's pattern
+            auto p = plan_build(&dC->m, 0, &B->m, 1, &A->m, unit, s);
+            numeric_prepare_output(*p, mode, dA->m, s);
+            numeric_launch(*p, mode, dA->m, s);
+        }
+        if (dB) {
+            // dB = (A^T * dC) restricted to B's pattern
+            auto p = plan_build(&A->m, 1, &dC->m, 0, &B->m, unit, s);
+            numeric_prepare_output(*p, mode, dB->m, s);
+            numeric_launch(*p, mode, dB->m, s);
+        }
+    });
+}
+
+qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode, qbsm_matrix *outs, void *stream,
+                              qbsm_batch *batch) {
+    return guard([&] {
+        QB_CHECK(n >= 0 && batch && (n == 0 || (plans && outs)), QBSM_ERR_ARG, "null argument");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        hipStream_t s = as_stream(stream);
+        auto h = std::make_unique<qbsm_batch_>();
+        Batch &b = h->b;
+        b.n = n;
+        b.mode = mode;
+        b.num_cus = device_cu_count();
+        std::vector<K5Member> hm(n);
+        std::vector<std::vector<int32_t>> cost(n);
+        for (int i = 0; i < n; ++i) {
+            QB_CHECK(plans[i] && plans[i]->p && outs[i], QBSM_ERR_ARG, "null plan or output");
+            Plan &p = *plans[i]->p;
+            if (i == 0) b.unit = p.unit;
+            QB_CHECK(p.unit == b.unit, QBSM_ERR_UNSUPPORTED, "all members must use the same unit side");
+            for (int j = 0; j < i; ++j)
+                QB_CHECK(outs[j] != outs[i], QBSM_ERR_ARG, "two members share an output");
+            numeric_prepare_output(p, mode, outs[i]->m, s);
+            hm[i] = make_member(p, mode, outs[i]->m, s);
+            b.plans.push_back(&p);
+            b.outs.push_back(&outs[i]->m);
+            // operand packs replayed on each run (the raw column-major views need none)
+            for (int side = 0; side < 2; ++side) {
+                Matrix *mm = side == 0 ? p.L : p.R;
+                Role role = side == 0 ? (p.transL ? ROLE_COL : ROLE_ROW) : (p.transR ? ROLE_ROW : ROLE_COL);
+                const bool raw = role == ROLE_COL && ((mode == QBSM_F64 && mm->storage == ST_F64) ||
+                                                      (mode == QBSM_F32 && mm->storage == ST_F32));
+                if (raw) continue;
+                bool seen = false;
+                for (auto &j : b.packs) seen |= (j.m == mm && j.mode == mode && j.role == role);
+                if (!seen) b.packs.push_back({mm, mode, role});
+            }
+            // per-unit cost: number of node pairs (read back for ordering)
+            std::vector<int32_t> us(p.nunits + 1);
+            if (p.nunits)
+                QB_HIP(hipMemcpyAsync(us.data(), p.ustart.p, (p.nunits + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            QB_HIP(hipStreamSynchronize(s));
+            cost[i].resize(p.nunits);
+            for (int64_t u = 0; u < p.nunits; ++u) cost[i][u] = us[u + 1] - us[u];
+        }
+        // longest-processing-time-first order over all (member, unit) items
+        std::vector<int2> items;
+        for (int i = 0; i < n; ++i)
+            for (int64_t u = 0; u < (int64_t)cost[i].size(); ++u) items.push_back(make_int2(i, (int)u));
+        std::stable_sort(items.begin(), items.end(), [&](const int2 &x, const int2 &y) {
+            return cost[x.x][x.y] > cost[y.x][y.y];
+        });
+        b.nitems = (int64_t)items.size();
+        b.members.alloc(n ? n : 1, s);
+        b.items.alloc(items.empty() ? 1 : items.size(), s);
+        b.counter.alloc(1, s);
+        if (n) QB_HIP(hipMemcpyAsync(b.members.p, hm.data(), n * sizeof(K5Member), hipMemcpyHostToDevice, s));
+        if (!items.empty())
+            QB_HIP(hipMemcpyAsync(b.items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        QB_HIP(hipStreamSynchronize(s));
+        b.wg_per_cu = b.unit ? k5_occupancy(mode, b.unit) : 1;
+        *batch = h.release();
+    });
+}
+
+qbsm_status qbsm_batch_set_occupancy(qbsm_batch batch, int32_t wg_per_cu) {
+    return guard([&] {
+        QB_CHECK(batch && wg_per_cu >= 0, QBSM_ERR_ARG, "bad argument");
+        Batch &b = batch->b;
+        b.wg_per_cu = wg_per_cu ? wg_per_cu : (b.unit ? k5_occupancy(b.mode, b.unit) : 1);
+        if (b.exec) {
+            (void)hipGraphExecDestroy(b.exec);
+            (void)hipGraphDestroy(b.graph);
+            b.exec = nullptr;
+            b.graph = nullptr;
+        }
+    });
+}
+
+qbsm_status qbsm_batch_run(qbsm_batch batch, void *stream) {
+    return guard([&] {
+        QB_CHECK(batch, QBSM_ERR_ARG, "null batch");
+        batch_launch(batch->b, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_batch_run_graph(qbsm_batch batch, void *stream) {
+    return guard([&] {
+        QB_CHECK(batch, QBSM_ERR_ARG, "null batch");
+        QB_CHECK(stream, QBSM_ERR_ARG, "graph capture needs a non-null stream");
+        Batch &b = batch->b;
+        hipStream_t s = as_stream(stream);
+        if (!b.exec) {
+            QB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                batch_launch(b, s);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(s, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            QB_HIP(hipStreamEndCapture(s, &b.graph));
+            QB_HIP(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+        }
+        QB_HIP(hipGraphLaunch(b.exec, s));
+    });
+}
+
+qbsm_status qbsm_batch_destroy(qbsm_batch batch) {
+    return guard([&] {
+        if (!batch) return;
+        if (batch->b.exec) (void)hipGraphExecDestroy(batch->b.exec);
+        if (batch->b.graph) (void)hipGraphDestroy(batch->b.graph);
+        delete batch;
+    });
+}
+
+qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps, void *stream,
+                               int32_t *best_unit, double *times_ms) {
+    return guard([&] {
+        QB_CHECK(A && B && best_unit, QBSM_ERR_ARG, "null argument");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        QB_CHECK(reps >= 1, QBSM_ERR_ARG, "reps must be >= 1");
+        hipStream_t s = as_stream(stream);
+        const int bs = A->m.bs;
+        const int cand[2] = {64, 128};
+        double best = -1.0;
+        int bu = 0;
+        hipEvent_t e0, e1;
+        QB_HIP(hipEventCreate(&e0));
+        QB_HIP(hipEventCreate(&e1));
+        for (int ci = 0; ci < 2; ++ci) {
+            const int u = cand[ci];
+            double t = -1.0;
+            const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1;
+            if (ok) {
+                auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, s);
+                Matrix out;
+                out.nrows = p->out_rows;
+                out.ncols = p->out_cols;
+                out.bs = bs;
+                out.nbr = (out.nrows + bs - 1) / bs;
+                out.nbc = (out.ncols + bs - 1) / bs;
+                numeric_prepare_output(*p, mode, out, s);
+                numeric_launch(*p, mode, out, s);  // warm-up (packs operands)
+                QB_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r) numeric_launch(*p, mode, out, s);
+                QB_HIP(hipEventRecord(e1, s));
+                QB_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                QB_HIP(hipEventElapsedTime(&ms, e0, e1));
+                t = ms / reps;
+                if (best < 0 || t < best) {
+                    best = t;
+                    bu = u;
+                }
+            }
+            if (times_ms) times_ms[ci] = t;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *best_unit = bu;
+    });
+}
+
+}  // extern "C"

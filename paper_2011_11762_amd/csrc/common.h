@@ -1,0 +1,253 @@
+// Internal declarations of libqbsm (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/qbsm.h"
+
+namespace qbsm {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+    qbsm_status st;
+    Error(qbsm_status s, const std::string &m) : std::runtime_error(m), st(s) {}
+};
+
+#define QB_HIP(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::qbsm::Error(QBSM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define QB_CHECK(cond, st, msg)                                                           \
+    do {                                                                                  \
+        if (!(cond)) throw ::qbsm::Error((st), (msg));                                    \
+    } while (0)
+
+#define QB_LAUNCH_CHECK() QB_HIP(hipGetLastError())
+
+// --------------------------------------------------------------- allocation
+void *dalloc(size_t bytes, hipStream_t s);
+void dfree(void *p, hipStream_t s);
+
+// Owning device array; memory is returned on the stream it was taken on.
+template <class T>
+struct DArr {
+    T *p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+
+    DArr() = default;
+    DArr(size_t count, hipStream_t st) { alloc(count, st); }
+    DArr(const DArr &) = delete;
+    DArr &operator=(const DArr &) = delete;
+    DArr(DArr &&o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+    DArr &operator=(DArr &&o) noexcept {
+        if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DArr() { reset(); }
+    void alloc(size_t count, hipStream_t st) {
+        reset();
+        s = st;
+        n = count;
+        p = count ? static_cast<T *>(dalloc(count * sizeof(T), st)) : nullptr;
+    }
+    void reset() {
+        if (p) dfree(p, s);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// ------------------------------------------------------------ device utils
+// Device-wide exclusive scan of int32 counts.  out[0..n] receives the
+// exclusive prefix sums followed by the total at out[n]; the 64-bit total is
+// also written to *total64 (device).  Throws if the total exceeds INT32_MAX
+// only when the caller reads it back; callers check.
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *total64,
+                        hipStream_t s);
+// Same for int64 values (no overflow concerns at these sizes).
+void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+void fill_bytes_zero(void *p, size_t bytes, hipStream_t s);
+
+// Reads a device value back (synchronises the stream).
+template <class T>
+T read_back(const T *dev, hipStream_t s) {
+    T v{};
+    QB_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+inline int ceil_log2(int64_t x) {
+    int d = 0;
+    while ((int64_t(1) << d) < x) ++d;
+    return d;
+}
+
+inline unsigned grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > 1 << 30) g = 1 << 30;
+    return (unsigned)g;
+}
+
+// Rank of unique keys via a presence bitmap: for keys < range, writes
+// rank[i] = number of keys smaller than key[i].  Duplicate keys set
+// *dup_flag (device) to 1.  Keys are uint32.  Returns nothing; the count of
+// distinct keys is written to *count (device int64).
+void bitmap_rank(const uint32_t *keys, const uint8_t *active, int64_t n, uint64_t range,
+                 int32_t *rank, int32_t *dup_flag, int64_t *count, hipStream_t s);
+
+// ----------------------------------------------------------------- handles
+enum Storage { ST_NONE = 0, ST_F64 = 1, ST_F32 = 2 };
+enum Role { ROLE_ROW = 0, ROLE_COL = 1 };  // lines = rows / lines = columns
+
+// Sparse quadtree of one matrix at a given depth (paper Sec. 2.1: a node
+// refers to four children, nil = -1 means an identically zero quadrant).
+struct Tree {
+    int D = 0;
+    std::vector<int64_t> n;               // nodes per level, 0..D
+    std::vector<DArr<int32_t>> child;     // levels 0..D-1: [n_l * 4], slot q = 2*rowbit + colbit
+    std::vector<DArr<uint32_t>> key;      // levels 0..D: node Morton key at that level
+    std::map<int, DArr<int32_t>> desc;    // s -> leaf indices below level D-s nodes [n * 4^s]
+};
+
+struct Pack {
+    DArr<uint8_t> buf;
+    uint64_t version = 0;
+};
+
+struct Matrix {
+    int64_t nrows = 0, ncols = 0;
+    int32_t bs = 0;
+    int64_t nbr = 0, nbc = 0;
+    int64_t nblk = 0;
+    bool has_blocks = false;
+    DArr<uint32_t> keys;  // Morton keys of the stored blocks, ascending (storage order)
+    DArr<double> v64;     // FP64 values [nblk * bs * bs] (storage order, column-major)
+    DArr<float> v32;      // FP32 values when the matrix is an FP32 result
+    Storage storage = ST_NONE;
+    uint64_t version = 0;    // bumped on every value change
+    uint64_t pattern_id = 0; // bumped on every pattern change
+    std::map<int, std::unique_ptr<Tree>> trees;         // by depth
+    std::map<std::pair<int, int>, Pack> packs;          // (mode, role)
+    hipStream_t stream = nullptr;                       // stream of the last allocation
+};
+
+// Work description of one output (C) quadtree node at the unit level.
+struct Plan {
+    Matrix *L = nullptr, *R = nullptr, *M = nullptr;
+    int transL = 0, transR = 0;
+    uint64_t patL = 0, patR = 0, patM = 0;
+    int D = 0, s = 0, unit = 0, bs = 0, lpu = 1;
+    int64_t out_rows = 0, out_cols = 0;
+    int64_t nunits = 0, npairs = 0, nprod = 0, nout = 0, flops = 0;
+    DArr<int32_t> ustart;   // [nunits + 1] pair range of each unit
+    DArr<uint32_t> ukey;    // [nunits] Morton key of the unit node
+    DArr<int32_t> umask;    // [nunits] mask-tree node of the unit (masked plans)
+    DArr<int32_t> pl, pr;   // [npairs] L / R node indices at the unit level
+    DArr<uint64_t> pmask;   // [npairs] leaf-product bits ((kb*lpu + ib)*lpu + jb)
+    DArr<int32_t> cdesc;    // [nunits * lpu*lpu] output leaf index, -1 none (row-major ib,jb)
+    DArr<uint32_t> okeys;   // [nout] output Morton keys (unmasked plans)
+    hipStream_t stream = nullptr;
+};
+
+struct Allocator {
+    qbsm_alloc_fn alloc = nullptr;
+    qbsm_release_fn release = nullptr;
+    void *ctx = nullptr;
+};
+Allocator &allocator();
+
+// -------------------------------------------------------------- operations
+int64_t matrix_set_blocks(Matrix &m, int64_t nblk, const int32_t *brow, const int32_t *bcol,
+                          const double *vals, double drop_tol, hipStream_t s);
+Tree &matrix_tree(Matrix &m, int D, hipStream_t s);
+const int32_t *tree_desc(Matrix &m, Tree &t, int s_lvl, hipStream_t st);
+void matrix_get_pattern(Matrix &m, int32_t *brow, int32_t *bcol, hipStream_t s);
+void matrix_get_values(Matrix &m, double *vals, hipStream_t s);
+void matrix_morton_to_rowmajor_rank(Matrix &m, int32_t *rank, hipStream_t s);
+
+std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M,
+                                 int unit, hipStream_t s);
+void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t s);
+
+// Packs operand values for (mode, role); returns the device buffer and the
+// strides (in elements) the numeric kernel uses to address leaf lines.
+struct PackView {
+    const void *ptr = nullptr;
+    int64_t leaf_stride = 0;  // elements between consecutive leaves
+    int64_t part_stride = 0;  // elements between hi and lo parts
+    int32_t line_stride = 0;  // elements between consecutive lines of a leaf chunk
+    int32_t chunk_stride = 0; // elements between consecutive K chunks
+};
+PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s);
+int mode_bk(qbsm_mode mode, int bs);
+
+void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
+void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
+
+// Kernel-side member description (also used by the batched launch).
+struct K5Member {
+    const int32_t *ustart;
+    const uint32_t *ukey;
+    const int32_t *pl;
+    const int32_t *pr;
+    const uint64_t *pmask;
+    const int32_t *descL;  // nullptr: identity (s == 0)
+    const int32_t *descR;
+    const int32_t *cdesc;
+    const void *packL;
+    const void *packR;
+    void *C;
+    int64_t leafStrideL, partStrideL, leafStrideR, partStrideR;
+    int32_t lineStrideL, chunkStrideL, lineStrideR, chunkStrideR;
+    int64_t out_rows, out_cols;
+    int32_t nunits, bs, s, lpu, transL, transR, pad0, pad1;
+};
+
+struct Batch {
+    int32_t n = 0;
+    qbsm_mode mode = QBSM_F64;
+    int unit = 0;
+    std::vector<Plan *> plans;
+    std::vector<Matrix *> outs;
+    DArr<K5Member> members;
+    DArr<int2> items;        // (member, unit) in LPT order
+    DArr<int32_t> counter;   // work counter of the persistent launch
+    int64_t nitems = 0;
+    int wg_per_cu = 0;
+    int num_cus = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    // packing jobs replayed on every run
+    struct PackJob { Matrix *m; qbsm_mode mode; Role role; };
+    std::vector<PackJob> packs;
+};
+
+void batch_launch(Batch &b, hipStream_t s);
+void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s);
+void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t nmembers_host_unused,
+               const int2 *items, int64_t nitems, int32_t *counter, int grid, int persistent,
+               const K5Member &single, hipStream_t s);
+
+int device_cu_count();
+
+}  // namespace qbsm

@@ -1,0 +1,450 @@
+// Matrix handles: construction from leaf blocks, block truncation, the
+// sparse quadtree (Morton-ordered node tables), readback and operand packing.
+#include <cmath>
+
+#include "common.h"
+#include "device_math.h"
+
+namespace qbsm {
+
+namespace {
+
+// Morton key of block (I, J): bits of I and J interleaved, I's bit above J's
+// at every level, so the two low bits of a key are the child slot
+// q = 2*rowbit + colbit (quadrant order 00, 01, 10, 11).
+__device__ __forceinline__ uint32_t morton2(uint32_t i, uint32_t j) {
+    uint32_t k = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        k |= ((i >> b) & 1u) << (2 * b + 1);
+        k |= ((j >> b) & 1u) << (2 * b);
+    }
+    return k;
+}
+
+__device__ __forceinline__ void demorton2(uint32_t k, uint32_t &i, uint32_t &j) {
+    i = 0;
+    j = 0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        i |= ((k >> (2 * b + 1)) & 1u) << b;
+        j |= ((k >> (2 * b)) & 1u) << b;
+    }
+}
+
+struct SetStatus {
+    int32_t range_err;
+    int32_t dup;
+    int64_t nkept;
+    int64_t ndistinct;
+};
+
+// Keys + range check for every input block.
+__global__ void k_keys(const int32_t *brow, const int32_t *bcol, int64_t n, int64_t nbr, int64_t nbc,
+                       uint32_t *keys, uint8_t *valid, SetStatus *st) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int32_t i = brow[t], j = bcol[t];
+    bool ok = i >= 0 && j >= 0 && i < nbr && j < nbc;
+    valid[t] = ok ? 1 : 0;
+    keys[t] = ok ? morton2((uint32_t)i, (uint32_t)j) : 0u;
+    if (!ok) st->range_err = 1;
+}
+
+// FP64 Frobenius norm of the logical part of each block; keep iff not (norm < tol).
+__global__ void __launch_bounds__(256) k_norm_keep(const double *vals, const int32_t *brow,
+                                                   const int32_t *bcol, const uint8_t *valid,
+                                                   int64_t n, int32_t bs, int64_t nrows,
+                                                   int64_t ncols, double tol, uint8_t *keep) {
+    int64_t t = blockIdx.x;
+    if (t >= n) return;
+    __shared__ double red[256];
+    double s = 0.0;
+    if (valid[t]) {
+        const int64_t mr = min((int64_t)bs, nrows - (int64_t)brow[t] * bs);
+        const int64_t nc = min((int64_t)bs, ncols - (int64_t)bcol[t] * bs);
+        const double *x = vals + t * (int64_t)bs * bs;
+        const int r = threadIdx.x % bs;  // bs <= 128 divides 256
+        for (int c = threadIdx.x / bs; c < bs; c += 256 / bs) {
+            if (r < mr && c < nc) {
+                double v = x[r + (int64_t)c * bs];
+                s += v * v;
+            }
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double nrm = sqrt(red[0]);
+        keep[t] = (valid[t] && !(nrm < tol)) ? 1 : 0;
+    }
+}
+
+__global__ void k_copy_flags(const uint8_t *valid, int64_t n, uint8_t *keep) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) keep[t] = valid[t];
+}
+
+// Scatter kept blocks into Morton order, zeroing the padding.
+__global__ void __launch_bounds__(256) k_store_blocks(const double *vals, const int32_t *brow,
+                                                      const int32_t *bcol, const uint32_t *keys,
+                                                      const int32_t *rank, int64_t n, int32_t bs,
+                                                      int64_t nrows, int64_t ncols, double *pool,
+                                                      uint32_t *okeys) {
+    int64_t t = blockIdx.x;
+    if (t >= n) return;
+    int32_t r = rank[t];
+    if (r < 0) return;
+    const int64_t mr = min((int64_t)bs, nrows - (int64_t)brow[t] * bs);
+    const int64_t nc = min((int64_t)bs, ncols - (int64_t)bcol[t] * bs);
+    const int64_t n2 = (int64_t)bs * bs;
+    const double *x = vals + t * n2;
+    double *y = pool + (int64_t)r * n2;
+    if (mr == bs && nc == bs) {
+        for (int64_t e = threadIdx.x; e < n2 / 2; e += 256)
+            reinterpret_cast<double2 *>(y)[e] = reinterpret_cast<const double2 *>(x)[e];
+    } else {
+        const int rr = threadIdx.x % bs;
+        for (int cc = threadIdx.x / bs; cc < bs; cc += 256 / bs) {
+            int64_t e = rr + (int64_t)cc * bs;
+            y[e] = (rr < mr && cc < nc) ? x[e] : 0.0;
+        }
+    }
+    if (threadIdx.x == 0) okeys[r] = keys[t];
+}
+
+// ---- quadtree build: one level from its children level
+__global__ void k_tree_flags(const uint32_t *ckeys, const int64_t *ncount, int64_t cap, int32_t *flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    int64_t n = *ncount;
+    int32_t f = 0;
+    if (i < n) f = (i == 0 || (ckeys[i] >> 2) != (ckeys[i - 1] >> 2)) ? 1 : 0;
+    flags[i] = f;
+}
+
+__global__ void k_tree_link(const uint32_t *ckeys, const int64_t *ncount, int64_t cap,
+                            const int32_t *scan, uint32_t *pkeys, int32_t *child) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    int64_t n = *ncount;
+    if (i >= n) return;
+    // parent index = number of parent starts at or before i, minus one
+    bool start = (i == 0 || (ckeys[i] >> 2) != (ckeys[i - 1] >> 2));
+    int32_t p = scan[i] + (start ? 1 : 0) - 1;
+    if (start) pkeys[p] = ckeys[i] >> 2;
+    child[(int64_t)p * 4 + (ckeys[i] & 3u)] = (int32_t)i;
+}
+
+__global__ void k_desc2(const int32_t *child_hi, const int32_t *child_lo, int64_t n, int32_t *desc) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 16) return;
+    int64_t node = t >> 4;
+    int q = (int)(t & 15);
+    int qh = q >> 2, ql = q & 3;
+    int32_t c = child_hi[node * 4 + qh];
+    desc[t] = c < 0 ? -1 : child_lo[(int64_t)c * 4 + ql];
+}
+
+// ---- readback
+__global__ void k_rm_keys(const uint32_t *keys, int64_t n, int64_t nbc, uint32_t *rmk, int32_t *bi,
+                          int32_t *bj) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    uint32_t i, j;
+    demorton2(keys[t], i, j);
+    rmk[t] = (uint32_t)((uint64_t)i * (uint64_t)nbc + j);
+    if (bi) { bi[t] = (int32_t)i; bj[t] = (int32_t)j; }
+}
+
+__global__ void k_scatter_pattern(const int32_t *bi, const int32_t *bj, const int32_t *rank, int64_t n,
+                                  int32_t *brow, int32_t *bcol) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    brow[rank[t]] = bi[t];
+    bcol[rank[t]] = bj[t];
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_scatter_values(const T *pool, const int32_t *rank, int64_t n,
+                                                        int32_t bs, double *out) {
+    int64_t t = blockIdx.x;
+    if (t >= n) return;
+    const int64_t n2 = (int64_t)bs * bs;
+    const T *x = pool + t * n2;
+    double *y = out + (int64_t)rank[t] * n2;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) y[e] = (double)x[e];
+}
+
+// ---- operand packing
+// Packed leaf layout: [part][chunk][line][BK], lines = rows (ROLE_ROW) or
+// columns (ROLE_COL); the contraction index runs along a line.
+template <class Src, int MODE>
+__global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int32_t bs, int32_t bk,
+                                              int role, void *dst) {
+    const int64_t nc = bs / bk;
+    const int64_t per_leaf = nc * bs;  // (chunk, line) pairs per leaf
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk * per_leaf) return;
+    const int64_t leaf = t / per_leaf;
+    const int64_t rem = t - leaf * per_leaf;
+    const int64_t c = rem / bs;
+    const int64_t l = rem - c * bs;
+    const int64_t n2 = (int64_t)bs * bs;
+    const Src *x = src + leaf * n2;
+    // element kk of this line chunk
+    auto at = [&](int64_t kk) -> double {
+        int64_t k = c * bk + kk;
+        return role == ROLE_COL ? (double)x[k + l * bs] : (double)x[l + k * bs];
+    };
+    const int64_t off = c * (int64_t)bs * bk + l * bk;  // within a part
+    if (MODE == QBSM_F64) {
+        double *y = static_cast<double *>(dst) + leaf * n2 + off;
+        for (int64_t kk = 0; kk < bk; ++kk) y[kk] = at(kk);
+    } else if (MODE == QBSM_F32) {
+        float *y = static_cast<float *>(dst) + leaf * n2 + off;
+        for (int64_t kk = 0; kk < bk; ++kk) y[kk] = (float)at(kk);
+    } else if (MODE == QBSM_BF16) {
+        uint16_t *y = static_cast<uint16_t *>(dst) + leaf * n2 + off;
+        for (int64_t kk = 0; kk < bk; ++kk) y[kk] = bf16_rne_bits(at(kk));
+    } else {  // BF16X3: hi part then lo part
+        uint16_t *yh = static_cast<uint16_t *>(dst) + leaf * 2 * n2 + off;
+        uint16_t *yl = yh + n2;
+        for (int64_t kk = 0; kk < bk; ++kk) {
+            double v = at(kk);
+            uint16_t h = bf16_rne_bits(v);
+            yh[kk] = h;
+            yl[kk] = bf16_rne_bits(v - bf16_bits_to_double(h));
+        }
+    }
+}
+
+size_t mode_elem_bytes(qbsm_mode mode) {
+    switch (mode) {
+        case QBSM_F64: return 8;
+        case QBSM_F32: return 4;
+        default: return 2;
+    }
+}
+int mode_parts(qbsm_mode mode) { return mode == QBSM_BF16X3 ? 2 : 1; }
+
+}  // namespace
+
+int mode_bk(qbsm_mode mode, int bs) {
+    int bk = 128 / (int)mode_elem_bytes(mode);
+    return bk < bs ? bk : bs;
+}
+
+int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32_t *bcol,
+                          const double *vals, double drop_tol, hipStream_t s) {
+    QB_CHECK(n >= 0, QBSM_ERR_ARG, "nblk must be >= 0");
+    QB_CHECK(n == 0 || (brow && bcol && vals), QBSM_ERR_ARG, "null block arrays");
+    QB_CHECK(!(drop_tol < 0.0) && !std::isnan(drop_tol), QBSM_ERR_ARG, "drop_tol must be >= 0");
+    QB_CHECK(n <= (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many blocks");
+    DArr<SetStatus> st(1, s);
+    QB_HIP(hipMemsetAsync(st.p, 0, sizeof(SetStatus), s));
+    DArr<uint32_t> keys(n ? n : 1, s);
+    DArr<uint8_t> valid(n ? n : 1, s), keep(n ? n : 1, s);
+    DArr<int32_t> rank(n ? n : 1, s), rank2(n ? n : 1, s);
+    const uint64_t range = (uint64_t)1 << (2 * ceil_log2(m.nbr > m.nbc ? m.nbr : m.nbc));
+    if (n) {
+        k_keys<<<grid_for(n, 256), 256, 0, s>>>(brow, bcol, n, m.nbr, m.nbc, keys.p, valid.p, st.p);
+        QB_LAUNCH_CHECK();
+    }
+    // duplicates among all in-range input blocks
+    bitmap_rank(keys.p, valid.p, n, range, rank2.p, &st.p->dup, &st.p->ndistinct, s);
+    if (n) {
+        if (drop_tol > 0.0) {
+            k_norm_keep<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, valid.p, n, m.bs, m.nrows, m.ncols,
+                                                    drop_tol, keep.p);
+        } else {
+            k_copy_flags<<<grid_for(n, 256), 256, 0, s>>>(valid.p, n, keep.p);
+        }
+        QB_LAUNCH_CHECK();
+    }
+    DArr<int32_t> dummy(1, s);
+    bitmap_rank(keys.p, keep.p, n, range, rank.p, dummy.p, &st.p->nkept, s);
+    SetStatus h = read_back(st.p, s);
+    QB_CHECK(!h.range_err, QBSM_ERR_PATTERN, "block coordinate outside the block grid");
+    QB_CHECK(!h.dup, QBSM_ERR_PATTERN, "repeated block coordinate");
+    const int64_t nk = h.nkept;
+    DArr<double> pool(nk * (int64_t)m.bs * m.bs, s);
+    DArr<uint32_t> okeys(nk, s);
+    if (n && nk) {
+        k_store_blocks<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, keys.p, rank.p, n, m.bs, m.nrows,
+                                                   m.ncols, pool.p, okeys.p);
+        QB_LAUNCH_CHECK();
+    }
+    m.v64 = std::move(pool);
+    m.v32.reset();
+    m.keys = std::move(okeys);
+    m.nblk = nk;
+    m.storage = ST_F64;
+    m.has_blocks = true;
+    m.version++;
+    m.pattern_id++;
+    m.trees.clear();
+    m.packs.clear();
+    m.stream = s;
+    return nk;
+}
+
+Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
+    auto it = m.trees.find(D);
+    if (it != m.trees.end()) return *it->second;
+    auto t = std::make_unique<Tree>();
+    t->D = D;
+    t->n.assign(D + 1, 0);
+    t->child.resize(D);
+    t->key.resize(D + 1);
+    const int64_t cap = m.nblk;
+    DArr<int64_t> counts(D + 1, s);
+    // level D: the leaves themselves (storage order is Morton order)
+    t->key[D].alloc(cap ? cap : 1, s);
+    if (cap)
+        QB_HIP(hipMemcpyAsync(t->key[D].p, m.keys.p, cap * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    int64_t nleaf = cap;
+    QB_HIP(hipMemcpyAsync(counts.p + D, &nleaf, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    DArr<int32_t> flags(cap ? cap : 1, s), scan((cap ? cap : 1) + 1, s);
+    for (int l = D - 1; l >= 0; --l) {
+        t->key[l].alloc(cap ? cap : 1, s);
+        t->child[l].alloc((cap ? cap : 1) * 4, s);
+        fill_i32(t->child[l].p, -1, (cap ? cap : 1) * 4, s);
+        if (cap) {
+            k_tree_flags<<<grid_for(cap, 256), 256, 0, s>>>(t->key[l + 1].p, counts.p + l + 1, cap, flags.p);
+            QB_LAUNCH_CHECK();
+            exclusive_scan_i32(flags.p, scan.p, cap, counts.p + l, s);
+            k_tree_link<<<grid_for(cap, 256), 256, 0, s>>>(t->key[l + 1].p, counts.p + l + 1, cap, scan.p,
+                                                           t->key[l].p, t->child[l].p);
+            QB_LAUNCH_CHECK();
+        } else {
+            int64_t zero = 0;
+            QB_HIP(hipMemcpyAsync(counts.p + l, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        }
+    }
+    QB_HIP(hipMemcpyAsync(t->n.data(), counts.p, (D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    Tree &ref = *t;
+    m.trees[D] = std::move(t);
+    return ref;
+}
+
+const int32_t *tree_desc(Matrix &m, Tree &t, int s_lvl, hipStream_t st) {
+    (void)m;
+    if (s_lvl == 0) return nullptr;
+    if (s_lvl == 1) return t.D >= 1 ? t.child[t.D - 1].p : nullptr;
+    auto it = t.desc.find(s_lvl);
+    if (it != t.desc.end()) return it->second.p;
+    QB_CHECK(s_lvl == 2 && t.D >= 2, QBSM_ERR_UNSUPPORTED, "unit level too far above the leaves");
+    const int64_t n = t.n[t.D - 2];
+    DArr<int32_t> d((n ? n : 1) * 16, st);
+    if (n) {
+        k_desc2<<<grid_for(n * 16, 256), 256, 0, st>>>(t.child[t.D - 2].p, t.child[t.D - 1].p, n, d.p);
+        QB_LAUNCH_CHECK();
+    }
+    const int32_t *p = d.p;
+    t.desc[s_lvl] = std::move(d);
+    return p;
+}
+
+void matrix_morton_to_rowmajor_rank(Matrix &m, int32_t *rank, hipStream_t s) {
+    const int64_t n = m.nblk;
+    if (!n) return;
+    DArr<uint32_t> rmk(n, s);
+    k_rm_keys<<<grid_for(n, 256), 256, 0, s>>>(m.keys.p, n, m.nbc, rmk.p, nullptr, nullptr);
+    QB_LAUNCH_CHECK();
+    DArr<int32_t> dup(1, s);
+    DArr<int64_t> cnt(1, s);
+    bitmap_rank(rmk.p, nullptr, n, (uint64_t)m.nbr * (uint64_t)m.nbc, rank, dup.p, cnt.p, s);
+}
+
+void matrix_get_pattern(Matrix &m, int32_t *brow, int32_t *bcol, hipStream_t s) {
+    const int64_t n = m.nblk;
+    if (!n) return;
+    DArr<uint32_t> rmk(n, s);
+    DArr<int32_t> bi(n, s), bj(n, s), rank(n, s);
+    k_rm_keys<<<grid_for(n, 256), 256, 0, s>>>(m.keys.p, n, m.nbc, rmk.p, bi.p, bj.p);
+    QB_LAUNCH_CHECK();
+    DArr<int32_t> dup(1, s);
+    DArr<int64_t> cnt(1, s);
+    bitmap_rank(rmk.p, nullptr, n, (uint64_t)m.nbr * (uint64_t)m.nbc, rank.p, dup.p, cnt.p, s);
+    k_scatter_pattern<<<grid_for(n, 256), 256, 0, s>>>(bi.p, bj.p, rank.p, n, brow, bcol);
+    QB_LAUNCH_CHECK();
+}
+
+void matrix_get_values(Matrix &m, double *vals, hipStream_t s) {
+    const int64_t n = m.nblk;
+    if (!n) return;
+    DArr<int32_t> rank(n, s);
+    matrix_morton_to_rowmajor_rank(m, rank.p, s);
+    if (m.storage == ST_F64)
+        k_scatter_values<double><<<(unsigned)n, 256, 0, s>>>(m.v64.p, rank.p, n, m.bs, vals);
+    else
+        k_scatter_values<float><<<(unsigned)n, 256, 0, s>>>(m.v32.p, rank.p, n, m.bs, vals);
+    QB_LAUNCH_CHECK();
+}
+
+void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) {
+    const int bk = mode_bk(mode, m.bs);
+    const int64_t work = m.nblk * (m.bs / bk) * (int64_t)m.bs;
+    if (!work) return;
+    const unsigned g = grid_for(work, 256);
+    void *dst = pk.buf.p;
+#define QB_PACK(SRC, PTR, MODE) \
+    k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst)
+    if (m.storage == ST_F64) {
+        switch (mode) {
+            case QBSM_F64: QB_PACK(double, m.v64.p, QBSM_F64); break;
+            case QBSM_F32: QB_PACK(double, m.v64.p, QBSM_F32); break;
+            case QBSM_BF16: QB_PACK(double, m.v64.p, QBSM_BF16); break;
+            case QBSM_BF16X3: QB_PACK(double, m.v64.p, QBSM_BF16X3); break;
+        }
+    } else {
+        switch (mode) {
+            case QBSM_F64: QB_PACK(float, m.v32.p, QBSM_F64); break;
+            case QBSM_F32: QB_PACK(float, m.v32.p, QBSM_F32); break;
+            case QBSM_BF16: QB_PACK(float, m.v32.p, QBSM_BF16); break;
+            case QBSM_BF16X3: QB_PACK(float, m.v32.p, QBSM_BF16X3); break;
+        }
+    }
+#undef QB_PACK
+    QB_LAUNCH_CHECK();
+}
+
+PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
+    const int bs = m.bs;
+    const int bk = mode_bk(mode, bs);
+    const int64_t n2 = (int64_t)bs * bs;
+    PackView v;
+    // the stored column-major pool already is a column-line layout with
+    // line stride bs and chunk stride bk
+    if (role == ROLE_COL && ((mode == QBSM_F64 && m.storage == ST_F64) ||
+                             (mode == QBSM_F32 && m.storage == ST_F32))) {
+        v.ptr = m.storage == ST_F64 ? (const void *)m.v64.p : (const void *)m.v32.p;
+        v.leaf_stride = n2;
+        v.part_stride = 0;
+        v.line_stride = bs;
+        v.chunk_stride = bk;
+        return v;
+    }
+    auto key = std::make_pair((int)mode, (int)role);
+    Pack &pk = m.packs[key];
+    const size_t bytes = (size_t)m.nblk * n2 * mode_elem_bytes(mode) * mode_parts(mode);
+    if (pk.buf.n != bytes || pk.version != m.version || !pk.buf.p) {
+        if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
+        pack_launch(m, mode, role, pk, s);
+        pk.version = m.version;
+    }
+    v.ptr = pk.buf.p;
+    v.leaf_stride = n2 * mode_parts(mode);
+    v.part_stride = n2;
+    v.line_stride = bk;
+    v.chunk_stride = (int32_t)((int64_t)bs * bk);
+    return v;
+}
+
+}  // namespace qbsm

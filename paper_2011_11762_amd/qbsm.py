@@ -1,0 +1,341 @@
+"""Thin Python binding of libqbsm (the C ABI in ``include/qbsm.h``).
+
+Argument marshalling only: every step of the multiply runs in the library's
+HIP kernels.  PyTorch provides device memory (the library allocates through
+torch's caching allocator once :func:`load` has installed the hooks) and
+streams (every call uses ``torch.cuda.current_stream()``).
+
+The library must have been built (``python -m paper_2011_11762_amd.build``);
+importing works without it, but every call raises if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_size_t, c_void_p
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqbsm.so")
+
+F64, F32, BF16, BF16X3 = 0, 1, 2, 3
+MODES = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
+MODE_NAMES = {v: k for k, v in MODES.items()}
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "invalid block pattern",
+          4: "out of device memory", 5: "HIP runtime error", 6: "unsupported", 7: "invalid state"}
+
+
+class QbsmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("unit", c_int32), ("reserved", c_int32 * 7)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
+_RELEASE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p)
+
+_lib = None
+_hooks = None
+
+_SIGS = {
+    "qbsm_set_allocator": [_ALLOC_FN, _RELEASE_FN, c_void_p],
+    "qbsm_status_string": [c_int32],
+    "qbsm_last_error": [],
+    "qbsm_version": [],
+    "qbsm_matrix_create": [c_int64, c_int64, c_int32, POINTER(c_void_p)],
+    "qbsm_matrix_destroy": [c_void_p],
+    "qbsm_matrix_set_blocks": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
+                               POINTER(c_int64)],
+    "qbsm_matrix_info": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)],
+    "qbsm_matrix_get_pattern": [c_void_p, c_void_p, c_void_p, c_void_p],
+    "qbsm_matrix_get_values": [c_void_p, c_void_p, c_void_p],
+    "qbsm_multiply_symbolic": [c_void_p, c_void_p, POINTER(PlanOpts), c_void_p, POINTER(c_void_p),
+                               POINTER(c_int64), POINTER(c_int64)],
+    "qbsm_multiply_symbolic_ex": [c_void_p, c_int32, c_void_p, c_int32, c_void_p, POINTER(PlanOpts), c_void_p,
+                                  POINTER(c_void_p), POINTER(c_int64), POINTER(c_int64)],
+    "qbsm_plan_info": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), POINTER(c_int32),
+                       POINTER(c_int64), POINTER(c_int64)],
+    "qbsm_plan_get_products": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
+    "qbsm_plan_destroy": [c_void_p],
+    "qbsm_multiply_numeric": [c_void_p, c_int32, c_void_p, c_void_p],
+    "qbsm_multiply_backward": [c_void_p, c_void_p, c_void_p, c_int32, POINTER(PlanOpts), c_void_p, c_void_p,
+                               c_void_p],
+    "qbsm_batch_create": [c_int32, POINTER(c_void_p), c_int32, POINTER(c_void_p), c_void_p, POINTER(c_void_p)],
+    "qbsm_batch_run": [c_void_p, c_void_p],
+    "qbsm_batch_run_graph": [c_void_p, c_void_p],
+    "qbsm_batch_set_occupancy": [c_void_p, c_int32],
+    "qbsm_batch_destroy": [c_void_p],
+    "qbsm_autotune_unit": [c_void_p, c_void_p, c_int32, c_int32, c_void_p, POINTER(c_int32), POINTER(c_double)],
+}
+
+ABI_SYMBOLS = tuple(_SIGS)
+
+
+def load(install_torch_allocator: bool = True):
+    """Loads libqbsm.so (raises if it has not been built)."""
+    global _lib, _hooks
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2011_11762_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = c_char_p if name in ("qbsm_status_string", "qbsm_last_error") else c_int32
+    _lib = lib
+    if install_torch_allocator and torch.cuda.is_available():
+        _install_torch_allocator()
+    return lib
+
+
+def _install_torch_allocator():
+    global _hooks
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                      int(stream or 0))
+        except Exception:  # out of memory -> NULL, the library reports it
+            return None
+
+    def _release(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    _hooks = (_ALLOC_FN(_alloc), _RELEASE_FN(_release))
+    _check(_lib.qbsm_set_allocator(_hooks[0], _hooks[1], None))
+
+
+def _check(st: int):
+    if st != 0:
+        msg = _lib.qbsm_last_error()
+        raise QbsmError(st, msg.decode() if msg else "")
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    return c_void_p(t.data_ptr() if t is not None and t.numel() else None)
+
+
+def mode_id(mode) -> int:
+    return MODES[mode] if isinstance(mode, str) else int(mode)
+
+
+# --------------------------------------------------------------------------
+class Matrix:
+    """A block-sparse matrix handle (device-resident sparse quadtree)."""
+
+    def __init__(self, nrows: int, ncols: int, bs: int):
+        load()
+        h = c_void_p()
+        _check(_lib.qbsm_matrix_create(int(nrows), int(ncols), int(bs), ctypes.byref(h)))
+        self._h = h
+        self.nrows, self.ncols, self.bs = int(nrows), int(ncols), int(bs)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qbsm_matrix_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_blocks(self, brow: torch.Tensor, bcol: torch.Tensor, vals: torch.Tensor,
+                   drop_tol: float = 0.0) -> int:
+        """brow/bcol: int32 cuda [n]; vals: float64 cuda [n, bs*bs] column-major blocks."""
+        n = int(brow.numel())
+        assert brow.dtype == torch.int32 and bcol.dtype == torch.int32 and vals.dtype == torch.float64
+        assert brow.is_contiguous() and bcol.is_contiguous() and vals.is_contiguous()
+        assert vals.numel() == n * self.bs * self.bs
+        kept = c_int64()
+        _check(_lib.qbsm_matrix_set_blocks(self._h, n, _ptr(brow), _ptr(bcol), _ptr(vals),
+                                           float(drop_tol), _stream(), ctypes.byref(kept)))
+        return kept.value
+
+    @property
+    def nblk(self) -> int:
+        n = c_int64()
+        _check(_lib.qbsm_matrix_info(self._h, None, None, None, ctypes.byref(n)))
+        return n.value
+
+    def pattern(self):
+        n = self.nblk
+        brow = torch.empty(n, dtype=torch.int32, device="cuda")
+        bcol = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(_lib.qbsm_matrix_get_pattern(self._h, _ptr(brow), _ptr(bcol), _stream()))
+        return brow, bcol
+
+    def values(self) -> torch.Tensor:
+        n = self.nblk
+        out = torch.empty((n, self.bs * self.bs), dtype=torch.float64, device="cuda")
+        _check(_lib.qbsm_matrix_get_values(self._h, _ptr(out), _stream()))
+        return out
+
+
+class Plan:
+    """Symbolic phase result (work list + output pattern) of op(L) op(R) [masked]."""
+
+    def __init__(self, L: Matrix, R: Matrix, trans_l=False, trans_r=False, mask: Matrix | None = None,
+                 unit: int = 0):
+        load()
+        h = c_void_p()
+        nout, nprod = c_int64(), c_int64()
+        opts = PlanOpts(unit=int(unit))
+        _check(_lib.qbsm_multiply_symbolic_ex(L.handle, int(trans_l), R.handle, int(trans_r),
+                                              mask.handle if mask is not None else None, ctypes.byref(opts),
+                                              _stream(), ctypes.byref(h), ctypes.byref(nout),
+                                              ctypes.byref(nprod)))
+        self._h = h
+        self._keep = (L, R, mask)  # the plan refers to these handles
+        self.nrows = L.ncols if trans_l else L.nrows
+        self.ncols = R.nrows if trans_r else R.ncols
+        self.bs = L.bs
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qbsm_plan_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        v = [c_int64(), c_int64(), c_int64(), c_int32(), c_int64(), c_int64()]
+        _check(_lib.qbsm_plan_info(self._h, *[ctypes.byref(x) for x in v]))
+        keys = ("nblk_out", "nprod", "flops", "unit", "nunits", "npairs")
+        return {k: x.value for k, x in zip(keys, v)}
+
+    def products(self):
+        n = self.info()["nprod"]
+        I, K, J = (torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(3))
+        _check(_lib.qbsm_plan_get_products(self._h, _ptr(I), _ptr(K), _ptr(J), _stream()))
+        return I, K, J
+
+    def numeric(self, mode, out: Matrix | None = None) -> Matrix:
+        if out is None:
+            out = Matrix(self.nrows, self.ncols, self.bs)
+        _check(_lib.qbsm_multiply_numeric(self._h, mode_id(mode), out.handle, _stream()))
+        return out
+
+
+def matmul(A: Matrix, B: Matrix, mode="f64", unit: int = 0) -> Matrix:
+    """C = A B (symbolic + numeric)."""
+    return Plan(A, B, unit=unit).numeric(mode)
+
+
+def backward(A: Matrix, B: Matrix, dC: Matrix, mode="f64", unit: int = 0, need_a=True, need_b=True):
+    """dA = (dC B^T) on A's pattern, dB = (A^T dC) on B's pattern."""
+    dA = Matrix(A.nrows, A.ncols, A.bs) if need_a else None
+    dB = Matrix(B.nrows, B.ncols, B.bs) if need_b else None
+    opts = PlanOpts(unit=int(unit))
+    _check(_lib.qbsm_multiply_backward(A.handle, B.handle, dC.handle, mode_id(mode), ctypes.byref(opts),
+                                       dA.handle if dA is not None else None,
+                                       dB.handle if dB is not None else None, _stream()))
+    return dA, dB
+
+
+class Batch:
+    """Batched numeric phase: one persistent launch (optionally a replayed HIP graph)."""
+
+    def __init__(self, plans, mode, outs=None):
+        load()
+        self.plans = list(plans)
+        self.outs = outs if outs is not None else [Matrix(p.nrows, p.ncols, p.bs) for p in self.plans]
+        n = len(self.plans)
+        ph = (c_void_p * n)(*[p.handle.value for p in self.plans])
+        oh = (c_void_p * n)(*[o.handle.value for o in self.outs])
+        h = c_void_p()
+        _check(_lib.qbsm_batch_create(n, ph, mode_id(mode), oh, _stream(), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.qbsm_batch_destroy(h)
+            self._h = None
+
+    def run(self):
+        _check(_lib.qbsm_batch_run(self._h, _stream()))
+
+    def run_graph(self):
+        _check(_lib.qbsm_batch_run_graph(self._h, _stream()))
+
+    def set_occupancy(self, wg_per_cu: int):
+        _check(_lib.qbsm_batch_set_occupancy(self._h, int(wg_per_cu)))
+
+
+def autotune_unit(A: Matrix, B: Matrix, mode, reps: int = 3):
+    best = c_int32()
+    times = (c_double * 2)()
+    _check(_lib.qbsm_autotune_unit(A.handle, B.handle, mode_id(mode), int(reps), _stream(),
+                                   ctypes.byref(best), times))
+    return best.value, {64: times[0], 128: times[1]}
+
+
+# --------------------------------------------------------------------------
+# Convenience: host BlockMatrix (paper_2011_11762_amd.workloads) -> device handle
+def from_host(m, drop_tol: float = 0.0) -> Matrix:
+    h = Matrix(m.nrows, m.ncols, m.bs)
+    brow = torch.from_numpy(m.brow.astype("int32")).cuda()
+    bcol = torch.from_numpy(m.bcol.astype("int32")).cuda()
+    vals = torch.from_numpy(m.vals).cuda()
+    h.set_blocks(brow, bcol, vals, drop_tol)
+    return h
+
+
+# --------------------------------------------------------------------------
+# Autograd: gradients with respect to the block values
+class _MatmulFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, a_vals, b_vals, a_pat, b_pat, shapes, mode, unit):
+        (m, k, n, bs) = shapes
+        A = Matrix(m, k, bs)
+        B = Matrix(k, n, bs)
+        A.set_blocks(a_pat[0], a_pat[1], a_vals.detach().contiguous())
+        B.set_blocks(b_pat[0], b_pat[1], b_vals.detach().contiguous())
+        C = Plan(A, B, unit=unit).numeric(mode)
+        cr, cc = C.pattern()
+        ctx.save_for_backward(cr, cc)
+        ctx.handles = (A, B)
+        ctx.meta = (m, n, bs, mode, unit)
+        ctx.mark_non_differentiable(cr, cc)
+        return C.values(), cr, cc
+
+    @staticmethod
+    def backward(ctx, g_vals, _g1, _g2):
+        cr, cc = ctx.saved_tensors
+        A, B = ctx.handles
+        m, n, bs, mode, unit = ctx.meta
+        dC = Matrix(m, n, bs)
+        dC.set_blocks(cr, cc, g_vals.contiguous().to(torch.float64))
+        dA, dB = backward(A, B, dC, mode, unit, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        ga = dA.values() if dA is not None else None
+        gb = dB.values() if dB is not None else None
+        return ga, gb, None, None, None, None, None
+
+
+def block_matmul(a_vals, a_pat, b_vals, b_pat, m, k, n, bs, mode="f64", unit=0):
+    """Differentiable C = A B on block values.
+
+    a_pat / b_pat are (brow, bcol) int32 cuda tensors in canonical row-major
+    order (the order the library reports patterns in), so that gradients
+    line up with the value rows.  Returns (c_vals, c_brow, c_bcol).
+    """
+    for r, c in (a_pat, b_pat):
+        key = r.to(torch.int64) * (max(k, n) // bs + 2) + c.to(torch.int64)
+        if key.numel() > 1 and not bool((key[1:] > key[:-1]).all()):
+            raise ValueError("block patterns must be in canonical row-major order")
+    return _MatmulFn.apply(a_vals, b_vals, a_pat, b_pat, (m, k, n, bs), mode_id(mode), int(unit))

@@ -41,6 +41,7 @@ __all__ = [
     "config4_member",
     "config5",
     "small_random",
+    "zero_padding",
 ]
 
 
@@ -83,7 +84,7 @@ def _pad_mask(n_logical: int, bs: int, b: int) -> int:
     return max(0, min(bs, n_logical - b * bs))
 
 
-def _zero_padding(m: BlockMatrix) -> None:
+def zero_padding(m: BlockMatrix) -> None:
     """Zero the elements of edge blocks that lie beyond the logical size."""
     bs = m.bs
     if m.nrows % bs == 0 and m.ncols % bs == 0:
@@ -121,7 +122,7 @@ def banded(n: int, bs: int, h: int, rng, ncols: int | None = None,
     m = BlockMatrix(n, ncols, bs, brow, bcol,
                     _fill_uniform(rng, brow.shape[0], bs, fp32_values),
                     {"kind": "banded", "h": h})
-    _zero_padding(m)
+    zero_padding(m)
     return m
 
 
@@ -135,7 +136,7 @@ def random_blocks(n: int, bs: int, p: float, rng, ncols: int | None = None,
     m = BlockMatrix(n, ncols, bs, brow, bcol,
                     _fill_uniform(rng, brow.shape[0], bs, fp32_values),
                     {"kind": "random", "p": p})
-    _zero_padding(m)
+    zero_padding(m)
     return m
 
 

@@ -1,0 +1,69 @@
+"""Shared helpers of the GPU parity tests (device upload, oracle comparison)."""
+import numpy as np
+import torch
+
+from oracle import oracle as O
+
+# relative Frobenius tolerances against the FP64 oracle on the original inputs
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2, "bf16x3": 1e-4}
+# BF16: against the FP64 oracle applied to the bf16-rounded inputs (isolates
+# the FP32 accumulation)
+TOL_BF16_ROUNDED = 1e-5
+UNITS = {32: (64, 128), 64: (64, 128), 128: (128,)}
+
+
+def upload(q, m, drop_tol=0.0):
+    return q.from_host(m, drop_tol)
+
+
+def pattern_np(M):
+    r, c = M.pattern()
+    return r.cpu().numpy().astype(np.int64), c.cpu().numpy().astype(np.int64)
+
+
+def values_np(M):
+    return M.values().cpu().numpy()
+
+
+def rounded(om, fn):
+    return O.OMatrix(om.nrows, om.ncols, om.bs, om.brow, om.bcol, fn(om.vals))
+
+
+def check_product(q, a, b, mode, unit, drop_tol=0.0, ref=None, check_products=True):
+    """Runs C = A B on the GPU and compares with the oracle; returns (C, ref, err)."""
+    A = upload(q, a, drop_tol)
+    B = A if b is a else upload(q, b, drop_tol)
+    oa = O.from_workload(a, drop_tol)
+    ob = oa if b is a else O.from_workload(b, drop_tol)
+    if ref is None:
+        ref = O.multiply(oa, ob)
+    P = q.Plan(A, B, unit=unit)
+    info = P.info()
+    C = P.numeric(mode)
+    torch.cuda.synchronize()
+    cr, cc = pattern_np(C)
+    assert np.array_equal(cr, ref.brow) and np.array_equal(cc, ref.bcol), "C pattern differs"
+    assert info["nblk_out"] == ref.brow.size and info["nprod"] == ref.I.size
+    assert info["flops"] == O.block_flops(ref.I, ref.J, ref.K, a.nrows, a.ncols, b.ncols, a.bs)
+    if check_products:
+        I, K, J = (t.cpu().numpy().astype(np.int64) for t in P.products())
+        assert np.array_equal(I, ref.I) and np.array_equal(J, ref.J) and np.array_equal(K, ref.K), \
+            "product list differs"
+    got = values_np(C)
+    err = O.rel_fro(got, ref.vals)
+    assert err <= TOL[mode], f"{mode} unit={unit}: rel err {err:.3e} > {TOL[mode]:.1e}"
+    if mode == "bf16":
+        rr = O.multiply(rounded(oa, O.round_to_bf16), rounded(ob, O.round_to_bf16))
+        e2 = O.rel_fro(got, rr.vals)
+        assert e2 <= TOL_BF16_ROUNDED, f"bf16 vs rounded-input oracle {e2:.3e}"
+    return C, ref, err, got
+
+
+def padding_is_zero(vals, brow, bcol, nrows, ncols, bs):
+    v = vals.reshape(-1, bs, bs)  # [blk, c, r]
+    for t in range(brow.size):
+        mr = min(bs, nrows - brow[t] * bs)
+        nc = min(bs, ncols - bcol[t] * bs)
+        if np.any(v[t, nc:, :] != 0) or np.any(v[t, :, mr:] != 0):
+            return False
+    return True

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Patterns and product lists bit-exact; values within the per-mode relative
+Frobenius tolerances of tests/gpu_helpers.py.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_11762_amd import workloads as W
+from tests.gpu_helpers import TOL, UNITS, check_product, padding_is_zero, pattern_np, upload, values_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2011_11762_amd import qbsm
+    assert torch.cuda.is_available()
+    qbsm.load()
+    return qbsm
+
+
+SMALL = [
+    # (m, k, n, bs, p, seed): rectangular, ragged in every dimension
+    (300, 260, 200, 64, 0.5, 1),
+    (190, 170, 150, 32, 0.5, 2),
+    (400, 300, 520, 128, 0.6, 3),
+    (1000, 900, 1100, 32, 0.15, 4),   # deeper tree, several units per side
+    (64 * 9 + 5, 64 * 7, 64 * 11 + 63, 64, 0.3, 5),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-bs{c[3]}")
+@pytest.mark.parametrize("mode", ["f64", "f32", "bf16", "bf16x3"])
+def test_small_random(q, case, mode):
+    m, k, n, bs, p, seed = case
+    a, b = W.small_random(m, k, n, bs, p, seed)
+    for unit in UNITS[bs]:
+        C, ref, err, got = check_product(q, a, b, mode, unit)
+        assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
+
+
+def test_config1_full_f64(q):
+    c = W.config1()
+    for unit in UNITS[32]:
+        C, ref, err, _ = check_product(q, c["A"], c["B"], "f64", unit)
+        assert ref.brow.size == 1016 and ref.I.size == 4884
+
+
+def test_empty_and_degenerate(q):
+    bs = 64
+    rng = np.random.default_rng(0)
+    # A empty
+    a = W.random_blocks(200, bs, 0.0, rng, ncols=150)
+    b = W.random_blocks(150, bs, 1.0, rng, ncols=100)
+    A, B = upload(q, a), upload(q, b)
+    C = q.matmul(A, B, "f64")
+    assert C.nblk == 0 and C.values().numel() == 0
+    # disjoint inner patterns -> no product
+    a2 = W.BlockMatrix(128, 128, 64, np.array([0], np.int32), np.array([0], np.int32), rng.uniform(-1, 1, (1, 4096)))
+    b2 = W.BlockMatrix(128, 128, 64, np.array([1], np.int32), np.array([1], np.int32), rng.uniform(-1, 1, (1, 4096)))
+    C2 = q.matmul(upload(q, a2), upload(q, b2), "f32")
+    assert C2.nblk == 0
+    # a single block smaller than the leaf (1x1 block grid, ragged)
+    for mode in ("f64", "f32", "bf16x3"):
+        a3, b3 = W.small_random(37, 50, 21, 64, 1.0, 9)
+        check_product(q, a3, b3, mode, 64)
+    # depth mismatch: tall-skinny times short-wide
+    a4, b4 = W.small_random(64 * 40, 64, 64 * 3, 64, 0.7, 10)
+    check_product(q, a4, b4, "f64", 128)
+
+
+def test_determinism(q):
+    a, b = W.small_random(1000, 1000, 1000, 64, 0.3, 11)
+    A, B = upload(q, a), upload(q, b)
+    for mode in ("f64", "f32", "bf16x3"):
+        P = q.Plan(A, B)
+        outs = [values_np(P.numeric(mode)) for _ in range(3)]
+        assert all(np.array_equal(outs[0], o) for o in outs[1:]), mode
+
+
+def test_drop_rule_decay(q):
+    pts = W.decay_points(2048, 0.1, np.random.default_rng(12))
+    a = W.decay_blocks(pts, 64)
+    tol = 1e-3  # keeps a visibly sparse pattern at this small size
+    assert not np.any(O.borderline(a.vals, 64, tol))
+    keep = O.keep_mask(a.vals, 64, tol)
+    A = upload(q, a, tol)
+    assert A.nblk == int(keep.sum())
+    r, c = pattern_np(A)
+    oa = O.from_workload(a, tol)
+    assert np.array_equal(r, oa.brow) and np.array_equal(c, oa.bcol)
+    assert np.array_equal(values_np(A), oa.vals)
+    check_product(q, a, a, "f64", 128, drop_tol=tol)
+
+
+def test_nan_inf_propagate(q):
+    a, b = W.small_random(256, 256, 256, 64, 1.0, 13)
+    a.vals[5, 17] = np.nan
+    a.vals[9, 100] = np.inf
+    for mode in ("f64", "f32"):
+        A, B = upload(q, a), upload(q, b)
+        got = values_np(q.matmul(A, B, mode))
+        ref = O.multiply(O.from_workload(a), O.from_workload(b)).vals
+        assert np.array_equal(np.isnan(got), np.isnan(ref))
+        assert np.array_equal(np.isinf(got), np.isinf(ref))
+        fin = np.isfinite(ref)
+        assert np.allclose(got[fin], ref[fin], rtol=1e-5 if mode == "f32" else 1e-12, atol=1e-4)
+    # NaN norm keeps the block under a drop tolerance
+    A = upload(q, a, 1e30)
+    assert A.nblk == 2  # only the NaN block and the Inf block survive
+
+
+def test_error_paths(q):
+    lib = q.load()
+    a, b = W.small_random(128, 128, 192, 64, 1.0, 14)
+    A, B = upload(q, a), upload(q, b)
+    with pytest.raises(q.QbsmError) as e:
+        q.Plan(B, A)  # 128x192 times 128x128: inner dims differ
+    assert e.value.status == 2
+    C32 = q.Matrix(128, 128, 32)
+    C32.set_blocks(torch.zeros(1, dtype=torch.int32, device="cuda"), torch.zeros(1, dtype=torch.int32, device="cuda"),
+                   torch.zeros(1, 1024, dtype=torch.float64, device="cuda"))
+    with pytest.raises(q.QbsmError) as e:
+        q.Plan(A, C32)
+    assert e.value.status == 2
+    M = q.Matrix(128, 128, 64)
+    v = torch.zeros(2, 4096, dtype=torch.float64, device="cuda")
+    with pytest.raises(q.QbsmError) as e:  # duplicate
+        M.set_blocks(torch.tensor([0, 0], dtype=torch.int32, device="cuda"),
+                     torch.tensor([1, 1], dtype=torch.int32, device="cuda"), v)
+    assert e.value.status == 3
+    with pytest.raises(q.QbsmError) as e:  # out of range
+        M.set_blocks(torch.tensor([0, 2], dtype=torch.int32, device="cuda"),
+                     torch.tensor([1, 0], dtype=torch.int32, device="cuda"), v)
+    assert e.value.status == 3
+    with pytest.raises(q.QbsmError) as e:  # never given blocks
+        q.Plan(M, B)
+    assert e.value.status == 7
+    # null pointers through the raw ABI
+    assert lib.qbsm_matrix_set_blocks(M.handle, 2, None, None, None, 0.0, None, None) == 1
+    assert lib.qbsm_multiply_numeric(None, 0, None, None) == 1
+    assert lib.qbsm_multiply_numeric(q.Plan(A, B).handle, 9, M.handle, None) == 1
+    # output with the wrong shape
+    P = q.Plan(A, B)
+    with pytest.raises(q.QbsmError) as e:
+        P.numeric("f64", q.Matrix(128, 128, 64))
+    assert e.value.status == 2
+    # the allocator returning NULL -> out of memory, no abort
+    fail_alloc = q._ALLOC_FN(lambda n, s, c: None)
+    rel = q._RELEASE_FN(lambda p, s, c: None)
+    assert lib.qbsm_set_allocator(fail_alloc, rel, None) == 0
+    try:
+        st = lib.qbsm_multiply_symbolic(A.handle, B.handle, None, None, ctypes.byref(ctypes.c_void_p()), None, None)
+        assert st == 4
+    finally:
+        q._install_torch_allocator()
+    # still usable afterwards
+    check_product(q, a, b, "f64", 128)
+
+
+def test_backward_small_vs_oracle(q):
+    for (m, k, n, bs, p, seed) in [(300, 260, 200, 64, 0.5, 21), (190, 170, 150, 32, 0.6, 22),
+                                    (400, 300, 520, 128, 0.6, 23)]:
+        a, b = W.small_random(m, k, n, bs, p, seed)
+        oa, ob = O.from_workload(a), O.from_workload(b)
+        ref = O.multiply(oa, ob)
+        rng = np.random.default_rng(seed)
+        dcv = rng.uniform(-1, 1, size=ref.vals.shape)
+        W.zero_padding(W.BlockMatrix(m, n, bs, ref.brow, ref.bcol, dcv))
+        odc = O.canonical(m, n, bs, ref.brow, ref.bcol, dcv)
+        ga, gb = O.backward(oa, ob, odc)
+        A, B = upload(q, a), upload(q, b)
+        dC = q.Matrix(m, n, bs)
+        dC.set_blocks(torch.from_numpy(ref.brow.astype(np.int32)).cuda(),
+                      torch.from_numpy(ref.bcol.astype(np.int32)).cuda(), torch.from_numpy(dcv).cuda())
+        for mode in ("f64", "f32", "bf16x3"):
+            for unit in UNITS[bs]:
+                dA, dB = q.backward(A, B, dC, mode, unit)
+                ra, ca = pattern_np(dA)
+                assert np.array_equal(ra, oa.brow) and np.array_equal(ca, oa.bcol)
+                rb, cb = pattern_np(dB)
+                assert np.array_equal(rb, ob.brow) and np.array_equal(cb, ob.bcol)
+                ea = O.rel_fro(values_np(dA), ga)
+                eb = O.rel_fro(values_np(dB), gb)
+                assert ea <= TOL[mode] and eb <= TOL[mode], (mode, unit, ea, eb)
+
+
+def test_masked_plan_products(q):
+    a, b = W.small_random(300, 260, 200, 64, 0.5, 31)
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    ref = O.multiply(oa, ob)
+    A, B = upload(q, a), upload(q, b)
+    dC = q.Matrix(300, 200, 64)
+    dC.set_blocks(torch.from_numpy(ref.brow.astype(np.int32)).cuda(),
+                  torch.from_numpy(ref.bcol.astype(np.int32)).cuda(), torch.from_numpy(ref.vals).cuda())
+    # dA plan: dC * B^T restricted to A: its products are the forward triples regrouped by (I, K)
+    P = q.Plan(dC, B, trans_r=True, mask=A, unit=128)
+    I, K, J = (t.cpu().numpy().astype(np.int64) for t in P.products())
+    fw = sorted(zip(ref.I.tolist(), ref.K.tolist(), ref.J.tolist()))
+    got = sorted(zip(I.tolist(), J.tolist(), K.tolist()))  # (I, Kout=K_A, Jcontr)
+    assert got == fw
+
+
+def test_batched_matches_single_and_graph_replays(q):
+    rng = np.random.default_rng(41)
+    members = []
+    for t, (n, bs) in enumerate([(700, 32), (1000, 64), (513, 64), (900, 32), (1500, 64)]):
+        if t % 2 == 0:
+            a = W.banded(n, bs, 3, rng, fp32_values=True)
+            b = W.banded(n, bs, 3, rng, fp32_values=True)
+        else:
+            a, b = W.small_random(n, n, n, bs, 0.4, 100 + t, fp32_values=True)
+        members.append((a, b))
+    As = [(upload(q, a), upload(q, b)) for a, b in members]
+    plans = [q.Plan(A, B, unit=128) for A, B in As]
+    singles = [values_np(p.numeric("f32")) for p in plans]
+    batch = q.Batch(plans, "f32")
+    batch.run()
+    torch.cuda.synchronize()
+    for o, s in zip(batch.outs, singles):
+        assert np.array_equal(values_np(o), s)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for rep in range(3):
+            # eager work between replays
+            junk = torch.randn(1000, 1000, device="cuda") @ torch.randn(1000, 1000, device="cuda")
+            for o in batch.outs:
+                o.values()
+            batch.run_graph()
+            stream.synchronize()
+            for o, s in zip(batch.outs, singles):
+                assert np.array_equal(values_np(o), s), rep
+            del junk
+    # oracle check of every member
+    for (a, b), s in zip(members, singles):
+        ref = O.multiply(O.from_workload(a), O.from_workload(b))
+        assert O.rel_fro(s, ref.vals) <= TOL["f32"]
+
+
+def test_autograd_gradcheck(q):
+    a, b = W.small_random(80, 70, 90, 32, 0.6, 51)
+    ra, ca = (torch.from_numpy(x.astype(np.int32)).cuda() for x in (a.brow, a.bcol))
+    rb, cb = (torch.from_numpy(x.astype(np.int32)).cuda() for x in (b.brow, b.bcol))
+    av = torch.from_numpy(a.vals).cuda().requires_grad_(True)
+    bv = torch.from_numpy(b.vals).cuda().requires_grad_(True)
+    # padding entries are not free parameters of the logical matrix: mask them
+    pa = torch.from_numpy((a.vals != 0).astype(np.float64)).cuda()
+    pb = torch.from_numpy((b.vals != 0).astype(np.float64)).cuda()
+
+    def f(x, y):
+        c, _, _ = q.block_matmul(x * pa, (ra, ca), y * pb, (rb, cb), 80, 70, 90, 32, "f64")
+        return c
+
+    assert torch.autograd.gradcheck(f, (av, bv), eps=1e-6, atol=1e-8, rtol=1e-6, fast_mode=True)
+    # FP64 oracle gradient of L = sum(C * W)
+    c = f(av, bv)
+    w = torch.rand_like(c)
+    (c * w).sum().backward()
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    ref = O.multiply(oa, ob)
+    odc = O.canonical(80, 90, 32, ref.brow, ref.bcol, w.detach().cpu().numpy())
+    ga, gb = O.backward(oa, ob, odc)
+    assert O.rel_fro(av.grad.cpu().numpy() * (a.vals != 0), ga * (a.vals != 0)) <= 1e-12
+    assert O.rel_fro(bv.grad.cpu().numpy() * (b.vals != 0), gb * (b.vals != 0)) <= 1e-12
+
+
+def test_autotune_unit(q):
+    a, b = W.small_random(2048, 2048, 2048, 64, 0.3, 61)
+    A, B = upload(q, a), upload(q, b)
+    best, times = q.autotune_unit(A, B, "f32", reps=2)
+    assert best in (64, 128) and times[best] > 0
