@@ -1,0 +1,237 @@
+"""Benchmark: block-sparse C = A A on the 3-D exponential-decay workload.
+
+Workload: 16384 points uniform in a cube at 0.1 points per cubic Angstrom,
+Morton-ordered, A_ij = exp(-0.5 |p_i - p_j|), 64 x 64 leaves, blocks with
+Frobenius norm < 1e-10 dropped (about 98% of the 256 x 256 blocks stay), A
+and B the same matrix.
+
+One step = the whole device path from FP64 leaf blocks already resident in
+HBM: construction (block norms + drop, Morton ranking, quadtree), symbolic
+phase (quadtree walk, work list, C pattern) and numeric phase (operand
+packing + the leaf-product kernel).  ``value`` is the chosen precision
+mode's effective GFLOP/s = block-level flops of the nonzero leaf products
+(2 m k n each) / step time; the plain FP64 GPU path is reported beside it,
+with each mode's relative Frobenius error on a sampled set of C blocks
+against the FP64 CPU oracle (the cpu_baseline leg).
+
+Usage: python bench.py [--steps K] [--warmup W] [--mode bf16x3] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "effective GFLOP/s on nonzero leaf products, plain FP64 vs chosen form at stated error"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+MFMA_TERMS = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3}
+DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16"}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="bf16x3", choices=["f32", "bf16", "bf16x3"])
+    ap.add_argument("--unit", type=int, default=128)
+    ap.add_argument("--npoints", type=int, default=16384)
+    ap.add_argument("--modes", default="f64,f32", help="reference modes timed beside the chosen one")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (no error statement)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline_leg(wl, tol, bs, seconds):
+    """Times the FP64 oracle on a bounded random sample of C blocks.
+
+    Returns the baseline record and the oracle's values of the sampled
+    blocks (the reference for the error statement of every mode).
+    """
+    from oracle import oracle as O
+
+    oa = O.from_workload(wl["A"], tol)
+    nb = -(-wl["A"].nrows // bs)
+    rng = np.random.default_rng(99)
+    # calibration on a few blocks, then a sample sized to the time budget
+    cal_i, cal_j = rng.integers(0, nb, 16), rng.integers(0, nb, 16)
+    t0 = time.perf_counter()
+    O.multiply_blocks(oa, oa, cal_i, cal_j)
+    dt = max(time.perf_counter() - t0, 1e-3)
+    nsample = int(min(nb * nb, max(64, 16 * seconds / dt)))
+    si, sj = rng.integers(0, nb, nsample), rng.integers(0, nb, nsample)
+    key = np.unique(si * nb + sj)
+    si, sj = key // nb, key % nb
+    # products per sampled block: common K of row I of A and column J of A
+    ncommon = 0
+    rowsets = {}
+    for i in np.unique(si):
+        rowsets[int(i)] = set(oa.bcol[oa.brow == i].tolist())
+    colsets = {}
+    for j in np.unique(sj):
+        colsets[int(j)] = set(oa.brow[oa.bcol == j].tolist())
+    for i, j in zip(si.tolist(), sj.tolist()):
+        ncommon += len(rowsets[i] & colsets[j])
+    flops = 2.0 * bs ** 3 * ncommon
+    t0 = time.perf_counter()
+    ref = O.multiply_blocks(oa, oa, si, sj)
+    el = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rec = {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
+           "sample": f"{si.size} random C blocks of the workload ({ncommon} leaf products, "
+                     f"{flops / 1e9:.1f} GFLOP) in {el:.1f} s, FP64 oracle, OpenMP over C blocks"}
+    return rec, (si, sj, ref)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not built "
+                                   "(the sharding design is described in DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2011_11762_amd import qbsm
+    from paper_2011_11762_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    qbsm.load()
+    bs, tol = 64, 1e-10
+    t_gen = time.perf_counter()
+    wl = W.config2(npoints=args.npoints, bs=bs)
+    a = wl["A"]
+    brow = torch.from_numpy(a.brow.astype(np.int32)).cuda()
+    bcol = torch.from_numpy(a.bcol.astype(np.int32)).cuda()
+    vals = torch.from_numpy(a.vals).cuda()
+    torch.cuda.synchronize()
+    print(f"[bench] workload generated and resident in HBM in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+
+    A = qbsm.Matrix(a.nrows, a.ncols, bs)
+    C = qbsm.Matrix(a.nrows, a.ncols, bs)
+    state = {}
+
+    def step(mode):
+        A.set_blocks(brow, bcol, vals, tol)
+        P = qbsm.Plan(A, A, unit=args.unit)
+        P.numeric(mode, C)
+        state["plan"] = P
+
+    def time_mode(mode, steps, warmup, profile):
+        for _ in range(warmup):
+            step(mode)
+        torch.cuda.synchronize()
+        if profile:
+            qbsm.profile_reset()
+            qbsm.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kern = None
+        if profile:
+            qbsm.profile_enable(False)
+            n, tot = qbsm.profile_read(qbsm.PROF_NUMERIC)
+            kern = tot / max(n, 1)
+            qbsm.profile_reset()
+        info = state["plan"].info()
+        # numeric phase alone on the last plan (operands already packed)
+        P = state["plan"]
+        P.numeric(mode, C)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(steps):
+            P.numeric(mode, C)
+        torch.cuda.synchronize()
+        num_ms = (time.perf_counter() - t1) / steps * 1e3
+        return el / steps * 1e3, kern, num_ms, info
+
+    modes = [m for m in args.modes.split(",") if m and m != args.mode] + [args.mode]
+    results = {}
+    for mode in modes:
+        ms, kern, num_ms, info = time_mode(mode, args.steps, args.warmup, profile=True)
+        flops = info["flops"]
+        results[mode] = {
+            "ms_per_step": round(ms, 4),
+            "effective_gflops": round(flops / (ms * 1e-3) / 1e9, 2),
+            "numeric_ms": round(num_ms, 4),
+            "numeric_gflops": round(flops / (num_ms * 1e-3) / 1e9, 2),
+            "kernel_ms": round(kern, 4),
+            "kernel_mfma_tflops": round(MFMA_TERMS[mode] * flops / (kern * 1e-3) / 1e12, 2),
+        }
+        print(f"[bench] {mode}: {ms:.3f} ms/step, {results[mode]['effective_gflops']} GFLOP/s "
+              f"(kernel {kern:.3f} ms)", file=sys.stderr, flush=True)
+        results[mode]["_vals"] = None
+    info = state["plan"].info()
+
+    # CPU oracle leg: baseline timing + reference values of sampled C blocks
+    cpu = None
+    if not args.no_cpu:
+        cpu, (si, sj, ref) = cpu_baseline_leg(wl, tol, bs, args.cpu_seconds)
+        nbc = -(-a.ncols // bs)
+        for mode in modes:
+            step(mode)
+            cr, cc = C.pattern()
+            key = cr.to(torch.int64) * nbc + cc.to(torch.int64)
+            want = torch.from_numpy(si * nbc + sj).cuda()
+            pos = torch.searchsorted(key, want)
+            got = C.values()[pos].cpu().numpy()
+            err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+            results[mode]["rel_err_vs_fp64_oracle"] = float(f"{err:.3e}")
+        print(f"[bench] cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads", file=sys.stderr,
+              flush=True)
+    for mode in modes:
+        results[mode].pop("_vals", None)
+
+    ch = results[args.mode]
+    f64 = results.get("f64")
+    peak = PEAK_TFLOPS[args.mode]
+    achieved = ch["kernel_mfma_tflops"]
+    out = {
+        "metric": METRIC,
+        "value": ch["effective_gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ch["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.mode],
+        "data": "synthetic",
+        "config": {
+            "workload": f"decay3d-n{args.npoints}-bs{bs}-tol1e-10 (C = A*A, {info['nblk_out']} C blocks, "
+                        f"{info['nprod']} leaf products)",
+            "mode": args.mode,
+            "unit": info["unit"],
+            "flops_per_step": info["flops"],
+            "step": "set_blocks(norms+drop, Morton rank, quadtree) + symbolic + numeric(pack + MFMA kernel)",
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": None,
+            "kernel": f"numeric leaf-product kernel, mode {args.mode}, unit {info['unit']} "
+                      f"({MFMA_TERMS[args.mode]} MFMA term(s) per leaf product)",
+        },
+        "modes": results,
+        "vs_f64_gpu": round(ch["effective_gflops"] / f64["effective_gflops"], 3) if f64 else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

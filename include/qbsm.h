@@ -225,6 +225,17 @@ qbsm_status qbsm_batch_destroy(qbsm_batch batch);
 qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps,
                                void *stream, int32_t *best_unit, double *times_ms);
 
+/* --------------------------------------------------------------- profiling */
+
+/* Kernel timing: when enabled, HIP events are recorded on the launch stream
+ * around every launch of the given kernel class (0 = numeric leaf-product
+ * kernel, 1 = operand packing).  qbsm_profile_read synchronises the
+ * recorded events and returns the launch count and summed GPU time in ms
+ * since the last reset.  Not thread safe; off by default. */
+qbsm_status qbsm_profile_enable(int32_t on);
+qbsm_status qbsm_profile_reset(void);
+qbsm_status qbsm_profile_read(int32_t kernel_class, int64_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

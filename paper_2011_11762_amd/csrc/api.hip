@@ -62,6 +62,38 @@ int device_cu_count() {
     return n;
 }
 
+namespace {
+struct ProfState {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[PROF_NCLASS];
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get() {
+        hipEvent_t e = nullptr;
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+};
+ProfState g_prof;
+}  // namespace
+
+ProfScope::ProfScope(int c, hipStream_t st) : cls(c), s(st) {
+    if (!g_prof.on) return;
+    hipEvent_t e0 = g_prof.get();
+    e1 = g_prof.get();
+    if (!e0 || !e1) { e1 = nullptr; return; }
+    (void)hipEventRecord(e0, s);
+    g_prof.ev[cls].push_back({e0, e1});
+}
+
+ProfScope::~ProfScope() {
+    if (e1) (void)hipEventRecord(e1, s);
+}
+
 }  // namespace qbsm
 
 using namespace qbsm;
@@ -419,6 +451,38 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *best_unit = bu;
+    });
+}
+
+qbsm_status qbsm_profile_enable(int32_t on) {
+    return guard([&] { g_prof.on = on != 0; });
+}
+
+qbsm_status qbsm_profile_reset(void) {
+    return guard([&] {
+        for (auto &v : g_prof.ev) {
+            for (auto &p : v) {
+                QB_HIP(hipEventSynchronize(p.second));
+                g_prof.pool.push_back(p.first);
+                g_prof.pool.push_back(p.second);
+            }
+            v.clear();
+        }
+    });
+}
+
+qbsm_status qbsm_profile_read(int32_t kernel_class, int64_t *launches, double *total_ms) {
+    return guard([&] {
+        QB_CHECK(kernel_class >= 0 && kernel_class < PROF_NCLASS, QBSM_ERR_ARG, "kernel class");
+        double tot = 0.0;
+        for (auto &p : g_prof.ev[kernel_class]) {
+            QB_HIP(hipEventSynchronize(p.second));
+            float ms = 0.f;
+            QB_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+            tot += ms;
+        }
+        if (launches) *launches = (int64_t)g_prof.ev[kernel_class].size();
+        if (total_ms) *total_ms = tot;
     });
 }
 

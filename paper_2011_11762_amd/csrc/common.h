@@ -144,6 +144,7 @@ struct Matrix {
     DArr<float> v32;      // FP32 values when the matrix is an FP32 result
     Storage storage = ST_NONE;
     uint64_t version = 0;    // bumped on every value change
+    uint64_t filled_by = 0;  // id of the plan that last wrote this matrix as an output
     uint64_t pattern_id = 0; // bumped on every pattern change
     std::map<int, std::unique_ptr<Tree>> trees;         // by depth
     std::map<std::pair<int, int>, Pack> packs;          // (mode, role)
@@ -166,6 +167,7 @@ struct Plan {
     DArr<int32_t> cdesc;    // [nunits * lpu*lpu] output leaf index, -1 none (row-major ib,jb)
     DArr<uint32_t> okeys;   // [nout] output Morton keys (unmasked plans)
     hipStream_t stream = nullptr;
+    uint64_t id = 0;        // process-unique plan id
 };
 
 struct Allocator {
@@ -249,5 +251,15 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t nmembe
                const K5Member &single, hipStream_t s);
 
 int device_cu_count();
+
+// Optional event timing around kernel launches (kernel classes below).
+enum ProfClass { PROF_NUMERIC = 0, PROF_PACK = 1, PROF_NCLASS = 2 };
+struct ProfScope {
+    int cls;
+    hipStream_t s;
+    hipEvent_t e1 = nullptr;
+    ProfScope(int c, hipStream_t st);
+    ~ProfScope();
+};
 
 }  // namespace qbsm

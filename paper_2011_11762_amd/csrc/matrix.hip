@@ -287,6 +287,7 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     m.has_blocks = true;
     m.version++;
     m.pattern_id++;
+    m.filled_by = 0;
     m.trees.clear();
     m.packs.clear();
     m.stream = s;
@@ -394,6 +395,7 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
     if (!work) return;
     const unsigned g = grid_for(work, 256);
     void *dst = pk.buf.p;
+    ProfScope prof(PROF_PACK, s);
 #define QB_PACK(SRC, PTR, MODE) \
     k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst)
     if (m.storage == ST_F64) {

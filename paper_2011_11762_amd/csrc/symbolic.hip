@@ -332,7 +332,9 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     if (D < sl) D = sl;
     QB_CHECK(D <= 16, QBSM_ERR_UNSUPPORTED, "block grid side above 65536");
 
+    static uint64_t next_id = 0;
     auto p = std::make_unique<Plan>();
+    p->id = ++next_id;
     p->L = L; p->R = R; p->M = M;
     p->transL = transL; p->transR = transR;
     p->patL = L->pattern_id; p->patR = R->pattern_id; p->patM = M ? M->pattern_id : 0;

@@ -72,6 +72,9 @@ _SIGS = {
     "qbsm_batch_set_occupancy": [c_void_p, c_int32],
     "qbsm_batch_destroy": [c_void_p],
     "qbsm_autotune_unit": [c_void_p, c_void_p, c_int32, c_int32, c_void_p, POINTER(c_int32), POINTER(c_double)],
+    "qbsm_profile_enable": [c_int32],
+    "qbsm_profile_reset": [],
+    "qbsm_profile_read": [c_int32, POINTER(c_int64), POINTER(c_double)],
 }
 
 ABI_SYMBOLS = tuple(_SIGS)
@@ -283,6 +286,25 @@ def autotune_unit(A: Matrix, B: Matrix, mode, reps: int = 3):
     _check(_lib.qbsm_autotune_unit(A.handle, B.handle, mode_id(mode), int(reps), _stream(),
                                    ctypes.byref(best), times))
     return best.value, {64: times[0], 128: times[1]}
+
+
+PROF_NUMERIC, PROF_PACK = 0, 1
+
+
+def profile_enable(on: bool = True):
+    load()
+    _check(_lib.qbsm_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(_lib.qbsm_profile_reset())
+
+
+def profile_read(kernel_class: int = PROF_NUMERIC):
+    """(launches, total_ms) of the recorded launches of a kernel class."""
+    n, t = c_int64(), c_double()
+    _check(_lib.qbsm_profile_read(int(kernel_class), ctypes.byref(n), ctypes.byref(t)))
+    return n.value, t.value
 
 
 # --------------------------------------------------------------------------
