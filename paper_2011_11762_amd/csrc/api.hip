@@ -314,13 +314,10 @@ qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode,
             hm[i] = make_member(p, mode, outs[i]->m, s);
             b.plans.push_back(&p);
             b.outs.push_back(&outs[i]->m);
-            // operand packs replayed on each run (the raw column-major views need none)
+            // operand packs replayed on each run
             for (int side = 0; side < 2; ++side) {
                 Matrix *mm = side == 0 ? p.L : p.R;
                 Role role = side == 0 ? (p.transL ? ROLE_COL : ROLE_ROW) : (p.transR ? ROLE_ROW : ROLE_COL);
-                const bool raw = role == ROLE_COL && ((mode == QBSM_F64 && mm->storage == ST_F64) ||
-                                                      (mode == QBSM_F32 && mm->storage == ST_F32));
-                if (raw) continue;
                 bool seen = false;
                 for (auto &j : b.packs) seen |= (j.m == mm && j.mode == mode && j.role == role);
                 if (!seen) b.packs.push_back({mm, mode, role});

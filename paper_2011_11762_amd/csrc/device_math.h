@@ -35,4 +35,11 @@ __device__ __forceinline__ double bf16_bits_to_double(uint16_t h) {
     return (double)__uint_as_float(((uint32_t)h) << 16);
 }
 
+// Swizzle of the 16-byte pieces of a packed operand line (64 or 128 bytes):
+// piece p of line l is stored at slot p ^ piece_swizzle(l, LB).  Shared by
+// the pack kernel (writer) and the leaf-product kernel (LDS reader).
+__device__ __forceinline__ int piece_swizzle(int line, int LB) {
+    return LB == 128 ? (line & 7) : ((line >> 1) & 3);
+}
+
 }  // namespace qbsm

@@ -181,44 +181,64 @@ __global__ void __launch_bounds__(256) k_scatter_values(const T *pool, const int
 }
 
 // ---- operand packing
-// Packed leaf layout: [part][chunk][line][BK], lines = rows (ROLE_ROW) or
-// columns (ROLE_COL); the contraction index runs along a line.
+// Packed leaf layout: [part][chunk][line][LB bytes], lines = rows (ROLE_ROW)
+// or columns (ROLE_COL) with the contraction index running along a line;
+// the 16-byte pieces of a line are stored at slot piece ^ piece_swizzle(line).
+// One thread converts and writes one 16-byte piece.  Column lines read
+// contiguous source runs (piece-fastest thread order); row lines read
+// across the column-major source (line-fastest thread order).
 template <class Src, int MODE>
-__global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int32_t bs, int32_t bk,
-                                              int role, void *dst) {
+__global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int32_t bs, int32_t bk, int role,
+                                              uint8_t *dst) {
+    constexpr int EB = MODE == QBSM_F64 ? 8 : MODE == QBSM_F32 ? 4 : 2;  // bytes per element
+    constexpr int EPP = 16 / EB;                                          // elements per piece
+    constexpr int PARTS = MODE == QBSM_BF16X3 ? 2 : 1;
+    const int LB = bk * EB;
+    const int ppl = LB / 16;
     const int64_t nc = bs / bk;
-    const int64_t per_leaf = nc * bs;  // (chunk, line) pairs per leaf
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_leaf = nc * bs * ppl;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nblk * per_leaf) return;
     const int64_t leaf = t / per_leaf;
     const int64_t rem = t - leaf * per_leaf;
-    const int64_t c = rem / bs;
-    const int64_t l = rem - c * bs;
+    int64_t c, l, piece;
+    if (role == ROLE_COL) {
+        piece = rem % ppl;
+        l = (rem / ppl) % bs;
+        c = rem / (ppl * (int64_t)bs);
+    } else {
+        l = rem % bs;
+        piece = (rem / bs) % ppl;
+        c = rem / ((int64_t)bs * ppl);
+    }
     const int64_t n2 = (int64_t)bs * bs;
     const Src *x = src + leaf * n2;
-    // element kk of this line chunk
-    auto at = [&](int64_t kk) -> double {
-        int64_t k = c * bk + kk;
-        return role == ROLE_COL ? (double)x[k + l * bs] : (double)x[l + k * bs];
-    };
-    const int64_t off = c * (int64_t)bs * bk + l * bk;  // within a part
+    const int64_t k0 = c * bk + piece * EPP;
+    double v[EPP];
+#pragma unroll
+    for (int e = 0; e < EPP; ++e)
+        v[e] = role == ROLE_COL ? (double)x[(k0 + e) + l * bs] : (double)x[l + (k0 + e) * bs];
+    uint8_t *o = dst + leaf * (PARTS * n2 * EB) + c * (int64_t)bs * LB + l * LB +
+                 ((piece ^ piece_swizzle((int)l, LB)) << 4);
     if (MODE == QBSM_F64) {
-        double *y = static_cast<double *>(dst) + leaf * n2 + off;
-        for (int64_t kk = 0; kk < bk; ++kk) y[kk] = at(kk);
+        *reinterpret_cast<double2 *>(o) = make_double2(v[0], v[1]);
     } else if (MODE == QBSM_F32) {
-        float *y = static_cast<float *>(dst) + leaf * n2 + off;
-        for (int64_t kk = 0; kk < bk; ++kk) y[kk] = (float)at(kk);
-    } else if (MODE == QBSM_BF16) {
-        uint16_t *y = static_cast<uint16_t *>(dst) + leaf * n2 + off;
-        for (int64_t kk = 0; kk < bk; ++kk) y[kk] = bf16_rne_bits(at(kk));
-    } else {  // BF16X3: hi part then lo part
-        uint16_t *yh = static_cast<uint16_t *>(dst) + leaf * 2 * n2 + off;
-        uint16_t *yl = yh + n2;
-        for (int64_t kk = 0; kk < bk; ++kk) {
-            double v = at(kk);
-            uint16_t h = bf16_rne_bits(v);
-            yh[kk] = h;
-            yl[kk] = bf16_rne_bits(v - bf16_bits_to_double(h));
+        *reinterpret_cast<float4 *>(o) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+    } else {
+        uint16_t h[8], lo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            h[e] = bf16_rne_bits(v[e]);
+            lo[e] = bf16_rne_bits(v[e] - bf16_bits_to_double(h[e]));
+        }
+        uint4 hv, lv;
+        hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
+        hv.z = h[4] | ((uint32_t)h[5] << 16); hv.w = h[6] | ((uint32_t)h[7] << 16);
+        *reinterpret_cast<uint4 *>(o) = hv;
+        if (PARTS == 2) {
+            lv.x = lo[0] | ((uint32_t)lo[1] << 16); lv.y = lo[2] | ((uint32_t)lo[3] << 16);
+            lv.z = lo[4] | ((uint32_t)lo[5] << 16); lv.w = lo[6] | ((uint32_t)lo[7] << 16);
+            *reinterpret_cast<uint4 *>(o + n2 * EB) = lv;
         }
     }
 }
@@ -235,7 +255,9 @@ int mode_parts(qbsm_mode mode) { return mode == QBSM_BF16X3 ? 2 : 1; }
 }  // namespace
 
 int mode_bk(qbsm_mode mode, int bs) {
-    int bk = 128 / (int)mode_elem_bytes(mode);
+    // K chunk per packed line: 128-byte lines, except the two-part split mode
+    // (64-byte lines) so that two LDS stages of both parts fit in 64 KB
+    int bk = (mode == QBSM_BF16X3 ? 64 : 128) / (int)mode_elem_bytes(mode);
     return bk < bs ? bk : bs;
 }
 
@@ -391,10 +413,11 @@ void matrix_get_values(Matrix &m, double *vals, hipStream_t s) {
 
 void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) {
     const int bk = mode_bk(mode, m.bs);
-    const int64_t work = m.nblk * (m.bs / bk) * (int64_t)m.bs;
+    const int ppl = bk * (int)mode_elem_bytes(mode) / 16;
+    const int64_t work = m.nblk * (m.bs / bk) * (int64_t)m.bs * ppl;
     if (!work) return;
     const unsigned g = grid_for(work, 256);
-    void *dst = pk.buf.p;
+    uint8_t *dst = pk.buf.p;
     ProfScope prof(PROF_PACK, s);
 #define QB_PACK(SRC, PTR, MODE) \
     k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst)
@@ -422,17 +445,6 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
     const int bk = mode_bk(mode, bs);
     const int64_t n2 = (int64_t)bs * bs;
     PackView v;
-    // the stored column-major pool already is a column-line layout with
-    // line stride bs and chunk stride bk
-    if (role == ROLE_COL && ((mode == QBSM_F64 && m.storage == ST_F64) ||
-                             (mode == QBSM_F32 && m.storage == ST_F32))) {
-        v.ptr = m.storage == ST_F64 ? (const void *)m.v64.p : (const void *)m.v32.p;
-        v.leaf_stride = n2;
-        v.part_stride = 0;
-        v.line_stride = bs;
-        v.chunk_stride = bk;
-        return v;
-    }
     auto key = std::make_pair((int)mode, (int)role);
     Pack &pk = m.packs[key];
     const size_t bytes = (size_t)m.nblk * n2 * mode_elem_bytes(mode) * mode_parts(mode);

@@ -3,14 +3,22 @@
 //
 // One workgroup owns one output quadtree node of side U (the "unit", a
 // 2^s x 2^s group of leaf blocks; U = 64 or 128 elements) and visits the
-// unit's node pairs in contraction order.  For every pair and every leaf
-// column kb inside it, the unit's A rows and B columns are staged in LDS
-// chunk by chunk (coalesced 16-byte loads of the packed operands) and each
-// wave multiplies its 64x64 part of the unit with 16x16 MFMA tiles; a tile
-// is skipped when its leaf product is absent (nil operand).  Every output
-// block is written once, by its owner, after its last product: no atomics,
-// and the order of the additions is fixed (contraction index ascending).
+// unit's node pairs in contraction order.  A "step" is one K chunk of one
+// leaf column kb of one pair: the unit's A rows and B columns of that chunk
+// are copied from HBM straight into LDS (global_load_lds, 1 KB per wave
+// instruction, two LDS stages so the copy of step i+1 overlaps the MFMAs of
+// step i; one barrier per step), and each wave multiplies its 64x64 part of
+// the unit with 16x16 MFMA tiles.  A tile is skipped when its leaf product
+// is absent (nil operand).  Every output block is written once, by its
+// owner, after its last product: no atomics, and the order of the additions
+// is fixed (contraction index ascending across steps).
+//
+// Operand layout (written by the pack kernel): per leaf [part][chunk][line]
+// with lines of LB = 64 or 128 bytes whose 16-byte pieces are XOR-swizzled
+// by the line index, so the LDS copy is a contiguous 1 KB per instruction
+// and the MFMA fragment reads of 16 consecutive lines hit distinct banks.
 #include "common.h"
+#include "device_math.h"
 
 namespace qbsm {
 
@@ -20,8 +28,17 @@ typedef __attribute__((ext_vector_type(4))) float f4;
 typedef __attribute__((ext_vector_type(4))) double d4;
 typedef __attribute__((ext_vector_type(8))) __bf16 bf8;
 
-constexpr int LINEB = 144;  // bytes per LDS line: 128 data + 16 pad (bank spread)
+#define QB_GAS __attribute__((address_space(1)))
+#define QB_LAS __attribute__((address_space(3)))
 
+__device__ __forceinline__ uint4 lds_piece(const uint8_t *arr, int line, int LB, int piece) {
+    return *reinterpret_cast<const uint4 *>(arr + line * LB + ((piece ^ piece_swizzle(line, LB)) << 4));
+}
+
+// Per-mode traits.  A "read group" is the K range one set of fragment reads
+// covers: lane group g = lane/16 reads logical pieces g*SUBS .. g*SUBS+SUBS-1
+// of the group; MFMA step j of the group uses element j of those pieces for
+// both operands (the same K permutation on A and B leaves the sum unchanged).
 template <int MODE>
 struct MT;
 
@@ -29,12 +46,16 @@ template <>
 struct MT<QBSM_F64> {
     using T = double;
     using Acc = d4;
-    using Frag = double;
     using Out = double;
-    static constexpr int KSTEP = 4, EPL = 1, PARTS = 1;
-    __device__ static Frag frag(const unsigned char *p) { return *reinterpret_cast<const double *>(p); }
+    static constexpr int BK = 16, PARTS = 1, LBMAX = 128, KPG = 16, PPG = 8, SUBS = 2;
+    struct Frag { uint4 q[2]; };
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], c, 0, 0, 0);
+        const double2 a0 = __builtin_bit_cast(double2, a[0].q[0]), a1 = __builtin_bit_cast(double2, a[0].q[1]);
+        const double2 b0 = __builtin_bit_cast(double2, b[0].q[0]), b1 = __builtin_bit_cast(double2, b[0].q[1]);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b0.x, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b0.y, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1.x, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b1.y, c, 0, 0, 0);
     }
     // accumulator element i of a lane holds row (lane/16) + 4*i
     __device__ static int row_of(int lane, int i) { return (lane >> 4) + 4 * i; }
@@ -44,12 +65,15 @@ template <>
 struct MT<QBSM_F32> {
     using T = float;
     using Acc = f4;
-    using Frag = float;
     using Out = float;
-    static constexpr int KSTEP = 4, EPL = 1, PARTS = 1;
-    __device__ static Frag frag(const unsigned char *p) { return *reinterpret_cast<const float *>(p); }
+    static constexpr int BK = 32, PARTS = 1, LBMAX = 128, KPG = 16, PPG = 4, SUBS = 1;
+    struct Frag { uint4 q[1]; };
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
+        const f4 x = __builtin_bit_cast(f4, a[0].q[0]), y = __builtin_bit_cast(f4, b[0].q[0]);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[0], y[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[1], y[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[2], y[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(x[3], y[3], c, 0, 0, 0);
     }
     // accumulator element i of a lane holds row 4*(lane/16) + i
     __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
@@ -59,14 +83,12 @@ template <>
 struct MT<QBSM_BF16> {
     using T = uint16_t;
     using Acc = f4;
-    using Frag = bf8;
     using Out = float;
-    static constexpr int KSTEP = 32, EPL = 8, PARTS = 1;
-    __device__ static Frag frag(const unsigned char *p) {
-        return __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(p));
-    }
+    static constexpr int BK = 64, PARTS = 1, LBMAX = 128, KPG = 32, PPG = 4, SUBS = 1;
+    struct Frag { uint4 q[1]; };
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[0].q[0]),
+                                                    __builtin_bit_cast(bf8, b[0].q[0]), c, 0, 0, 0);
     }
     __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
@@ -75,17 +97,17 @@ template <>
 struct MT<QBSM_BF16X3> {
     using T = uint16_t;
     using Acc = f4;
-    using Frag = bf8;
     using Out = float;
-    static constexpr int KSTEP = 32, EPL = 8, PARTS = 2;
-    __device__ static Frag frag(const unsigned char *p) {
-        return __builtin_bit_cast(bf8, *reinterpret_cast<const uint4 *>(p));
-    }
-    // a*b ~ hi*lo + lo*hi + hi*hi (the lo*lo term is below FP32 resolution)
+    static constexpr int BK = 32, PARTS = 2, LBMAX = 64, KPG = 32, PPG = 4, SUBS = 1;
+    struct Frag { uint4 q[1]; };
+    // a*b ~ hi*lo + lo*hi + hi*hi (the lo*lo term is below FP32 resolution);
+    // a[0]/b[0] are the hi parts, a[1]/b[1] the lo parts
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
+        const bf8 ah = __builtin_bit_cast(bf8, a[0].q[0]), al = __builtin_bit_cast(bf8, a[1].q[0]);
+        const bf8 bh = __builtin_bit_cast(bf8, b[0].q[0]), bl = __builtin_bit_cast(bf8, b[1].q[0]);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
     }
     __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
@@ -114,30 +136,128 @@ __device__ __forceinline__ int xcd_remap(int b, int n) {
     return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Values that are the same in every lane (read from one LDS address) are
+// moved to scalar registers so that the step bookkeeping, the address
+// arithmetic and the tile-skip branches run on the scalar unit.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ int pick4(const int *v, int i) {
     return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
 }
 
-template <int MODE, int U>
-__device__ void process_unit(const K5Member &m, int u, unsigned char *smem) {
+// LDS copy of the metadata of a batch of pairs: product bits and the leaf
+// indices of every leaf column kb (A side: row leaves ib, B side: column
+// leaves jb), so that the step loop never waits on a dependent global read.
+constexpr int META_BYTES = 10240;
+
+struct Meta {
+    uint64_t *pm;  // [cap]
+    int32_t *la;   // [cap * nsub], index kb*lpu + ib
+    int32_t *lb;   // [cap * nsub], index kb*lpu + jb
+};
+
+__device__ __forceinline__ Meta meta_view(uint8_t *base, int cap, int nsub) {
+    Meta mt;
+    mt.pm = reinterpret_cast<uint64_t *>(base);
+    mt.la = reinterpret_cast<int32_t *>(base + 8 * cap);
+    mt.lb = mt.la + cap * nsub;
+    return mt;
+}
+
+// Next (pair, kb) at or after (i, kb) inside the batch with a leaf product.
+__device__ __forceinline__ bool seek_step(const Meta &mt, int nb, int lpu, int nsub, int &i, int &kb,
+                                          uint32_t &km) {
+    const uint32_t sub = (uint32_t)((1ull << nsub) - 1ull);
+    while (i < nb) {
+        const uint64_t pm = uni64(mt.pm[i]);
+        while (kb < lpu) {
+            km = (uint32_t)(pm >> (kb * nsub)) & sub;
+            if (km) return true;
+            ++kb;
+        }
+        ++i;
+        kb = 0;
+    }
+    return false;
+}
+
+template <int MODE, int U, int BS>
+struct Geo {
     using M = MT<MODE>;
     using T = typename M::T;
+    static constexpr int LPU = U / BS;                   // leaves per unit side
+    static constexpr int S = LPU == 1 ? 0 : LPU == 2 ? 1 : 2;
+    static constexpr int NSUB = LPU * LPU;
+    static constexpr int BK = M::BK < BS ? M::BK : BS;   // K per chunk (one packed line)
+    static constexpr int LB = BK * (int)sizeof(T);       // bytes per line
+    static constexpr int NCHUNK = BS / BK;
+    static constexpr int NGROUPS = BK / M::KPG;
+    static constexpr int LPI = 1024 / LB;                // lines per 1 KB load instruction
+    static constexpr int IPA = U / LPI;                  // load instructions per array
+    static constexpr int NW = (U / 64) * (U / 64);
+    static constexpr int NARR = 2 * M::PARTS;
+    static constexpr int PER_WAVE = NARR * IPA / NW;
+    static constexpr int ARRB = U * M::LBMAX;
+    static constexpr int STAGEB = NARR * ARRB;
+    static constexpr int CAP = META_BYTES / (8 + 8 * NSUB);
+    static_assert(NARR * IPA % NW == 0, "load instructions must split evenly over the waves");
+    static_assert(LB <= M::LBMAX && LPI <= BS, "line geometry");
+};
+
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void issue_loads(const K5Member &m, const Meta &mt, int i, int kb, int c, uint8_t *stage,
+                                            int w) {
+    using G = Geo<MODE, U, BS>;
+    using T = typename G::T;
+    const int lane = threadIdx.x & 63;
+    int la[G::LPU], lb[G::LPU];
+#pragma unroll
+    for (int q = 0; q < G::LPU; ++q) {
+        la[q] = uni(mt.la[i * G::NSUB + kb * G::LPU + q]);
+        lb[q] = uni(mt.lb[i * G::NSUB + kb * G::LPU + q]);
+    }
+    const uint8_t *baseL = static_cast<const uint8_t *>(m.packL) +
+                           ((int64_t)c * m.chunkStrideL) * (int64_t)sizeof(T) + lane * 16;
+    const uint8_t *baseR = static_cast<const uint8_t *>(m.packR) +
+                           ((int64_t)c * m.chunkStrideR) * (int64_t)sizeof(T) + lane * 16;
+#pragma unroll
+    for (int k = 0; k < G::PER_WAVE; ++k) {
+        const int j = w + k * G::NW;             // this wave's k-th load instruction
+        const int arr = j / G::IPA, jj = j - arr * G::IPA;
+        const int op = arr / MT<MODE>::PARTS, part = arr - op * MT<MODE>::PARTS;
+        const int line0 = jj * G::LPI;
+        const int slot = line0 / BS;
+        const int off = (line0 - slot * BS) * G::LB;
+        int leaf = -1;
+#pragma unroll
+        for (int q = 0; q < G::LPU; ++q)
+            if (slot == q) leaf = op == 0 ? la[q] : lb[q];
+        if (leaf < 0) continue;
+        const uint8_t *g = op == 0
+            ? baseL + ((int64_t)leaf * m.leafStrideL + (int64_t)part * m.partStrideL) * (int64_t)sizeof(T)
+            : baseR + ((int64_t)leaf * m.leafStrideR + (int64_t)part * m.partStrideR) * (int64_t)sizeof(T);
+        __builtin_amdgcn_global_load_lds((const QB_GAS void *)(g + off),
+                                         (QB_LAS void *)(stage + arr * G::ARRB + jj * 1024), 16, 0, 0);
+    }
+}
+
+template <int MODE, int U, int BS>
+__device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *meta) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
     constexpr int WPS = U / 64;
-    constexpr int NT = 64 * WPS * WPS;
+    constexpr int NT = 64 * G::NW;
     constexpr int PARTS = M::PARTS;
-    constexpr int MAXPPL = 8;  // 16-byte pieces in a 128-byte line
-    constexpr int SLOTS = (U * MAXPPL + NT - 1) / NT;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB, S = G::S;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int w = tid >> 6;
+    const int w = uni(tid >> 6);
     const int wr = w / WPS, wc = w % WPS;
-    const int bs = m.bs, lpu = m.lpu, s = m.s, nsub = lpu * lpu;
-    const int bk = (128 / (int)sizeof(T)) < bs ? (128 / (int)sizeof(T)) : bs;
-    const int nchunk = bs / bk;
-    const int ppl = bk * (int)sizeof(T) / 16;
-    const int ksteps = bk / M::KSTEP;
-    unsigned char *As = smem;
-    unsigned char *Bs = smem + PARTS * U * LINEB;
 
     typename M::Acc acc[4][4];
 #pragma unroll
@@ -146,80 +266,107 @@ __device__ void process_unit(const K5Member &m, int u, unsigned char *smem) {
         for (int b = 0; b < 4; ++b) acc[a][b] = typename M::Acc{};
 
     const int p0 = m.ustart[u], p1 = m.ustart[u + 1];
-    for (int p = p0; p < p1; ++p) {
-        const uint64_t pm = m.pmask[p];
-        const int a = m.pl[p], b = m.pr[p];
-        for (int kb = 0; kb < lpu; ++kb) {
-            const uint32_t km = (uint32_t)(pm >> (kb * nsub)) & (uint32_t)((1ull << nsub) - 1ull);
-            if (!km) continue;
-            int la[4], lb[4];
+    const Meta mt = meta_view(meta, G::CAP, NSUB);
+    for (int b0 = p0; b0 < p1; b0 += G::CAP) {
+        const int nb = (p1 - b0) < G::CAP ? (p1 - b0) : G::CAP;
+        __syncthreads();  // LDS (stages, metadata) of the previous batch or unit is free
+        for (int i = tid; i < nb; i += NT) {
+            const int p = b0 + i;
+            const int a = m.pl[p], b = m.pr[p];
+            mt.pm[i] = m.pmask[p];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                la[i] = -1;
-                lb[i] = -1;
-                if (i < lpu) {
-                    const int qa = m.transL ? morton_sub(kb, i, s) : morton_sub(i, kb, s);
-                    la[i] = m.descL ? m.descL[(int64_t)a * nsub + qa] : a;
-                    const int qb = m.transR ? morton_sub(i, kb, s) : morton_sub(kb, i, s);
-                    lb[i] = m.descR ? m.descR[(int64_t)b * nsub + qb] : b;
+            for (int kb = 0; kb < LPU; ++kb)
+#pragma unroll
+                for (int q = 0; q < LPU; ++q) {
+                    const int qa = m.transL ? morton_sub(kb, q, S) : morton_sub(q, kb, S);
+                    const int qb = m.transR ? morton_sub(q, kb, S) : morton_sub(kb, q, S);
+                    mt.la[i * NSUB + kb * LPU + q] = m.descL ? m.descL[(int64_t)a * NSUB + qa] : a;
+                    mt.lb[i * NSUB + kb * LPU + q] = m.descR ? m.descR[(int64_t)b * NSUB + qb] : b;
                 }
+        }
+        __syncthreads();
+        int i = 0, kb = 0, c = 0;
+        uint32_t km = 0;
+        bool have = seek_step(mt, nb, LPU, NSUB, i, kb, km);
+        if (have) issue_loads<MODE, U, BS>(m, mt, i, kb, c, smem, w);
+        __syncthreads();
+        int stage = 0;
+        while (have) {
+            // prefetch the next step into the other stage
+            int ni = i, nkb = kb, nc = c + 1;
+            uint32_t nkm = km;
+            bool nhave = true;
+            if (nc == G::NCHUNK) {
+                nc = 0;
+                ++nkb;
+                nhave = seek_step(mt, nb, LPU, NSUB, ni, nkb, nkm);
             }
+            if (nhave) issue_loads<MODE, U, BS>(m, mt, ni, nkb, nc, smem + (stage ^ 1) * G::STAGEB, w);
+            // tiles of this wave whose leaf product exists in this step
             uint32_t en = 0;
 #pragma unroll
             for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
                 for (int tn = 0; tn < 4; ++tn) {
-                    const int ib = (64 * wr + 16 * tm) / bs, jb = (64 * wc + 16 * tn) / bs;
-                    if ((km >> (ib * lpu + jb)) & 1u) en |= 1u << (tm * 4 + tn);
+                    const int ib = (64 * wr + 16 * tm) / BS, jb = (64 * wc + 16 * tn) / BS;
+                    if ((km >> (ib * LPU + jb)) & 1u) en |= 1u << (tm * 4 + tn);
                 }
-            for (int c = 0; c < nchunk; ++c) {
-                __syncthreads();
-                // stage the unit's A lines (rows) and B lines (columns) of chunk c
+            en = (uint32_t)uni((int)en);
+            if (en) {
+                const uint8_t *Ab = smem + stage * G::STAGEB;
+                const uint8_t *Bb = Ab + PARTS * G::ARRB;
 #pragma unroll
-                for (int j = 0; j < SLOTS; ++j) {
-                    const int idx = tid + j * NT;
-                    if (idx < U * ppl) {
-                        const int line = idx / ppl, piece = idx - (idx / ppl) * ppl;
-                        const int lbk = line / bs, lr = line - lbk * bs;
-                        const int leafA = pick4(la, lbk), leafB = pick4(lb, lbk);
+                for (int rg = 0; rg < G::NGROUPS; ++rg) {
+                    const int pbase = rg * M::PPG + (lane >> 4) * M::SUBS;
+                    typename M::Frag fa[4][PARTS];
 #pragma unroll
-                        for (int part = 0; part < PARTS; ++part) {
-                            if (leafA >= 0) {
-                                const T *src = static_cast<const T *>(m.packL) + (int64_t)leafA * m.leafStrideL +
-                                               (int64_t)part * m.partStrideL + (int64_t)c * m.chunkStrideL +
-                                               (int64_t)lr * m.lineStrideL + piece * (16 / (int)sizeof(T));
-                                *reinterpret_cast<uint4 *>(As + (part * U + line) * LINEB + piece * 16) =
-                                    *reinterpret_cast<const uint4 *>(src);
-                            }
-                            if (leafB >= 0) {
-                                const T *src = static_cast<const T *>(m.packR) + (int64_t)leafB * m.leafStrideR +
-                                               (int64_t)part * m.partStrideR + (int64_t)c * m.chunkStrideR +
-                                               (int64_t)lr * m.lineStrideR + piece * (16 / (int)sizeof(T));
-                                *reinterpret_cast<uint4 *>(Bs + (part * U + line) * LINEB + piece * 16) =
-                                    *reinterpret_cast<const uint4 *>(src);
-                            }
+                    for (int t = 0; t < 4; ++t) {
+                        const int ln = 64 * wr + 16 * t + (lane & 15);
+#pragma unroll
+                        for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                            for (int q = 0; q < M::SUBS; ++q)
+                                fa[t][part].q[q] = lds_piece(Ab + part * G::ARRB, ln, G::LB, pbase + q);
+                    }
+                    if (en == 0xFFFFu) {
+                        // every tile of the wave has its leaf product: no branches
+#pragma unroll
+                        for (int tn = 0; tn < 4; ++tn) {
+                            typename M::Frag fb[PARTS];
+                            const int ln = 64 * wc + 16 * tn + (lane & 15);
+#pragma unroll
+                            for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                                for (int q = 0; q < M::SUBS; ++q)
+                                    fb[part].q[q] = lds_piece(Bb + part * G::ARRB, ln, G::LB, pbase + q);
+#pragma unroll
+                            for (int tm = 0; tm < 4; ++tm) M::mma(acc[tm][tn], fa[tm], fb);
+                        }
+                    } else {
+#pragma unroll
+                        for (int tn = 0; tn < 4; ++tn) {
+                            if (!((en >> tn) & 0x1111u)) continue;
+                            typename M::Frag fb[PARTS];
+                            const int ln = 64 * wc + 16 * tn + (lane & 15);
+#pragma unroll
+                            for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                                for (int q = 0; q < M::SUBS; ++q)
+                                    fb[part].q[q] = lds_piece(Bb + part * G::ARRB, ln, G::LB, pbase + q);
+#pragma unroll
+                            for (int tm = 0; tm < 4; ++tm)
+                                if ((en >> (tm * 4 + tn)) & 1u) M::mma(acc[tm][tn], fa[tm], fb);
                         }
                     }
                 }
-                __syncthreads();
-                if (!en) continue;
-                for (int ks = 0; ks < ksteps; ++ks) {
-                    const int kofs = (ks * M::KSTEP + (lane >> 4) * M::EPL) * (int)sizeof(T);
-                    typename M::Frag fa[4][PARTS], fb[4][PARTS];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-#pragma unroll
-                        for (int part = 0; part < PARTS; ++part) {
-                            fa[t][part] = M::frag(As + (part * U + 64 * wr + 16 * t + (lane & 15)) * LINEB + kofs);
-                            fb[t][part] = M::frag(Bs + (part * U + 64 * wc + 16 * t + (lane & 15)) * LINEB + kofs);
-                        }
-#pragma unroll
-                    for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-                        for (int tn = 0; tn < 4; ++tn)
-                            if ((en >> (tm * 4 + tn)) & 1u) M::mma(acc[tm][tn], fa[tm], fb[tn]);
-                }
             }
+            __syncthreads();
+            i = ni;
+            kb = nkb;
+            c = nc;
+            km = nkm;
+            have = nhave;
+            stage ^= 1;
         }
     }
 
@@ -227,63 +374,91 @@ __device__ void process_unit(const K5Member &m, int u, unsigned char *smem) {
     uint32_t ui, uj;
     demorton(m.ukey[u], ui, uj);
     typename M::Out *C = static_cast<typename M::Out *>(m.C);
-    const int64_t n2 = (int64_t)bs * bs;
+    constexpr int64_t N2 = (int64_t)BS * BS;
 #pragma unroll
     for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
         for (int tn = 0; tn < 4; ++tn) {
             const int col = 64 * wc + 16 * tn + (lane & 15);
-            const int jb = col / bs, cc = col - jb * bs;
+            const int jb = col / BS, cc = col - jb * BS;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int row = 64 * wr + 16 * tm + M::row_of(lane, i);
-                const int ib = row / bs, r = row - ib * bs;
-                const int32_t leaf = m.cdesc[(int64_t)u * nsub + ib * lpu + jb];
+                const int ib = row / BS, r = row - ib * BS;
+                const int32_t leaf = m.cdesc[(int64_t)u * NSUB + ib * LPU + jb];
                 if (leaf < 0) continue;
-                const int64_t I = (int64_t)ui * lpu + ib, J = (int64_t)uj * lpu + jb;
-                const bool ok = (I * bs + r) < m.out_rows && (J * bs + cc) < m.out_cols;
-                C[(int64_t)leaf * n2 + r + (int64_t)cc * bs] =
+                const int64_t I = (int64_t)ui * LPU + ib, J = (int64_t)uj * LPU + jb;
+                const bool ok = (I * BS + r) < m.out_rows && (J * BS + cc) < m.out_cols;
+                C[(int64_t)leaf * N2 + r + (int64_t)cc * BS] =
                     ok ? (typename M::Out)acc[tm][tn][i] : (typename M::Out)0;
             }
         }
 }
 
 template <int MODE, int U>
-__global__ void __launch_bounds__(64 * (U / 64) * (U / 64))
-    k5(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter,
-       int persistent) {
-    __shared__ __attribute__((aligned(16))) unsigned char smem[MT<MODE>::PARTS * 2 * U * LINEB];
-    __shared__ int s_item;
-    if (!persistent) {
-        const int u = xcd_remap((int)blockIdx.x, single.nunits);
-        process_unit<MODE, U>(single, u, smem);
-        return;
+__device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *smem, uint8_t *meta) {
+    if (m.bs == 32) {
+        process_unit<MODE, U, 32>(m, u, smem, meta);
+    } else if (m.bs == 64) {
+        process_unit<MODE, U, 64>(m, u, smem, meta);
+    } else if constexpr (U >= 128) {
+        process_unit<MODE, U, 128>(m, u, smem, meta);
     }
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = s_item;
-        __syncthreads();
-        if ((int64_t)it >= nitems) break;
-        const int2 w = items[it];
-        const K5Member mm = members[w.x];
-        process_unit<MODE, U>(mm, w.y, smem);
+}
+
+// BS > 0: one launch of one multiply with that leaf size, one workgroup per
+// unit.  BS == 0: persistent launch over a work list of (member, unit) items
+// of members with any leaf size, pulled from a device counter.
+template <int MODE, int U, int BS>
+__global__ void __launch_bounds__(64 * (U / 64) * (U / 64), MODE == QBSM_F64 ? 1 : 2)
+    k5(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
+    __shared__ __attribute__((aligned(1024))) uint8_t smem[2 * 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX];
+    __shared__ __attribute__((aligned(16))) uint8_t meta[META_BYTES];
+    if constexpr (BS != 0) {
+        const int u = xcd_remap((int)blockIdx.x, single.nunits);
+        process_unit<MODE, U, BS>(single, u, smem, meta);
+    } else {
+        __shared__ int s_item;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+            __syncthreads();
+            const int it = s_item;
+            __syncthreads();
+            if ((int64_t)it >= nitems) break;
+            const int2 w = items[it];
+            const K5Member mm = members[w.x];
+            process_any<MODE, U>(mm, w.y, smem, meta);
+        }
     }
 }
 
 template <int MODE, int U>
-void launch_one(const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter, int grid,
-                int persistent, const K5Member &single, hipStream_t s) {
+void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter, int grid,
+              int persistent, const K5Member &single, hipStream_t s) {
     constexpr int NT = 64 * (U / 64) * (U / 64);
-    k5<MODE, U><<<grid, NT, 0, s>>>(single, members, items, nitems, counter, persistent);
+    if (persistent) {
+        k5<MODE, U, 0><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+        return;
+    }
+    switch (bs) {
+        case 32: k5<MODE, U, 32><<<grid, NT, 0, s>>>(single, members, items, nitems, counter); break;
+        case 64: k5<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter); break;
+        case 128:
+            if constexpr (U >= 128) {
+                k5<MODE, U, 128><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Error(QBSM_ERR_UNSUPPORTED, "leaf size for this unit side");
+    }
 }
 
 template <int MODE>
-void launch_mode(int unit, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter,
+void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter,
                  int grid, int persistent, const K5Member &single, hipStream_t s) {
     switch (unit) {
-        case 64: launch_one<MODE, 64>(members, items, nitems, counter, grid, persistent, single, s); break;
-        case 128: launch_one<MODE, 128>(members, items, nitems, counter, grid, persistent, single, s); break;
+        case 64: launch_u<MODE, 64>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
+        case 128: launch_u<MODE, 128>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
         default: throw Error(QBSM_ERR_UNSUPPORTED, "unit side");
     }
 }
@@ -293,11 +468,12 @@ void launch_mode(int unit, const K5Member *members, const int2 *items, int64_t n
 void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const int2 *items, int64_t nitems,
                int32_t *counter, int grid, int persistent, const K5Member &single, hipStream_t s) {
     if (grid <= 0) return;
+    const int bs = single.bs;
     switch (mode) {
-        case QBSM_F64: launch_mode<QBSM_F64>(unit, members, items, nitems, counter, grid, persistent, single, s); break;
-        case QBSM_F32: launch_mode<QBSM_F32>(unit, members, items, nitems, counter, grid, persistent, single, s); break;
-        case QBSM_BF16: launch_mode<QBSM_BF16>(unit, members, items, nitems, counter, grid, persistent, single, s); break;
-        case QBSM_BF16X3: launch_mode<QBSM_BF16X3>(unit, members, items, nitems, counter, grid, persistent, single, s); break;
+        case QBSM_F64: launch_mode<QBSM_F64>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
+        case QBSM_F32: launch_mode<QBSM_F32>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
+        case QBSM_BF16: launch_mode<QBSM_BF16>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
+        case QBSM_BF16X3: launch_mode<QBSM_BF16X3>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
         default: throw Error(QBSM_ERR_ARG, "mode");
     }
     QB_LAUNCH_CHECK();
@@ -308,7 +484,7 @@ int k5_occupancy(qbsm_mode mode, int unit) {
     const int NT = 64 * (unit / 64) * (unit / 64);
 #define QB_OCC(MD, UU)                                                                                     \
     if (mode == MD && unit == UU)                                                                          \
-        QB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k5<MD, UU>), NT, 0));
+        QB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k5<MD, UU, 0>), NT, 0));
     QB_OCC(QBSM_F64, 64) QB_OCC(QBSM_F64, 128)
     QB_OCC(QBSM_F32, 64) QB_OCC(QBSM_F32, 128)
     QB_OCC(QBSM_BF16, 64) QB_OCC(QBSM_BF16, 128)
