@@ -40,12 +40,14 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="bf16x3", choices=["f32", "bf16", "bf16x3"])
+    ap.add_argument("--mode", default="bf16x3", choices=["f64", "f32", "bf16", "bf16x3"])
     ap.add_argument("--unit", type=int, default=128)
     ap.add_argument("--npoints", type=int, default=16384)
     ap.add_argument("--modes", default="f64,f32", help="reference modes timed beside the chosen one")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (no error statement)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -113,6 +115,13 @@ def main():
     torch.cuda.synchronize()
     print(f"[bench] workload generated and resident in HBM in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     A = qbsm.Matrix(a.nrows, a.ncols, bs)
     C = qbsm.Matrix(a.nrows, a.ncols, bs)

@@ -20,7 +20,7 @@ struct qbsm_batch_ {
 namespace qbsm {
 
 K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
-int k5_occupancy(qbsm_mode mode, int unit);
+int k5_occupancy(qbsm_mode mode, int unit, int bs);
 
 namespace {
 thread_local std::string g_last_error;
@@ -345,7 +345,7 @@ qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode,
         if (!items.empty())
             QB_HIP(hipMemcpyAsync(b.items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
         QB_HIP(hipStreamSynchronize(s));
-        b.wg_per_cu = b.unit ? k5_occupancy(mode, b.unit) : 1;
+        b.wg_per_cu = b.unit ? k5_occupancy(mode, b.unit, 0) : 1;
         *batch = h.release();
     });
 }
@@ -354,7 +354,7 @@ qbsm_status qbsm_batch_set_occupancy(qbsm_batch batch, int32_t wg_per_cu) {
     return guard([&] {
         QB_CHECK(batch && wg_per_cu >= 0, QBSM_ERR_ARG, "bad argument");
         Batch &b = batch->b;
-        b.wg_per_cu = wg_per_cu ? wg_per_cu : (b.unit ? k5_occupancy(b.mode, b.unit) : 1);
+        b.wg_per_cu = wg_per_cu ? wg_per_cu : (b.unit ? k5_occupancy(b.mode, b.unit, 0) : 1);
         if (b.exec) {
             (void)hipGraphExecDestroy(b.exec);
             (void)hipGraphDestroy(b.graph);

@@ -292,7 +292,7 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
         __syncthreads();
         int stage = 0;
         while (have) {
-            // prefetch the next step into the other stage
+            // coordinates of the next step
             int ni = i, nkb = kb, nc = c + 1;
             uint32_t nkm = km;
             bool nhave = true;
@@ -301,7 +301,6 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
                 ++nkb;
                 nhave = seek_step(mt, nb, LPU, NSUB, ni, nkb, nkm);
             }
-            if (nhave) issue_loads<MODE, U, BS>(m, mt, ni, nkb, nc, smem + (stage ^ 1) * G::STAGEB, w);
             // tiles of this wave whose leaf product exists in this step
             uint32_t en = 0;
 #pragma unroll
@@ -312,53 +311,47 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
                     if ((km >> (ib * LPU + jb)) & 1u) en |= 1u << (tm * 4 + tn);
                 }
             en = (uint32_t)uni((int)en);
+            // 1) all LDS fragment reads of this step ...
+            typename M::Frag fa[G::NGROUPS][4][PARTS], fb[G::NGROUPS][4][PARTS];
             if (en) {
                 const uint8_t *Ab = smem + stage * G::STAGEB;
                 const uint8_t *Bb = Ab + PARTS * G::ARRB;
 #pragma unroll
                 for (int rg = 0; rg < G::NGROUPS; ++rg) {
                     const int pbase = rg * M::PPG + (lane >> 4) * M::SUBS;
-                    typename M::Frag fa[4][PARTS];
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        const int ln = 64 * wr + 16 * t + (lane & 15);
+                        const int la_ = 64 * wr + 16 * t + (lane & 15);
+                        const int lb_ = 64 * wc + 16 * t + (lane & 15);
 #pragma unroll
                         for (int part = 0; part < PARTS; ++part)
 #pragma unroll
-                            for (int q = 0; q < M::SUBS; ++q)
-                                fa[t][part].q[q] = lds_piece(Ab + part * G::ARRB, ln, G::LB, pbase + q);
-                    }
-                    if (en == 0xFFFFu) {
-                        // every tile of the wave has its leaf product: no branches
-#pragma unroll
-                        for (int tn = 0; tn < 4; ++tn) {
-                            typename M::Frag fb[PARTS];
-                            const int ln = 64 * wc + 16 * tn + (lane & 15);
-#pragma unroll
-                            for (int part = 0; part < PARTS; ++part)
-#pragma unroll
-                                for (int q = 0; q < M::SUBS; ++q)
-                                    fb[part].q[q] = lds_piece(Bb + part * G::ARRB, ln, G::LB, pbase + q);
-#pragma unroll
-                            for (int tm = 0; tm < 4; ++tm) M::mma(acc[tm][tn], fa[tm], fb);
-                        }
-                    } else {
-#pragma unroll
-                        for (int tn = 0; tn < 4; ++tn) {
-                            if (!((en >> tn) & 0x1111u)) continue;
-                            typename M::Frag fb[PARTS];
-                            const int ln = 64 * wc + 16 * tn + (lane & 15);
-#pragma unroll
-                            for (int part = 0; part < PARTS; ++part)
-#pragma unroll
-                                for (int q = 0; q < M::SUBS; ++q)
-                                    fb[part].q[q] = lds_piece(Bb + part * G::ARRB, ln, G::LB, pbase + q);
-#pragma unroll
-                            for (int tm = 0; tm < 4; ++tm)
-                                if ((en >> (tm * 4 + tn)) & 1u) M::mma(acc[tm][tn], fa[tm], fb);
-                        }
+                            for (int q = 0; q < M::SUBS; ++q) {
+                                fa[rg][t][part].q[q] = lds_piece(Ab + part * G::ARRB, la_, G::LB, pbase + q);
+                                fb[rg][t][part].q[q] = lds_piece(Bb + part * G::ARRB, lb_, G::LB, pbase + q);
+                            }
                     }
                 }
+            }
+            // 2) ... are issued before the next step's copy into the other
+            // stage, so that the copy (tracked by the same counter as the
+            // LDS reads' dependency on earlier copies) runs under 3) the MFMAs
+            if (nhave) issue_loads<MODE, U, BS>(m, mt, ni, nkb, nc, smem + (stage ^ 1) * G::STAGEB, w);
+            if (en == 0xFFFFu) {
+#pragma unroll
+                for (int rg = 0; rg < G::NGROUPS; ++rg)
+#pragma unroll
+                    for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+                        for (int tm = 0; tm < 4; ++tm) M::mma(acc[tm][tn], fa[rg][tm], fb[rg][tn]);
+            } else if (en) {
+#pragma unroll
+                for (int rg = 0; rg < G::NGROUPS; ++rg)
+#pragma unroll
+                    for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+                        for (int tm = 0; tm < 4; ++tm)
+                            if ((en >> (tm * 4 + tn)) & 1u) M::mma(acc[tm][tn], fa[rg][tm], fb[rg][tn]);
             }
             __syncthreads();
             i = ni;
@@ -370,7 +363,9 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
         }
     }
 
-    // write the owned output blocks once (padding beyond the logical size = 0)
+    // write the owned output blocks once (padding beyond the logical size = 0);
+    // a 16x16 tile lies inside one leaf, so its leaf index and edge test are
+    // wave-uniform
     uint32_t ui, uj;
     demorton(m.ukey[u], ui, uj);
     typename M::Out *C = static_cast<typename M::Out *>(m.C);
@@ -379,18 +374,31 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
     for (int tm = 0; tm < 4; ++tm)
 #pragma unroll
         for (int tn = 0; tn < 4; ++tn) {
-            const int col = 64 * wc + 16 * tn + (lane & 15);
-            const int jb = col / BS, cc = col - jb * BS;
+            const int row0 = 64 * wr + 16 * tm, col0 = 64 * wc + 16 * tn;
+            const int ib = row0 / BS, jb = col0 / BS;
+            const int32_t leaf = uni(m.cdesc[(int64_t)u * NSUB + ib * LPU + jb]);
+            if (leaf < 0) continue;
+            const int64_t I = (int64_t)ui * LPU + ib, J = (int64_t)uj * LPU + jb;
+            const bool interior = (I + 1) * BS <= m.out_rows && (J + 1) * BS <= m.out_cols;
+            const int cc = col0 - jb * BS + (lane & 15);
+            typename M::Out *dst = C + (int64_t)leaf * N2 + (int64_t)cc * BS + (row0 - ib * BS);
+            if (M::row_of(0, 1) == 1 && interior) {
+                // rows 4*(lane/16) .. +3 of the tile are contiguous in the column
+                if constexpr (sizeof(typename M::Out) == 4) {
+                    *reinterpret_cast<float4 *>(dst + 4 * (lane >> 4)) =
+                        make_float4(acc[tm][tn][0], acc[tm][tn][1], acc[tm][tn][2], acc[tm][tn][3]);
+                } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = 64 * wr + 16 * tm + M::row_of(lane, i);
-                const int ib = row / BS, r = row - ib * BS;
-                const int32_t leaf = m.cdesc[(int64_t)u * NSUB + ib * LPU + jb];
-                if (leaf < 0) continue;
-                const int64_t I = (int64_t)ui * LPU + ib, J = (int64_t)uj * LPU + jb;
-                const bool ok = (I * BS + r) < m.out_rows && (J * BS + cc) < m.out_cols;
-                C[(int64_t)leaf * N2 + r + (int64_t)cc * BS] =
-                    ok ? (typename M::Out)acc[tm][tn][i] : (typename M::Out)0;
+                    for (int i = 0; i < 4; ++i) dst[4 * (lane >> 4) + i] = (typename M::Out)acc[tm][tn][i];
+                }
+            } else {
+                const bool colok = (J * BS + cc) < m.out_cols;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = row0 - ib * BS + M::row_of(lane, i);
+                    const bool ok = colok && (I * BS + r) < m.out_rows;
+                    dst[M::row_of(lane, i)] = ok ? (typename M::Out)acc[tm][tn][i] : (typename M::Out)0;
+                }
             }
         }
 }
@@ -479,17 +487,22 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const
     QB_LAUNCH_CHECK();
 }
 
-int k5_occupancy(qbsm_mode mode, int unit) {
+// Resident workgroups per CU of the launched variant (bs = 0: persistent
+// work-list variant).
+int k5_occupancy(qbsm_mode mode, int unit, int bs) {
     int nb = 0;
     const int NT = 64 * (unit / 64) * (unit / 64);
-#define QB_OCC(MD, UU)                                                                                     \
-    if (mode == MD && unit == UU)                                                                          \
-        QB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(&k5<MD, UU, 0>), NT, 0));
-    QB_OCC(QBSM_F64, 64) QB_OCC(QBSM_F64, 128)
-    QB_OCC(QBSM_F32, 64) QB_OCC(QBSM_F32, 128)
-    QB_OCC(QBSM_BF16, 64) QB_OCC(QBSM_BF16, 128)
-    QB_OCC(QBSM_BF16X3, 64) QB_OCC(QBSM_BF16X3, 128)
+    const void *fn = nullptr;
+#define QB_OCC(MD, UU, BB) \
+    if (mode == MD && unit == UU && bs == BB) fn = reinterpret_cast<const void *>(&k5<MD, UU, BB>);
+#define QB_OCC_M(MD)                                                                               \
+    QB_OCC(MD, 64, 0) QB_OCC(MD, 64, 32) QB_OCC(MD, 64, 64) QB_OCC(MD, 128, 0) QB_OCC(MD, 128, 32) \
+    QB_OCC(MD, 128, 64) QB_OCC(MD, 128, 128)
+    QB_OCC_M(QBSM_F64) QB_OCC_M(QBSM_F32) QB_OCC_M(QBSM_BF16) QB_OCC_M(QBSM_BF16X3)
+#undef QB_OCC_M
 #undef QB_OCC
+    QB_CHECK(fn, QBSM_ERR_UNSUPPORTED, "no kernel for this mode, unit and leaf size");
+    QB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, 0));
     return nb < 1 ? 1 : nb;
 }
 
