@@ -114,6 +114,12 @@ qbsm_status qbsm_matrix_set_blocks(qbsm_matrix m, int64_t nblk, const int32_t *b
                                    const int32_t *bcol, const double *vals, double drop_tol,
                                    void *stream, int64_t *nkept);
 
+/* Rounds the stored values to binary32 (round to nearest even) and frees
+ * the FP64 copy, halving the matrix's memory when it only feeds FP32 or
+ * BF16 modes.  A later QBSM_F64 multiply of this matrix uses the rounded
+ * values; readback widens them exactly.  No effect on an FP32-stored matrix. */
+qbsm_status qbsm_matrix_store_f32(qbsm_matrix m, void *stream);
+
 /* Shape and stored-block count (host outs; any may be NULL). */
 qbsm_status qbsm_matrix_info(qbsm_matrix m, int64_t *nrows, int64_t *ncols, int32_t *bs,
                              int64_t *nblk);
@@ -126,6 +132,15 @@ qbsm_status qbsm_matrix_get_pattern(qbsm_matrix m, int32_t *brow, int32_t *bcol,
  * blocks into device double[nblk * bs * bs].  Results of an FP32 mode are
  * widened exactly. */
 qbsm_status qbsm_matrix_get_values(qbsm_matrix m, double *vals, void *stream);
+
+/* Extraction of selected blocks (Sec. 2.2, extraction of the elements given
+ * by index vectors, at leaf-block granularity): for q in [0, n), block
+ * (brow[q], bcol[q]) is written as an FP64 column-major bs x bs block to
+ * vals + q*bs*bs (device), zero when the block is not stored.  Errors:
+ * QBSM_ERR_PATTERN if a coordinate lies outside the block grid (checked on
+ * the device; synchronises the stream). */
+qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *brow,
+                                       const int32_t *bcol, double *vals, void *stream);
 
 /* ---------------------------------------------------------------- multiply */
 

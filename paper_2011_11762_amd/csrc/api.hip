@@ -185,6 +185,14 @@ qbsm_status qbsm_matrix_set_blocks(qbsm_matrix m, int64_t nblk, const int32_t *b
     });
 }
 
+qbsm_status qbsm_matrix_store_f32(qbsm_matrix m, void *stream) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        QB_CHECK(m->m.has_blocks, QBSM_ERR_STATE, "matrix has no blocks yet");
+        matrix_store_f32(m->m, as_stream(stream));
+    });
+}
+
 qbsm_status qbsm_matrix_info(qbsm_matrix m, int64_t *nrows, int64_t *ncols, int32_t *bs, int64_t *nblk) {
     return guard([&] {
         QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
@@ -208,6 +216,14 @@ qbsm_status qbsm_matrix_get_values(qbsm_matrix m, double *vals, void *stream) {
         QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
         QB_CHECK(m->m.nblk == 0 || vals, QBSM_ERR_ARG, "null output array");
         matrix_get_values(m->m, vals, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *brow, const int32_t *bcol,
+                                       double *vals, void *stream) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        matrix_extract_blocks(m->m, n, brow, bcol, vals, as_stream(stream));
     });
 }
 

@@ -180,10 +180,13 @@ Allocator &allocator();
 // -------------------------------------------------------------- operations
 int64_t matrix_set_blocks(Matrix &m, int64_t nblk, const int32_t *brow, const int32_t *bcol,
                           const double *vals, double drop_tol, hipStream_t s);
+void matrix_store_f32(Matrix &m, hipStream_t s);
 Tree &matrix_tree(Matrix &m, int D, hipStream_t s);
 const int32_t *tree_desc(Matrix &m, Tree &t, int s_lvl, hipStream_t st);
 void matrix_get_pattern(Matrix &m, int32_t *brow, int32_t *bcol, hipStream_t s);
 void matrix_get_values(Matrix &m, double *vals, hipStream_t s);
+void matrix_extract_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32_t *bcol, double *vals,
+                           hipStream_t s);
 void matrix_morton_to_rowmajor_rank(Matrix &m, int32_t *rank, hipStream_t s);
 
 std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M,

@@ -117,6 +117,12 @@ __global__ void __launch_bounds__(256) k_store_blocks(const double *vals, const 
     if (threadIdx.x == 0) okeys[r] = keys[t];
 }
 
+__global__ void k_narrow(const double *x, float *y, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) y[i] = (float)x[i];
+}
+
 // ---- quadtree build: one level from its children level
 __global__ void k_tree_flags(const uint32_t *ckeys, const int64_t *ncount, int64_t cap, int32_t *flags) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,6 +184,39 @@ __global__ void __launch_bounds__(256) k_scatter_values(const T *pool, const int
     const T *x = pool + t * n2;
     double *y = out + (int64_t)rank[t] * n2;
     for (int64_t e = threadIdx.x; e < n2; e += 256) y[e] = (double)x[e];
+}
+
+// One workgroup per requested block: binary search of its Morton key among
+// the stored (sorted) keys, then a copy or a zero block.
+template <class T>
+__global__ void __launch_bounds__(256) k_extract(const uint32_t *keys, int64_t nblk, const T *pool, int32_t bs,
+                                                 int64_t nbr, int64_t nbc, const int32_t *qi, const int32_t *qj,
+                                                 int64_t nq, double *out, int32_t *bad) {
+    const int64_t q = blockIdx.x;
+    if (q >= nq) return;
+    __shared__ int64_t s_idx;
+    const int32_t i = qi[q], j = qj[q];
+    const bool ok = i >= 0 && j >= 0 && i < nbr && j < nbc;
+    if (threadIdx.x == 0) {
+        int64_t idx = -1;
+        if (ok) {
+            const uint32_t k = morton2((uint32_t)i, (uint32_t)j);
+            int64_t lo = 0, hi = nblk;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (keys[mid] < k) lo = mid + 1; else hi = mid;
+            }
+            if (lo < nblk && keys[lo] == k) idx = lo;
+        } else {
+            *bad = 1;
+        }
+        s_idx = idx;
+    }
+    __syncthreads();
+    const int64_t n2 = (int64_t)bs * bs;
+    const int64_t idx = s_idx;
+    double *y = out + q * n2;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) y[e] = idx >= 0 ? (double)pool[idx * n2 + e] : 0.0;
 }
 
 // ---- operand packing
@@ -316,6 +355,22 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     return nk;
 }
 
+void matrix_store_f32(Matrix &m, hipStream_t s) {
+    if (m.storage != ST_F64) return;
+    const int64_t n = m.nblk * (int64_t)m.bs * m.bs;
+    DArr<float> v(n ? n : 1, s);
+    if (n) {
+        const unsigned g = grid_for(n, 256) > 65536 ? 65536 : grid_for(n, 256);
+        k_narrow<<<g, 256, 0, s>>>(m.v64.p, v.p, n);
+        QB_LAUNCH_CHECK();
+    }
+    m.v32 = std::move(v);
+    m.v64.reset();
+    m.storage = ST_F32;
+    m.version++;
+    m.packs.clear();
+}
+
 Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
     auto it = m.trees.find(D);
     if (it != m.trees.end()) return *it->second;
@@ -409,6 +464,24 @@ void matrix_get_values(Matrix &m, double *vals, hipStream_t s) {
     else
         k_scatter_values<float><<<(unsigned)n, 256, 0, s>>>(m.v32.p, rank.p, n, m.bs, vals);
     QB_LAUNCH_CHECK();
+}
+
+void matrix_extract_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32_t *bcol, double *vals,
+                           hipStream_t s) {
+    QB_CHECK(n >= 0, QBSM_ERR_ARG, "negative count");
+    if (!n) return;
+    QB_CHECK(brow && bcol && vals, QBSM_ERR_ARG, "null arrays");
+    QB_CHECK(n <= (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many blocks requested");
+    DArr<int32_t> bad(1, s);
+    fill_i32(bad.p, 0, 1, s);
+    if (m.storage == ST_F32)
+        k_extract<float><<<(unsigned)n, 256, 0, s>>>(m.keys.p, m.nblk, m.v32.p, m.bs, m.nbr, m.nbc, brow, bcol, n,
+                                                      vals, bad.p);
+    else
+        k_extract<double><<<(unsigned)n, 256, 0, s>>>(m.keys.p, m.nblk, m.v64.p, m.bs, m.nbr, m.nbc, brow, bcol, n,
+                                                       vals, bad.p);
+    QB_LAUNCH_CHECK();
+    QB_CHECK(read_back(bad.p, s) == 0, QBSM_ERR_PATTERN, "block coordinate outside the block grid");
 }
 
 void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) {

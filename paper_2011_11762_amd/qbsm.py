@@ -52,9 +52,11 @@ _SIGS = {
     "qbsm_matrix_destroy": [c_void_p],
     "qbsm_matrix_set_blocks": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                                POINTER(c_int64)],
+    "qbsm_matrix_store_f32": [c_void_p, c_void_p],
     "qbsm_matrix_info": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)],
     "qbsm_matrix_get_pattern": [c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_matrix_get_values": [c_void_p, c_void_p, c_void_p],
+    "qbsm_matrix_extract_blocks": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_multiply_symbolic": [c_void_p, c_void_p, POINTER(PlanOpts), c_void_p, POINTER(c_void_p),
                                POINTER(c_int64), POINTER(c_int64)],
     "qbsm_multiply_symbolic_ex": [c_void_p, c_int32, c_void_p, c_int32, c_void_p, POINTER(PlanOpts), c_void_p,
@@ -166,6 +168,10 @@ class Matrix:
                                            float(drop_tol), _stream(), ctypes.byref(kept)))
         return kept.value
 
+    def store_f32(self):
+        """Round stored values to binary32 and drop the FP64 copy (halves memory)."""
+        _check(_lib.qbsm_matrix_store_f32(self._h, _stream()))
+
     @property
     def nblk(self) -> int:
         n = c_int64()
@@ -183,6 +189,16 @@ class Matrix:
         n = self.nblk
         out = torch.empty((n, self.bs * self.bs), dtype=torch.float64, device="cuda")
         _check(_lib.qbsm_matrix_get_values(self._h, _ptr(out), _stream()))
+        return out
+
+
+    def extract(self, brow, bcol) -> torch.Tensor:
+        """FP64 values of blocks (brow[q], bcol[q]) (zero blocks where not stored)."""
+        brow = torch.as_tensor(brow, dtype=torch.int32).cuda().contiguous()
+        bcol = torch.as_tensor(bcol, dtype=torch.int32).cuda().contiguous()
+        out = torch.empty((brow.numel(), self.bs * self.bs), dtype=torch.float64, device="cuda")
+        _check(_lib.qbsm_matrix_extract_blocks(self._h, brow.numel(), _ptr(brow), _ptr(bcol), _ptr(out),
+                                               _stream()))
         return out
 
 

@@ -42,6 +42,7 @@ __all__ = [
     "config5",
     "small_random",
     "zero_padding",
+    "decay_blocks_device",
 ]
 
 
@@ -180,6 +181,32 @@ def decay_blocks(points: np.ndarray, bs: int, alpha: float = 0.5) -> BlockMatrix
         # [r, J, c] -> [J, c, r]
         v[bi] = full.reshape(bs, nb, bs).transpose(1, 2, 0)
     return BlockMatrix(n, n, bs, brow, bcol, vals, {"kind": "decay", "alpha": alpha})
+
+
+def decay_blocks_device(points: np.ndarray, bs: int, alpha: float = 0.5, device="cuda"):
+    """Same blocks as :func:`decay_blocks`, generated with torch on a device.
+
+    Returns (brow, bcol, vals) as int32 / int32 / float64 device tensors in
+    canonical order.  Elementwise FP64 arithmetic on the device may differ
+    from numpy's ``exp`` in the last bit, so consumers that compare against
+    a reference must read the values back from these tensors.
+    """
+    import torch
+
+    n = points.shape[0]
+    nb = -(-n // bs)
+    p = torch.from_numpy(np.ascontiguousarray(points)).to(device=device, dtype=torch.float64)
+    vals = torch.zeros((nb, nb, bs, bs), dtype=torch.float64, device=device)  # [I, J, c, r]
+    for bi in range(nb):
+        r0, r1 = bi * bs, min(n, (bi + 1) * bs)
+        diff = p[r0:r1, None, :] - p[None, :, :]
+        rowblk = torch.exp(-alpha * torch.sqrt((diff * diff).sum(dim=2)))  # [r, col]
+        full = torch.zeros((bs, nb * bs), dtype=torch.float64, device=device)
+        full[: r1 - r0, :n] = rowblk
+        vals[bi] = full.reshape(bs, nb, bs).permute(1, 2, 0)
+    ii, jj = torch.meshgrid(torch.arange(nb, device=device), torch.arange(nb, device=device), indexing="ij")
+    return (ii.reshape(-1).to(torch.int32).contiguous(), jj.reshape(-1).to(torch.int32).contiguous(),
+            vals.reshape(nb * nb, bs * bs))
 
 
 # --------------------------------------------------------------------------
