@@ -19,6 +19,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--mode bf16x3] [--gpus 1]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,6 +34,22 @@ METRIC = "effective GFLOP/s on nonzero leaf products, plain FP64 vs chosen form 
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
 MFMA_TERMS = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3}
 DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16"}
+# bytes per element of the packed operands and of the result, per mode
+OPERAND_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4}
+RESULT_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "bf16x3": 4}
+KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
+# HBM bytes of one numeric-kernel launch on the default workload (unit 128),
+# from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per
+# dispatch), scaled by what the same counters read for a 1 GiB
+# device-to-device copy in the same runs (FETCH_SIZE x2.0, WRITE_SIZE x1.0).
+# They describe only the kernel sources with this digest; for any other
+# source, unit or workload the traffic is reported as null.
+TRAFFIC = {
+    "sources_sha256_16": "83f4bdff65491086",
+    "unit": 128,
+    "npoints": 16384,
+    "bytes": {"f64": 413941879603, "f32": 213918175130, "bf16x3": 145079133491},
+}
 
 
 def parse():
@@ -49,6 +66,21 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def kernel_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2011_11762_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(mode, unit, npoints):
+    t = TRAFFIC
+    if (t["sources_sha256_16"], t["unit"], t["npoints"]) != (kernel_digest(), unit, npoints):
+        return None
+    return t["bytes"].get(mode)
 
 
 def cpu_baseline_leg(wl, tol, bs, seconds):
@@ -204,6 +236,10 @@ def main():
     f64 = results.get("f64")
     peak = PEAK_TFLOPS[args.mode]
     achieved = ch["kernel_mfma_tflops"]
+    bs2 = bs * bs
+    # algorithmic bytes of one launch: both packed operands read once, C written once
+    alg_bytes = (2 * A.nblk * bs2 * OPERAND_BYTES[args.mode]
+                 + info["nblk_out"] * bs2 * RESULT_BYTES[args.mode])
     out = {
         "metric": METRIC,
         "value": ch["effective_gflops"],
@@ -231,7 +267,9 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": None,
+            "traffic": measured_traffic(args.mode, info["unit"], args.npoints),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes": alg_bytes,
             "kernel": f"numeric leaf-product kernel, mode {args.mode}, unit {info['unit']} "
                       f"({MFMA_TERMS[args.mode]} MFMA term(s) per leaf product)",
         },
