@@ -147,7 +147,10 @@ qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *
 /* Options of the symbolic phase.  unit: side, in elements, of the C quadtree
  * node that one GPU workgroup owns (the depth where the recursion hands over
  * to a dense kernel); 0 picks the default (128).  Must be bs * 2^s with s in
- * 0..2 and a value in {64, 128}. */
+ * 0..2 and a value in {64, 128, 256}.  A plan with unit 256 serves the
+ * 4-byte-accumulator modes (F32, BF16, BF16X3); its FP64 numeric phase
+ * returns QBSM_ERR_UNSUPPORTED (a 256 x 256 FP64 accumulator exceeds the
+ * register file of one compute unit). */
 typedef struct {
     int32_t unit;
     int32_t reserved[7];
@@ -235,8 +238,9 @@ qbsm_status qbsm_batch_destroy(qbsm_batch batch);
 
 /* Times the numeric phase of C = A * B for every valid unit side (symbolic
  * + numeric, `reps` timed repetitions after one warm-up) and reports the
- * fastest.  times_ms (host, may be NULL) receives 2 entries in the order
- * unit = 64, 128 (negative when not applicable to the leaf size). */
+ * fastest.  times_ms (host, may be NULL) receives 3 entries in the order
+ * unit = 64, 128, 256 (negative when not applicable to the leaf size or the
+ * mode). */
 qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps,
                                void *stream, int32_t *best_unit, double *times_ms);
 

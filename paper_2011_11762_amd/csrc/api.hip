@@ -427,16 +427,16 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
         QB_CHECK(reps >= 1, QBSM_ERR_ARG, "reps must be >= 1");
         hipStream_t s = as_stream(stream);
         const int bs = A->m.bs;
-        const int cand[2] = {64, 128};
+        const int cand[3] = {64, 128, 256};
         double best = -1.0;
         int bu = 0;
         hipEvent_t e0, e1;
         QB_HIP(hipEventCreate(&e0));
         QB_HIP(hipEventCreate(&e1));
-        for (int ci = 0; ci < 2; ++ci) {
+        for (int ci = 0; ci < 3; ++ci) {
             const int u = cand[ci];
             double t = -1.0;
-            const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1;
+            const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64);
             if (ok) {
                 auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, s);
                 Matrix out;

@@ -199,7 +199,12 @@ struct Geo {
     static constexpr int NGROUPS = BK / M::KPG;
     static constexpr int LPI = 1024 / LB;                // lines per 1 KB load instruction
     static constexpr int IPA = U / LPI;                  // load instructions per array
-    static constexpr int NW = (U / 64) * (U / 64);
+    static constexpr int WT = U >= 256 ? 128 : 64;       // side of the part one wave computes
+    static constexpr int WPS = U / WT;                   // waves per unit side
+    static constexpr int NW = WPS * WPS;
+    static constexpr int TPW = WT / 16;                  // 16x16 tiles per wave side
+    static constexpr int NLW = WT > BS ? WT / BS : 1;    // leaves per wave side
+    static constexpr int TPL = (WT < BS ? WT : BS) / 16; // tiles per leaf side inside a wave
     static constexpr int NARR = 2 * M::PARTS;
     static constexpr int PER_WAVE = NARR * IPA / NW;
     static constexpr int ARRB = U * M::LBMAX;
@@ -207,7 +212,14 @@ struct Geo {
     static constexpr int CAP = META_BYTES / (8 + 8 * NSUB);
     static_assert(NARR * IPA % NW == 0, "load instructions must split evenly over the waves");
     static_assert(LB <= M::LBMAX && LPI <= BS, "line geometry");
+    static_assert(NSUB * LPU <= 64, "leaf-product bits of a pair must fit 64 bits");
 };
+
+template <int MODE, int U>
+constexpr int k5_nt = 64 * (U / (U >= 256 ? 128 : 64)) * (U / (U >= 256 ? 128 : 64));
+
+template <int MODE, int U>
+constexpr int k5_stage_bytes = 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX;
 
 template <int MODE, int U, int BS>
 __device__ __forceinline__ void issue_loads(const K5Member &m, const Meta &mt, int i, int kb, int c, uint8_t *stage,
@@ -246,24 +258,109 @@ __device__ __forceinline__ void issue_loads(const K5Member &m, const Meta &mt, i
     }
 }
 
+// Wave-uniform enable bits of the leaves a wave covers in one step: bit
+// (a * NLW + b) is set when the product of the wave's leaf row a and leaf
+// column b exists in this step.
 template <int MODE, int U, int BS>
-__device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *meta) {
+__device__ __forceinline__ uint32_t wave_leaves(uint32_t km, int wr, int wc) {
+    using G = Geo<MODE, U, BS>;
+    uint32_t wl = 0;
+#pragma unroll
+    for (int a = 0; a < G::NLW; ++a)
+#pragma unroll
+        for (int b = 0; b < G::NLW; ++b) {
+            const int ib = (G::WT * wr) / BS + a, jb = (G::WT * wc) / BS + b;
+            wl |= ((km >> (ib * G::LPU + jb)) & 1u) << (a * G::NLW + b);
+        }
+    return (uint32_t)uni((int)wl);
+}
+
+// One step on the LDS stage `cur` while the copy of the next step (if any)
+// lands in `nxt`.  The two stages are distinct shared arrays, so the
+// compiler knows the copy into `nxt` cannot alias the fragment reads of
+// `cur` and issues no wait between them: the copy is issued first and runs
+// under the whole step.  The step ends with every wave's copies complete and
+// a barrier, after which `cur` may be overwritten.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
+                                         typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                         int &i, int &kb, int &c, uint32_t &km, bool &have, int w, int wr, int wc) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
-    constexpr int WPS = U / 64;
-    constexpr int NT = 64 * G::NW;
-    constexpr int PARTS = M::PARTS;
-    constexpr int LPU = G::LPU, NSUB = G::NSUB, S = G::S;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = uni(tid >> 6);
-    const int wr = w / WPS, wc = w % WPS;
+    constexpr int PARTS = M::PARTS, TPW = G::TPW, TPL = G::TPL, NLW = G::NLW;
+    const int lane = threadIdx.x & 63;
+    int ni = i, nkb = kb, nc = c + 1;
+    uint32_t nkm = km;
+    bool nhave = true;
+    if (nc == G::NCHUNK) {
+        nc = 0;
+        ++nkb;
+        nhave = seek_step(mt, nb, G::LPU, G::NSUB, ni, nkb, nkm);
+    }
+    if (nhave) issue_loads<MODE, U, BS>(m, mt, ni, nkb, nc, nxt, w);
+    const uint32_t wl = wave_leaves<MODE, U, BS>(km, wr, wc);
+    if (wl) {
+        const uint8_t *Ab = cur;
+        const uint8_t *Bb = cur + PARTS * G::ARRB;
+#pragma unroll
+        for (int rg = 0; rg < G::NGROUPS; ++rg) {
+            const int pbase = rg * M::PPG + (lane >> 4) * M::SUBS;
+            typename M::Frag fa[TPW][PARTS];
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int la_ = G::WT * wr + 16 * t + (lane & 15);
+#pragma unroll
+                for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                    for (int q = 0; q < M::SUBS; ++q)
+                        fa[t][part].q[q] = lds_piece(Ab + part * G::ARRB, la_, G::LB, pbase + q);
+            }
+            // B fragments of column tile tn + 1 are read while the MFMAs of
+            // column tile tn run
+            typename M::Frag fb[2][PARTS];
+            auto read_b = [&](int tn, typename M::Frag (&dst)[PARTS]) {
+                const int lb_ = G::WT * wc + 16 * tn + (lane & 15);
+#pragma unroll
+                for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                    for (int q = 0; q < M::SUBS; ++q)
+                        dst[part].q[q] = lds_piece(Bb + part * G::ARRB, lb_, G::LB, pbase + q);
+            };
+            read_b(0, fb[0]);
+#pragma unroll
+            for (int tn = 0; tn < TPW; ++tn) {
+                if (tn + 1 < TPW) read_b(tn + 1, fb[(tn + 1) & 1]);
+#pragma unroll
+                for (int tm = 0; tm < TPW; ++tm)
+                    if ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u) M::mma(acc[tm][tn], fa[tm], fb[tn & 1]);
+            }
+        }
+    }
+    // every wave's copy into nxt has landed and nobody reads cur any more
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    i = ni;
+    kb = nkb;
+    c = nc;
+    km = nkm;
+    have = nhave;
+}
 
-    typename M::Acc acc[4][4];
+template <int MODE, int U, int BS>
+__device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    constexpr int NT = 64 * G::NW;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB, S = G::S, TPW = G::TPW;
+    const int tid = threadIdx.x;
+    const int w = uni(tid >> 6);
+    const int wr = w / G::WPS, wc = w % G::WPS;
+
+    typename M::Acc acc[TPW][TPW];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < TPW; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = typename M::Acc{};
+        for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
 
     const int p0 = m.ustart[u], p1 = m.ustart[u + 1];
     const Meta mt = meta_view(meta, G::CAP, NSUB);
@@ -288,93 +385,31 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
         int i = 0, kb = 0, c = 0;
         uint32_t km = 0;
         bool have = seek_step(mt, nb, LPU, NSUB, i, kb, km);
-        if (have) issue_loads<MODE, U, BS>(m, mt, i, kb, c, smem, w);
+        if (have) issue_loads<MODE, U, BS>(m, mt, i, kb, c, st0, w);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
-        int stage = 0;
+        // steps alternate between the two stages; unrolled by two so that
+        // every access names its stage array at compile time
         while (have) {
-            // coordinates of the next step
-            int ni = i, nkb = kb, nc = c + 1;
-            uint32_t nkm = km;
-            bool nhave = true;
-            if (nc == G::NCHUNK) {
-                nc = 0;
-                ++nkb;
-                nhave = seek_step(mt, nb, LPU, NSUB, ni, nkb, nkm);
-            }
-            // tiles of this wave whose leaf product exists in this step
-            uint32_t en = 0;
-#pragma unroll
-            for (int tm = 0; tm < 4; ++tm)
-#pragma unroll
-                for (int tn = 0; tn < 4; ++tn) {
-                    const int ib = (64 * wr + 16 * tm) / BS, jb = (64 * wc + 16 * tn) / BS;
-                    if ((km >> (ib * LPU + jb)) & 1u) en |= 1u << (tm * 4 + tn);
-                }
-            en = (uint32_t)uni((int)en);
-            // 1) all LDS fragment reads of this step ...
-            typename M::Frag fa[G::NGROUPS][4][PARTS], fb[G::NGROUPS][4][PARTS];
-            if (en) {
-                const uint8_t *Ab = smem + stage * G::STAGEB;
-                const uint8_t *Bb = Ab + PARTS * G::ARRB;
-#pragma unroll
-                for (int rg = 0; rg < G::NGROUPS; ++rg) {
-                    const int pbase = rg * M::PPG + (lane >> 4) * M::SUBS;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int la_ = 64 * wr + 16 * t + (lane & 15);
-                        const int lb_ = 64 * wc + 16 * t + (lane & 15);
-#pragma unroll
-                        for (int part = 0; part < PARTS; ++part)
-#pragma unroll
-                            for (int q = 0; q < M::SUBS; ++q) {
-                                fa[rg][t][part].q[q] = lds_piece(Ab + part * G::ARRB, la_, G::LB, pbase + q);
-                                fb[rg][t][part].q[q] = lds_piece(Bb + part * G::ARRB, lb_, G::LB, pbase + q);
-                            }
-                    }
-                }
-            }
-            // 2) ... are issued before the next step's copy into the other
-            // stage, so that the copy (tracked by the same counter as the
-            // LDS reads' dependency on earlier copies) runs under 3) the MFMAs
-            if (nhave) issue_loads<MODE, U, BS>(m, mt, ni, nkb, nc, smem + (stage ^ 1) * G::STAGEB, w);
-            if (en == 0xFFFFu) {
-#pragma unroll
-                for (int rg = 0; rg < G::NGROUPS; ++rg)
-#pragma unroll
-                    for (int tn = 0; tn < 4; ++tn)
-#pragma unroll
-                        for (int tm = 0; tm < 4; ++tm) M::mma(acc[tm][tn], fa[rg][tm], fb[rg][tn]);
-            } else if (en) {
-#pragma unroll
-                for (int rg = 0; rg < G::NGROUPS; ++rg)
-#pragma unroll
-                    for (int tn = 0; tn < 4; ++tn)
-#pragma unroll
-                        for (int tm = 0; tm < 4; ++tm)
-                            if ((en >> (tm * 4 + tn)) & 1u) M::mma(acc[tm][tn], fa[rg][tm], fb[rg][tn]);
-            }
-            __syncthreads();
-            i = ni;
-            kb = nkb;
-            c = nc;
-            km = nkm;
-            have = nhave;
-            stage ^= 1;
+            run_step<MODE, U, BS>(m, mt, nb, st0, st1, acc, i, kb, c, km, have, w, wr, wc);
+            if (!have) break;
+            run_step<MODE, U, BS>(m, mt, nb, st1, st0, acc, i, kb, c, km, have, w, wr, wc);
         }
     }
 
     // write the owned output blocks once (padding beyond the logical size = 0);
     // a 16x16 tile lies inside one leaf, so its leaf index and edge test are
     // wave-uniform
+    const int lane = tid & 63;
     uint32_t ui, uj;
     demorton(m.ukey[u], ui, uj);
     typename M::Out *C = static_cast<typename M::Out *>(m.C);
     constexpr int64_t N2 = (int64_t)BS * BS;
 #pragma unroll
-    for (int tm = 0; tm < 4; ++tm)
+    for (int tm = 0; tm < TPW; ++tm)
 #pragma unroll
-        for (int tn = 0; tn < 4; ++tn) {
-            const int row0 = 64 * wr + 16 * tm, col0 = 64 * wc + 16 * tn;
+        for (int tn = 0; tn < TPW; ++tn) {
+            const int row0 = G::WT * wr + 16 * tm, col0 = G::WT * wc + 16 * tn;
             const int ib = row0 / BS, jb = col0 / BS;
             const int32_t leaf = uni(m.cdesc[(int64_t)u * NSUB + ib * LPU + jb]);
             if (leaf < 0) continue;
@@ -404,27 +439,35 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *smem, uint8_t *m
 }
 
 template <int MODE, int U>
-__device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *smem, uint8_t *meta) {
-    if (m.bs == 32) {
-        process_unit<MODE, U, 32>(m, u, smem, meta);
-    } else if (m.bs == 64) {
-        process_unit<MODE, U, 64>(m, u, smem, meta);
+__device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
+    if constexpr (U <= 128) {
+        if (m.bs == 32) {
+            process_unit<MODE, U, 32>(m, u, st0, st1, meta);
+            return;
+        }
+    }
+    if (m.bs == 64) {
+        process_unit<MODE, U, 64>(m, u, st0, st1, meta);
     } else if constexpr (U >= 128) {
-        process_unit<MODE, U, 128>(m, u, smem, meta);
+        if (m.bs == 128) process_unit<MODE, U, 128>(m, u, st0, st1, meta);
     }
 }
+
+template <int MODE, int U>
+constexpr int k5_min_blocks = (MODE == QBSM_F64 || U >= 256) ? 1 : 2;
 
 // BS > 0: one launch of one multiply with that leaf size, one workgroup per
 // unit.  BS == 0: persistent launch over a work list of (member, unit) items
 // of members with any leaf size, pulled from a device counter.
 template <int MODE, int U, int BS>
-__global__ void __launch_bounds__(64 * (U / 64) * (U / 64), MODE == QBSM_F64 ? 1 : 2)
+__global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     k5(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
-    __shared__ __attribute__((aligned(1024))) uint8_t smem[2 * 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX];
+    __shared__ __attribute__((aligned(1024))) uint8_t st0[k5_stage_bytes<MODE, U>];
+    __shared__ __attribute__((aligned(1024))) uint8_t st1[k5_stage_bytes<MODE, U>];
     __shared__ __attribute__((aligned(16))) uint8_t meta[META_BYTES];
     if constexpr (BS != 0) {
         const int u = xcd_remap((int)blockIdx.x, single.nunits);
-        process_unit<MODE, U, BS>(single, u, smem, meta);
+        process_unit<MODE, U, BS>(single, u, st0, st1, meta);
     } else {
         __shared__ int s_item;
         for (;;) {
@@ -435,7 +478,7 @@ __global__ void __launch_bounds__(64 * (U / 64) * (U / 64), MODE == QBSM_F64 ? 1
             if ((int64_t)it >= nitems) break;
             const int2 w = items[it];
             const K5Member mm = members[w.x];
-            process_any<MODE, U>(mm, w.y, smem, meta);
+            process_any<MODE, U>(mm, w.y, st0, st1, meta);
         }
     }
 }
@@ -443,22 +486,28 @@ __global__ void __launch_bounds__(64 * (U / 64) * (U / 64), MODE == QBSM_F64 ? 1
 template <int MODE, int U>
 void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter, int grid,
               int persistent, const K5Member &single, hipStream_t s) {
-    constexpr int NT = 64 * (U / 64) * (U / 64);
+    constexpr int NT = k5_nt<MODE, U>;
     if (persistent) {
         k5<MODE, U, 0><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
         return;
     }
-    switch (bs) {
-        case 32: k5<MODE, U, 32><<<grid, NT, 0, s>>>(single, members, items, nitems, counter); break;
-        case 64: k5<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter); break;
-        case 128:
-            if constexpr (U >= 128) {
-                k5<MODE, U, 128><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
-                break;
-            }
-            [[fallthrough]];
-        default: throw Error(QBSM_ERR_UNSUPPORTED, "leaf size for this unit side");
+    if constexpr (U <= 128) {
+        if (bs == 32) {
+            k5<MODE, U, 32><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+            return;
+        }
     }
+    if (bs == 64) {
+        k5<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+        return;
+    }
+    if constexpr (U >= 128) {
+        if (bs == 128) {
+            k5<MODE, U, 128><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+            return;
+        }
+    }
+    throw Error(QBSM_ERR_UNSUPPORTED, "leaf size for this unit side");
 }
 
 template <int MODE>
@@ -467,7 +516,15 @@ void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, i
     switch (unit) {
         case 64: launch_u<MODE, 64>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
         case 128: launch_u<MODE, 128>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
-        default: throw Error(QBSM_ERR_UNSUPPORTED, "unit side");
+        case 256:
+            // the 128 x 128 part of a wave holds 64 KB of accumulators in FP32
+            // but twice that in FP64, beyond the register file
+            if constexpr (MODE != QBSM_F64) {
+                launch_u<MODE, 256>(bs, members, items, nitems, counter, grid, persistent, single, s);
+                break;
+            }
+            [[fallthrough]];
+        default: throw Error(QBSM_ERR_UNSUPPORTED, "unit side for this mode");
     }
 }
 
@@ -491,14 +548,17 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const
 // work-list variant).
 int k5_occupancy(qbsm_mode mode, int unit, int bs) {
     int nb = 0;
-    const int NT = 64 * (unit / 64) * (unit / 64);
+    const int NT = 64 * (unit >= 256 ? 4 : (unit / 64) * (unit / 64));
     const void *fn = nullptr;
 #define QB_OCC(MD, UU, BB) \
     if (mode == MD && unit == UU && bs == BB) fn = reinterpret_cast<const void *>(&k5<MD, UU, BB>);
 #define QB_OCC_M(MD)                                                                               \
     QB_OCC(MD, 64, 0) QB_OCC(MD, 64, 32) QB_OCC(MD, 64, 64) QB_OCC(MD, 128, 0) QB_OCC(MD, 128, 32) \
     QB_OCC(MD, 128, 64) QB_OCC(MD, 128, 128)
+#define QB_OCC_256(MD) QB_OCC(MD, 256, 0) QB_OCC(MD, 256, 64) QB_OCC(MD, 256, 128)
     QB_OCC_M(QBSM_F64) QB_OCC_M(QBSM_F32) QB_OCC_M(QBSM_BF16) QB_OCC_M(QBSM_BF16X3)
+    QB_OCC_256(QBSM_F32) QB_OCC_256(QBSM_BF16) QB_OCC_256(QBSM_BF16X3)
+#undef QB_OCC_256
 #undef QB_OCC_M
 #undef QB_OCC
     QB_CHECK(fn, QBSM_ERR_UNSUPPORTED, "no kernel for this mode, unit and leaf size");
@@ -549,6 +609,8 @@ void plan_check_current(const Plan &p) {
 
 void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     plan_check_current(p);
+    QB_CHECK(!(mode == QBSM_F64 && p.unit >= 256), QBSM_ERR_UNSUPPORTED,
+             "unit 256 serves the FP32-accumulating modes only");
     QB_CHECK(&out != p.L && &out != p.R && &out != p.M, QBSM_ERR_ARG, "output aliases an operand");
     QB_CHECK(out.nrows == p.out_rows && out.ncols == p.out_cols && out.bs == p.bs, QBSM_ERR_SHAPE,
              "output shape or leaf size differs from the product");

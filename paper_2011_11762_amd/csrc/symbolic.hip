@@ -319,12 +319,12 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     const int64_t cols = transR ? R->nrows : R->ncols;
     QB_CHECK(inner == innerR, QBSM_ERR_SHAPE, "inner dimensions differ");
     if (M) QB_CHECK(M->nrows == rows && M->ncols == cols, QBSM_ERR_SHAPE, "mask shape differs from the product");
-    if (unit == 0) unit = bs == 128 ? 128 : 128;
+    if (unit == 0) unit = 128;
     int sl = -1;
     for (int t = 0; t <= 2; ++t)
         if ((bs << t) == unit) sl = t;
-    QB_CHECK(sl >= 0 && (unit == 64 || unit == 128), QBSM_ERR_UNSUPPORTED,
-             "unit must be bs*2^s (s<=2) and one of 64, 128");
+    QB_CHECK(sl >= 0 && (unit == 64 || unit == 128 || unit == 256), QBSM_ERR_UNSUPPORTED,
+             "unit must be bs*2^s (s<=2) and one of 64, 128, 256");
     const int64_t nbI = (rows + bs - 1) / bs, nbK = (inner + bs - 1) / bs, nbJ = (cols + bs - 1) / bs;
     int64_t nbmax = nbI > nbK ? nbI : nbK;
     nbmax = nbmax > nbJ ? nbmax : nbJ;

@@ -298,10 +298,10 @@ class Batch:
 
 def autotune_unit(A: Matrix, B: Matrix, mode, reps: int = 3):
     best = c_int32()
-    times = (c_double * 2)()
+    times = (c_double * 3)()
     _check(_lib.qbsm_autotune_unit(A.handle, B.handle, mode_id(mode), int(reps), _stream(),
                                    ctypes.byref(best), times))
-    return best.value, {64: times[0], 128: times[1]}
+    return best.value, {64: times[0], 128: times[1], 256: times[2]}
 
 
 PROF_NUMERIC, PROF_PACK = 0, 1

@@ -9,7 +9,13 @@ TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2, "bf16x3": 1e-4}
 # BF16: against the FP64 oracle applied to the bf16-rounded inputs (isolates
 # the FP32 accumulation)
 TOL_BF16_ROUNDED = 1e-5
-UNITS = {32: (64, 128), 64: (64, 128), 128: (128,)}
+# work-unit sides valid per leaf size (unit = bs * 2^s, s <= 2); unit 256
+# serves the FP32-accumulating modes only
+UNITS = {32: (64, 128), 64: (64, 128, 256), 128: (128, 256)}
+
+
+def units(bs, mode):
+    return tuple(u for u in UNITS[bs] if not (u == 256 and mode == "f64"))
 
 
 def upload(q, m, drop_tol=0.0):

@@ -11,7 +11,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_11762_amd import workloads as W
-from tests.gpu_helpers import TOL, UNITS, check_product, padding_is_zero, pattern_np, upload, values_np
+from tests.gpu_helpers import TOL, check_product, padding_is_zero, pattern_np, units, upload, values_np
 
 pytestmark = pytest.mark.gpu
 
@@ -39,14 +39,14 @@ SMALL = [
 def test_small_random(q, case, mode):
     m, k, n, bs, p, seed = case
     a, b = W.small_random(m, k, n, bs, p, seed)
-    for unit in UNITS[bs]:
+    for unit in units(bs, mode):
         C, ref, err, got = check_product(q, a, b, mode, unit)
         assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
 
 
 def test_config1_full_f64(q):
     c = W.config1()
-    for unit in UNITS[32]:
+    for unit in units(32, "f64"):
         C, ref, err, _ = check_product(q, c["A"], c["B"], "f64", unit)
         assert ref.brow.size == 1016 and ref.I.size == 4884
 
@@ -179,7 +179,7 @@ def test_backward_small_vs_oracle(q):
         dC.set_blocks(torch.from_numpy(ref.brow.astype(np.int32)).cuda(),
                       torch.from_numpy(ref.bcol.astype(np.int32)).cuda(), torch.from_numpy(dcv).cuda())
         for mode in ("f64", "f32", "bf16x3"):
-            for unit in UNITS[bs]:
+            for unit in units(bs, mode):
                 dA, dB = q.backward(A, B, dC, mode, unit)
                 ra, ca = pattern_np(dA)
                 assert np.array_equal(ra, oa.brow) and np.array_equal(ca, oa.bcol)
@@ -273,4 +273,61 @@ def test_autotune_unit(q):
     a, b = W.small_random(2048, 2048, 2048, 64, 0.3, 61)
     A, B = upload(q, a), upload(q, b)
     best, times = q.autotune_unit(A, B, "f32", reps=2)
-    assert best in (64, 128) and times[best] > 0
+    assert best in (64, 128, 256) and times[best] > 0
+    assert all(times[u] > 0 for u in (64, 128, 256))
+    best, times = q.autotune_unit(A, B, "f64", reps=1)
+    assert best in (64, 128) and times[256] < 0
+
+
+UNIT256 = [
+    # (m, k, n, bs, p, seed): several 256-wide units per side with ragged
+    # edges (a wave's 128 x 128 part partly or wholly outside C), sparse
+    # patterns (partial leaf masks inside a wave), 128-wide leaves
+    (64 * 9 + 5, 64 * 7 + 33, 64 * 11 + 63, 64, 0.3, 71),
+    (1100, 700, 900, 64, 0.08, 72),
+    (128 * 5 + 17, 128 * 3, 128 * 4 + 100, 128, 0.5, 73),
+    (300, 1500, 200, 64, 1.0, 74),
+]
+
+
+@pytest.mark.parametrize("case", UNIT256, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-bs{c[3]}-p{c[4]}")
+@pytest.mark.parametrize("mode", ["f32", "bf16", "bf16x3"])
+def test_unit256(q, case, mode):
+    m, k, n, bs, p, seed = case
+    a, b = W.small_random(m, k, n, bs, p, seed)
+    C, ref, err, got = check_product(q, a, b, mode, 256)
+    assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
+
+
+def test_unit256_rejects_f64(q):
+    a, b = W.small_random(300, 260, 200, 64, 0.5, 75)
+    A, B = upload(q, a), upload(q, b)
+    P = q.Plan(A, B, unit=256)
+    with pytest.raises(q.QbsmError, match="unsupported|FP32"):
+        P.numeric("f64")
+    assert P.numeric("f32").nblk > 0
+
+
+def test_unit256_batched(q):
+    """Persistent launch at unit 256 over members with 64- and 128-wide leaves."""
+    rng = np.random.default_rng(76)
+    members = []
+    for t, (n, bs) in enumerate([(700, 64), (1000, 128), (513, 64), (1500, 128), (900, 64)]):
+        if t % 2 == 0:
+            a = W.banded(n, bs, 2, rng, fp32_values=True)
+            b = W.banded(n, bs, 2, rng, fp32_values=True)
+        else:
+            a, b = W.small_random(n, n, n, bs, 0.4, 200 + t, fp32_values=True)
+        members.append((a, b))
+    As = [(upload(q, a), upload(q, b)) for a, b in members]
+    plans = [q.Plan(A, B, unit=256) for A, B in As]
+    for mode in ("f32", "bf16x3"):
+        singles = [values_np(p.numeric(mode)) for p in plans]
+        batch = q.Batch(plans, mode)
+        batch.run()
+        torch.cuda.synchronize()
+        for o, s_ in zip(batch.outs, singles):
+            assert np.array_equal(values_np(o), s_)
+        for (a, b), s_ in zip(members, singles):
+            ref = O.multiply(O.from_workload(a), O.from_workload(b))
+            assert O.rel_fro(s_, ref.vals) <= TOL[mode]
