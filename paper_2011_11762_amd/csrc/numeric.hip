@@ -221,41 +221,74 @@ constexpr int k5_nt = 64 * (U / (U >= 256 ? 128 : 64)) * (U / (U >= 256 ? 128 : 
 template <int MODE, int U>
 constexpr int k5_stage_bytes = 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX;
 
+// Source addresses of one step's copy: the packed line chunk of every leaf
+// row (left operand) and leaf column (right operand) of the unit.  All of it
+// is wave-uniform; only the 16-byte lane offset is per lane.
+template <int MODE, int U, int BS>
+struct LoadCtx {
+    const uint8_t *baseL, *baseR;
+    int la[Geo<MODE, U, BS>::LPU], lb[Geo<MODE, U, BS>::LPU];
+};
+
+template <int MODE, int U, int BS>
+__device__ __forceinline__ LoadCtx<MODE, U, BS> load_ctx(const K5Member &m, const Meta &mt, int i, int kb, int c) {
+    using G = Geo<MODE, U, BS>;
+    using T = typename G::T;
+    LoadCtx<MODE, U, BS> lc;
+#pragma unroll
+    for (int q = 0; q < G::LPU; ++q) {
+        lc.la[q] = uni(mt.la[i * G::NSUB + kb * G::LPU + q]);
+        lc.lb[q] = uni(mt.lb[i * G::NSUB + kb * G::LPU + q]);
+    }
+    lc.baseL = static_cast<const uint8_t *>(m.packL) + ((int64_t)c * m.chunkStrideL) * (int64_t)sizeof(T);
+    lc.baseR = static_cast<const uint8_t *>(m.packR) + ((int64_t)c * m.chunkStrideR) * (int64_t)sizeof(T);
+    return lc;
+}
+
+// The k-th 1 KB copy instruction of wave w (64 lanes x 16 bytes, straight
+// into LDS); k < PER_WAVE.  Wave w's instructions k cover array k / IPW
+// (left operand parts, then right operand parts) at 1 KB blocks
+// (k % IPW) * NW + w, so the array and part are compile-time constants and
+// every address term but the lane offset is scalar.  Instructions of nil
+// leaves are skipped: their LDS lines are never read (the tiles of an absent
+// product are skipped).
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void issue_one(const K5Member &m, const LoadCtx<MODE, U, BS> &lc, int k, uint8_t *stage,
+                                          int w) {
+    using G = Geo<MODE, U, BS>;
+    using T = typename G::T;
+    constexpr int IPW = G::IPA / G::NW;
+    static_assert(G::IPA % G::NW == 0, "copy blocks of an array must split evenly over the waves");
+    const int arr = k / IPW;
+    const int op = arr / MT<MODE>::PARTS, part = arr - op * MT<MODE>::PARTS;
+    const int jj = (k % IPW) * G::NW + w;
+    const int line0 = jj * G::LPI;
+    const int slot = line0 / BS;
+    const int off = (line0 - slot * BS) * G::LB;
+    int leaf = -1;
+#pragma unroll
+    for (int q = 0; q < G::LPU; ++q)
+        if (slot == q) leaf = op == 0 ? lc.la[q] : lc.lb[q];
+    if (leaf < 0) return;
+    const uint8_t *g = op == 0
+        ? lc.baseL + ((int64_t)leaf * m.leafStrideL + (int64_t)part * m.partStrideL) * (int64_t)sizeof(T)
+        : lc.baseR + ((int64_t)leaf * m.leafStrideR + (int64_t)part * m.partStrideR) * (int64_t)sizeof(T);
+    // an opaque lane offset keeps the sum "scalar base + 32-bit lane offset"
+    // (the instruction's scalar-base form) from being re-associated into a
+    // hoisted per-lane 64-bit base, which would hold two VGPRs per distinct
+    // offset for the whole loop
+    uint32_t lane16 = (threadIdx.x & 63u) * 16u;
+    asm volatile("" : "+v"(lane16));
+    __builtin_amdgcn_global_load_lds((const QB_GAS void *)(g + off + lane16),
+                                     (QB_LAS void *)(stage + arr * G::ARRB + jj * 1024), 16, 0, 0);
+}
+
 template <int MODE, int U, int BS>
 __device__ __forceinline__ void issue_loads(const K5Member &m, const Meta &mt, int i, int kb, int c, uint8_t *stage,
                                             int w) {
-    using G = Geo<MODE, U, BS>;
-    using T = typename G::T;
-    const int lane = threadIdx.x & 63;
-    int la[G::LPU], lb[G::LPU];
+    const LoadCtx<MODE, U, BS> lc = load_ctx<MODE, U, BS>(m, mt, i, kb, c);
 #pragma unroll
-    for (int q = 0; q < G::LPU; ++q) {
-        la[q] = uni(mt.la[i * G::NSUB + kb * G::LPU + q]);
-        lb[q] = uni(mt.lb[i * G::NSUB + kb * G::LPU + q]);
-    }
-    const uint8_t *baseL = static_cast<const uint8_t *>(m.packL) +
-                           ((int64_t)c * m.chunkStrideL) * (int64_t)sizeof(T) + lane * 16;
-    const uint8_t *baseR = static_cast<const uint8_t *>(m.packR) +
-                           ((int64_t)c * m.chunkStrideR) * (int64_t)sizeof(T) + lane * 16;
-#pragma unroll
-    for (int k = 0; k < G::PER_WAVE; ++k) {
-        const int j = w + k * G::NW;             // this wave's k-th load instruction
-        const int arr = j / G::IPA, jj = j - arr * G::IPA;
-        const int op = arr / MT<MODE>::PARTS, part = arr - op * MT<MODE>::PARTS;
-        const int line0 = jj * G::LPI;
-        const int slot = line0 / BS;
-        const int off = (line0 - slot * BS) * G::LB;
-        int leaf = -1;
-#pragma unroll
-        for (int q = 0; q < G::LPU; ++q)
-            if (slot == q) leaf = op == 0 ? la[q] : lb[q];
-        if (leaf < 0) continue;
-        const uint8_t *g = op == 0
-            ? baseL + ((int64_t)leaf * m.leafStrideL + (int64_t)part * m.partStrideL) * (int64_t)sizeof(T)
-            : baseR + ((int64_t)leaf * m.leafStrideR + (int64_t)part * m.partStrideR) * (int64_t)sizeof(T);
-        __builtin_amdgcn_global_load_lds((const QB_GAS void *)(g + off),
-                                         (QB_LAS void *)(stage + arr * G::ARRB + jj * 1024), 16, 0, 0);
-    }
+    for (int k = 0; k < Geo<MODE, U, BS>::PER_WAVE; ++k) issue_one<MODE, U, BS>(m, lc, k, stage, w);
 }
 
 // Wave-uniform enable bits of the leaves a wave covers in one step: bit
@@ -297,7 +330,19 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
         ++nkb;
         nhave = seek_step(mt, nb, G::LPU, G::NSUB, ni, nkb, nkm);
     }
-    if (nhave) issue_loads<MODE, U, BS>(m, mt, ni, nkb, nc, nxt, w);
+    // the next step's copy instructions are spread over the column tiles of
+    // this step, so that the wave keeps issuing MFMAs while the memory
+    // pipeline accepts them
+    // (with 128 x 128 per wave the register file has no room for the copy
+    // state across the MFMAs: there the copy is issued in one go)
+    constexpr bool SPREAD = G::WT <= 64;
+    LoadCtx<MODE, U, BS> lc{};
+    if (nhave) lc = load_ctx<MODE, U, BS>(m, mt, ni, nkb, nc);
+    if (!SPREAD && nhave) {
+#pragma unroll
+        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(m, lc, k, nxt, w);
+    }
+    constexpr int KPT = (G::PER_WAVE + TPW - 1) / TPW;
     const uint32_t wl = wave_leaves<MODE, U, BS>(km, wr, wc);
     if (wl) {
         const uint8_t *Ab = cur;
@@ -329,12 +374,20 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
             read_b(0, fb[0]);
 #pragma unroll
             for (int tn = 0; tn < TPW; ++tn) {
+                if (SPREAD && rg == 0 && nhave) {
+#pragma unroll
+                    for (int j = 0; j < KPT; ++j)
+                        if (tn * KPT + j < G::PER_WAVE) issue_one<MODE, U, BS>(m, lc, tn * KPT + j, nxt, w);
+                }
                 if (tn + 1 < TPW) read_b(tn + 1, fb[(tn + 1) & 1]);
 #pragma unroll
                 for (int tm = 0; tm < TPW; ++tm)
                     if ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u) M::mma(acc[tm][tn], fa[tm], fb[tn & 1]);
             }
         }
+    } else if (SPREAD && nhave) {
+#pragma unroll
+        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(m, lc, k, nxt, w);
     }
     // every wave's copy into nxt has landed and nobody reads cur any more
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
