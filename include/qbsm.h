@@ -62,9 +62,13 @@ typedef enum {
  *   QBSM_F32    operands rounded to binary32 (RNE), FP32 accumulation, FP32 result.
  *   QBSM_BF16   operands rounded to bfloat16 (RNE, straight from FP64), FP32
  *               accumulation, FP32 result.
- *   QBSM_BF16X3 split precision: x = hi + lo with hi = bf16(x), lo = bf16(x - hi);
- *               a*b ~ hi_a*hi_b + hi_a*lo_b + lo_a*hi_b, FP32 accumulation,
- *               FP32 result. */
+ *   QBSM_BF16X3 split precision: x = hi + lo with hi = bf16(x), lo = bf16(x - hi)
+ *               (lo = 0 where hi is not finite); a*b ~ hi_a*hi_b + hi_a*lo_b +
+ *               lo_a*hi_b, FP32 accumulation, FP32 result.  An infinite input
+ *               gives a non-finite result (Inf, or NaN where the split terms of
+ *               its partner differ in sign) in exactly the elements it reaches.
+ * In every mode a product exists only where both leaf blocks are stored: an
+ * Inf or NaN never meets the implicit zeros of a nil block. */
 typedef enum {
     QBSM_F64 = 0,
     QBSM_F32 = 1,

@@ -350,9 +350,17 @@ def round_to_bf16(x: np.ndarray) -> np.ndarray:
 
 
 def split_bf16(x: np.ndarray):
-    """hi = bf16(x), lo = bf16(x - hi) with x - hi formed in FP64 (exact)."""
+    """hi = bf16(x), lo = bf16(x - hi) with x - hi formed in FP64 (exact).
+
+    Where hi is not finite (x is Inf or NaN, or overflows bfloat16) the
+    residual is undefined and lo is taken as zero, so that hi + lo keeps the
+    infinity (a NaN stays NaN through hi).
+    """
+    x = np.asarray(x, dtype=np.float64)
     hi = round_to_bf16(x)
-    lo = round_to_bf16(np.asarray(x, dtype=np.float64) - hi)
+    fin = np.isfinite(hi)
+    lo = np.zeros_like(x)
+    lo[fin] = round_to_bf16(x[fin] - hi[fin])
     return hi, lo
 
 

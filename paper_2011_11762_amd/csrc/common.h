@@ -130,6 +130,7 @@ struct Tree {
 
 struct Pack {
     DArr<uint8_t> buf;
+    DArr<int32_t> nonfinite;  // [1]: set by the pack kernel when a packed value is Inf or NaN
     uint64_t version = 0;
 };
 
@@ -201,6 +202,7 @@ struct PackView {
     int64_t part_stride = 0;  // elements between hi and lo parts
     int32_t line_stride = 0;  // elements between consecutive lines of a leaf chunk
     int32_t chunk_stride = 0; // elements between consecutive K chunks
+    const int32_t *nonfinite = nullptr;  // device flag of the pack
 };
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s);
 int mode_bk(qbsm_mode mode, int bs);
@@ -223,6 +225,7 @@ struct K5Member {
     void *C;
     int64_t leafStrideL, partStrideL, leafStrideR, partStrideR;
     int32_t lineStrideL, chunkStrideL, lineStrideR, chunkStrideR;
+    const int32_t *nfL, *nfR;  // non-finite flags of the two packs (device)
     int64_t out_rows, out_cols;
     int32_t nunits, bs, s, lpu, transL, transR, pad0, pad1;
 };

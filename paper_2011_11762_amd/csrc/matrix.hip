@@ -228,7 +228,7 @@ __global__ void __launch_bounds__(256) k_extract(const uint32_t *keys, int64_t n
 // across the column-major source (line-fastest thread order).
 template <class Src, int MODE>
 __global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int32_t bs, int32_t bk, int role,
-                                              uint8_t *dst) {
+                                              uint8_t *dst, int32_t *nonfinite) {
     constexpr int EB = MODE == QBSM_F64 ? 8 : MODE == QBSM_F32 ? 4 : 2;  // bytes per element
     constexpr int EPP = 16 / EB;                                          // elements per piece
     constexpr int PARTS = MODE == QBSM_BF16X3 ? 2 : 1;
@@ -259,16 +259,24 @@ __global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int3
         v[e] = role == ROLE_COL ? (double)x[(k0 + e) + l * bs] : (double)x[l + (k0 + e) * bs];
     uint8_t *o = dst + leaf * (PARTS * n2 * EB) + c * (int64_t)bs * LB + l * LB +
                  ((piece ^ piece_swizzle((int)l, LB)) << 4);
+    bool bad = false;  // a packed value (after the conversion to the mode) is Inf or NaN
     if (MODE == QBSM_F64) {
+        bad = !isfinite(v[0]) || !isfinite(v[1]);
         *reinterpret_cast<double2 *>(o) = make_double2(v[0], v[1]);
     } else if (MODE == QBSM_F32) {
-        *reinterpret_cast<float4 *>(o) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+        const float4 f = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+        bad = !isfinite(f.x) || !isfinite(f.y) || !isfinite(f.z) || !isfinite(f.w);
+        *reinterpret_cast<float4 *>(o) = f;
     } else {
         uint16_t h[8], lo[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             h[e] = bf16_rne_bits(v[e]);
-            lo[e] = bf16_rne_bits(v[e] - bf16_bits_to_double(h[e]));
+            const bool hinf = (h[e] & 0x7F80u) == 0x7F80u;  // hi part Inf or NaN
+            // the residual of an infinite (or overflowing) value is not
+            // defined: its lo part is zero, so Inf stays Inf in the product
+            lo[e] = hinf ? (uint16_t)0 : bf16_rne_bits(v[e] - bf16_bits_to_double(h[e]));
+            bad |= hinf;
         }
         uint4 hv, lv;
         hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
@@ -280,6 +288,7 @@ __global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int3
             *reinterpret_cast<uint4 *>(o + n2 * EB) = lv;
         }
     }
+    if (bad) *nonfinite = 1;
 }
 
 size_t mode_elem_bytes(qbsm_mode mode) {
@@ -488,12 +497,16 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
     const int bk = mode_bk(mode, m.bs);
     const int ppl = bk * (int)mode_elem_bytes(mode) / 16;
     const int64_t work = m.nblk * (m.bs / bk) * (int64_t)m.bs * ppl;
-    if (!work) return;
+    if (!work) {
+        fill_i32(pk.nonfinite.p, 0, 1, s);
+        return;
+    }
     const unsigned g = grid_for(work, 256);
     uint8_t *dst = pk.buf.p;
     ProfScope prof(PROF_PACK, s);
+    fill_i32(pk.nonfinite.p, 0, 1, s);
 #define QB_PACK(SRC, PTR, MODE) \
-    k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst)
+    k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst, pk.nonfinite.p)
     if (m.storage == ST_F64) {
         switch (mode) {
             case QBSM_F64: QB_PACK(double, m.v64.p, QBSM_F64); break;
@@ -523,6 +536,7 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
     const size_t bytes = (size_t)m.nblk * n2 * mode_elem_bytes(mode) * mode_parts(mode);
     if (pk.buf.n != bytes || pk.version != m.version || !pk.buf.p) {
         if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
+        if (!pk.nonfinite.p) pk.nonfinite.alloc(1, s);
         pack_launch(m, mode, role, pk, s);
         pk.version = m.version;
     }
@@ -531,6 +545,7 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
     v.part_stride = n2;
     v.line_stride = bk;
     v.chunk_stride = (int32_t)((int64_t)bs * bk);
+    v.nonfinite = pk.nonfinite.p;
     return v;
 }
 

@@ -112,6 +112,10 @@ struct MT<QBSM_BF16X3> {
     __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
+// Source of the copies of nil leaves on the branch-free path: its LDS lines
+// then hold zeros, so the products of a nil leaf add exact zeros.
+__device__ __attribute__((aligned(1024))) uint8_t g_zero_page[1024] = {};
+
 __device__ __forceinline__ int morton_sub(int r, int c, int s) {
     int q = 0;
     for (int b = 0; b < s; ++b) q |= (((r >> b) & 1) << (2 * b + 1)) | (((c >> b) & 1) << (2 * b));
@@ -221,74 +225,69 @@ constexpr int k5_nt = 64 * (U / (U >= 256 ? 128 : 64)) * (U / (U >= 256 ? 128 : 
 template <int MODE, int U>
 constexpr int k5_stage_bytes = 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX;
 
-// Source addresses of one step's copy: the packed line chunk of every leaf
-// row (left operand) and leaf column (right operand) of the unit.  All of it
-// is wave-uniform; only the 16-byte lane offset is per lane.
-template <int MODE, int U, int BS>
-struct LoadCtx {
-    const uint8_t *baseL, *baseR;
-    int la[Geo<MODE, U, BS>::LPU], lb[Geo<MODE, U, BS>::LPU];
-};
-
-template <int MODE, int U, int BS>
-__device__ __forceinline__ LoadCtx<MODE, U, BS> load_ctx(const K5Member &m, const Meta &mt, int i, int kb, int c) {
-    using G = Geo<MODE, U, BS>;
-    using T = typename G::T;
-    LoadCtx<MODE, U, BS> lc;
-#pragma unroll
-    for (int q = 0; q < G::LPU; ++q) {
-        lc.la[q] = uni(mt.la[i * G::NSUB + kb * G::LPU + q]);
-        lc.lb[q] = uni(mt.lb[i * G::NSUB + kb * G::LPU + q]);
-    }
-    lc.baseL = static_cast<const uint8_t *>(m.packL) + ((int64_t)c * m.chunkStrideL) * (int64_t)sizeof(T);
-    lc.baseR = static_cast<const uint8_t *>(m.packR) + ((int64_t)c * m.chunkStrideR) * (int64_t)sizeof(T);
-    return lc;
-}
-
-// The k-th 1 KB copy instruction of wave w (64 lanes x 16 bytes, straight
-// into LDS); k < PER_WAVE.  Wave w's instructions k cover array k / IPW
-// (left operand parts, then right operand parts) at 1 KB blocks
-// (k % IPW) * NW + w, so the array and part are compile-time constants and
-// every address term but the lane offset is scalar.  Instructions of nil
-// leaves are skipped: their LDS lines are never read (the tiles of an absent
-// product are skipped).
-template <int MODE, int U, int BS>
-__device__ __forceinline__ void issue_one(const K5Member &m, const LoadCtx<MODE, U, BS> &lc, int k, uint8_t *stage,
-                                          int w) {
+// Source addresses of one step's copy, one per lane: lane k < PER_WAVE of
+// wave w holds the address of the wave's copy instruction k.  Wave w's instructions k cover array k / IPW (left operand parts,
+// then right operand parts) at 1 KB blocks (k % IPW) * NW + w, so the array
+// and the LDS destination are compile-time constants plus a scalar.  Kept in
+// one 64-bit register pair for the whole step; each instruction reads its
+// address back as a scalar.
+template <int MODE, int U, int BS, bool DENSE>
+__device__ __forceinline__ uint64_t copy_addr(const K5Member &m, const Meta &mt, int i, int kb, int c, int w) {
     using G = Geo<MODE, U, BS>;
     using T = typename G::T;
     constexpr int IPW = G::IPA / G::NW;
     static_assert(G::IPA % G::NW == 0, "copy blocks of an array must split evenly over the waves");
+    static_assert(G::PER_WAVE <= 64, "one lane per copy instruction");
+    const int k = threadIdx.x & 63;
+    if (k >= G::PER_WAVE) return 0;
     const int arr = k / IPW;
     const int op = arr / MT<MODE>::PARTS, part = arr - op * MT<MODE>::PARTS;
     const int jj = (k % IPW) * G::NW + w;
     const int line0 = jj * G::LPI;
     const int slot = line0 / BS;
     const int off = (line0 - slot * BS) * G::LB;
-    int leaf = -1;
-#pragma unroll
-    for (int q = 0; q < G::LPU; ++q)
-        if (slot == q) leaf = op == 0 ? lc.la[q] : lc.lb[q];
-    if (leaf < 0) return;
-    const uint8_t *g = op == 0
-        ? lc.baseL + ((int64_t)leaf * m.leafStrideL + (int64_t)part * m.partStrideL) * (int64_t)sizeof(T)
-        : lc.baseR + ((int64_t)leaf * m.leafStrideR + (int64_t)part * m.partStrideR) * (int64_t)sizeof(T);
+    int leaf = op == 0 ? mt.la[i * G::NSUB + kb * G::LPU + slot] : mt.lb[i * G::NSUB + kb * G::LPU + slot];
+    // a nil leaf: zeros on the branch-free path; otherwise its lines are never
+    // read (the tiles of an absent product are skipped) and leaf 0 is copied
+    // there, which keeps the copy loop free of branches
+    if (DENSE && leaf < 0) return reinterpret_cast<uint64_t>(&g_zero_page[0]);
+    if (leaf < 0) leaf = 0;
+    // both candidates from scalars, then a per-lane select (selecting the
+    // struct fields per lane would index a private copy of the struct)
+    const uint8_t *gL = static_cast<const uint8_t *>(m.packL) +
+                        ((int64_t)leaf * m.leafStrideL + (int64_t)part * m.partStrideL +
+                         (int64_t)c * m.chunkStrideL) * (int64_t)sizeof(T);
+    const uint8_t *gR = static_cast<const uint8_t *>(m.packR) +
+                        ((int64_t)leaf * m.leafStrideR + (int64_t)part * m.partStrideR +
+                         (int64_t)c * m.chunkStrideR) * (int64_t)sizeof(T);
+    return reinterpret_cast<uint64_t>((op == 0 ? gL : gR) + off);
+}
+
+// Copy instruction k of wave w: 64 lanes x 16 bytes straight into LDS.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void issue_one(uint64_t addrs, int k, uint8_t *stage, int w) {
+    using G = Geo<MODE, U, BS>;
+    constexpr int IPW = G::IPA / G::NW;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)addrs, k);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(addrs >> 32), k);
+    const uint64_t a = ((uint64_t)hi << 32) | lo;
+    const int arr = k / IPW;
+    const int jj = (k % IPW) * G::NW + w;
     // an opaque lane offset keeps the sum "scalar base + 32-bit lane offset"
     // (the instruction's scalar-base form) from being re-associated into a
-    // hoisted per-lane 64-bit base, which would hold two VGPRs per distinct
-    // offset for the whole loop
+    // hoisted per-lane 64-bit base
     uint32_t lane16 = (threadIdx.x & 63u) * 16u;
     asm volatile("" : "+v"(lane16));
-    __builtin_amdgcn_global_load_lds((const QB_GAS void *)(g + off + lane16),
+    __builtin_amdgcn_global_load_lds((const QB_GAS void *)(reinterpret_cast<const uint8_t *>(a) + lane16),
                                      (QB_LAS void *)(stage + arr * G::ARRB + jj * 1024), 16, 0, 0);
 }
 
-template <int MODE, int U, int BS>
+template <int MODE, int U, int BS, bool DENSE>
 __device__ __forceinline__ void issue_loads(const K5Member &m, const Meta &mt, int i, int kb, int c, uint8_t *stage,
                                             int w) {
-    const LoadCtx<MODE, U, BS> lc = load_ctx<MODE, U, BS>(m, mt, i, kb, c);
+    const uint64_t addrs = copy_addr<MODE, U, BS, DENSE>(m, mt, i, kb, c, w);
 #pragma unroll
-    for (int k = 0; k < Geo<MODE, U, BS>::PER_WAVE; ++k) issue_one<MODE, U, BS>(m, lc, k, stage, w);
+    for (int k = 0; k < Geo<MODE, U, BS>::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, stage, w);
 }
 
 // Wave-uniform enable bits of the leaves a wave covers in one step: bit
@@ -314,7 +313,7 @@ __device__ __forceinline__ uint32_t wave_leaves(uint32_t km, int wr, int wc) {
 // `cur` and issues no wait between them: the copy is issued first and runs
 // under the whole step.  The step ends with every wave's copies complete and
 // a barrier, after which `cur` may be overwritten.
-template <int MODE, int U, int BS>
+template <int MODE, int U, int BS, bool DENSE>
 __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
                                          int &i, int &kb, int &c, uint32_t &km, bool &have, int w, int wr, int wc) {
@@ -331,20 +330,20 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
         nhave = seek_step(mt, nb, G::LPU, G::NSUB, ni, nkb, nkm);
     }
     // the next step's copy instructions are spread over the column tiles of
-    // this step, so that the wave keeps issuing MFMAs while the memory
-    // pipeline accepts them
-    // (with 128 x 128 per wave the register file has no room for the copy
-    // state across the MFMAs: there the copy is issued in one go)
-    constexpr bool SPREAD = G::WT <= 64;
-    LoadCtx<MODE, U, BS> lc{};
-    if (nhave) lc = load_ctx<MODE, U, BS>(m, mt, ni, nkb, nc);
+    // this step for 64-wide wave parts; with 128 x 128 per wave the register
+    // file has no room for that schedule and the copy is issued in one go
+    constexpr bool SPREAD = G::WT <= 64 || DENSE;
+    // (after the last step the copies still go out, from the zero page into
+    // the stage nobody reads, so that the MFMA loop has no branch)
+    const uint64_t addrs = nhave ? copy_addr<MODE, U, BS, DENSE>(m, mt, ni, nkb, nc, w)
+                                 : reinterpret_cast<uint64_t>(&g_zero_page[0]);
     if (!SPREAD && nhave) {
 #pragma unroll
-        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(m, lc, k, nxt, w);
+        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, nxt, w);
     }
     constexpr int KPT = (G::PER_WAVE + TPW - 1) / TPW;
     const uint32_t wl = wave_leaves<MODE, U, BS>(km, wr, wc);
-    if (wl) {
+    if (DENSE || wl) {
         const uint8_t *Ab = cur;
         const uint8_t *Bb = cur + PARTS * G::ARRB;
 #pragma unroll
@@ -374,20 +373,24 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
             read_b(0, fb[0]);
 #pragma unroll
             for (int tn = 0; tn < TPW; ++tn) {
-                if (SPREAD && rg == 0 && nhave) {
+                if (SPREAD && rg == 0) {
+                    // pinned in place: hoisting the copies' scalar state
+                    // across the MFMAs would cost registers
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int j = 0; j < KPT; ++j)
-                        if (tn * KPT + j < G::PER_WAVE) issue_one<MODE, U, BS>(m, lc, tn * KPT + j, nxt, w);
+                        if (tn * KPT + j < G::PER_WAVE) issue_one<MODE, U, BS>(addrs, tn * KPT + j, nxt, w);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 if (tn + 1 < TPW) read_b(tn + 1, fb[(tn + 1) & 1]);
 #pragma unroll
                 for (int tm = 0; tm < TPW; ++tm)
-                    if ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u) M::mma(acc[tm][tn], fa[tm], fb[tn & 1]);
+                    if (DENSE || ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u)) M::mma(acc[tm][tn], fa[tm], fb[tn & 1]);
             }
         }
-    } else if (SPREAD && nhave) {
+    } else if (SPREAD) {
 #pragma unroll
-        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(m, lc, k, nxt, w);
+        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, nxt, w);
     }
     // every wave's copy into nxt has landed and nobody reads cur any more
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -399,7 +402,10 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
     have = nhave;
 }
 
-template <int MODE, int U, int BS>
+// DENSE: the branch-free path (every tile multiplied, nil leaves copied as
+// zeros), valid when neither pack holds Inf or NaN (an infinite value times
+// the zero of a nil partner would give NaN where no product exists).
+template <int MODE, int U, int BS, bool DENSE>
 __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
@@ -438,15 +444,15 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         int i = 0, kb = 0, c = 0;
         uint32_t km = 0;
         bool have = seek_step(mt, nb, LPU, NSUB, i, kb, km);
-        if (have) issue_loads<MODE, U, BS>(m, mt, i, kb, c, st0, w);
+        if (have) issue_loads<MODE, U, BS, DENSE>(m, mt, i, kb, c, st0, w);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         // steps alternate between the two stages; unrolled by two so that
         // every access names its stage array at compile time
         while (have) {
-            run_step<MODE, U, BS>(m, mt, nb, st0, st1, acc, i, kb, c, km, have, w, wr, wc);
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, i, kb, c, km, have, w, wr, wc);
             if (!have) break;
-            run_step<MODE, U, BS>(m, mt, nb, st1, st0, acc, i, kb, c, km, have, w, wr, wc);
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, i, kb, c, km, have, w, wr, wc);
         }
     }
 
@@ -491,18 +497,31 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         }
 }
 
+// Unit 256 takes the branch-free path when both packs are finite; the
+// smaller units (two workgroups per compute unit) keep the skipping path.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void process_sel(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
+    if constexpr (U >= 256) {
+        if ((*m.nfL | *m.nfR) == 0) {
+            process_unit<MODE, U, BS, true>(m, u, st0, st1, meta);
+            return;
+        }
+    }
+    process_unit<MODE, U, BS, false>(m, u, st0, st1, meta);
+}
+
 template <int MODE, int U>
 __device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
     if constexpr (U <= 128) {
         if (m.bs == 32) {
-            process_unit<MODE, U, 32>(m, u, st0, st1, meta);
+            process_sel<MODE, U, 32>(m, u, st0, st1, meta);
             return;
         }
     }
     if (m.bs == 64) {
-        process_unit<MODE, U, 64>(m, u, st0, st1, meta);
+        process_sel<MODE, U, 64>(m, u, st0, st1, meta);
     } else if constexpr (U >= 128) {
-        if (m.bs == 128) process_unit<MODE, U, 128>(m, u, st0, st1, meta);
+        if (m.bs == 128) process_sel<MODE, U, 128>(m, u, st0, st1, meta);
     }
 }
 
@@ -520,7 +539,7 @@ __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     __shared__ __attribute__((aligned(16))) uint8_t meta[META_BYTES];
     if constexpr (BS != 0) {
         const int u = xcd_remap((int)blockIdx.x, single.nunits);
-        process_unit<MODE, U, BS>(single, u, st0, st1, meta);
+        process_sel<MODE, U, BS>(single, u, st0, st1, meta);
     } else {
         __shared__ int s_item;
         for (;;) {
@@ -644,6 +663,8 @@ K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     m.partStrideR = vR.part_stride;
     m.lineStrideR = vR.line_stride;
     m.chunkStrideR = vR.chunk_stride;
+    m.nfL = vL.nonfinite;
+    m.nfR = vR.nonfinite;
     m.out_rows = p.out_rows;
     m.out_cols = p.out_cols;
     m.nunits = (int32_t)p.nunits;

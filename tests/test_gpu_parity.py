@@ -299,6 +299,30 @@ def test_unit256(q, case, mode):
     assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
 
 
+def test_unit256_nonfinite_sparse(q):
+    """Unit 256 with Inf/NaN in a sparse pattern: a nil partner of an infinite
+    value must contribute nothing (the zero-copy path is not taken)."""
+    # whole leaves (no element padding), ragged at the 256-wide units
+    a, b = W.small_random(64 * 11, 64 * 9, 64 * 10, 64, 0.35, 77)
+    a.vals[3, 100] = np.inf
+    a.vals[7, 5] = np.nan
+    b.vals[2, 4000] = -np.inf
+    ref = O.multiply(O.from_workload(a), O.from_workload(b)).vals
+    assert np.isfinite(ref).sum() > 0 and (~np.isfinite(ref)).sum() > 0
+    for mode in ("f32", "bf16x3"):
+        A, B = upload(q, a), upload(q, b)
+        got = values_np(q.matmul(A, B, mode, unit=256))
+        if mode == "f32":
+            assert np.array_equal(np.isnan(got), np.isnan(ref)), mode
+            assert np.array_equal(np.isinf(got), np.isinf(ref)), mode
+        else:
+            # split products of an infinity may cancel to NaN: non-finite
+            # exactly where the FP64 product is
+            assert np.array_equal(np.isfinite(got), np.isfinite(ref)), mode
+        fin = np.isfinite(ref)
+        assert O.rel_fro(got[fin], ref[fin]) <= TOL[mode], mode
+
+
 def test_unit256_rejects_f64(q):
     a, b = W.small_random(300, 260, 200, 64, 0.5, 75)
     A, B = upload(q, a), upload(q, b)

@@ -361,6 +361,11 @@ def test_bf16_rounding():
     hi, lo = O.split_bf16(xd)
     assert np.array_equal(O.round_to_bf16(hi), hi) and np.array_equal(O.round_to_bf16(lo), lo)
     assert np.all(np.abs(xd - hi - lo) <= 2.0 ** -16 * np.abs(xd) + 1e-300)
+    # non-finite hi part: zero residual (Inf stays Inf in hi*lo + lo*hi + hi*hi)
+    hi, lo = O.split_bf16(np.array([np.inf, -np.inf, np.nan, 1e39, -4e38, 3.0e38]))
+    assert np.isposinf(hi[0]) and np.isneginf(hi[1]) and np.isnan(hi[2])
+    assert np.isposinf(hi[3]) and np.isneginf(hi[4]) and np.isfinite(hi[5])
+    assert np.array_equal(lo[:5], np.zeros(5)) and np.isfinite(lo[5])
 
 
 def test_canonical_rejects_bad_input():
