@@ -173,21 +173,69 @@ __device__ __forceinline__ Meta meta_view(uint8_t *base, int cap, int nsub) {
     return mt;
 }
 
-// Next (pair, kb) at or after (i, kb) inside the batch with a leaf product.
-__device__ __forceinline__ bool seek_step(const Meta &mt, int nb, int lpu, int nsub, int &i, int &kb,
-                                          uint32_t &km) {
-    const uint32_t sub = (uint32_t)((1ull << nsub) - 1ull);
-    while (i < nb) {
-        const uint64_t pm = uni64(mt.pm[i]);
-        while (kb < lpu) {
-            km = (uint32_t)(pm >> (kb * nsub)) & sub;
-            if (km) return true;
-            ++kb;
-        }
-        ++i;
-        kb = 0;
+// Position in a batch of pairs: pair i, leaf column kb, K chunk c; pm is
+// pair i's product bits and km those of leaf column kb.  Every field is
+// wave-uniform and kept in scalar registers.
+struct Step {
+    int i, kb, c;
+    uint32_t pm_lo, pm_hi, km;
+};
+
+__device__ __forceinline__ Step uni_step(int i, int kb, int c, uint64_t pm, uint32_t km) {
+    Step st;
+    st.i = uni(i);
+    st.kb = uni(kb);
+    st.c = uni(c);
+    st.pm_lo = (uint32_t)uni((int)(uint32_t)pm);
+    st.pm_hi = (uint32_t)uni((int)(uint32_t)(pm >> 32));
+    st.km = (uint32_t)uni((int)km);
+    return st;
+}
+
+__device__ __forceinline__ uint64_t step_pm(const Step &st) { return ((uint64_t)st.pm_hi << 32) | st.pm_lo; }
+
+// Leaf columns of a pair with at least one product (bit kb).
+template <int LPU, int NSUB>
+__device__ __forceinline__ uint32_t kb_mask(uint64_t pm) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int kb = 0; kb < LPU; ++kb)
+        r |= (uint32_t)(((pm >> (kb * NSUB)) & ((1ull << NSUB) - 1ull)) != 0ull) << kb;
+    return r;
+}
+
+template <int NSUB>
+__device__ __forceinline__ uint32_t col_bits(uint64_t pm, int kb) {
+    return (uint32_t)(pm >> (kb * NSUB)) & (uint32_t)((1ull << NSUB) - 1ull);
+}
+
+// First leaf column with a product at or after pair i (pairs without any
+// product are skipped); i == nb at the end of the batch.
+template <int LPU, int NSUB>
+__device__ __forceinline__ Step first_step(const Meta &mt, int nb, int i) {
+    uint64_t pm = 0;
+    uint32_t kbm = 0;
+    for (; i < nb; i = uni(i + 1)) {
+        pm = uni64(mt.pm[i]);
+        kbm = kb_mask<LPU, NSUB>(pm);
+        if (kbm) break;
     }
-    return false;
+    const int kb = kbm ? __builtin_ctz(kbm) : 0;
+    return uni_step(i, kb, 0, pm, col_bits<NSUB>(pm, kb));
+}
+
+// The step after st (i == nb at the end of the batch).  Only a new pair
+// reads its product bits from LDS.
+template <int LPU, int NSUB, int NCHUNK>
+__device__ __forceinline__ Step next_step(const Meta &mt, int nb, const Step &st) {
+    if (st.c + 1 < NCHUNK) return uni_step(st.i, st.kb, st.c + 1, step_pm(st), st.km);
+    const uint64_t pm = step_pm(st);
+    const uint32_t rest = kb_mask<LPU, NSUB>(pm) & ~((2u << st.kb) - 1u);
+    if (rest) {
+        const int kb = __builtin_ctz(rest);
+        return uni_step(st.i, kb, 0, pm, col_bits<NSUB>(pm, kb));
+    }
+    return first_step<LPU, NSUB>(mt, nb, st.i + 1);
 }
 
 template <int MODE, int U, int BS>
@@ -263,6 +311,15 @@ __device__ __forceinline__ uint64_t copy_addr(const K5Member &m, const Meta &mt,
     return reinterpret_cast<uint64_t>((op == 0 ? gL : gR) + off);
 }
 
+// Copy addresses of the next K chunk of the same leaf column: one chunk
+// further in every lane except those reading the zero page.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ uint64_t next_chunk_addr(uint64_t a, const K5Member &m) {
+    using T = typename Geo<MODE, U, BS>::T;
+    const uint64_t zp = reinterpret_cast<uint64_t>(&g_zero_page[0]);
+    return a == zp ? a : a + (uint64_t)m.chunkStrideL * sizeof(T);
+}
+
 // Copy instruction k of wave w: 64 lanes x 16 bytes straight into LDS.
 template <int MODE, int U, int BS>
 __device__ __forceinline__ void issue_one(uint64_t addrs, int k, uint8_t *stage, int w) {
@@ -280,14 +337,6 @@ __device__ __forceinline__ void issue_one(uint64_t addrs, int k, uint8_t *stage,
     asm volatile("" : "+v"(lane16));
     __builtin_amdgcn_global_load_lds((const QB_GAS void *)(reinterpret_cast<const uint8_t *>(a) + lane16),
                                      (QB_LAS void *)(stage + arr * G::ARRB + jj * 1024), 16, 0, 0);
-}
-
-template <int MODE, int U, int BS, bool DENSE>
-__device__ __forceinline__ void issue_loads(const K5Member &m, const Meta &mt, int i, int kb, int c, uint8_t *stage,
-                                            int w) {
-    const uint64_t addrs = copy_addr<MODE, U, BS, DENSE>(m, mt, i, kb, c, w);
-#pragma unroll
-    for (int k = 0; k < Geo<MODE, U, BS>::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, stage, w);
 }
 
 // Wave-uniform enable bits of the leaves a wave covers in one step: bit
@@ -313,35 +362,53 @@ __device__ __forceinline__ uint32_t wave_leaves(uint32_t km, int wr, int wc) {
 // `cur` and issues no wait between them: the copy is issued first and runs
 // under the whole step.  The step ends with every wave's copies complete and
 // a barrier, after which `cur` may be overwritten.
+// The step after st and its copy addresses: one chunk on within a leaf
+// column, looked up again for a new column (after the last step the copies
+// still go out, from the zero page into the stage nobody reads, so that the
+// MFMA loop has no branch).
+struct Advance {
+    Step nx;
+    uint64_t addrs;
+};
+
+template <int MODE, int U, int BS, bool DENSE>
+__device__ __forceinline__ Advance advance(const K5Member &m, const Meta &mt, int nb, const Step &st, uint64_t addrs,
+                                           int w) {
+    using G = Geo<MODE, U, BS>;
+    Advance a;
+    a.nx = next_step<G::LPU, G::NSUB, G::NCHUNK>(mt, nb, st);
+    if (a.nx.i >= nb)
+        a.addrs = reinterpret_cast<uint64_t>(&g_zero_page[0]);
+    else if (a.nx.c != 0)
+        a.addrs = next_chunk_addr<MODE, U, BS>(addrs, m);
+    else
+        a.addrs = copy_addr<MODE, U, BS, DENSE>(m, mt, a.nx.i, a.nx.kb, 0, w);
+    return a;
+}
+
 template <int MODE, int U, int BS, bool DENSE>
 __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
-                                         int &i, int &kb, int &c, uint32_t &km, bool &have, int w, int wr, int wc) {
+                                         Step &st, uint64_t &addrs, bool &have, int w, int wr, int wc) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
     constexpr int PARTS = M::PARTS, TPW = G::TPW, TPL = G::TPL, NLW = G::NLW;
     const int lane = threadIdx.x & 63;
-    int ni = i, nkb = kb, nc = c + 1;
-    uint32_t nkm = km;
-    bool nhave = true;
-    if (nc == G::NCHUNK) {
-        nc = 0;
-        ++nkb;
-        nhave = seek_step(mt, nb, G::LPU, G::NSUB, ni, nkb, nkm);
-    }
+    const uint32_t km = st.km;
+    const Advance nxa = advance<MODE, U, BS, DENSE>(m, mt, nb, st, addrs, w);
     // the next step's copy instructions are spread over the column tiles of
-    // this step for 64-wide wave parts; with 128 x 128 per wave the register
-    // file has no room for that schedule and the copy is issued in one go
+    // this step for 64-wide wave parts and on the branch-free path; with
+    // 128 x 128 per wave and tile skipping the register file has no room for
+    // that schedule and the copy is issued in one go
     constexpr bool SPREAD = G::WT <= 64 || DENSE;
-    // (after the last step the copies still go out, from the zero page into
-    // the stage nobody reads, so that the MFMA loop has no branch)
-    const uint64_t addrs = nhave ? copy_addr<MODE, U, BS, DENSE>(m, mt, ni, nkb, nc, w)
-                                 : reinterpret_cast<uint64_t>(&g_zero_page[0]);
-    if (!SPREAD && nhave) {
+    if constexpr (!SPREAD) {
+        if (nxa.nx.i < nb) {
 #pragma unroll
-        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, nxt, w);
+            for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, nxt, w);
+        }
     }
-    constexpr int KPT = (G::PER_WAVE + TPW - 1) / TPW;
+    constexpr int TSPAN = TPW;
+    constexpr int KPT = (G::PER_WAVE + TSPAN - 1) / TSPAN;
     const uint32_t wl = wave_leaves<MODE, U, BS>(km, wr, wc);
     if (DENSE || wl) {
         const uint8_t *Ab = cur;
@@ -373,13 +440,13 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
             read_b(0, fb[0]);
 #pragma unroll
             for (int tn = 0; tn < TPW; ++tn) {
-                if (SPREAD && rg == 0) {
+                if (SPREAD && rg == 0 && tn < TSPAN) {
                     // pinned in place: hoisting the copies' scalar state
                     // across the MFMAs would cost registers
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int j = 0; j < KPT; ++j)
-                        if (tn * KPT + j < G::PER_WAVE) issue_one<MODE, U, BS>(addrs, tn * KPT + j, nxt, w);
+                        if (tn * KPT + j < G::PER_WAVE) issue_one<MODE, U, BS>(nxa.addrs, tn * KPT + j, nxt, w);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 if (tn + 1 < TPW) read_b(tn + 1, fb[(tn + 1) & 1]);
@@ -390,16 +457,14 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
         }
     } else if (SPREAD) {
 #pragma unroll
-        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, nxt, w);
+        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, nxt, w);
     }
     // every wave's copy into nxt has landed and nobody reads cur any more
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
-    i = ni;
-    kb = nkb;
-    c = nc;
-    km = nkm;
-    have = nhave;
+    st = nxa.nx;
+    addrs = nxa.addrs;
+    have = nxa.nx.i < nb;
 }
 
 // DENSE: the branch-free path (every tile multiplied, nil leaves copied as
@@ -441,18 +506,22 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
                 }
         }
         __syncthreads();
-        int i = 0, kb = 0, c = 0;
-        uint32_t km = 0;
-        bool have = seek_step(mt, nb, LPU, NSUB, i, kb, km);
-        if (have) issue_loads<MODE, U, BS, DENSE>(m, mt, i, kb, c, st0, w);
+        Step st = first_step<LPU, NSUB>(mt, nb, 0);
+        bool have = st.i < nb;
+        uint64_t addrs = 0;
+        if (have) {
+            addrs = copy_addr<MODE, U, BS, DENSE>(m, mt, st.i, st.kb, 0, w);
+#pragma unroll
+            for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
+        }
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         // steps alternate between the two stages; unrolled by two so that
         // every access names its stage array at compile time
         while (have) {
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, i, kb, c, km, have, w, wr, wc);
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, st, addrs, have, w, wr, wc);
             if (!have) break;
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, i, kb, c, km, have, w, wr, wc);
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, st, addrs, have, w, wr, wc);
         }
     }
 
@@ -663,6 +732,7 @@ K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     m.partStrideR = vR.part_stride;
     m.lineStrideR = vR.line_stride;
     m.chunkStrideR = vR.chunk_stride;
+    QB_CHECK(m.chunkStrideL == m.chunkStrideR, QBSM_ERR_STATE, "operand packs differ in chunk geometry");
     m.nfL = vL.nonfinite;
     m.nfR = vR.nonfinite;
     m.out_rows = p.out_rows;
