@@ -38,17 +38,25 @@ DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16"}
 OPERAND_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4}
 RESULT_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "bf16x3": 4}
 KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
-# HBM bytes of one numeric-kernel launch on the default workload (unit 128),
-# from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB per
-# dispatch), scaled by what the same counters read for a 1 GiB
+# HBM bytes of one numeric-kernel launch on the default workload, per
+# "mode@unit", from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB
+# per dispatch), scaled by what the same counters read for a 1 GiB
 # device-to-device copy in the same runs (FETCH_SIZE x2.0, WRITE_SIZE x1.0).
 # They describe only the kernel sources with this digest; for any other
-# source, unit or workload the traffic is reported as null.
+# source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "83f4bdff65491086",
-    "unit": 128,
+    "sources_sha256_16": "d6f3633e8fb19881",
     "npoints": 16384,
-    "bytes": {"f64": 413941879603, "f32": 213918175130, "bf16x3": 145079133491},
+    "bytes": {
+        "bf16x3@128": 119688991317,
+        "bf16x3@256": 41690477355,
+        "bf16x3@64": 340024201579,
+        "f32@128": 207989410539,
+        "f32@256": 76328000437,
+        "f32@64": 346352778133,
+        "f64@128": 281900051413,
+        "f64@64": 725625268053,
+    },
 }
 
 
@@ -58,7 +66,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="bf16x3", choices=["f64", "f32", "bf16", "bf16x3"])
-    ap.add_argument("--unit", type=int, default=128)
+    ap.add_argument("--unit", type=int, default=0,
+                    help="work-unit side; 0 = chosen per mode by the library's autotuner before timing")
     ap.add_argument("--npoints", type=int, default=16384)
     ap.add_argument("--modes", default="f64,f32", help="reference modes timed beside the chosen one")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (no error statement)")
@@ -78,9 +87,9 @@ def kernel_digest():
 
 def measured_traffic(mode, unit, npoints):
     t = TRAFFIC
-    if (t["sources_sha256_16"], t["unit"], t["npoints"]) != (kernel_digest(), unit, npoints):
+    if (t["sources_sha256_16"], t["npoints"]) != (kernel_digest(), npoints):
         return None
-    return t["bytes"].get(mode)
+    return t["bytes"].get(f"{mode}@{unit}")
 
 
 def cpu_baseline_leg(wl, tol, bs, seconds):
@@ -159,9 +168,11 @@ def main():
     C = qbsm.Matrix(a.nrows, a.ncols, bs)
     state = {}
 
+    units, tuning = {}, {}
+
     def step(mode):
         A.set_blocks(brow, bcol, vals, tol)
-        P = qbsm.Plan(A, A, unit=args.unit)
+        P = qbsm.Plan(A, A, unit=units[mode])
         P.numeric(mode, C)
         state["plan"] = P
 
@@ -196,6 +207,16 @@ def main():
         return el / steps * 1e3, kern, num_ms, info
 
     modes = [m for m in args.modes.split(",") if m and m != args.mode] + [args.mode]
+    A.set_blocks(brow, bcol, vals, tol)
+    for mode in modes:
+        if args.unit:
+            units[mode] = args.unit
+        else:
+            best, times = qbsm.autotune_unit(A, A, mode, reps=2)
+            units[mode] = best
+            tuning[mode] = {str(u): round(t, 3) for u, t in times.items() if t > 0}
+            print(f"[bench] {mode}: unit {best} (autotune ms per numeric phase: {tuning[mode]})",
+                  file=sys.stderr, flush=True)
     results = {}
     for mode in modes:
         ms, kern, num_ms, info = time_mode(mode, args.steps, args.warmup, profile=True)
@@ -207,7 +228,10 @@ def main():
             "numeric_gflops": round(flops / (num_ms * 1e-3) / 1e9, 2),
             "kernel_ms": round(kern, 4),
             "kernel_mfma_tflops": round(MFMA_TERMS[mode] * flops / (kern * 1e-3) / 1e12, 2),
+            "unit": units[mode],
         }
+        if mode in tuning:
+            results[mode]["autotune_ms"] = tuning[mode]
         print(f"[bench] {mode}: {ms:.3f} ms/step, {results[mode]['effective_gflops']} GFLOP/s "
               f"(kernel {kern:.3f} ms)", file=sys.stderr, flush=True)
         results[mode]["_vals"] = None
