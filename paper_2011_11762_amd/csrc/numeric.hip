@@ -154,22 +154,23 @@ __device__ __forceinline__ int pick4(const int *v, int i) {
     return i == 0 ? v[0] : i == 1 ? v[1] : i == 2 ? v[2] : v[3];
 }
 
-// LDS copy of the metadata of a batch of pairs: product bits and the leaf
-// indices of every leaf column kb (A side: row leaves ib, B side: column
-// leaves jb), so that the step loop never waits on a dependent global read.
-constexpr int META_BYTES = 10240;
+// LDS copy of the metadata of a batch of pairs: product bits and, for every
+// leaf column kb, the packed-operand address of each leaf row (A side) and
+// leaf column (B side), so that the step loop never waits on a dependent
+// global read and needs no stride arithmetic.  A nil leaf has address 0.
+// Two workgroups of the smaller units share a compute unit's LDS.
+template <int U>
+constexpr int k5_meta_bytes = U >= 256 ? 20480 : 15360;
 
 struct Meta {
     uint64_t *pm;  // [cap]
-    int32_t *la;   // [cap * nsub], index kb*lpu + ib
-    int32_t *lb;   // [cap * nsub], index kb*lpu + jb
+    uint64_t *ad;  // [cap][kb][op][slot]: leaf address, op 0 = left operand
 };
 
-__device__ __forceinline__ Meta meta_view(uint8_t *base, int cap, int nsub) {
+__device__ __forceinline__ Meta meta_view(uint8_t *base, int cap) {
     Meta mt;
     mt.pm = reinterpret_cast<uint64_t *>(base);
-    mt.la = reinterpret_cast<int32_t *>(base + 8 * cap);
-    mt.lb = mt.la + cap * nsub;
+    mt.ad = mt.pm + cap;
     return mt;
 }
 
@@ -261,7 +262,7 @@ struct Geo {
     static constexpr int PER_WAVE = NARR * IPA / NW;
     static constexpr int ARRB = U * M::LBMAX;
     static constexpr int STAGEB = NARR * ARRB;
-    static constexpr int CAP = META_BYTES / (8 + 8 * NSUB);
+    static constexpr int CAP = k5_meta_bytes<U> / (8 + 16 * NSUB);
     static_assert(NARR * IPA % NW == 0, "load instructions must split evenly over the waves");
     static_assert(LB <= M::LBMAX && LPI <= BS, "line geometry");
     static_assert(NSUB * LPU <= 64, "leaf-product bits of a pair must fit 64 bits");
@@ -273,51 +274,54 @@ constexpr int k5_nt = 64 * (U / (U >= 256 ? 128 : 64)) * (U / (U >= 256 ? 128 : 
 template <int MODE, int U>
 constexpr int k5_stage_bytes = 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX;
 
-// Source addresses of one step's copy, one per lane: lane k < PER_WAVE of
-// wave w holds the address of the wave's copy instruction k.  Wave w's instructions k cover array k / IPW (left operand parts,
-// then right operand parts) at 1 KB blocks (k % IPW) * NW + w, so the array
-// and the LDS destination are compile-time constants plus a scalar.  Kept in
-// one 64-bit register pair for the whole step; each instruction reads its
-// address back as a scalar.
-template <int MODE, int U, int BS, bool DENSE>
-__device__ __forceinline__ uint64_t copy_addr(const K5Member &m, const Meta &mt, int i, int kb, int c, int w) {
+// Per-lane constants of the copy: lane k < PER_WAVE of wave w issues the
+// wave's copy instruction k, which covers array k / IPW (left operand parts,
+// then right operand parts) at 1 KB blocks (k % IPW) * NW + w; so the array
+// and the LDS destination are compile-time constants plus a scalar.  The lane
+// reads the leaf address at index op * LPU + slot of a leaf column's metadata
+// and adds its part and line offset.
+struct CopyLane {
+    int idx;       // op * LPU + slot
+    uint32_t off;  // part and line offset inside the leaf, bytes
+};
+
+template <int MODE, int U, int BS>
+__device__ __forceinline__ CopyLane copy_lane(const K5Member &m, int w) {
     using G = Geo<MODE, U, BS>;
     using T = typename G::T;
     constexpr int IPW = G::IPA / G::NW;
     static_assert(G::IPA % G::NW == 0, "copy blocks of an array must split evenly over the waves");
     static_assert(G::PER_WAVE <= 64, "one lane per copy instruction");
-    const int k = threadIdx.x & 63;
-    if (k >= G::PER_WAVE) return 0;
+    const int k = (threadIdx.x & 63) < G::PER_WAVE ? (threadIdx.x & 63) : 0;
     const int arr = k / IPW;
     const int op = arr / MT<MODE>::PARTS, part = arr - op * MT<MODE>::PARTS;
     const int jj = (k % IPW) * G::NW + w;
     const int line0 = jj * G::LPI;
     const int slot = line0 / BS;
-    const int off = (line0 - slot * BS) * G::LB;
-    int leaf = op == 0 ? mt.la[i * G::NSUB + kb * G::LPU + slot] : mt.lb[i * G::NSUB + kb * G::LPU + slot];
-    // a nil leaf: zeros on the branch-free path; otherwise its lines are never
-    // read (the tiles of an absent product are skipped) and leaf 0 is copied
-    // there, which keeps the copy loop free of branches
-    if (DENSE && leaf < 0) return reinterpret_cast<uint64_t>(&g_zero_page[0]);
-    if (leaf < 0) leaf = 0;
-    // both candidates from scalars, then a per-lane select (selecting the
-    // struct fields per lane would index a private copy of the struct)
-    const uint8_t *gL = static_cast<const uint8_t *>(m.packL) +
-                        ((int64_t)leaf * m.leafStrideL + (int64_t)part * m.partStrideL +
-                         (int64_t)c * m.chunkStrideL) * (int64_t)sizeof(T);
-    const uint8_t *gR = static_cast<const uint8_t *>(m.packR) +
-                        ((int64_t)leaf * m.leafStrideR + (int64_t)part * m.partStrideR +
-                         (int64_t)c * m.chunkStrideR) * (int64_t)sizeof(T);
-    return reinterpret_cast<uint64_t>((op == 0 ? gL : gR) + off);
+    CopyLane cl;
+    cl.idx = op * G::LPU + slot;
+    cl.off = (uint32_t)((int64_t)part * m.partStrideL * (int64_t)sizeof(T)) + (uint32_t)((line0 - slot * BS) * G::LB);
+    return cl;
+}
+
+// Source addresses of one step's copy, one per lane (lane k: the wave's
+// instruction k); kept in one 64-bit register pair for the whole step, each
+// instruction reads its address back as a scalar.  A nil leaf reads the zero
+// page (on the tile-skipping path its lines are never read).
+template <int MODE, int U, int BS>
+__device__ __forceinline__ uint64_t copy_addr(const Meta &mt, int i, int kb, int c, const CopyLane &cl,
+                                              uint32_t chunk_bytes) {
+    using G = Geo<MODE, U, BS>;
+    const uint64_t b = mt.ad[(int64_t)i * 2 * G::NSUB + kb * 2 * G::LPU + cl.idx];
+    const uint64_t zp = reinterpret_cast<uint64_t>(&g_zero_page[0]);
+    return b == 0 ? zp : b + cl.off + (uint64_t)c * chunk_bytes;
 }
 
 // Copy addresses of the next K chunk of the same leaf column: one chunk
 // further in every lane except those reading the zero page.
-template <int MODE, int U, int BS>
-__device__ __forceinline__ uint64_t next_chunk_addr(uint64_t a, const K5Member &m) {
-    using T = typename Geo<MODE, U, BS>::T;
+__device__ __forceinline__ uint64_t next_chunk_addr(uint64_t a, uint32_t chunk_bytes) {
     const uint64_t zp = reinterpret_cast<uint64_t>(&g_zero_page[0]);
-    return a == zp ? a : a + (uint64_t)m.chunkStrideL * sizeof(T);
+    return a == zp ? a : a + chunk_bytes;
 }
 
 // Copy instruction k of wave w: 64 lanes x 16 bytes straight into LDS.
@@ -371,31 +375,34 @@ struct Advance {
     uint64_t addrs;
 };
 
-template <int MODE, int U, int BS, bool DENSE>
-__device__ __forceinline__ Advance advance(const K5Member &m, const Meta &mt, int nb, const Step &st, uint64_t addrs,
-                                           int w) {
+template <int MODE, int U, int BS>
+__device__ __forceinline__ Advance advance(const Meta &mt, int nb, const Step &st, uint64_t addrs,
+                                           const CopyLane &cl, uint32_t chunk_bytes) {
     using G = Geo<MODE, U, BS>;
     Advance a;
     a.nx = next_step<G::LPU, G::NSUB, G::NCHUNK>(mt, nb, st);
     if (a.nx.i >= nb)
         a.addrs = reinterpret_cast<uint64_t>(&g_zero_page[0]);
     else if (a.nx.c != 0)
-        a.addrs = next_chunk_addr<MODE, U, BS>(addrs, m);
+        a.addrs = next_chunk_addr(addrs, chunk_bytes);
     else
-        a.addrs = copy_addr<MODE, U, BS, DENSE>(m, mt, a.nx.i, a.nx.kb, 0, w);
+        a.addrs = copy_addr<MODE, U, BS>(mt, a.nx.i, a.nx.kb, 0, cl, chunk_bytes);
     return a;
 }
 
+// One step on stage cur: st is this step, nxa the next one with its copy
+// addresses (looked up during the previous step).  The step after next is
+// looked up once this step's MFMAs are issued, while the copies land.
 template <int MODE, int U, int BS, bool DENSE>
 __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
-                                         Step &st, uint64_t &addrs, bool &have, int w, int wr, int wc) {
+                                         Step &st, Advance &nxa, const CopyLane &cl, uint32_t chunk_bytes, int w,
+                                         int wr, int wc) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
     constexpr int PARTS = M::PARTS, TPW = G::TPW, TPL = G::TPL, NLW = G::NLW;
     const int lane = threadIdx.x & 63;
     const uint32_t km = st.km;
-    const Advance nxa = advance<MODE, U, BS, DENSE>(m, mt, nb, st, addrs, w);
     // the next step's copy instructions are spread over the column tiles of
     // this step for 64-wide wave parts and on the branch-free path; with
     // 128 x 128 per wave and tile skipping the register file has no room for
@@ -459,12 +466,12 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
 #pragma unroll
         for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, nxt, w);
     }
+    const Advance nn = nxa.nx.i < nb ? advance<MODE, U, BS>(mt, nb, nxa.nx, nxa.addrs, cl, chunk_bytes) : nxa;
     // every wave's copy into nxt has landed and nobody reads cur any more
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
     st = nxa.nx;
-    addrs = nxa.addrs;
-    have = nxa.nx.i < nb;
+    nxa = nn;
 }
 
 // DENSE: the branch-free path (every tile multiplied, nil leaves copied as
@@ -487,7 +494,9 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
 
     const int p0 = m.ustart[u], p1 = m.ustart[u + 1];
-    const Meta mt = meta_view(meta, G::CAP, NSUB);
+    const Meta mt = meta_view(meta, G::CAP);
+    const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
+    const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
     for (int b0 = p0; b0 < p1; b0 += G::CAP) {
         const int nb = (p1 - b0) < G::CAP ? (p1 - b0) : G::CAP;
         __syncthreads();  // LDS (stages, metadata) of the previous batch or unit is free
@@ -501,27 +510,34 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
                 for (int q = 0; q < LPU; ++q) {
                     const int qa = m.transL ? morton_sub(kb, q, S) : morton_sub(q, kb, S);
                     const int qb = m.transR ? morton_sub(q, kb, S) : morton_sub(kb, q, S);
-                    mt.la[i * NSUB + kb * LPU + q] = m.descL ? m.descL[(int64_t)a * NSUB + qa] : a;
-                    mt.lb[i * NSUB + kb * LPU + q] = m.descR ? m.descR[(int64_t)b * NSUB + qb] : b;
+                    const int la = m.descL ? m.descL[(int64_t)a * NSUB + qa] : a;
+                    const int lb = m.descR ? m.descR[(int64_t)b * NSUB + qb] : b;
+                    uint64_t *d = mt.ad + (int64_t)i * 2 * NSUB + kb * 2 * LPU;
+                    d[q] = la < 0 ? 0 : reinterpret_cast<uint64_t>(static_cast<const uint8_t *>(m.packL) +
+                                                                   (int64_t)la * m.leafStrideL * (int64_t)sizeof(typename G::T));
+                    d[LPU + q] = lb < 0 ? 0 : reinterpret_cast<uint64_t>(static_cast<const uint8_t *>(m.packR) +
+                                                                         (int64_t)lb * m.leafStrideR * (int64_t)sizeof(typename G::T));
                 }
         }
         __syncthreads();
         Step st = first_step<LPU, NSUB>(mt, nb, 0);
-        bool have = st.i < nb;
-        uint64_t addrs = 0;
-        if (have) {
-            addrs = copy_addr<MODE, U, BS, DENSE>(m, mt, st.i, st.kb, 0, w);
+        Advance nxa;
+        nxa.nx = st;
+        nxa.addrs = 0;
+        if (st.i < nb) {
+            const uint64_t addrs = copy_addr<MODE, U, BS>(mt, st.i, st.kb, 0, cl, chunk_bytes);
 #pragma unroll
             for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
+            nxa = advance<MODE, U, BS>(mt, nb, st, addrs, cl, chunk_bytes);
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         // steps alternate between the two stages; unrolled by two so that
         // every access names its stage array at compile time
-        while (have) {
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, st, addrs, have, w, wr, wc);
-            if (!have) break;
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, st, addrs, have, w, wr, wc);
+        while (st.i < nb) {
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, st, nxa, cl, chunk_bytes, w, wr, wc);
+            if (st.i >= nb) break;
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, st, nxa, cl, chunk_bytes, w, wr, wc);
         }
     }
 
@@ -605,7 +621,7 @@ __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     k5(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
     __shared__ __attribute__((aligned(1024))) uint8_t st0[k5_stage_bytes<MODE, U>];
     __shared__ __attribute__((aligned(1024))) uint8_t st1[k5_stage_bytes<MODE, U>];
-    __shared__ __attribute__((aligned(16))) uint8_t meta[META_BYTES];
+    __shared__ __attribute__((aligned(16))) uint8_t meta[k5_meta_bytes<U>];
     if constexpr (BS != 0) {
         const int u = xcd_remap((int)blockIdx.x, single.nunits);
         process_sel<MODE, U, BS>(single, u, st0, st1, meta);
@@ -732,7 +748,8 @@ K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     m.partStrideR = vR.part_stride;
     m.lineStrideR = vR.line_stride;
     m.chunkStrideR = vR.chunk_stride;
-    QB_CHECK(m.chunkStrideL == m.chunkStrideR, QBSM_ERR_STATE, "operand packs differ in chunk geometry");
+    QB_CHECK(m.chunkStrideL == m.chunkStrideR && m.partStrideL == m.partStrideR, QBSM_ERR_STATE,
+             "operand packs differ in chunk geometry");
     m.nfL = vL.nonfinite;
     m.nfR = vR.nonfinite;
     m.out_rows = p.out_rows;
