@@ -493,12 +493,14 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
 #pragma unroll
         for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
 
-    const int p0 = m.ustart[u], p1 = m.ustart[u + 1];
+    // (loaded values are not known to be wave-uniform: say so, or every
+    // comparison with the batch size makes the step iterator divergent)
+    const int p0 = uni(m.ustart[u]), p1 = uni(m.ustart[u + 1]);
     const Meta mt = meta_view(meta, G::CAP);
     const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
     const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
     for (int b0 = p0; b0 < p1; b0 += G::CAP) {
-        const int nb = (p1 - b0) < G::CAP ? (p1 - b0) : G::CAP;
+        const int nb = uni((p1 - b0) < G::CAP ? (p1 - b0) : G::CAP);
         __syncthreads();  // LDS (stages, metadata) of the previous batch or unit is free
         for (int i = tid; i < nb; i += NT) {
             const int p = b0 + i;
