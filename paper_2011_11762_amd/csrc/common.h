@@ -205,6 +205,9 @@ struct PackView {
     const int32_t *nonfinite = nullptr;  // device flag of the pack
 };
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s);
+// Brings both packs (row and column lines) of m up to date in one pass when
+// both are stale; otherwise leaves them to matrix_pack.
+void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s);
 int mode_bk(qbsm_mode mode, int bs);
 
 void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);

@@ -226,6 +226,50 @@ __global__ void __launch_bounds__(256) k_extract(const uint32_t *keys, int64_t n
 // One thread converts and writes one 16-byte piece.  Column lines read
 // contiguous source runs (piece-fastest thread order); row lines read
 // across the column-major source (line-fastest thread order).
+// Converts one 16-byte piece (EPP source values) to the mode and stores it
+// (both parts for the split mode, the lo part n2 * EB bytes after the hi
+// part); returns whether a packed value is Inf or NaN.
+template <int MODE>
+__device__ __forceinline__ bool store_piece(const double *v, uint8_t *o, int64_t n2) {
+    constexpr int EB = MODE == QBSM_F64 ? 8 : MODE == QBSM_F32 ? 4 : 2;
+    constexpr int PARTS = MODE == QBSM_BF16X3 ? 2 : 1;
+    bool bad = false;  // a packed value (after the conversion to the mode) is Inf or NaN
+    if (MODE == QBSM_F64) {
+        bad = !isfinite(v[0]) || !isfinite(v[1]);
+        *reinterpret_cast<double2 *>(o) = make_double2(v[0], v[1]);
+    } else if (MODE == QBSM_F32) {
+        const float4 f = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+        bad = !isfinite(f.x) || !isfinite(f.y) || !isfinite(f.z) || !isfinite(f.w);
+        *reinterpret_cast<float4 *>(o) = f;
+    } else {
+        uint16_t h[8], lo[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            h[e] = bf16_rne_bits(v[e]);
+            const bool hinf = (h[e] & 0x7F80u) == 0x7F80u;  // hi part Inf or NaN
+            // the residual of an infinite (or overflowing) value is not
+            // defined: its lo part is zero, so Inf stays Inf in the product
+            lo[e] = hinf ? (uint16_t)0 : bf16_rne_bits(v[e] - bf16_bits_to_double(h[e]));
+            bad |= hinf;
+        }
+        uint4 hv, lv;
+        hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
+        hv.z = h[4] | ((uint32_t)h[5] << 16); hv.w = h[6] | ((uint32_t)h[7] << 16);
+        *reinterpret_cast<uint4 *>(o) = hv;
+        if (PARTS == 2) {
+            lv.x = lo[0] | ((uint32_t)lo[1] << 16); lv.y = lo[2] | ((uint32_t)lo[3] << 16);
+            lv.z = lo[4] | ((uint32_t)lo[5] << 16); lv.w = lo[6] | ((uint32_t)lo[7] << 16);
+            *reinterpret_cast<uint4 *>(o + n2 * EB) = lv;
+        }
+    }
+    return bad;
+}
+
+// Packed layout per leaf: [part][chunk c][line l][LB bytes], LB = bk * EB;
+// the 16-byte pieces of a line are stored at slot piece ^ piece_swizzle(line).
+// One thread converts and writes one 16-byte piece.  Column lines read
+// contiguous source runs (piece-fastest thread order); row lines read
+// across the column-major source (line-fastest thread order).
 template <class Src, int MODE>
 __global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int32_t bs, int32_t bk, int role,
                                               uint8_t *dst, int32_t *nonfinite) {
@@ -259,36 +303,66 @@ __global__ void __launch_bounds__(256) k_pack(const Src *src, int64_t nblk, int3
         v[e] = role == ROLE_COL ? (double)x[(k0 + e) + l * bs] : (double)x[l + (k0 + e) * bs];
     uint8_t *o = dst + leaf * (PARTS * n2 * EB) + c * (int64_t)bs * LB + l * LB +
                  ((piece ^ piece_swizzle((int)l, LB)) << 4);
-    bool bad = false;  // a packed value (after the conversion to the mode) is Inf or NaN
-    if (MODE == QBSM_F64) {
-        bad = !isfinite(v[0]) || !isfinite(v[1]);
-        *reinterpret_cast<double2 *>(o) = make_double2(v[0], v[1]);
-    } else if (MODE == QBSM_F32) {
-        const float4 f = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
-        bad = !isfinite(f.x) || !isfinite(f.y) || !isfinite(f.z) || !isfinite(f.w);
-        *reinterpret_cast<float4 *>(o) = f;
-    } else {
-        uint16_t h[8], lo[8];
+    if (store_piece<MODE>(v, o, n2)) *nonfinite = 1;
+}
+
+// Both roles of one matrix in one pass (the left and the right operand of
+// A * A): one workgroup per leaf reads the leaf once into LDS and writes the
+// row-line and the column-line packs from there.  Leaves of 32 and 64.
+
+template <class Src, int MODE, int BS>
+__global__ void __launch_bounds__(256) k_pack2(const Src *src, int32_t bk, uint8_t *dst_row, uint8_t *dst_col,
+                                               int32_t *nf_row, int32_t *nf_col) {
+    constexpr int EB = MODE == QBSM_F64 ? 8 : MODE == QBSM_F32 ? 4 : 2;
+    constexpr int EPP = 16 / EB;
+    constexpr int PARTS = MODE == QBSM_BF16X3 ? 2 : 1;
+    constexpr int bs = BS;
+    constexpr int64_t n2 = (int64_t)BS * BS;
+    static_assert(n2 % 256 == 0, "whole leaf rounds");
+    // the leaf in LDS with a column stride of bs + 1 doubles: the row-line
+    // reads (consecutive rows) and the column-line reads (consecutive pieces
+    // and columns) then fall on distinct banks
+    constexpr int ld = BS + 1;
+    __shared__ double x[ld * BS];
+    const int64_t leaf = blockIdx.x;
+    const Src *g = src + leaf * n2;
+    Src t[n2 / 256];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            h[e] = bf16_rne_bits(v[e]);
-            const bool hinf = (h[e] & 0x7F80u) == 0x7F80u;  // hi part Inf or NaN
-            // the residual of an infinite (or overflowing) value is not
-            // defined: its lo part is zero, so Inf stays Inf in the product
-            lo[e] = hinf ? (uint16_t)0 : bf16_rne_bits(v[e] - bf16_bits_to_double(h[e]));
-            bad |= hinf;
-        }
-        uint4 hv, lv;
-        hv.x = h[0] | ((uint32_t)h[1] << 16); hv.y = h[2] | ((uint32_t)h[3] << 16);
-        hv.z = h[4] | ((uint32_t)h[5] << 16); hv.w = h[6] | ((uint32_t)h[7] << 16);
-        *reinterpret_cast<uint4 *>(o) = hv;
-        if (PARTS == 2) {
-            lv.x = lo[0] | ((uint32_t)lo[1] << 16); lv.y = lo[2] | ((uint32_t)lo[3] << 16);
-            lv.z = lo[4] | ((uint32_t)lo[5] << 16); lv.w = lo[6] | ((uint32_t)lo[7] << 16);
-            *reinterpret_cast<uint4 *>(o + n2 * EB) = lv;
-        }
+    for (int q = 0; q < n2 / 256; ++q) t[q] = g[threadIdx.x + 256 * q];  // all loads in flight at once
+#pragma unroll
+    for (int q = 0; q < n2 / 256; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        x[(i % BS) + (i / BS) * ld] = (double)t[q];
     }
-    if (bad) *nonfinite = 1;
+    __syncthreads();
+    const int LB = bk * EB;
+    const int ppl = LB / 16;
+    const int per_role = (bs / bk) * bs * ppl;
+    bool bad_row = false, bad_col = false;
+    for (int r = threadIdx.x; r < 2 * per_role; r += 256) {
+        const bool col = r >= per_role;
+        const int rem = col ? r - per_role : r;
+        int c, l, piece;
+        if (col) {
+            piece = rem % ppl;
+            l = (rem / ppl) % bs;
+            c = rem / (ppl * bs);
+        } else {
+            l = rem % bs;
+            piece = (rem / bs) % ppl;
+            c = rem / (bs * ppl);
+        }
+        const int k0 = c * bk + piece * EPP;
+        double v[EPP];
+#pragma unroll
+        for (int e = 0; e < EPP; ++e) v[e] = col ? x[(k0 + e) + l * ld] : x[l + (k0 + e) * ld];
+        uint8_t *o = (col ? dst_col : dst_row) + leaf * (PARTS * n2 * EB) + (int64_t)c * bs * LB + l * LB +
+                     ((piece ^ piece_swizzle(l, LB)) << 4);
+        const bool bad = store_piece<MODE>(v, o, n2);
+        if (col) bad_col |= bad; else bad_row |= bad;
+    }
+    if (bad_row) *nf_row = 1;
+    if (bad_col) *nf_col = 1;
 }
 
 size_t mode_elem_bytes(qbsm_mode mode) {
@@ -524,6 +598,50 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
     }
 #undef QB_PACK
     QB_LAUNCH_CHECK();
+}
+
+void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
+    const int bs = m.bs;
+    const int64_t n2 = (int64_t)bs * bs;
+    const size_t bytes = (size_t)m.nblk * n2 * mode_elem_bytes(mode) * mode_parts(mode);
+    Pack &pr = m.packs[std::make_pair((int)mode, (int)ROLE_ROW)];
+    Pack &pc = m.packs[std::make_pair((int)mode, (int)ROLE_COL)];
+    const bool stale_r = pr.buf.n != bytes || pr.version != m.version || !pr.buf.p;
+    const bool stale_c = pc.buf.n != bytes || pc.version != m.version || !pc.buf.p;
+    if (!stale_r || !stale_c || (bs != 32 && bs != 64) || m.nblk == 0) return;  // per-role packs do the rest
+    if (pr.buf.n != bytes) pr.buf.alloc(bytes, s);
+    if (pc.buf.n != bytes) pc.buf.alloc(bytes, s);
+    if (!pr.nonfinite.p) pr.nonfinite.alloc(1, s);
+    if (!pc.nonfinite.p) pc.nonfinite.alloc(1, s);
+    const int bk = mode_bk(mode, bs);
+    ProfScope prof(PROF_PACK, s);
+    fill_i32(pr.nonfinite.p, 0, 1, s);
+    fill_i32(pc.nonfinite.p, 0, 1, s);
+    const unsigned g = (unsigned)m.nblk;
+#define QB_PACK2(SRC, PTR, MODE)                                                                          \
+    if (bs == 32)                                                                                         \
+        k_pack2<SRC, MODE, 32><<<g, 256, 0, s>>>(PTR, bk, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p); \
+    else                                                                                                  \
+        k_pack2<SRC, MODE, 64><<<g, 256, 0, s>>>(PTR, bk, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p)
+    if (m.storage == ST_F64) {
+        switch (mode) {
+            case QBSM_F64: QB_PACK2(double, m.v64.p, QBSM_F64); break;
+            case QBSM_F32: QB_PACK2(double, m.v64.p, QBSM_F32); break;
+            case QBSM_BF16: QB_PACK2(double, m.v64.p, QBSM_BF16); break;
+            case QBSM_BF16X3: QB_PACK2(double, m.v64.p, QBSM_BF16X3); break;
+        }
+    } else {
+        switch (mode) {
+            case QBSM_F64: QB_PACK2(float, m.v32.p, QBSM_F64); break;
+            case QBSM_F32: QB_PACK2(float, m.v32.p, QBSM_F32); break;
+            case QBSM_BF16: QB_PACK2(float, m.v32.p, QBSM_BF16); break;
+            case QBSM_BF16X3: QB_PACK2(float, m.v32.p, QBSM_BF16X3); break;
+        }
+    }
+#undef QB_PACK2
+    QB_LAUNCH_CHECK();
+    pr.version = m.version;
+    pc.version = m.version;
 }
 
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {

@@ -728,8 +728,10 @@ int k5_occupancy(qbsm_mode mode, int unit, int bs) {
 K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     Tree &tL = matrix_tree(*p.L, p.D, s);
     Tree &tR = matrix_tree(*p.R, p.D, s);
-    const PackView vL = matrix_pack(*p.L, mode, p.transL ? ROLE_COL : ROLE_ROW, s);
-    const PackView vR = matrix_pack(*p.R, mode, p.transR ? ROLE_ROW : ROLE_COL, s);
+    const Role roleL = p.transL ? ROLE_COL : ROLE_ROW, roleR = p.transR ? ROLE_ROW : ROLE_COL;
+    if (p.L == p.R && roleL != roleR) matrix_pack_pair(*p.L, mode, s);
+    const PackView vL = matrix_pack(*p.L, mode, roleL, s);
+    const PackView vR = matrix_pack(*p.R, mode, roleR, s);
     K5Member m{};
     m.ustart = p.ustart.p;
     m.ukey = p.ukey.p;

@@ -355,3 +355,28 @@ def test_unit256_batched(q):
         for (a, b), s_ in zip(members, singles):
             ref = O.multiply(O.from_workload(a), O.from_workload(b))
             assert O.rel_fro(s_, ref.vals) <= TOL[mode]
+
+
+@pytest.mark.parametrize("bs", [32, 64, 128])
+def test_square_packs_both_roles_at_once(q, bs):
+    """A * A through one handle (both operand layouts packed in one pass for
+    leaves up to 64) equals A * B with B a second handle of the same values
+    (one pack per role), bit for bit, in every mode; the non-finite flags of
+    both layouts are set."""
+    n = 5 * bs + bs // 2
+    a, _ = W.small_random(n, n, n, bs, 0.5, 78)
+    A1, A2 = upload(q, a), upload(q, a)
+    oa = O.from_workload(a)
+    ref = O.multiply(oa, oa)
+    for mode in ("f64", "f32", "bf16", "bf16x3"):
+        for unit in units(bs, mode):
+            same = values_np(q.matmul(A1, A1, mode, unit=unit))
+            other = values_np(q.matmul(A1, A2, mode, unit=unit))
+            assert np.array_equal(same, other), (mode, unit)
+            assert O.rel_fro(same, ref.vals) <= TOL[mode], (mode, unit)
+    b = W.BlockMatrix(a.nrows, a.ncols, bs, a.brow.copy(), a.bcol.copy(), a.vals.copy())
+    b.vals[1, 3] = np.nan
+    B1 = upload(q, b)
+    got = values_np(q.matmul(B1, B1, "f32", unit=max(units(bs, "f32"))))
+    refb = O.multiply(O.from_workload(b), O.from_workload(b)).vals
+    assert np.array_equal(np.isnan(got), np.isnan(refb))
