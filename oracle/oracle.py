@@ -364,6 +364,62 @@ def split_bf16(x: np.ndarray):
     return hi, lo
 
 
+# Ozaki splitting (Ozaki, Ogita, Oishi and Rump, "Error-free transformations
+# of matrix multiplication by using fast routines of matrix multiplication
+# and its applications", Numer. Algorithms 59, 2012): an addition to the
+# paper's FP64-only leaves.  Reading taken here: one exponent per leaf row of
+# the left operand and per leaf column of the right operand; OZ_SLICES slices
+# of OZ_BITS-bit digits, each exactly representable in bfloat16; the slice
+# pairs with t + u <= OZ_SLICES + 1 are kept.
+OZ_SLICES, OZ_BITS = 6, 8
+
+
+def ozaki_split(vals: np.ndarray, bs: int, line: str, slices: int = OZ_SLICES, bits: int = OZ_BITS) -> np.ndarray:
+    """Exponent-aligned slices of leaf blocks: returns [slices, nblk, bs*bs].
+
+    line = "row" (left operand: one exponent per leaf row) or "col" (right
+    operand: one per leaf column).  With m the largest finite magnitude of a
+    line and e the exponent with m < 2^e, every finite element x of the line
+    is cut into N = floor(|x| 2^(slices*bits - e)) < 2^(slices*bits) and
+    slice t (t = 1 .. slices) is sign(x) * digit_t(N) * 2^(e - t*bits), digit
+    t being bits [(slices-t)*bits, (slices-t+1)*bits) of N.  An Inf or NaN
+    element is its own first slice (the rest zero).
+    """
+    v = np.asarray(vals, dtype=np.float64).reshape(-1, bs, bs)   # [block, column, row]
+    fin = np.isfinite(v)
+    a = np.where(fin, np.abs(v), 0.0)
+    m = a.max(axis=1, keepdims=True) if line == "row" else a.max(axis=2, keepdims=True)
+    _, e = np.frexp(m)                     # m = f 2^e with 0.5 <= f < 1, so m < 2^e (0 for m = 0)
+    total = slices * bits
+    n = np.floor(np.ldexp(a, total - e))   # exact: a 2^(total-e) < 2^total <= 2^53
+    sign = np.sign(v)
+    out = np.zeros((slices,) + v.shape)
+    for t in range(1, slices + 1):
+        digit = np.mod(np.floor(np.ldexp(n, -(total - bits * t))), 2.0 ** bits)
+        out[t - 1] = np.where(fin, sign * np.ldexp(digit, e - bits * t), 0.0)
+    out[0] = np.where(fin, out[0], v)
+    return out.reshape(slices, -1, bs * bs)
+
+
+def ozaki_multiply(a: OMatrix, b: OMatrix, slices: int = OZ_SLICES, bits: int = OZ_BITS) -> OProduct:
+    """C = sum over t + u <= slices + 1 of A_t B_u, every slice product in FP64
+    through the plain multiply (the slice products are exact; only their
+    accumulation rounds)."""
+    sa = ozaki_split(a.vals, a.bs, "row", slices, bits)
+    sb = ozaki_split(b.vals, b.bs, "col", slices, bits)
+    total = None
+    for t in range(1, slices + 1):
+        for u in range(1, slices + 2 - t):
+            at = OMatrix(a.nrows, a.ncols, a.bs, a.brow, a.bcol, np.ascontiguousarray(sa[t - 1]))
+            bu = OMatrix(b.nrows, b.ncols, b.bs, b.brow, b.bcol, np.ascontiguousarray(sb[u - 1]))
+            p = multiply(at, bu)
+            if total is None:
+                total = p
+            else:
+                total.vals = total.vals + p.vals
+    return total
+
+
 def rel_fro(x: np.ndarray, ref: np.ndarray) -> float:
     """Relative Frobenius error ||x - ref|| / ||ref||."""
     num = np.linalg.norm((np.asarray(x) - np.asarray(ref)).ravel())
