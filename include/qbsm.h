@@ -67,13 +67,25 @@ typedef enum {
  *               lo_a*hi_b, FP32 accumulation, FP32 result.  An infinite input
  *               gives a non-finite result (Inf, or NaN where the split terms of
  *               its partner differ in sign) in exactly the elements it reaches.
+ *   QBSM_OZAKI_BF16 Ozaki splitting (Ozaki, Ogita, Oishi and Rump 2012) on
+ *               bfloat16 MFMA: each line of a leaf (a row of the left operand,
+ *               a column of the right one) gets the exponent e of its largest
+ *               finite magnitude m (m < 2^e), and each element is cut into 6
+ *               slices of 8-bit digits on the grid 2^(e - 8t), t = 1..6, each
+ *               exact in bfloat16 (the 48 leading bits of the element below
+ *               e).  The 21 slice pairs with t + u <= 7 are multiplied; the
+ *               products of one pair group (t + u fixed) over a 32-element K
+ *               chunk sum exactly in FP32 and are accumulated in FP64; FP64
+ *               result.  Needs a plan with unit 64 (see qbsm_plan_opts).
+ *               An infinite input gives a non-finite result where reached.
  * In every mode a product exists only where both leaf blocks are stored: an
  * Inf or NaN never meets the implicit zeros of a nil block. */
 typedef enum {
     QBSM_F64 = 0,
     QBSM_F32 = 1,
     QBSM_BF16 = 2,
-    QBSM_BF16X3 = 3
+    QBSM_BF16X3 = 3,
+    QBSM_OZAKI_BF16 = 4
 } qbsm_mode;
 
 typedef struct qbsm_matrix_ *qbsm_matrix;
@@ -154,7 +166,9 @@ qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *
  * 0..2 and a value in {64, 128, 256}.  A plan with unit 256 serves the
  * 4-byte-accumulator modes (F32, BF16, BF16X3); its FP64 numeric phase
  * returns QBSM_ERR_UNSUPPORTED (a 256 x 256 FP64 accumulator exceeds the
- * register file of one compute unit). */
+ * register file of one compute unit).  QBSM_OZAKI_BF16 runs on plans with
+ * unit 64 only (its six slices per operand fill the LDS) and returns
+ * QBSM_ERR_UNSUPPORTED otherwise. */
 typedef struct {
     int32_t unit;
     int32_t reserved[7];
@@ -244,7 +258,7 @@ qbsm_status qbsm_batch_destroy(qbsm_batch batch);
  * + numeric, `reps` timed repetitions after one warm-up) and reports the
  * fastest.  times_ms (host, may be NULL) receives 3 entries in the order
  * unit = 64, 128, 256 (negative when not applicable to the leaf size or the
- * mode). */
+ * mode; QBSM_OZAKI_BF16 has unit 64 only). */
 qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps,
                                void *stream, int32_t *best_unit, double *times_ms);
 

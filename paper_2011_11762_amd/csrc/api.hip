@@ -122,7 +122,9 @@ qbsm_status guard(F &&f) {
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
-bool valid_mode(qbsm_mode m) { return m == QBSM_F64 || m == QBSM_F32 || m == QBSM_BF16 || m == QBSM_BF16X3; }
+bool valid_mode(qbsm_mode m) {
+    return m == QBSM_F64 || m == QBSM_F32 || m == QBSM_BF16 || m == QBSM_BF16X3 || m == QBSM_OZAKI_BF16;
+}
 
 }  // namespace
 
@@ -436,7 +438,8 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
         for (int ci = 0; ci < 3; ++ci) {
             const int u = cand[ci];
             double t = -1.0;
-            const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64);
+            const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64) &&
+                            !(mode == QBSM_OZAKI_BF16 && u != 64);
             if (ok) {
                 auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, s);
                 Matrix out;

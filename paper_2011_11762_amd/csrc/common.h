@@ -131,6 +131,7 @@ struct Tree {
 struct Pack {
     DArr<uint8_t> buf;
     DArr<int32_t> nonfinite;  // [1]: set by the pack kernel when a packed value is Inf or NaN
+    DArr<int32_t> aux;        // Ozaki mode: exponent of every packed line [nblk * bs]
     uint64_t version = 0;
 };
 

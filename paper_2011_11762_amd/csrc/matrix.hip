@@ -365,6 +365,93 @@ __global__ void __launch_bounds__(256) k_pack2(const Src *src, int32_t bk, uint8
     if (bad_col) *nf_col = 1;
 }
 
+// Ozaki splitting: 6 slices of 8-bit digits per element (each exact in
+// bfloat16) on the exponent grid of the element's packed line.
+constexpr int OZ_SLICES = 6, OZ_BITS = 8;
+
+// Exponent e of every packed line (a row of a leaf for the left operand, a
+// column for the right one): the largest finite magnitude m of the line
+// satisfies m < 2^e (e = 0 for an all-zero line).
+template <class Src>
+__global__ void __launch_bounds__(256) k_oz_exp(const Src *src, int64_t nblk, int32_t bs, int role, int32_t *ex) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk * bs) return;
+    const int64_t leaf = t / bs;
+    const int l = (int)(t - leaf * bs);
+    const Src *x = src + leaf * (int64_t)bs * bs;
+    double m = 0.0;
+    for (int k = 0; k < bs; ++k) {
+        const double v = fabs((double)(role == ROLE_COL ? x[k + (int64_t)l * bs] : x[l + (int64_t)k * bs]));
+        if (isfinite(v) && v > m) m = v;
+    }
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);
+    ex[t] = e;
+}
+
+// One 16-byte piece (8 elements) of one packed line, all 6 slices: element x
+// with line exponent e is cut into N = floor(|x| 2^(48 - e)) < 2^48 and slice
+// t holds sign(x) * digit_t(N) * 2^(e - 8t), digit t being bits
+// [48 - 8t, 56 - 8t) of N.  An Inf or NaN element is its own first slice.
+template <class Src>
+__global__ void __launch_bounds__(256) k_pack_oz(const Src *src, int64_t nblk, int32_t bs, int32_t bk, int role,
+                                                 const int32_t *ex, uint8_t *dst, int32_t *nonfinite) {
+    constexpr int EB = 2, EPP = 8;
+    const int LB = bk * EB;
+    const int ppl = LB / 16;
+    const int64_t nc = bs / bk;
+    const int64_t per_leaf = nc * bs * ppl;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nblk * per_leaf) return;
+    const int64_t leaf = t / per_leaf;
+    const int64_t rem = t - leaf * per_leaf;
+    int64_t c, l, piece;
+    if (role == ROLE_COL) {
+        piece = rem % ppl;
+        l = (rem / ppl) % bs;
+        c = rem / (ppl * (int64_t)bs);
+    } else {
+        l = rem % bs;
+        piece = (rem / bs) % ppl;
+        c = rem / ((int64_t)bs * ppl);
+    }
+    const int64_t n2 = (int64_t)bs * bs;
+    const Src *x = src + leaf * n2;
+    const int64_t k0 = c * bk + piece * EPP;
+    const int e = ex[leaf * bs + l];
+    uint16_t d[OZ_SLICES][EPP];
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < EPP; ++k) {
+        const double v = role == ROLE_COL ? (double)x[(k0 + k) + l * bs] : (double)x[l + (k0 + k) * bs];
+        if (!isfinite(v)) {
+            bad = true;
+            d[0][k] = bf16_rne_bits(v);
+#pragma unroll
+            for (int q = 1; q < OZ_SLICES; ++q) d[q][k] = 0;
+            continue;
+        }
+        const uint64_t n = (uint64_t)floor(ldexp(fabs(v), OZ_SLICES * OZ_BITS - e));
+        const double sg = v < 0.0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < OZ_SLICES; ++q) {
+            const int sh = OZ_BITS * (OZ_SLICES - 1 - q);
+            const double digit = (double)((n >> sh) & 0xFFu);
+            d[q][k] = bf16_rne_bits(sg * ldexp(digit, e - OZ_BITS * (q + 1)));  // exact: 8 significant bits
+        }
+    }
+    uint8_t *o = dst + leaf * (OZ_SLICES * n2 * EB) + c * (int64_t)bs * LB + l * LB +
+                 ((piece ^ piece_swizzle((int)l, LB)) << 4);
+#pragma unroll
+    for (int q = 0; q < OZ_SLICES; ++q) {
+        uint4 w;
+        w.x = d[q][0] | ((uint32_t)d[q][1] << 16); w.y = d[q][2] | ((uint32_t)d[q][3] << 16);
+        w.z = d[q][4] | ((uint32_t)d[q][5] << 16); w.w = d[q][6] | ((uint32_t)d[q][7] << 16);
+        *reinterpret_cast<uint4 *>(o + q * n2 * EB) = w;
+    }
+    if (bad) *nonfinite = 1;
+}
+
 size_t mode_elem_bytes(qbsm_mode mode) {
     switch (mode) {
         case QBSM_F64: return 8;
@@ -372,14 +459,14 @@ size_t mode_elem_bytes(qbsm_mode mode) {
         default: return 2;
     }
 }
-int mode_parts(qbsm_mode mode) { return mode == QBSM_BF16X3 ? 2 : 1; }
+int mode_parts(qbsm_mode mode) { return mode == QBSM_BF16X3 ? 2 : mode == QBSM_OZAKI_BF16 ? OZ_SLICES : 1; }
 
 }  // namespace
 
 int mode_bk(qbsm_mode mode, int bs) {
     // K chunk per packed line: 128-byte lines, except the two-part split mode
     // (64-byte lines) so that two LDS stages of both parts fit in 64 KB
-    int bk = (mode == QBSM_BF16X3 ? 64 : 128) / (int)mode_elem_bytes(mode);
+    int bk = (mode == QBSM_BF16X3 || mode == QBSM_OZAKI_BF16 ? 64 : 128) / (int)mode_elem_bytes(mode);
     return bk < bs ? bk : bs;
 }
 
@@ -579,6 +666,18 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
     uint8_t *dst = pk.buf.p;
     ProfScope prof(PROF_PACK, s);
     fill_i32(pk.nonfinite.p, 0, 1, s);
+    if (mode == QBSM_OZAKI_BF16) {
+        const unsigned ge = grid_for(m.nblk * m.bs, 256);
+        if (m.storage == ST_F64) {
+            k_oz_exp<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, (int)role, pk.aux.p);
+            k_pack_oz<double><<<g, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, bk, (int)role, pk.aux.p, dst, pk.nonfinite.p);
+        } else {
+            k_oz_exp<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, (int)role, pk.aux.p);
+            k_pack_oz<float><<<g, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, bk, (int)role, pk.aux.p, dst, pk.nonfinite.p);
+        }
+        QB_LAUNCH_CHECK();
+        return;
+    }
 #define QB_PACK(SRC, PTR, MODE) \
     k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst, pk.nonfinite.p)
     if (m.storage == ST_F64) {
@@ -587,6 +686,7 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
             case QBSM_F32: QB_PACK(double, m.v64.p, QBSM_F32); break;
             case QBSM_BF16: QB_PACK(double, m.v64.p, QBSM_BF16); break;
             case QBSM_BF16X3: QB_PACK(double, m.v64.p, QBSM_BF16X3); break;
+            default: break;  // Ozaki: packed above
         }
     } else {
         switch (mode) {
@@ -594,6 +694,7 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
             case QBSM_F32: QB_PACK(float, m.v32.p, QBSM_F32); break;
             case QBSM_BF16: QB_PACK(float, m.v32.p, QBSM_BF16); break;
             case QBSM_BF16X3: QB_PACK(float, m.v32.p, QBSM_BF16X3); break;
+            default: break;  // Ozaki: packed above
         }
     }
 #undef QB_PACK
@@ -608,7 +709,8 @@ void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
     Pack &pc = m.packs[std::make_pair((int)mode, (int)ROLE_COL)];
     const bool stale_r = pr.buf.n != bytes || pr.version != m.version || !pr.buf.p;
     const bool stale_c = pc.buf.n != bytes || pc.version != m.version || !pc.buf.p;
-    if (!stale_r || !stale_c || (bs != 32 && bs != 64) || m.nblk == 0) return;  // per-role packs do the rest
+    if (!stale_r || !stale_c || (bs != 32 && bs != 64) || m.nblk == 0 || mode == QBSM_OZAKI_BF16)
+        return;  // per-role packs do the rest
     if (pr.buf.n != bytes) pr.buf.alloc(bytes, s);
     if (pc.buf.n != bytes) pc.buf.alloc(bytes, s);
     if (!pr.nonfinite.p) pr.nonfinite.alloc(1, s);
@@ -629,6 +731,7 @@ void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
             case QBSM_F32: QB_PACK2(double, m.v64.p, QBSM_F32); break;
             case QBSM_BF16: QB_PACK2(double, m.v64.p, QBSM_BF16); break;
             case QBSM_BF16X3: QB_PACK2(double, m.v64.p, QBSM_BF16X3); break;
+            default: break;  // Ozaki: one pack per role
         }
     } else {
         switch (mode) {
@@ -636,6 +739,7 @@ void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
             case QBSM_F32: QB_PACK2(float, m.v32.p, QBSM_F32); break;
             case QBSM_BF16: QB_PACK2(float, m.v32.p, QBSM_BF16); break;
             case QBSM_BF16X3: QB_PACK2(float, m.v32.p, QBSM_BF16X3); break;
+            default: break;  // Ozaki: one pack per role
         }
     }
 #undef QB_PACK2
@@ -655,6 +759,7 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
     if (pk.buf.n != bytes || pk.version != m.version || !pk.buf.p) {
         if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
         if (!pk.nonfinite.p) pk.nonfinite.alloc(1, s);
+        if (mode == QBSM_OZAKI_BF16 && pk.aux.n != (size_t)(m.nblk * bs)) pk.aux.alloc(m.nblk * bs ? m.nblk * bs : 1, s);
         pack_launch(m, mode, role, pk, s);
         pk.version = m.version;
     }

@@ -116,6 +116,34 @@ struct MT<QBSM_BF16X3> {
 // then hold zeros, so the products of a nil leaf add exact zeros.
 __device__ __attribute__((aligned(1024))) uint8_t g_zero_page[1024] = {};
 
+// Ozaki slices (6 per operand, each exact in bfloat16): for every pair group
+// g = t + u (2..7) the products of slice pairs (t, u) over one 32-element K
+// chunk are summed by one MFMA chain in FP32, exactly (each product has at
+// most 16 significant bits on the group's common exponent grid and the chain
+// at most 6 * 32 of them), then added to the FP64 accumulator.
+template <>
+struct MT<QBSM_OZAKI_BF16> {
+    using T = uint16_t;
+    using Acc = d4;
+    using Out = double;
+    static constexpr int BK = 32, PARTS = 6, LBMAX = 64, KPG = 32, PPG = 4, SUBS = 1;
+    struct Frag { uint4 q[1]; };
+    __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
+#pragma unroll
+        for (int g = 2; g <= PARTS + 1; ++g) {
+            f4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ta = 1; ta < g; ++ta)
+                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[ta - 1].q[0]),
+                                                            __builtin_bit_cast(bf8, b[g - ta - 1].q[0]), t, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] += (double)t[i];
+        }
+    }
+    // the FP32 MFMA layout: element i of a lane holds row 4*(lane/16) + i
+    __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+
 __device__ __forceinline__ int morton_sub(int r, int c, int s) {
     int q = 0;
     for (int b = 0; b < s; ++b) q |= (((r >> b) & 1) << (2 * b + 1)) | (((c >> b) & 1) << (2 * b));
@@ -252,7 +280,9 @@ struct Geo {
     static constexpr int NGROUPS = BK / M::KPG;
     static constexpr int LPI = 1024 / LB;                // lines per 1 KB load instruction
     static constexpr int IPA = U / LPI;                  // load instructions per array
-    static constexpr int WT = U >= 256 ? 128 : 64;       // side of the part one wave computes
+    // side of the part one wave computes (the six Ozaki slices per operand
+    // leave LDS for 64-wide units only: four waves of 32 x 32 there)
+    static constexpr int WT = MODE == QBSM_OZAKI_BF16 ? 32 : U >= 256 ? 128 : 64;
     static constexpr int WPS = U / WT;                   // waves per unit side
     static constexpr int NW = WPS * WPS;
     static constexpr int TPW = WT / 16;                  // 16x16 tiles per wave side
@@ -269,7 +299,10 @@ struct Geo {
 };
 
 template <int MODE, int U>
-constexpr int k5_nt = 64 * (U / (U >= 256 ? 128 : 64)) * (U / (U >= 256 ? 128 : 64));
+constexpr int k5_wt = MODE == QBSM_OZAKI_BF16 ? 32 : U >= 256 ? 128 : 64;
+
+template <int MODE, int U>
+constexpr int k5_nt = 64 * (U / k5_wt<MODE, U>) * (U / k5_wt<MODE, U>);
 
 template <int MODE, int U>
 constexpr int k5_stage_bytes = 2 * MT<MODE>::PARTS * U * MT<MODE>::LBMAX;
@@ -613,7 +646,7 @@ __device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *s
 }
 
 template <int MODE, int U>
-constexpr int k5_min_blocks = (MODE == QBSM_F64 || U >= 256) ? 1 : 2;
+constexpr int k5_min_blocks = (MODE == QBSM_F64 || MODE == QBSM_OZAKI_BF16 || U >= 256) ? 1 : 2;
 
 // BS > 0: one launch of one multiply with that leaf size, one workgroup per
 // unit.  BS == 0: persistent launch over a work list of (member, unit) items
@@ -674,11 +707,16 @@ void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, i
                  int grid, int persistent, const K5Member &single, hipStream_t s) {
     switch (unit) {
         case 64: launch_u<MODE, 64>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
-        case 128: launch_u<MODE, 128>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
+        case 128:
+            if constexpr (MODE != QBSM_OZAKI_BF16) {
+                launch_u<MODE, 128>(bs, members, items, nitems, counter, grid, persistent, single, s);
+                break;
+            }
+            throw Error(QBSM_ERR_UNSUPPORTED, "unit side for this mode");
         case 256:
             // the 128 x 128 part of a wave holds 64 KB of accumulators in FP32
             // but twice that in FP64, beyond the register file
-            if constexpr (MODE != QBSM_F64) {
+            if constexpr (MODE != QBSM_F64 && MODE != QBSM_OZAKI_BF16) {
                 launch_u<MODE, 256>(bs, members, items, nitems, counter, grid, persistent, single, s);
                 break;
             }
@@ -698,6 +736,9 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const
         case QBSM_F32: launch_mode<QBSM_F32>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
         case QBSM_BF16: launch_mode<QBSM_BF16>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
         case QBSM_BF16X3: launch_mode<QBSM_BF16X3>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
+        case QBSM_OZAKI_BF16:
+            launch_mode<QBSM_OZAKI_BF16>(unit, bs, members, items, nitems, counter, grid, persistent, single, s);
+            break;
         default: throw Error(QBSM_ERR_ARG, "mode");
     }
     QB_LAUNCH_CHECK();
@@ -707,7 +748,7 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const
 // work-list variant).
 int k5_occupancy(qbsm_mode mode, int unit, int bs) {
     int nb = 0;
-    const int NT = 64 * (unit >= 256 ? 4 : (unit / 64) * (unit / 64));
+    const int NT = mode == QBSM_OZAKI_BF16 ? 256 : 64 * (unit >= 256 ? 4 : (unit / 64) * (unit / 64));
     const void *fn = nullptr;
 #define QB_OCC(MD, UU, BB) \
     if (mode == MD && unit == UU && bs == BB) fn = reinterpret_cast<const void *>(&k5<MD, UU, BB>);
@@ -717,6 +758,7 @@ int k5_occupancy(qbsm_mode mode, int unit, int bs) {
 #define QB_OCC_256(MD) QB_OCC(MD, 256, 0) QB_OCC(MD, 256, 64) QB_OCC(MD, 256, 128)
     QB_OCC_M(QBSM_F64) QB_OCC_M(QBSM_F32) QB_OCC_M(QBSM_BF16) QB_OCC_M(QBSM_BF16X3)
     QB_OCC_256(QBSM_F32) QB_OCC_256(QBSM_BF16) QB_OCC_256(QBSM_BF16X3)
+    QB_OCC(QBSM_OZAKI_BF16, 64, 0) QB_OCC(QBSM_OZAKI_BF16, 64, 32) QB_OCC(QBSM_OZAKI_BF16, 64, 64)
 #undef QB_OCC_256
 #undef QB_OCC_M
 #undef QB_OCC
@@ -776,10 +818,11 @@ void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s)
     plan_check_current(p);
     QB_CHECK(!(mode == QBSM_F64 && p.unit >= 256), QBSM_ERR_UNSUPPORTED,
              "unit 256 serves the FP32-accumulating modes only");
+    QB_CHECK(mode != QBSM_OZAKI_BF16 || p.unit == 64, QBSM_ERR_UNSUPPORTED, "the Ozaki mode runs at unit 64");
     QB_CHECK(&out != p.L && &out != p.R && &out != p.M, QBSM_ERR_ARG, "output aliases an operand");
     QB_CHECK(out.nrows == p.out_rows && out.ncols == p.out_cols && out.bs == p.bs, QBSM_ERR_SHAPE,
              "output shape or leaf size differs from the product");
-    const Storage want = mode == QBSM_F64 ? ST_F64 : ST_F32;
+    const Storage want = mode == QBSM_F64 || mode == QBSM_OZAKI_BF16 ? ST_F64 : ST_F32;
     const int64_t nout = p.nout;
     // the same plan refilling its own output: pattern and storage are already in place
     // (masked outputs keep their zero blocks: only the plan's products are rewritten)

@@ -19,8 +19,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqbsm.so")
 
-F64, F32, BF16, BF16X3 = 0, 1, 2, 3
-MODES = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3}
+F64, F32, BF16, BF16X3, OZAKI_BF16 = 0, 1, 2, 3, 4
+MODES = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3, "ozaki": OZAKI_BF16}
 MODE_NAMES = {v: k for k, v in MODES.items()}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "invalid block pattern",

@@ -5,7 +5,10 @@ import torch
 from oracle import oracle as O
 
 # relative Frobenius tolerances against the FP64 oracle on the original inputs
-TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2, "bf16x3": 1e-4}
+TOL = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2, "bf16x3": 1e-4, "ozaki": 1e-11}
+# Ozaki mode against the oracle's own Ozaki splitting and product: the slice
+# products are exact on both sides, only the FP64 accumulation order differs
+TOL_OZAKI_EMULATED = 1e-13
 # BF16: against the FP64 oracle applied to the bf16-rounded inputs (isolates
 # the FP32 accumulation)
 TOL_BF16_ROUNDED = 1e-5
@@ -15,6 +18,8 @@ UNITS = {32: (64, 128), 64: (64, 128, 256), 128: (128, 256)}
 
 
 def units(bs, mode):
+    if mode == "ozaki":
+        return (64,) if bs <= 64 else ()
     return tuple(u for u in UNITS[bs] if not (u == 256 and mode == "f64"))
 
 

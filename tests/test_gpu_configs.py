@@ -56,6 +56,8 @@ def test_config2_decay_full(q):
         got = sampled_values(P.numeric(mode), si, sj)
         err = O.rel_fro(got, ref)
         assert err <= TOL[mode], (mode, err)
+    got = sampled_values(q.Plan(A, A, unit=64).numeric("ozaki"), si, sj)
+    assert O.rel_fro(got, ref) <= TOL["ozaki"], O.rel_fro(got, ref)
 
 
 def test_config3_random_blocks_full(q):

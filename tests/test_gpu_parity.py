@@ -11,7 +11,8 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_11762_amd import workloads as W
-from tests.gpu_helpers import TOL, check_product, padding_is_zero, pattern_np, units, upload, values_np
+from tests.gpu_helpers import (TOL, TOL_OZAKI_EMULATED, check_product, padding_is_zero, pattern_np, units,
+                               upload, values_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -380,3 +381,75 @@ def test_square_packs_both_roles_at_once(q, bs):
     got = values_np(q.matmul(B1, B1, "f32", unit=max(units(bs, "f32"))))
     refb = O.multiply(O.from_workload(b), O.from_workload(b)).vals
     assert np.array_equal(np.isnan(got), np.isnan(refb))
+
+
+OZAKI_CASES = [
+    (300, 260, 200, 64, 0.5, 81),
+    (190, 170, 150, 32, 0.5, 82),
+    (1000, 900, 1100, 32, 0.15, 83),
+    (64 * 9 + 5, 64 * 7, 64 * 11 + 63, 64, 0.3, 84),
+]
+
+
+@pytest.mark.parametrize("case", OZAKI_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-bs{c[3]}")
+def test_ozaki_against_oracle_split(q, case):
+    """Ozaki mode: FP64 result within the stated tolerance of the FP64 oracle
+    and within rounding of the oracle's own Ozaki emulation."""
+    m, k, n, bs, p, seed = case
+    a, b = W.small_random(m, k, n, bs, p, seed)
+    C, ref, err, got = check_product(q, a, b, "ozaki", 64)
+    assert C.values().dtype == torch.float64
+    oz = O.ozaki_multiply(O.from_workload(a), O.from_workload(b))
+    assert O.rel_fro(got, oz.vals) <= TOL_OZAKI_EMULATED
+    assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
+
+
+def test_ozaki_wide_dynamic_range(q):
+    """Blocks scaled over 40 decades: the per-leaf-line exponents keep the
+    relative accuracy of every block."""
+    a, b = W.small_random(640, 640, 640, 64, 0.6, 85)
+    rng = np.random.default_rng(85)
+    a.vals *= np.exp(rng.uniform(-46, 46, (a.vals.shape[0], 1)))
+    b.vals *= np.exp(rng.uniform(-46, 46, (b.vals.shape[0], 1)))
+    C, ref, err, got = check_product(q, a, b, "ozaki", 64)
+    oz = O.ozaki_multiply(O.from_workload(a), O.from_workload(b))
+    assert O.rel_fro(got, oz.vals) <= TOL_OZAKI_EMULATED
+    # block by block, relative to each block's own norm
+    nrm = np.linalg.norm(ref.vals, axis=1)
+    rel = np.linalg.norm(got - ref.vals, axis=1) / np.where(nrm > 0, nrm, 1.0)
+    assert np.max(rel) <= 1e-10
+
+
+def test_ozaki_unit_and_backward(q):
+    a, b = W.small_random(320, 256, 288, 64, 0.5, 86)
+    A, B = upload(q, a), upload(q, b)
+    with pytest.raises(q.QbsmError, match="unit 64"):
+        q.Plan(A, B, unit=128).numeric("ozaki")
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    ref = O.multiply(oa, ob)
+    rng = np.random.default_rng(86)
+    dcv = rng.uniform(-1, 1, size=ref.vals.shape)
+    W.zero_padding(W.BlockMatrix(320, 288, 64, ref.brow, ref.bcol, dcv))
+    odc = O.canonical(320, 288, 64, ref.brow, ref.bcol, dcv)
+    ga, gb = O.backward(oa, ob, odc)
+    dC = q.Matrix(320, 288, 64)
+    dC.set_blocks(torch.from_numpy(ref.brow.astype(np.int32)).cuda(),
+                  torch.from_numpy(ref.bcol.astype(np.int32)).cuda(), torch.from_numpy(dcv).cuda())
+    dA, dB = q.backward(A, B, dC, "ozaki", 64)
+    assert O.rel_fro(values_np(dA), ga) <= TOL["ozaki"]
+    assert O.rel_fro(values_np(dB), gb) <= TOL["ozaki"]
+
+
+def test_ozaki_batched(q):
+    rng = np.random.default_rng(87)
+    members = [W.small_random(n, n, n, bs, 0.4, 300 + t) for t, (n, bs) in
+               enumerate([(700, 32), (1000, 64), (513, 64)])]
+    plans = [q.Plan(upload(q, a), upload(q, b), unit=64) for a, b in members]
+    singles = [values_np(p.numeric("ozaki")) for p in plans]
+    batch = q.Batch(plans, "ozaki")
+    batch.run()
+    torch.cuda.synchronize()
+    for o, s_, (a, b) in zip(batch.outs, singles, members):
+        assert np.array_equal(values_np(o), s_)
+        ref = O.multiply(O.from_workload(a), O.from_workload(b))
+        assert O.rel_fro(s_, ref.vals) <= TOL["ozaki"]
