@@ -31,12 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "effective GFLOP/s on nonzero leaf products, plain FP64 vs chosen form at stated error"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
-MFMA_TERMS = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3}
-DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16"}
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "ozaki": 2500.0}
+MFMA_TERMS = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3, "ozaki": 21}
+DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16", "ozaki": "bf16"}
 # bytes per element of the packed operands and of the result, per mode
-OPERAND_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4}
-RESULT_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "bf16x3": 4}
+OPERAND_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4, "ozaki": 12}
+RESULT_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "bf16x3": 4, "ozaki": 8}
 KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
 # HBM bytes of one numeric-kernel launch on the default workload, per
 # "mode@unit", from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB
@@ -65,7 +65,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="bf16x3", choices=["f64", "f32", "bf16", "bf16x3"])
+    ap.add_argument("--mode", default="bf16x3", choices=["f64", "f32", "bf16", "bf16x3", "ozaki"])
     ap.add_argument("--unit", type=int, default=0,
                     help="work-unit side; 0 = chosen per mode by the library's autotuner before timing")
     ap.add_argument("--npoints", type=int, default=16384)
