@@ -136,6 +136,23 @@ qbsm_status qbsm_matrix_set_blocks(qbsm_matrix m, int64_t nblk, const int32_t *b
  * values; readback widens them exactly.  No effect on an FP32-stored matrix. */
 qbsm_status qbsm_matrix_store_f32(qbsm_matrix m, void *stream);
 
+/* Packs the matrix's current values for the numeric phase of `mode` ahead of
+ * use, so that the packing runs while the symbolic phase is still being
+ * worked out (Sec. 2.1: the task templates leave scheduling to the runtime,
+ * and the operand preparation of a multiply does not depend on its symbolic
+ * phase).
+ *   roles : 1 = as a left operand (row lines), 2 = as a right operand
+ *           (column lines), 3 = both (A * A).  A transposed use swaps them.
+ * The packing kernels run on a library-owned stream (one per device, default
+ * priority) that first waits for everything already queued on `stream`; the
+ * pack memory is taken on `stream`.  Nothing is synchronised.  Every later
+ * use of the packs (numeric phase, batch creation and runs, on any stream)
+ * waits for them, and replacing or freeing the matrix's values
+ * (set_blocks, store_f32, destroy, use as a numeric output) first orders the
+ * affected streams after them.  Packs that are already current are left
+ * alone.  Errors: QBSM_ERR_STATE without blocks, QBSM_ERR_ARG for bad roles. */
+qbsm_status qbsm_matrix_prepack(qbsm_matrix m, qbsm_mode mode, int32_t roles, void *stream);
+
 /* Shape and stored-block count (host outs; any may be NULL). */
 qbsm_status qbsm_matrix_info(qbsm_matrix m, int64_t *nrows, int64_t *ncols, int32_t *bs,
                              int64_t *nblk);

@@ -175,7 +175,10 @@ qbsm_status qbsm_matrix_create(int64_t nrows, int64_t ncols, int32_t bs, qbsm_ma
 }
 
 qbsm_status qbsm_matrix_destroy(qbsm_matrix m) {
-    return guard([&] { delete m; });
+    return guard([&] {
+        if (m) matrix_settle(m->m, m->m.v64.p ? m->m.v64.s : m->m.v32.s);
+        delete m;
+    });
 }
 
 qbsm_status qbsm_matrix_set_blocks(qbsm_matrix m, int64_t nblk, const int32_t *brow, const int32_t *bcol,
@@ -192,6 +195,14 @@ qbsm_status qbsm_matrix_store_f32(qbsm_matrix m, void *stream) {
         QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
         QB_CHECK(m->m.has_blocks, QBSM_ERR_STATE, "matrix has no blocks yet");
         matrix_store_f32(m->m, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_matrix_prepack(qbsm_matrix m, qbsm_mode mode, int32_t roles, void *stream) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        matrix_prepack(m->m, mode, roles, as_stream(stream));
     });
 }
 
@@ -385,6 +396,7 @@ qbsm_status qbsm_batch_set_occupancy(qbsm_batch batch, int32_t wg_per_cu) {
 qbsm_status qbsm_batch_run(qbsm_batch batch, void *stream) {
     return guard([&] {
         QB_CHECK(batch, QBSM_ERR_ARG, "null batch");
+        batch_settle(batch->b, as_stream(stream));
         batch_launch(batch->b, as_stream(stream));
     });
 }
@@ -395,6 +407,7 @@ qbsm_status qbsm_batch_run_graph(qbsm_batch batch, void *stream) {
         QB_CHECK(stream, QBSM_ERR_ARG, "graph capture needs a non-null stream");
         Batch &b = batch->b;
         hipStream_t s = as_stream(stream);
+        batch_settle(b, s);  // outside any capture
         if (!b.exec) {
             QB_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {

@@ -133,6 +133,17 @@ struct Pack {
     DArr<int32_t> nonfinite;  // [1]: set by the pack kernel when a packed value is Inf or NaN
     DArr<int32_t> aux;        // Ozaki mode: exponent of every packed line [nblk * bs]
     uint64_t version = 0;
+    // A pack made ahead of use runs on the library's side stream and records
+    // this event; until a stream has waited for it, the buffers may still be
+    // being written.
+    hipEvent_t ready = nullptr;
+    Pack() = default;
+    Pack(const Pack &) = delete;
+    Pack &operator=(const Pack &) = delete;
+    ~Pack();
+    // Orders s (and the streams the buffers were taken on) after a pending
+    // pack, then forgets the event.
+    void settle(hipStream_t s);
 };
 
 struct Matrix {
@@ -209,6 +220,15 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s);
 // Brings both packs (row and column lines) of m up to date in one pass when
 // both are stale; otherwise leaves them to matrix_pack.
 void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s);
+// Packs ahead of use on the side stream (roles: bit 0 row lines, bit 1
+// column lines), after the work queued on s; buffers are taken on s.
+void matrix_prepack(Matrix &m, qbsm_mode mode, int roles, hipStream_t s);
+// Orders s, and the streams of m's value arrays, after every pending pack of
+// m; called before m's values or packs are replaced or freed.
+void matrix_settle(Matrix &m, hipStream_t s);
+// The library's stream for work made ahead of use (one per device, default
+// priority, created on first use).
+hipStream_t side_stream();
 int mode_bk(qbsm_mode mode, int bs);
 
 void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
@@ -255,6 +275,8 @@ struct Batch {
 };
 
 void batch_launch(Batch &b, hipStream_t s);
+// Orders s after pending packs of the batch's operands (call outside capture).
+void batch_settle(Batch &b, hipStream_t s);
 void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s);
 void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t nmembers_host_unused,
                const int2 *items, int64_t nitems, int32_t *counter, int grid, int persistent,

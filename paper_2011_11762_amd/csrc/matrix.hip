@@ -1,6 +1,9 @@
 // Matrix handles: construction from leaf blocks, block truncation, the
 // sparse quadtree (Morton-ordered node tables), readback and operand packing.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <type_traits>
 
 #include "common.h"
 #include "device_math.h"
@@ -52,35 +55,47 @@ __global__ void k_keys(const int32_t *brow, const int32_t *bcol, int64_t n, int6
 }
 
 // FP64 Frobenius norm of the logical part of each block; keep iff not (norm < tol).
-__global__ void __launch_bounds__(256) k_norm_keep(const double *vals, const int32_t *brow,
+__global__ void __launch_bounds__(256) k_norm_keep(const double *__restrict__ vals, const int32_t *brow,
                                                    const int32_t *bcol, const uint8_t *valid,
                                                    int64_t n, int32_t bs, int64_t nrows,
                                                    int64_t ncols, double tol, uint8_t *keep) {
-    int64_t t = blockIdx.x;
+    const int64_t t = blockIdx.x;
     if (t >= n) return;
-    __shared__ double red[256];
+    __shared__ double red[4];
     double s = 0.0;
-    if (valid[t]) {
+    const bool ok = valid[t] != 0;
+    if (ok) {
         const int64_t mr = min((int64_t)bs, nrows - (int64_t)brow[t] * bs);
         const int64_t nc = min((int64_t)bs, ncols - (int64_t)bcol[t] * bs);
-        const double *x = vals + t * (int64_t)bs * bs;
-        const int r = threadIdx.x % bs;  // bs <= 128 divides 256
-        for (int c = threadIdx.x / bs; c < bs; c += 256 / bs) {
-            if (r < mr && c < nc) {
-                double v = x[r + (int64_t)c * bs];
-                s += v * v;
+        const int64_t n2 = (int64_t)bs * bs;
+        const double *x = vals + t * n2;
+        if (mr == bs && nc == bs && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+            // whole aligned block: 16-byte loads, several in flight per thread
+            const double2 *x2 = reinterpret_cast<const double2 *>(x);
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll 8
+            for (int64_t e = threadIdx.x; e < n2 / 2; e += 256) {
+                const double2 v = x2[e];
+                s0 += v.x * v.x;
+                s1 += v.y * v.y;
+            }
+            s = s0 + s1;
+        } else {
+            const int r = threadIdx.x % bs;  // bs <= 128 divides 256
+            for (int c = threadIdx.x / bs; c < bs; c += 256 / bs) {
+                if (r < mr && c < nc) {
+                    const double v = x[r + (int64_t)c * bs];
+                    s += v * v;
+                }
             }
         }
     }
-    red[threadIdx.x] = s;
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        double nrm = sqrt(red[0]);
-        keep[t] = (valid[t] && !(nrm < tol)) ? 1 : 0;
+        const double nrm = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+        keep[t] = (ok && !(nrm < tol)) ? 1 : 0;
     }
 }
 
@@ -90,10 +105,10 @@ __global__ void k_copy_flags(const uint8_t *valid, int64_t n, uint8_t *keep) {
 }
 
 // Scatter kept blocks into Morton order, zeroing the padding.
-__global__ void __launch_bounds__(256) k_store_blocks(const double *vals, const int32_t *brow,
+__global__ void __launch_bounds__(256) k_store_blocks(const double *__restrict__ vals, const int32_t *brow,
                                                       const int32_t *bcol, const uint32_t *keys,
                                                       const int32_t *rank, int64_t n, int32_t bs,
-                                                      int64_t nrows, int64_t ncols, double *pool,
+                                                      int64_t nrows, int64_t ncols, double *__restrict__ pool,
                                                       uint32_t *okeys) {
     int64_t t = blockIdx.x;
     if (t >= n) return;
@@ -104,9 +119,23 @@ __global__ void __launch_bounds__(256) k_store_blocks(const double *vals, const 
     const int64_t n2 = (int64_t)bs * bs;
     const double *x = vals + t * n2;
     double *y = pool + (int64_t)r * n2;
-    if (mr == bs && nc == bs) {
-        for (int64_t e = threadIdx.x; e < n2 / 2; e += 256)
-            reinterpret_cast<double2 *>(y)[e] = reinterpret_cast<const double2 *>(x)[e];
+    if (mr == bs && nc == bs && (reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+        // whole aligned block: groups of 8 16-byte loads in flight before their stores
+        const double2 *x2 = reinterpret_cast<const double2 *>(x);
+        double2 *y2 = reinterpret_cast<double2 *>(y);
+        constexpr int G = 8;
+        if ((n2 / 2) % (256 * G) == 0) {
+            // unconditional loads, so that all G are in flight together
+            for (int64_t b0 = 0; b0 < n2 / 2; b0 += 256 * G) {
+                double2 v[G];
+#pragma unroll
+                for (int q = 0; q < G; ++q) v[q] = x2[b0 + q * 256 + threadIdx.x];
+#pragma unroll
+                for (int q = 0; q < G; ++q) y2[b0 + q * 256 + threadIdx.x] = v[q];
+            }
+        } else {
+            for (int64_t e = threadIdx.x; e < n2 / 2; e += 256) y2[e] = x2[e];
+        }
     } else {
         const int rr = threadIdx.x % bs;
         for (int cc = threadIdx.x / bs; cc < bs; cc += 256 / bs) {
@@ -123,27 +152,51 @@ __global__ void k_narrow(const double *x, float *y, int64_t n) {
     for (; i < n; i += stride) y[i] = (float)x[i];
 }
 
-// ---- quadtree build: one level from its children level
-__global__ void k_tree_flags(const uint32_t *ckeys, const int64_t *ncount, int64_t cap, int32_t *flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cap) return;
-    int64_t n = *ncount;
-    int32_t f = 0;
-    if (i < n) f = (i == 0 || (ckeys[i] >> 2) != (ckeys[i - 1] >> 2)) ? 1 : 0;
-    flags[i] = f;
+// ---- quadtree build, all levels at once.  The leaves are stored in Morton
+// order, so the nodes of level l are the runs of equal key prefixes
+// key >> 2(D - l) over the leaves, numbered in order.  One pass flags the
+// first leaf of every node of every level, one scan over all levels numbers
+// them, and one pass writes node keys and child links.
+struct LevelPtrs {
+    uint32_t *key[17];
+    int32_t *child[17];
+};
+
+__global__ void k_tree_flags_all(const uint32_t *lkeys, int64_t n, int D, LevelPtrs lp, int32_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t k = lkeys[i];
+    const uint32_t kp = i ? lkeys[i - 1] : 0u;
+    for (int l = 0; l < D; ++l) {
+        const int sh = 2 * (D - l);
+        flags[(int64_t)l * n + i] = (i == 0 || (k >> sh) != (kp >> sh)) ? 1 : 0;
+        // every slot starts nil; the link pass (a later launch) fills the live ones
+        reinterpret_cast<int4 *>(lp.child[l])[i] = make_int4(-1, -1, -1, -1);
+    }
 }
 
-__global__ void k_tree_link(const uint32_t *ckeys, const int64_t *ncount, int64_t cap,
-                            const int32_t *scan, uint32_t *pkeys, int32_t *child) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= cap) return;
-    int64_t n = *ncount;
+__global__ void k_tree_link_all(const uint32_t *lkeys, int64_t n, int D, LevelPtrs lp, const int32_t *flags,
+                                const int32_t *scan, int64_t *counts) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // parent index = number of parent starts at or before i, minus one
-    bool start = (i == 0 || (ckeys[i] >> 2) != (ckeys[i - 1] >> 2));
-    int32_t p = scan[i] + (start ? 1 : 0) - 1;
-    if (start) pkeys[p] = ckeys[i] >> 2;
-    child[(int64_t)p * 4 + (ckeys[i] & 3u)] = (int32_t)i;
+    const uint32_t k = lkeys[i];
+    lp.key[D][i] = k;
+    // node of leaf i at level l: the number of level-l starts at or before i, minus one
+    int32_t below = (int32_t)i;  // the leaf itself at level D
+    for (int l = D - 1; l >= 0; --l) {
+        const int64_t f = (int64_t)l * n + i;
+        const int32_t start = flags[f];
+        const int32_t node = scan[f] - scan[(int64_t)l * n] + start - 1;
+        const int sh = 2 * (D - l);
+        if (start) lp.key[l][node] = k >> sh;
+        const bool child_start = l + 1 == D || flags[f + n];
+        if (child_start) lp.child[l][(int64_t)node * 4 + ((k >> (sh - 2)) & 3u)] = below;
+        below = node;
+    }
+    if (i == 0) {
+        for (int l = 0; l < D; ++l) counts[l] = scan[(int64_t)(l + 1) * n] - scan[(int64_t)l * n];
+        counts[D] = n;
+    }
 }
 
 __global__ void k_desc2(const int32_t *child_hi, const int32_t *child_lo, int64_t n, int32_t *desc) {
@@ -318,21 +371,23 @@ __global__ void __launch_bounds__(256) k_pack2(const Src *src, int32_t bk, uint8
     constexpr int PARTS = MODE == QBSM_BF16X3 ? 2 : 1;
     constexpr int bs = BS;
     constexpr int64_t n2 = (int64_t)BS * BS;
-    static_assert(n2 % 256 == 0, "whole leaf rounds");
+    static_assert(n2 % 512 == 0, "whole leaf rounds of 16-byte loads");
     // the leaf in LDS with a column stride of bs + 1 doubles: the row-line
     // reads (consecutive rows) and the column-line reads (consecutive pieces
     // and columns) then fall on distinct banks
     constexpr int ld = BS + 1;
     __shared__ double x[ld * BS];
     const int64_t leaf = blockIdx.x;
-    const Src *g = src + leaf * n2;
-    Src t[n2 / 256];
+    using Src2 = typename std::conditional<std::is_same<Src, double>::value, double2, float2>::type;
+    const Src2 *g = reinterpret_cast<const Src2 *>(src + leaf * n2);
+    Src2 t[n2 / 512];
 #pragma unroll
-    for (int q = 0; q < n2 / 256; ++q) t[q] = g[threadIdx.x + 256 * q];  // all loads in flight at once
+    for (int q = 0; q < n2 / 512; ++q) t[q] = g[threadIdx.x + 256 * q];  // all loads in flight at once
 #pragma unroll
-    for (int q = 0; q < n2 / 256; ++q) {
-        const int i = threadIdx.x + 256 * q;
-        x[(i % BS) + (i / BS) * ld] = (double)t[q];
+    for (int q = 0; q < n2 / 512; ++q) {
+        const int i = 2 * (threadIdx.x + 256 * q);  // i and i + 1 lie in one column (BS even)
+        x[(i % BS) + (i / BS) * ld] = (double)t[q].x;
+        x[(i % BS) + 1 + (i / BS) * ld] = (double)t[q].y;
     }
     __syncthreads();
     const int LB = bk * EB;
@@ -342,16 +397,10 @@ __global__ void __launch_bounds__(256) k_pack2(const Src *src, int32_t bk, uint8
     for (int r = threadIdx.x; r < 2 * per_role; r += 256) {
         const bool col = r >= per_role;
         const int rem = col ? r - per_role : r;
-        int c, l, piece;
-        if (col) {
-            piece = rem % ppl;
-            l = (rem / ppl) % bs;
-            c = rem / (ppl * bs);
-        } else {
-            l = rem % bs;
-            piece = (rem / bs) % ppl;
-            c = rem / (bs * ppl);
-        }
+        // consecutive threads write consecutive 16-byte pieces of the pack
+        const int piece = rem % ppl;
+        const int l = (rem / ppl) % bs;
+        const int c = rem / (ppl * bs);
         const int k0 = c * bk + piece * EPP;
         double v[EPP];
 #pragma unroll
@@ -476,6 +525,7 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     QB_CHECK(n == 0 || (brow && bcol && vals), QBSM_ERR_ARG, "null block arrays");
     QB_CHECK(!(drop_tol < 0.0) && !std::isnan(drop_tol), QBSM_ERR_ARG, "drop_tol must be >= 0");
     QB_CHECK(n <= (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many blocks");
+    matrix_settle(m, s);  // a pack made ahead may still read the old values
     DArr<SetStatus> st(1, s);
     QB_HIP(hipMemsetAsync(st.p, 0, sizeof(SetStatus), s));
     DArr<uint32_t> keys(n ? n : 1, s);
@@ -527,6 +577,7 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
 
 void matrix_store_f32(Matrix &m, hipStream_t s) {
     if (m.storage != ST_F64) return;
+    matrix_settle(m, s);
     const int64_t n = m.nblk * (int64_t)m.bs * m.bs;
     DArr<float> v(n ? n : 1, s);
     if (n) {
@@ -549,33 +600,32 @@ Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
     t->n.assign(D + 1, 0);
     t->child.resize(D);
     t->key.resize(D + 1);
-    const int64_t cap = m.nblk;
-    DArr<int64_t> counts(D + 1, s);
-    // level D: the leaves themselves (storage order is Morton order)
-    t->key[D].alloc(cap ? cap : 1, s);
-    if (cap)
-        QB_HIP(hipMemcpyAsync(t->key[D].p, m.keys.p, cap * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-    int64_t nleaf = cap;
-    QB_HIP(hipMemcpyAsync(counts.p + D, &nleaf, sizeof(int64_t), hipMemcpyHostToDevice, s));
-    DArr<int32_t> flags(cap ? cap : 1, s), scan((cap ? cap : 1) + 1, s);
-    for (int l = D - 1; l >= 0; --l) {
+    const int64_t cap = m.nblk;  // nodes of any level <= leaves
+    QB_CHECK(D <= 16, QBSM_ERR_UNSUPPORTED, "block grid side above 65536");
+    QB_CHECK((int64_t)D * cap < (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many leaves for the tree build");
+    LevelPtrs lp{};
+    for (int l = 0; l <= D; ++l) {
         t->key[l].alloc(cap ? cap : 1, s);
-        t->child[l].alloc((cap ? cap : 1) * 4, s);
-        fill_i32(t->child[l].p, -1, (cap ? cap : 1) * 4, s);
-        if (cap) {
-            k_tree_flags<<<grid_for(cap, 256), 256, 0, s>>>(t->key[l + 1].p, counts.p + l + 1, cap, flags.p);
-            QB_LAUNCH_CHECK();
-            exclusive_scan_i32(flags.p, scan.p, cap, counts.p + l, s);
-            k_tree_link<<<grid_for(cap, 256), 256, 0, s>>>(t->key[l + 1].p, counts.p + l + 1, cap, scan.p,
-                                                           t->key[l].p, t->child[l].p);
-            QB_LAUNCH_CHECK();
-        } else {
-            int64_t zero = 0;
-            QB_HIP(hipMemcpyAsync(counts.p + l, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        lp.key[l] = t->key[l].p;
+        if (l < D) {
+            t->child[l].alloc((cap ? cap : 1) * 4, s);
+            lp.child[l] = t->child[l].p;
         }
     }
-    QB_HIP(hipMemcpyAsync(t->n.data(), counts.p, (D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    QB_HIP(hipStreamSynchronize(s));
+    if (cap && D > 0) {
+        DArr<int64_t> counts(D + 1, s);
+        DArr<int32_t> flags(D * cap, s), scan(D * cap + 1, s);
+        k_tree_flags_all<<<grid_for(cap, 256), 256, 0, s>>>(m.keys.p, cap, D, lp, flags.p);
+        QB_LAUNCH_CHECK();
+        exclusive_scan_i32(flags.p, scan.p, D * cap, nullptr, s);
+        k_tree_link_all<<<grid_for(cap, 256), 256, 0, s>>>(m.keys.p, cap, D, lp, flags.p, scan.p, counts.p);
+        QB_LAUNCH_CHECK();
+        QB_HIP(hipMemcpyAsync(t->n.data(), counts.p, (D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+    } else if (cap) {  // D == 0: a single leaf is the root
+        QB_HIP(hipMemcpyAsync(t->key[0].p, m.keys.p, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        t->n[0] = cap;
+    }
     Tree &ref = *t;
     m.trees[D] = std::move(t);
     return ref;
@@ -701,30 +751,19 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
     QB_LAUNCH_CHECK();
 }
 
-void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
+// Both packs from one pass (k_pack2) on stream ks; buffers already sized.
+void pack2_launch(Matrix &m, qbsm_mode mode, Pack &pr, Pack &pc, hipStream_t ks) {
     const int bs = m.bs;
-    const int64_t n2 = (int64_t)bs * bs;
-    const size_t bytes = (size_t)m.nblk * n2 * mode_elem_bytes(mode) * mode_parts(mode);
-    Pack &pr = m.packs[std::make_pair((int)mode, (int)ROLE_ROW)];
-    Pack &pc = m.packs[std::make_pair((int)mode, (int)ROLE_COL)];
-    const bool stale_r = pr.buf.n != bytes || pr.version != m.version || !pr.buf.p;
-    const bool stale_c = pc.buf.n != bytes || pc.version != m.version || !pc.buf.p;
-    if (!stale_r || !stale_c || (bs != 32 && bs != 64) || m.nblk == 0 || mode == QBSM_OZAKI_BF16)
-        return;  // per-role packs do the rest
-    if (pr.buf.n != bytes) pr.buf.alloc(bytes, s);
-    if (pc.buf.n != bytes) pc.buf.alloc(bytes, s);
-    if (!pr.nonfinite.p) pr.nonfinite.alloc(1, s);
-    if (!pc.nonfinite.p) pc.nonfinite.alloc(1, s);
     const int bk = mode_bk(mode, bs);
-    ProfScope prof(PROF_PACK, s);
-    fill_i32(pr.nonfinite.p, 0, 1, s);
-    fill_i32(pc.nonfinite.p, 0, 1, s);
+    ProfScope prof(PROF_PACK, ks);
+    fill_i32(pr.nonfinite.p, 0, 1, ks);
+    fill_i32(pc.nonfinite.p, 0, 1, ks);
     const unsigned g = (unsigned)m.nblk;
 #define QB_PACK2(SRC, PTR, MODE)                                                                          \
     if (bs == 32)                                                                                         \
-        k_pack2<SRC, MODE, 32><<<g, 256, 0, s>>>(PTR, bk, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p); \
+        k_pack2<SRC, MODE, 32><<<g, 256, 0, ks>>>(PTR, bk, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p); \
     else                                                                                                  \
-        k_pack2<SRC, MODE, 64><<<g, 256, 0, s>>>(PTR, bk, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p)
+        k_pack2<SRC, MODE, 64><<<g, 256, 0, ks>>>(PTR, bk, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p)
     if (m.storage == ST_F64) {
         switch (mode) {
             case QBSM_F64: QB_PACK2(double, m.v64.p, QBSM_F64); break;
@@ -744,8 +783,118 @@ void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
     }
 #undef QB_PACK2
     QB_LAUNCH_CHECK();
+}
+
+namespace {
+size_t pack_bytes(const Matrix &m, qbsm_mode mode) {
+    return (size_t)m.nblk * m.bs * m.bs * mode_elem_bytes(mode) * mode_parts(mode);
+}
+bool pack_stale(const Matrix &m, qbsm_mode mode, const Pack &pk) {
+    return pk.buf.n != pack_bytes(m, mode) || pk.version != m.version || !pk.buf.p;
+}
+bool pair_ok(const Matrix &m, qbsm_mode mode) {
+    return (m.bs == 32 || m.bs == 64) && m.nblk > 0 && mode != QBSM_OZAKI_BF16;
+}
+// Sizes the buffers of a stale pack (memory taken on s).
+void pack_size(const Matrix &m, qbsm_mode mode, Pack &pk, hipStream_t s) {
+    const size_t bytes = pack_bytes(m, mode);
+    if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
+    if (!pk.nonfinite.p) pk.nonfinite.alloc(1, s);
+    if (mode == QBSM_OZAKI_BF16 && pk.aux.n != (size_t)(m.nblk * m.bs))
+        pk.aux.alloc(m.nblk * m.bs ? m.nblk * m.bs : 1, s);
+}
+}  // namespace
+
+void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s) {
+    Pack &pr = m.packs[std::make_pair((int)mode, (int)ROLE_ROW)];
+    Pack &pc = m.packs[std::make_pair((int)mode, (int)ROLE_COL)];
+    pr.settle(s);
+    pc.settle(s);
+    if (!pack_stale(m, mode, pr) || !pack_stale(m, mode, pc) || !pair_ok(m, mode))
+        return;  // per-role packs do the rest
+    pack_size(m, mode, pr, s);
+    pack_size(m, mode, pc, s);
+    pack2_launch(m, mode, pr, pc, s);
     pr.version = m.version;
     pc.version = m.version;
+}
+
+void Pack::settle(hipStream_t s) {
+    if (!ready) return;
+    QB_HIP(hipStreamWaitEvent(s, ready, 0));
+    if (buf.p && buf.s != s) QB_HIP(hipStreamWaitEvent(buf.s, ready, 0));
+    if (nonfinite.p && nonfinite.s != s) QB_HIP(hipStreamWaitEvent(nonfinite.s, ready, 0));
+    if (aux.p && aux.s != s) QB_HIP(hipStreamWaitEvent(aux.s, ready, 0));
+    (void)hipEventDestroy(ready);
+    ready = nullptr;
+}
+
+Pack::~Pack() {
+    if (!ready) return;
+    // the buffers are returned on their own streams: those wait for the pack
+    if (buf.p) (void)hipStreamWaitEvent(buf.s, ready, 0);
+    if (nonfinite.p) (void)hipStreamWaitEvent(nonfinite.s, ready, 0);
+    if (aux.p) (void)hipStreamWaitEvent(aux.s, ready, 0);
+    (void)hipEventDestroy(ready);
+}
+
+void matrix_settle(Matrix &m, hipStream_t s) {
+    for (auto &kv : m.packs) {
+        Pack &pk = kv.second;
+        if (!pk.ready) continue;
+        // the pack kernel reads the values: their next free waits for it too
+        if (m.v64.p) QB_HIP(hipStreamWaitEvent(m.v64.s, pk.ready, 0));
+        if (m.v32.p) QB_HIP(hipStreamWaitEvent(m.v32.s, pk.ready, 0));
+        pk.settle(s);
+    }
+}
+
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    int dev = 0;
+    QB_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    hipStream_t &st = streams[dev];
+    if (!st) QB_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));  // default priority
+    return st;
+}
+
+void matrix_prepack(Matrix &m, qbsm_mode mode, int roles, hipStream_t s) {
+    QB_CHECK(m.has_blocks, QBSM_ERR_STATE, "matrix has no blocks yet");
+    QB_CHECK(roles >= 1 && roles <= 3, QBSM_ERR_ARG, "roles must be 1 (row lines), 2 (column lines) or 3");
+    if (m.nblk == 0) return;
+    Pack *pk[2] = {nullptr, nullptr};
+    bool stale[2] = {false, false};
+    for (int r = 0; r < 2; ++r) {
+        if (!(roles & (1 << r))) continue;
+        pk[r] = &m.packs[std::make_pair((int)mode, r == 0 ? (int)ROLE_ROW : (int)ROLE_COL)];
+        pk[r]->settle(s);
+        stale[r] = pack_stale(m, mode, *pk[r]);
+    }
+    if (!stale[0] && !stale[1]) return;
+    for (int r = 0; r < 2; ++r)
+        if (stale[r]) pack_size(m, mode, *pk[r], s);
+    // the side stream starts after everything queued on s so far (the values
+    // and the buffers just taken)
+    const hipStream_t side = side_stream();
+    hipEvent_t start = nullptr;
+    QB_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    QB_HIP(hipEventRecord(start, s));
+    QB_HIP(hipStreamWaitEvent(side, start, 0));
+    (void)hipEventDestroy(start);
+    if (stale[0] && stale[1] && pair_ok(m, mode)) {
+        pack2_launch(m, mode, *pk[0], *pk[1], side);
+    } else {
+        for (int r = 0; r < 2; ++r)
+            if (stale[r]) pack_launch(m, mode, r == 0 ? ROLE_ROW : ROLE_COL, *pk[r], side);
+    }
+    for (int r = 0; r < 2; ++r) {
+        if (!stale[r]) continue;
+        QB_HIP(hipEventCreateWithFlags(&pk[r]->ready, hipEventDisableTiming));
+        QB_HIP(hipEventRecord(pk[r]->ready, side));
+        pk[r]->version = m.version;
+    }
 }
 
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
@@ -755,11 +904,9 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
     PackView v;
     auto key = std::make_pair((int)mode, (int)role);
     Pack &pk = m.packs[key];
-    const size_t bytes = (size_t)m.nblk * n2 * mode_elem_bytes(mode) * mode_parts(mode);
-    if (pk.buf.n != bytes || pk.version != m.version || !pk.buf.p) {
-        if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
-        if (!pk.nonfinite.p) pk.nonfinite.alloc(1, s);
-        if (mode == QBSM_OZAKI_BF16 && pk.aux.n != (size_t)(m.nblk * bs)) pk.aux.alloc(m.nblk * bs ? m.nblk * bs : 1, s);
+    pk.settle(s);
+    if (pack_stale(m, mode, pk)) {
+        pack_size(m, mode, pk, s);
         pack_launch(m, mode, role, pk, s);
         pk.version = m.version;
     }

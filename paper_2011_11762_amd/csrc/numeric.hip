@@ -826,6 +826,7 @@ void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s)
     const int64_t nout = p.nout;
     // the same plan refilling its own output: pattern and storage are already in place
     // (masked outputs keep their zero blocks: only the plan's products are rewritten)
+    matrix_settle(out, s);  // packs of out made ahead still read its values
     if (out.filled_by == p.id && out.storage == want && out.nblk == nout && out.has_blocks) {
         out.version++;
         return;
@@ -863,6 +864,10 @@ void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------ batched
+void batch_settle(Batch &b, hipStream_t s) {
+    for (auto &j : b.packs) j.m->packs[std::make_pair((int)j.mode, (int)j.role)].settle(s);
+}
+
 void batch_launch(Batch &b, hipStream_t s) {
     for (auto &j : b.packs) {
         Pack &pk = j.m->packs[std::make_pair((int)j.mode, (int)j.role)];

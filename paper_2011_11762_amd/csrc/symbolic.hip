@@ -32,11 +32,20 @@ __device__ __forceinline__ int slot_of(int rowbit, int colbit, int trans) {
     return trans ? (colbit * 2 + rowbit) : (rowbit * 2 + colbit);
 }
 
-__global__ void k_walk_count(int64_t np, const int32_t *pl, const int32_t *pr, const int32_t *gs,
-                             const int32_t *gm, const int32_t *pm, const int32_t *chL, const int32_t *chR,
-                             const int32_t *chM, int transL, int transR, int32_t *X) {
+// The pair count np of the level is read from device memory (the previous
+// level's scan total); the launch covers the level's capacity and the slots
+// beyond 4*np are zeroed, so that the scan over the whole capacity gives the
+// next level's count without a host round trip.
+__global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl, const int32_t *pr,
+                             const int32_t *gs, const int32_t *gm, const int32_t *pm, const int32_t *chL,
+                             const int32_t *chR, const int32_t *chM, int transL, int transR, int32_t *X) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= np * 4) return;
+    const int64_t np = *npp;
+    if (t >= cap4) return;
+    if (t >= np * 4) {
+        X[t] = 0;  // the layout below covers exactly [0, 4*np)
+        return;
+    }
     const int64_t p = t >> 2;
     const int q = (int)(t & 3);
     const int ib = q >> 1, jb = q & 1;
@@ -54,13 +63,13 @@ __global__ void k_walk_count(int64_t np, const int32_t *pl, const int32_t *pr, c
     X[4 * g + (int64_t)q * gm[p] + (p - g)] = cnt;
 }
 
-__global__ void k_walk_fill(int64_t np, const int32_t *pl, const int32_t *pr, const int32_t *gs,
+__global__ void k_walk_fill(const int64_t *npp, const int32_t *pl, const int32_t *pr, const int32_t *gs,
                             const int32_t *gm, const int32_t *pm, const uint32_t *ck, const int32_t *chL,
                             const int32_t *chR, const int32_t *chM, int transL, int transR,
-                            const int32_t *Y, int32_t *opl, int32_t *opr, int32_t *ogs, int32_t *ogm,
-                            int32_t *opm, uint32_t *ock) {
+                            const int32_t *Y, int64_t ocap, int32_t *opl, int32_t *opr, int32_t *ogs,
+                            int32_t *ogm, int32_t *opm, uint32_t *ock) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= np * 4) return;
+    if (t >= *npp * 4) return;
     const int64_t p = t >> 2;
     const int q = (int)(t & 3);
     const int ib = q >> 1, jb = q & 1;
@@ -80,7 +89,7 @@ __global__ void k_walk_fill(int64_t np, const int32_t *pl, const int32_t *pr, co
     for (int kb = 0; kb < 2; ++kb) {
         const int32_t cl = chL[a + slot_of(ib, kb, transL)];
         const int32_t cr = chR[b + slot_of(kb, jb, transR)];
-        if (cl >= 0 && cr >= 0) {
+        if (cl >= 0 && cr >= 0 && o < ocap) {  // o < ocap always; the host checks the count
             opl[o] = cl;
             opr[o] = cr;
             ogs[o] = ngs;
@@ -96,45 +105,120 @@ __global__ void k_walk_root(int32_t *pl, int32_t *pr, int32_t *gs, int32_t *gm, 
     pl[0] = 0; pr[0] = 0; gs[0] = 0; gm[0] = 1; pm[0] = 0; ck[0] = 0u;
 }
 
+// Histogram of the nodes of one tree level by their contraction coordinate
+// (column of a left operand, row of a right one; swapped when transposed).
+__global__ void k_level_hist(const uint32_t *key, int64_t n, int use_col, int32_t *hist) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t k = key[t];
+    uint32_t c = 0;
+    for (int b = 0; b < 16; ++b) c |= ((k >> (2 * b + (use_col ? 0 : 1))) & 1u) << b;
+    atomicAdd(hist + c, 1);
+}
+
+// Pairs of one level without a mask: sum over the contraction coordinate of
+// (left nodes there) * (right nodes there); an upper bound under a mask.
+__global__ void k_level_dot(const int32_t *hL, const int32_t *hR, int64_t n, unsigned long long *cap) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long v = t < n ? (unsigned long long)hL[t] * (unsigned long long)hR[t] : 0ull;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(cap, v);
+}
+
 // Runs the walk from the root to level `target`; returns the pair list there.
-Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s) {
+// Every level is sized beforehand from the node histograms (one host read)
+// and the levels run back to back.  The exact pair count is left on the
+// device in *count (int64); the returned n is its bound (the array size).
+// Without a mask the histogram bound is the exact count.  Under a mask it can
+// be far above it, so a level whose bound exceeds kMaskedBoundPairs reads its
+// exact count back before its arrays are allocated.
+constexpr int64_t kMaskedBoundPairs = int64_t(1) << 20;
+Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int64_t *count, hipStream_t s) {
     Pairs cur;
     const bool empty = tL.n[0] == 0 || tR.n[0] == 0 || (tM && tM->n[0] == 0);
-    cur.alloc(empty ? 0 : 1, s);
-    if (!empty) {
-        k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p);
-        QB_LAUNCH_CHECK();
-    }
-    DArr<int64_t> tot(1, s);
-    for (int l = 0; l < target && cur.n > 0; ++l) {
-        const int64_t np = cur.n;
-        DArr<int32_t> X(np * 4, s), Y(np * 4 + 1, s);
-        const unsigned g = grid_for(np * 4, 256);
-        const int32_t *chM = tM ? tM->child[l].p : nullptr;
-        k_walk_count<<<g, 256, 0, s>>>(np, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, tL.child[l].p,
-                                      tR.child[l].p, chM, transL, transR, X.p);
-        QB_LAUNCH_CHECK();
-        exclusive_scan_i32(X.p, Y.p, np * 4, tot.p, s);
-        const int64_t nn = read_back(tot.p, s);
-        QB_CHECK(nn <= (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many node pairs at one level");
-        Pairs nxt;
-        nxt.alloc(nn, s);
-        if (nn) {
-            k_walk_fill<<<g, 256, 0, s>>>(np, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p,
-                                         tL.child[l].p, tR.child[l].p, chM, transL, transR, Y.p, nxt.pl.p,
-                                         nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
+    if (empty || target == 0) {
+        cur.alloc(empty ? 0 : 1, s);
+        const int64_t c = empty ? 0 : 1;
+        QB_HIP(hipMemcpyAsync(count, &c, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        if (!empty) {
+            k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p);
             QB_LAUNCH_CHECK();
         }
-        cur = std::move(nxt);
+        return cur;
     }
+    // capacities of levels 1..target
+    std::vector<int64_t> hoff(target + 1, 0);
+    for (int l = 1; l <= target; ++l) hoff[l] = hoff[l - 1] + ((int64_t)1 << (l - 1));
+    const int64_t hsize = hoff[target] + ((int64_t)1 << target);
+    DArr<int32_t> hL(hsize, s), hR(hsize, s);
+    DArr<unsigned long long> capd(target + 1, s);
+    fill_bytes_zero(hL.p, hsize * sizeof(int32_t), s);
+    fill_bytes_zero(hR.p, hsize * sizeof(int32_t), s);
+    fill_bytes_zero(capd.p, (target + 1) * sizeof(unsigned long long), s);
+    for (int l = 1; l <= target; ++l) {
+        if (tL.n[l])
+            k_level_hist<<<grid_for(tL.n[l], 256), 256, 0, s>>>(tL.key[l].p, tL.n[l], transL ? 0 : 1, hL.p + hoff[l]);
+        if (tR.n[l])
+            k_level_hist<<<grid_for(tR.n[l], 256), 256, 0, s>>>(tR.key[l].p, tR.n[l], transR ? 1 : 0, hR.p + hoff[l]);
+        const int64_t w = (int64_t)1 << l;
+        k_level_dot<<<grid_for(w, 256), 256, 0, s>>>(hL.p + hoff[l], hR.p + hoff[l], w, capd.p + l);
+    }
+    QB_LAUNCH_CHECK();
+    std::vector<unsigned long long> cap(target + 1, 0);
+    QB_HIP(hipMemcpyAsync(cap.data(), capd.p, (target + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    for (int l = 1; l <= target; ++l)
+        QB_CHECK(cap[l] <= (unsigned long long)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many node pairs at one level");
+
+    // counts[l]: pairs at level l (device), written by the scans
+    DArr<int64_t> counts(target + 1, s);
+    const int64_t one = 1;
+    QB_HIP(hipMemcpyAsync(counts.p, &one, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    cur.alloc(1, s);
+    k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p);
+    QB_LAUNCH_CHECK();
+    int64_t capc = 1;  // capacity of the current level
+    for (int l = 0; l < target; ++l) {
+        int64_t capn = (int64_t)cap[l + 1];
+        Pairs nxt;
+        if (capc && capn) {
+            DArr<int32_t> X(capc * 4, s), Y(capc * 4 + 1, s);
+            const unsigned g = grid_for(capc * 4, 256);
+            const int32_t *chM = tM ? tM->child[l].p : nullptr;
+            k_walk_count<<<g, 256, 0, s>>>(counts.p + l, capc * 4, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
+                                          tL.child[l].p, tR.child[l].p, chM, transL, transR, X.p);
+            QB_LAUNCH_CHECK();
+            exclusive_scan_i32(X.p, Y.p, capc * 4, counts.p + l + 1, s);
+            if (tM && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
+            nxt.alloc(capn, s);
+            if (capn) {
+                k_walk_fill<<<g, 256, 0, s>>>(counts.p + l, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
+                                             cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, Y.p,
+                                             capn, nxt.pl.p, nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
+                QB_LAUNCH_CHECK();
+            }
+        } else {
+            capn = 0;
+            nxt.alloc(0, s);
+            const int64_t zero = 0;
+            QB_HIP(hipMemcpyAsync(counts.p + l + 1, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        }
+        cur = std::move(nxt);
+        capc = capn;
+    }
+    QB_HIP(hipMemcpyAsync(count, counts.p + target, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    cur.n = capc;
     return cur;
 }
 
-__device__ __forceinline__ int morton_sub(int r, int c, int s) {
-    // interleave the s low bits of r and c, r's bit above c's
-    int q = 0;
-    for (int b = 0; b < s; ++b) q |= (((r >> b) & 1) << (2 * b + 1)) | (((c >> b) & 1) << (2 * b));
-    return q;
+// The walk with its exact count read back.
+Pairs walk_exact(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s) {
+    DArr<int64_t> cnt(1, s);
+    Pairs pr = walk(tL, transL, tR, transR, tM, target, cnt.p, s);
+    const int64_t n = read_back(cnt.p, s);
+    QB_CHECK(n <= pr.n, QBSM_ERR_STATE, "pair count above its bound");
+    pr.n = n;
+    return pr;
 }
 
 __device__ __forceinline__ void demorton_u32(uint32_t k, uint32_t &i, uint32_t &j) {
@@ -146,9 +230,10 @@ __device__ __forceinline__ void demorton_u32(uint32_t k, uint32_t &i, uint32_t &
     }
 }
 
-__global__ void k_unit_flags(int64_t np, const int32_t *gs, int32_t *flags) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < np) flags[p] = (gs[p] == (int32_t)p) ? 1 : 0;
+// First pair of every unit (output group) among the *npp pairs; 0 beyond.
+__global__ void k_unit_flags(const int64_t *npp, int64_t cap, const int32_t *gs, int32_t *flags) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < cap) flags[p] = (p < *npp && gs[p] == (int32_t)p) ? 1 : 0;
 }
 
 __global__ void k_unit_fill(int64_t np, const int32_t *gs, const int32_t *pm, const uint32_t *ck,
@@ -180,51 +265,128 @@ __device__ __forceinline__ int64_t ext(int64_t idx, int64_t n, int32_t bs) {
 
 // Leaf-product bits of each unit-level pair, output-leaf bits of each unit,
 // product and flop totals.
+template <int S>
+__device__ __forceinline__ constexpr int msub(int r, int c) {
+    // interleave the S low bits of r and c, r's bit above c's
+    int q = 0;
+    for (int b = 0; b < S; ++b) q |= (((r >> b) & 1) << (2 * b + 1)) | (((c >> b) & 1) << (2 * b));
+    return q;
+}
+
+// Leaf-product bitmask of every unit-level pair.  The descendant leaves of
+// both nodes (and of the mask node) are loaded first; the 2^(3S) candidate
+// products are then tested with compile-time indexes.
+template <int S>
 __global__ void k_pair_masks(int64_t np, const int32_t *pl, const int32_t *pr, const int32_t *pu,
                              const uint32_t *ukey, const int32_t *umask, const int32_t *descL,
                              const int32_t *descR, const int32_t *descM, int hasM, const uint32_t *keyL,
-                             Dims d, uint64_t *pmask, uint32_t *ucmask, unsigned long long *nprod,
-                             unsigned long long *flops) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    const int lpu = d.lpu, s = d.s, nsub = lpu * lpu;
-    const int32_t a = pl[p], b = pr[p];
-    const int32_t u = pu[p];
+                             Dims d, uint64_t *pmask, uint32_t *ucmask, unsigned long long *part) {
+    constexpr int LPU = 1 << S, NSUB = LPU * LPU;
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = p < np;
+    const int32_t a = live ? pl[p] : 0, b = live ? pr[p] : 0;  // node 0 exists whenever np > 0
+    const int32_t u = live ? pu[p] : -1;
+    const int32_t us = live ? u : 0;
     uint32_t ui, uj, lr, lc;
-    demorton_u32(ukey[u], ui, uj);
+    demorton_u32(ukey[us], ui, uj);
     demorton_u32(keyL[a], lr, lc);
     const uint32_t uk = d.transL ? lr : lc;  // contraction coordinate of the L node
+    int32_t dl[NSUB], dr[NSUB], dm[NSUB];
+    if (S == 0) {
+        dl[0] = a;
+        dr[0] = b;
+        dm[0] = hasM ? umask[us] : 0;
+    } else {
+        const int32_t *xa = descL + (int64_t)a * NSUB;
+        const int32_t *xb = descR + (int64_t)b * NSUB;
+#pragma unroll
+        for (int q = 0; q < NSUB; ++q) {
+            dl[q] = xa[q];
+            dr[q] = xb[q];
+        }
+        if (hasM) {
+            const int32_t *xm = descM + (int64_t)umask[us] * NSUB;
+#pragma unroll
+            for (int q = 0; q < NSUB; ++q) dm[q] = xm[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NSUB; ++q) dm[q] = 0;
+        }
+    }
     uint64_t bits = 0;
     uint32_t cm = 0;
     unsigned long long fl = 0;
-    for (int kb = 0; kb < lpu; ++kb) {
-        for (int ib = 0; ib < lpu; ++ib) {
-            const int qa = d.transL ? morton_sub(kb, ib, s) : morton_sub(ib, kb, s);
-            const int32_t la = descL ? descL[(int64_t)a * nsub + qa] : a;
-            if (la < 0) continue;
-            for (int jb = 0; jb < lpu; ++jb) {
-                const int qb = d.transR ? morton_sub(jb, kb, s) : morton_sub(kb, jb, s);
-                const int32_t lb = descR ? descR[(int64_t)b * nsub + qb] : b;
-                if (lb < 0) continue;
-                if (hasM) {
-                    const int32_t lm = descM ? descM[(int64_t)umask[u] * nsub + morton_sub(ib, jb, s)] : umask[u];
-                    if (lm < 0) continue;
+    if (live) {
+#pragma unroll
+        for (int kb = 0; kb < LPU; ++kb) {
+            const int64_t K = (int64_t)uk * LPU + kb;
+            const int64_t ek = ext(K, d.inner, d.bs);
+#pragma unroll
+            for (int ib = 0; ib < LPU; ++ib) {
+                const int32_t la = d.transL ? dl[msub<S>(kb, ib)] : dl[msub<S>(ib, kb)];
+                const int64_t ei = ext((int64_t)ui * LPU + ib, d.out_rows, d.bs);
+#pragma unroll
+                for (int jb = 0; jb < LPU; ++jb) {
+                    const int32_t lb = d.transR ? dr[msub<S>(jb, kb)] : dr[msub<S>(kb, jb)];
+                    const bool on = la >= 0 && lb >= 0 && dm[msub<S>(ib, jb)] >= 0;
+                    if (on) {
+                        bits |= 1ull << ((kb * LPU + ib) * LPU + jb);
+                        cm |= 1u << (ib * LPU + jb);
+                        fl += (unsigned long long)(2 * ei * ek * ext((int64_t)uj * LPU + jb, d.out_cols, d.bs));
+                    }
                 }
-                bits |= 1ull << ((kb * lpu + ib) * lpu + jb);
-                cm |= 1u << (ib * lpu + jb);
-                const int64_t I = (int64_t)ui * lpu + ib, J = (int64_t)uj * lpu + jb, K = (int64_t)uk * lpu + kb;
-                fl += (unsigned long long)(2 * ext(I, d.out_rows, d.bs) * ext(K, d.inner, d.bs) *
-                                           ext(J, d.out_cols, d.bs));
             }
         }
     }
-    pmask[p] = bits;
-    if (cm) atomicOr(&ucmask[u], cm);
-    const int np_ = __popcll(bits);
-    if (np_) {
-        atomicAdd(nprod, (unsigned long long)np_);
-        atomicAdd(flops, fl);
+    if (live) pmask[p] = bits;
+    // The output mask takes one atomic per unit run inside a wave: the pairs
+    // of a unit are contiguous, so a run of lanes with the same unit is
+    // OR-reduced onto its first lane.  The product and flop totals go to one
+    // slot per block (summed by k_sum_parts) rather than to a single address.
+    unsigned long long cnt = (unsigned long long)__popcll(bits);
+    const int lane = (int)(threadIdx.x & 63);
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t cmo = __shfl_down(cm, o);
+        const int32_t uo = __shfl_down(u, o);
+        if (lane + o < 64 && uo == u) cm |= cmo;
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        cnt += __shfl_down(cnt, o);
+        fl += __shfl_down(fl, o);
+    }
+    const int32_t uprev = __shfl_up(u, 1);
+    if (live && cm && (lane == 0 || uprev != u)) atomicOr(&ucmask[u], cm);
+    __shared__ unsigned long long red[2][4];
+    if (lane == 0) {
+        red[0][threadIdx.x >> 6] = cnt;
+        red[1][threadIdx.x >> 6] = fl;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        part[2 * (int64_t)blockIdx.x + threadIdx.x] =
+            red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+}
+
+// Sums the per-block (products, flops) pairs into out[0..1].
+__global__ void __launch_bounds__(256) k_sum_parts(const unsigned long long *part, int64_t nblk,
+                                                   unsigned long long *out) {
+    unsigned long long c = 0, f = 0;
+    for (int64_t i = threadIdx.x; i < nblk; i += 256) {
+        c += part[2 * i];
+        f += part[2 * i + 1];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        c += __shfl_down(c, o);
+        f += __shfl_down(f, o);
+    }
+    __shared__ unsigned long long red[2][4];
+    if ((threadIdx.x & 63) == 0) {
+        red[0][threadIdx.x >> 6] = c;
+        red[1][threadIdx.x >> 6] = f;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        out[threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
 __global__ void k_unit_count(int64_t nu, const uint32_t *ucmask, int32_t *cnt) {
@@ -346,21 +508,27 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     Tree &tR = matrix_tree(*R, D, s);
     Tree *tM = M ? &matrix_tree(*M, D, s) : nullptr;
     const int Lw = D - sl;
-    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, s);
-    const int64_t np = pr.n;
-    p->npairs = np;
+    // pair and unit counts come back together: meta = {pairs, units}
+    DArr<int64_t> meta(2, s);
+    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, meta.p, s);
+    const int64_t cap = pr.n;
     const int nsub = p->lpu * p->lpu;
 
     // units = output groups at the unit level
-    DArr<int32_t> flags(np ? np : 1, s), uscan((np ? np : 1) + 1, s), pu(np ? np : 1, s);
-    DArr<int64_t> tot(1, s);
-    int64_t nu = 0;
-    if (np) {
-        k_unit_flags<<<grid_for(np, 256), 256, 0, s>>>(np, pr.gs.p, flags.p);
+    DArr<int32_t> flags(cap ? cap : 1, s), uscan((cap ? cap : 1) + 1, s), pu(cap ? cap : 1, s);
+    if (cap) {
+        k_unit_flags<<<grid_for(cap, 256), 256, 0, s>>>(meta.p, cap, pr.gs.p, flags.p);
         QB_LAUNCH_CHECK();
-        exclusive_scan_i32(flags.p, uscan.p, np, tot.p, s);
-        nu = read_back(tot.p, s);
+        exclusive_scan_i32(flags.p, uscan.p, cap, meta.p + 1, s);
+    } else {
+        fill_bytes_zero(meta.p + 1, sizeof(int64_t), s);
     }
+    int64_t hm[2];
+    QB_HIP(hipMemcpyAsync(hm, meta.p, sizeof(hm), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
+    const int64_t np = hm[0], nu = hm[1];
+    QB_CHECK(np <= cap && nu <= np, QBSM_ERR_STATE, "pair count above its bound");
+    p->npairs = np;
     p->nunits = nu;
     p->ustart.alloc(nu + 1, s);
     p->ukey.alloc(nu ? nu : 1, s);
@@ -369,9 +537,9 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     p->pr = std::move(pr.pr);
     p->pmask.alloc(np ? np : 1, s);
     p->cdesc.alloc((nu ? nu : 1) * nsub, s);
-    struct Tot { unsigned long long nprod, flops; };
+    struct Tot { unsigned long long nprod, flops; int64_t nout; };
     DArr<Tot> totals(1, s);
-    QB_HIP(hipMemsetAsync(totals.p, 0, sizeof(Tot), s));
+    fill_bytes_zero(totals.p, sizeof(Tot), s);
     DArr<uint32_t> ucmask(nu ? nu : 1, s);
     fill_u32(ucmask.p, 0u, nu ? nu : 1, s);
     if (np) {
@@ -384,32 +552,46 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
         const int32_t *dL = tree_desc(*L, tL, sl, s);
         const int32_t *dR = tree_desc(*R, tR, sl, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
-        k_pair_masks<<<grid_for(np, 256), 256, 0, s>>>(np, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, dL,
-                                                      dR, dM, M ? 1 : 0, tL.key[Lw].p, d, p->pmask.p,
-                                                      ucmask.p, &totals.p->nprod, &totals.p->flops);
+#define QB_PAIR_MASKS(S_)                                                                                   \
+    k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(np, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, dL, \
+                                                       dR, dM, M ? 1 : 0, tL.key[Lw].p, d, p->pmask.p,     \
+                                                       ucmask.p, part.p)
+        const int64_t nblk = grid_for(np, 256);
+        DArr<unsigned long long> part(2 * nblk, s);
+        if (sl == 0) QB_PAIR_MASKS(0);
+        else if (sl == 1) QB_PAIR_MASKS(1);
+        else QB_PAIR_MASKS(2);
+#undef QB_PAIR_MASKS
+        QB_LAUNCH_CHECK();
+        k_sum_parts<<<1, 256, 0, s>>>(part.p, nblk, &totals.p->nprod);
         QB_LAUNCH_CHECK();
     } else {
         int32_t zero = 0;
         QB_HIP(hipMemcpyAsync(p->ustart.p, &zero, sizeof(int32_t), hipMemcpyHostToDevice, s));
     }
-    // output leaves
-    int64_t nout = 0;
+    // output leaves; their keys go to a bounded array (nu * nsub) first and
+    // are trimmed once the count is back with the totals
+    DArr<uint32_t> okeys_b;
     if (nu) {
         DArr<int32_t> cnt(nu, s), cbase(nu + 1, s);
         k_unit_count<<<grid_for(nu, 256), 256, 0, s>>>(nu, ucmask.p, cnt.p);
         QB_LAUNCH_CHECK();
-        exclusive_scan_i32(cnt.p, cbase.p, nu, tot.p, s);
-        nout = read_back(tot.p, s);
-        if (!M) p->okeys.alloc(nout ? nout : 1, s);
+        exclusive_scan_i32(cnt.p, cbase.p, nu, &totals.p->nout, s);
+        if (!M) okeys_b.alloc(nu * nsub, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
         k_unit_cdesc<<<grid_for(nu, 256), 256, 0, s>>>(nu, ucmask.p, cbase.p, p->ukey.p, p->umask.p, dM,
                                                       M ? 1 : 0, sl, p->lpu, p->cdesc.p,
-                                                      M ? nullptr : p->okeys.p);
+                                                      M ? nullptr : okeys_b.p);
         QB_LAUNCH_CHECK();
-    } else if (!M) {
-        p->okeys.alloc(1, s);
     }
     Tot h = read_back(totals.p, s);
+    const int64_t nout = nu ? h.nout : 0;
+    QB_CHECK(nout <= nu * nsub, QBSM_ERR_STATE, "output leaf count above its bound");
+    if (!M) {
+        p->okeys.alloc(nout ? nout : 1, s);
+        if (nout)
+            QB_HIP(hipMemcpyAsync(p->okeys.p, okeys_b.p, nout * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
     p->nprod = (int64_t)h.nprod;
     p->flops = (int64_t)h.flops;
     p->nout = M ? M->nblk : nout;
@@ -421,7 +603,7 @@ void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t 
     Tree &tL = matrix_tree(*p.L, p.D, s);
     Tree &tR = matrix_tree(*p.R, p.D, s);
     Tree *tM = p.M ? &matrix_tree(*p.M, p.D, s) : nullptr;
-    Pairs lv = walk(tL, p.transL, tR, p.transR, tM, p.D, s);
+    Pairs lv = walk_exact(tL, p.transL, tR, p.transR, tM, p.D, s);
     const int64_t np = lv.n;
     QB_CHECK(np == p.nprod, QBSM_ERR_STATE, "leaf walk disagrees with the plan's product count");
     const int64_t nbc = (p.out_cols + p.bs - 1) / p.bs;

@@ -53,6 +53,7 @@ _SIGS = {
     "qbsm_matrix_set_blocks": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_double, c_void_p,
                                POINTER(c_int64)],
     "qbsm_matrix_store_f32": [c_void_p, c_void_p],
+    "qbsm_matrix_prepack": [c_void_p, c_int32, c_int32, c_void_p],
     "qbsm_matrix_info": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)],
     "qbsm_matrix_get_pattern": [c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_matrix_get_values": [c_void_p, c_void_p, c_void_p],
@@ -171,6 +172,14 @@ class Matrix:
     def store_f32(self):
         """Round stored values to binary32 and drop the FP64 copy (halves memory)."""
         _check(_lib.qbsm_matrix_store_f32(self._h, _stream()))
+
+    def prepack(self, mode="bf16x3", roles: int = 3):
+        """Pack the values for `mode` ahead of use on the library's side stream.
+
+        roles: 1 = as a left operand, 2 = as a right operand, 3 = both.  The
+        packing overlaps the symbolic phase that follows; later uses wait for it.
+        """
+        _check(_lib.qbsm_matrix_prepack(self._h, mode_id(mode), int(roles), _stream()))
 
     @property
     def nblk(self) -> int:

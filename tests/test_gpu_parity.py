@@ -383,6 +383,63 @@ def test_square_packs_both_roles_at_once(q, bs):
     assert np.array_equal(np.isnan(got), np.isnan(refb))
 
 
+def _set_values(A, m):
+    """Replaces the content of handle A with the blocks of host matrix m."""
+    A.set_blocks(torch.from_numpy(m.brow.astype(np.int32)).cuda(), torch.from_numpy(m.bcol.astype(np.int32)).cuda(),
+                 torch.from_numpy(m.vals).cuda(), 0.0)
+
+
+@pytest.mark.parametrize("bs", [32, 64, 128])
+def test_prepack_matches_packing_on_use(q, bs):
+    """Packs made ahead on the library's side stream give the same products,
+    bit for bit, as packs made on use: one role per operand (A * B), both
+    roles of one handle (A * A), every mode and unit.  A prepack made stale by
+    new values before use, one followed by the handle's destruction, and one
+    consumed by a persistent batch are ordered correctly."""
+    n = 5 * bs + bs // 2
+    a, b = W.small_random(n, n - bs // 3, n + bs, bs, 0.5, 91)
+    sq, _ = W.small_random(n, n, n, bs, 0.5, 92)
+    for mode in ("f64", "f32", "bf16", "bf16x3", "ozaki"):
+        for unit in units(bs, mode):
+            plain = values_np(q.matmul(upload(q, a), upload(q, b), mode, unit=unit))
+            A1, B1 = upload(q, a), upload(q, b)
+            A1.prepack(mode, 1)
+            B1.prepack(mode, 2)
+            assert np.array_equal(values_np(q.matmul(A1, B1, mode, unit=unit)), plain), (mode, unit)
+            S0, S1 = upload(q, sq), upload(q, sq)
+            S1.prepack(mode, 3)
+            assert np.array_equal(values_np(q.matmul(S1, S1, mode, unit=unit)),
+                                  values_np(q.matmul(S0, S0, mode, unit=unit))), (mode, unit)
+    # stale before use: new values replace the prepacked ones
+    sq2, _ = W.small_random(n, n, n, bs, 0.5, 93)
+    A = upload(q, sq)
+    A.prepack("bf16x3", 3)
+    _set_values(A, sq2)
+    got = values_np(q.matmul(A, A, "bf16x3", unit=units(bs, "bf16x3")[0]))
+    o2 = O.from_workload(sq2)
+    assert O.rel_fro(got, O.multiply(o2, o2).vals) <= TOL["bf16x3"]
+    # destroyed right after the prepack was queued
+    D = upload(q, sq)
+    D.prepack("f32", 3)
+    del D
+    torch.cuda.synchronize()
+    # a batch over operands packed ahead (FP32 storage keeps the pattern and
+    # the plan, makes the packs stale, and packs to the same f32 values)
+    A2, B2 = upload(q, a), upload(q, b)
+    plan = q.Plan(A2, B2, unit=units(bs, "f32")[0])
+    single = values_np(plan.numeric("f32"))
+    A2.store_f32()
+    B2.store_f32()
+    A2.prepack("f32", 1)
+    B2.prepack("f32", 2)
+    batch = q.Batch([plan], "f32")
+    batch.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(values_np(batch.outs[0]), single)
+    with pytest.raises(q.QbsmError):
+        A2.prepack("f32", 4)
+
+
 OZAKI_CASES = [
     (300, 260, 200, 64, 0.5, 81),
     (190, 170, 150, 32, 0.5, 82),
