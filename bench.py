@@ -71,6 +71,10 @@ def parse():
     ap.add_argument("--unit", type=int, default=0,
                     help="work-unit side; 0 = chosen per mode by the library's autotuner before timing")
     ap.add_argument("--npoints", type=int, default=16384)
+    ap.add_argument("--workload", default="decay", choices=["decay", "banded", "growing", "random"],
+                    help="decay: the 3-D decay matrix (headline); banded/growing/random: the paper's "
+                         "weak-scaling sequences (Sec. 3, Table 1) at size --n")
+    ap.add_argument("--n", type=int, default=100000, help="matrix size of the paper's sequences")
     ap.add_argument("--modes", default="f64,f32", help="reference modes timed beside the chosen one")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (no error statement)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -87,9 +91,9 @@ def kernel_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(mode, unit, npoints):
+def measured_traffic(mode, unit, npoints, workload="decay"):
     t = TRAFFIC
-    if (t["sources_sha256_16"], t["npoints"]) != (kernel_digest(), npoints):
+    if workload != "decay" or (t["sources_sha256_16"], t["npoints"]) != (kernel_digest(), npoints):
         return None
     return t["bytes"].get(f"{mode}@{unit}")
 
@@ -105,25 +109,38 @@ def cpu_baseline_leg(wl, tol, bs, seconds):
     oa = O.from_workload(wl["A"], tol)
     nb = -(-wl["A"].nrows // bs)
     rng = np.random.default_rng(99)
+    rowsets, colsets = {}, {}
+
+    def common(i, j):
+        # products of C block (i, j): common K of row i of A and column j of A
+        if i not in rowsets:
+            rowsets[i] = set(oa.bcol[oa.brow == i].tolist())
+        if j not in colsets:
+            colsets[j] = set(oa.brow[oa.bcol == j].tolist())
+        return len(rowsets[i] & colsets[j])
+
+    def draw(count):
+        # C blocks that have at least one product, uniformly among those
+        si, sj = [], []
+        for _ in range(200):
+            ci, cj = rng.integers(0, nb, 4 * count), rng.integers(0, nb, 4 * count)
+            for i, j in zip(ci.tolist(), cj.tolist()):
+                if common(i, j):
+                    si.append(i)
+                    sj.append(j)
+            if len(si) >= count:
+                break
+        key = np.unique(np.asarray(si[:count], dtype=np.int64) * nb + np.asarray(sj[:count], dtype=np.int64))
+        return key // nb, key % nb
+
     # calibration on a few blocks, then a sample sized to the time budget
-    cal_i, cal_j = rng.integers(0, nb, 16), rng.integers(0, nb, 16)
+    cal_i, cal_j = draw(16)
     t0 = time.perf_counter()
     O.multiply_blocks(oa, oa, cal_i, cal_j)
     dt = max(time.perf_counter() - t0, 1e-3)
     nsample = int(min(nb * nb, max(64, 16 * seconds / dt)))
-    si, sj = rng.integers(0, nb, nsample), rng.integers(0, nb, nsample)
-    key = np.unique(si * nb + sj)
-    si, sj = key // nb, key % nb
-    # products per sampled block: common K of row I of A and column J of A
-    ncommon = 0
-    rowsets = {}
-    for i in np.unique(si):
-        rowsets[int(i)] = set(oa.bcol[oa.brow == i].tolist())
-    colsets = {}
-    for j in np.unique(sj):
-        colsets[int(j)] = set(oa.brow[oa.bcol == j].tolist())
-    for i, j in zip(si.tolist(), sj.tolist()):
-        ncommon += len(rowsets[i] & colsets[j])
+    si, sj = draw(nsample)
+    ncommon = sum(common(i, j) for i, j in zip(si.tolist(), sj.tolist()))
     flops = 2.0 * bs ** 3 * ncommon
     t0 = time.perf_counter()
     ref = O.multiply_blocks(oa, oa, si, sj)
@@ -148,9 +165,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     qbsm.load()
-    bs, tol = 64, 1e-10
+    bs = 64
     t_gen = time.perf_counter()
-    wl = W.config2(npoints=args.npoints, bs=bs)
+    if args.workload == "decay":
+        tol = 1e-10
+        wl = W.config2(npoints=args.npoints, bs=bs)
+    else:
+        tol = 0.0
+        wl = {"A": W.paper_workload(args.workload, args.n, bs)}
     a = wl["A"]
     brow = torch.from_numpy(a.brow.astype(np.int32)).cuda()
     bcol = torch.from_numpy(a.bcol.astype(np.int32)).cuda()
@@ -244,14 +266,9 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu, (si, sj, ref) = cpu_baseline_leg(wl, tol, bs, args.cpu_seconds)
-        nbc = -(-a.ncols // bs)
         for mode in modes:
             step(mode)
-            cr, cc = C.pattern()
-            key = cr.to(torch.int64) * nbc + cc.to(torch.int64)
-            want = torch.from_numpy(si * nbc + sj).cuda()
-            pos = torch.searchsorted(key, want)
-            got = C.values()[pos].cpu().numpy()
+            got = C.extract(si, sj).cpu().numpy()
             err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
             results[mode]["rel_err_vs_fp64_oracle"] = float(f"{err:.3e}")
         print(f"[bench] cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads", file=sys.stderr,
@@ -281,8 +298,9 @@ def main():
         "dtype": DTYPE[args.mode],
         "data": "synthetic",
         "config": {
-            "workload": f"decay3d-n{args.npoints}-bs{bs}-tol1e-10 (C = A*A, {info['nblk_out']} C blocks, "
-                        f"{info['nprod']} leaf products)",
+            "workload": (f"decay3d-n{args.npoints}-bs{bs}-tol1e-10" if args.workload == "decay" else
+                         f"paper-{args.workload}-n{args.n}-h3000-bs{bs}")
+                        + f" (C = A*A, {info['nblk_out']} C blocks, {info['nprod']} leaf products)",
             "mode": args.mode,
             "unit": info["unit"],
             "flops_per_step": info["flops"],
@@ -295,7 +313,7 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "traffic": measured_traffic(args.mode, info["unit"], args.npoints),
+            "traffic": measured_traffic(args.mode, info["unit"], args.npoints, args.workload),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes": alg_bytes,
             "kernel": f"numeric leaf-product kernel, mode {args.mode}, unit {info['unit']} "
@@ -305,6 +323,11 @@ def main():
         "vs_f64_gpu": round(ch["effective_gflops"] / f64["effective_gflops"], 3) if f64 else None,
         "cpu_baseline": cpu,
     }
+    if args.workload != "decay":
+        # the paper's own count (Table 1): element-level multiply-adds of the structure
+        ef = a.meta["element_flops"]
+        out["config"]["element_flops_table1"] = ef
+        out["element_gflops"] = round(ef / (ch["ms_per_step"] * 1e-3) / 1e9, 2)
     print(json.dumps(out), flush=True)
 
 

@@ -159,13 +159,18 @@ __device__ __forceinline__ void demorton(uint32_t k, uint32_t &i, uint32_t &j) {
     }
 }
 
-// Consecutive workgroups are dispatched round-robin over the 8 XCDs; give
-// each XCD a contiguous run of units so that the units resident on one XCD
-// are neighbours in Morton order and share A rows / B columns in its L2.
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs.  The
+// units are dealt to the XCDs in chunks of XCD_CHUNK Morton-consecutive
+// units, chunk c to XCD c mod 8: the units resident on one XCD are
+// neighbours in Morton order (they share A rows / B columns in its L2), and
+// a region of costly units (a dense corner of C) is spread over every XCD
+// instead of landing on one.  The last partial round keeps the identity.
+constexpr int XCD_CHUNK = 64;
 __device__ __forceinline__ int xcd_remap(int b, int n) {
-    const int q = n >> 3, r = n & 7;
+    const int full = n / (8 * XCD_CHUNK) * (8 * XCD_CHUNK);
+    if (b >= full) return b;
     const int x = b & 7, i = b >> 3;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    return ((i / XCD_CHUNK) * 8 + x) * XCD_CHUNK + i % XCD_CHUNK;
 }
 
 // Values that are the same in every lane (read from one LDS address) are

@@ -43,6 +43,11 @@ __all__ = [
     "small_random",
     "zero_padding",
     "decay_blocks_device",
+    "PAPER_TABLE1",
+    "paper_block_size",
+    "paper_workload",
+    "paper_dense_blocks",
+    "paper_element_flops",
 ]
 
 
@@ -287,3 +292,132 @@ def small_random(m: int, k: int, n: int, bs: int, p: float, seed: int,
     a = random_blocks(m, bs, p, rng, ncols=k, fp32_values=fp32_values)
     b = random_blocks(k, bs, p, rng, ncols=n, fp32_values=fp32_values)
     return a, b
+
+
+# ---------------------------------------------------------------------------
+# The paper's weak-scaling workloads (Sec. 3, Table 1): element-level band of
+# half-width 3000 (bandwidth 2*3000 + 1), optionally with dense square blocks
+# on the diagonal, stored as block-sparse matrices of 64 x 64 leaves.
+
+# Table 1: n -> (growing-block size, random-blocks size, number of random blocks)
+PAPER_TABLE1 = {
+    100000: (15716, 15716, 1),
+    200000: (19652, 15705, 2),
+    400000: (24621, 15700, 4),
+    800000: (30899, 15697, 8),
+    1600000: (38825, 15696, 16),
+    3200000: (48828, 15695, 32),
+    6400000: (61446, 15695, 64),
+}
+PAPER_HALF_BAND = 3000
+
+
+def _column_counts(n: int, h: int, blocks) -> np.ndarray:
+    """Nonzeros per column of band(h) united with dense diagonal blocks
+    [p, p + s) (symmetric pattern: also the nonzeros per row)."""
+    k = np.arange(n, dtype=np.int64)
+    lo, hi = np.maximum(k - h, 0), np.minimum(k + h, n - 1)
+    c = hi - lo + 1
+    for p, sz in blocks:
+        l1, h1 = lo[p:p + sz], hi[p:p + sz]
+        ov = np.maximum(0, np.minimum(h1, p + sz - 1) - np.maximum(l1, p) + 1)
+        c[p:p + sz] = (h1 - l1 + 1) + sz - ov
+    return c
+
+
+def _mults(c: np.ndarray) -> int:
+    # scalar multiplications of A * A for a symmetric pattern: sum_k c_k^2
+    return int((c.astype(np.int64) ** 2).sum())
+
+
+def paper_block_size(n: int, h: int = PAPER_HALF_BAND) -> int:
+    """Side of the upper-left dense block that doubles the multiplications of
+    A * A against the band alone (the growing-block rule, nearest size)."""
+    target = 2 * _mults(_column_counts(n, h, []))
+    lo, hi = 1, n
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if _mults(_column_counts(n, h, [(0, mid)])) >= target:
+            hi = mid
+        else:
+            lo = mid + 1
+    cands = [sz for sz in (lo - 1, lo) if sz >= 1]
+    return min(cands, key=lambda sz: abs(_mults(_column_counts(n, h, [(0, sz)])) - target))
+
+
+def paper_dense_blocks(kind: str, n: int, h: int, rng) -> list:
+    """Dense diagonal blocks [(start, size)] of one paper workload; draws the
+    random positions from ``rng`` (the first draws of the workload)."""
+    if kind == "banded":
+        return []
+    if kind not in ("growing", "random"):
+        raise ValueError(f"unknown paper workload {kind!r}")
+    if n in PAPER_TABLE1 and h == PAPER_HALF_BAND:
+        sg, sr, k = PAPER_TABLE1[n]
+    else:
+        sg = paper_block_size(n, h)
+        sr, k = sg, 1
+    if kind == "growing":
+        return [(0, sg)]
+    assert k * sr <= n, "dense blocks do not fit"
+    x = np.sort(rng.integers(0, n - k * sr + 1, size=k))
+    return [(int(x[i]) + i * sr, sr) for i in range(k)]
+
+
+def paper_element_flops(kind: str, n: int = 100000, h: int = PAPER_HALF_BAND, seed: int = 11) -> int:
+    """Element-level flops (two per scalar multiply-add) of A * A for the
+    workload ``paper_workload(kind, n, h=h, seed=seed)``; Table 1's count."""
+    return 2 * _mults(_column_counts(n, h, paper_dense_blocks(kind, n, h, np.random.default_rng(seed))))
+
+
+def paper_workload(kind: str, n: int = 100000, bs: int = 64, h: int = PAPER_HALF_BAND, seed: int = 11,
+                   chunk: int = 4096) -> BlockMatrix:
+    """One matrix of the paper's Banded / Growing block / Random blocks sequences.
+
+    ``kind``: "banded", "growing" (one dense block at the upper-left corner) or
+    "random" (equally sized dense blocks at random non-overlapping diagonal
+    positions).  Block sizes and counts are Table 1's where ``n`` is printed
+    there, else the growing-block doubling rule with one block.  Entries of the
+    element structure are U[-1, 1] (the paper does not give values); every
+    other element, and the padding past ``n``, is zero.  The block pattern is
+    exactly the set of leaves that hold structure elements.  Draw order: the
+    random block positions, then the values of the stored blocks (canonical
+    order, each block column-major).
+    """
+    rng = np.random.default_rng(seed)
+    dense = paper_dense_blocks(kind, n, h, rng)
+    nb = -(-n // bs)
+    # candidate leaves: the block band plus the blocks covering each dense block
+    hb = (h + bs - 1) // bs
+    cand = set()
+    ii = np.arange(nb)
+    for d in range(-hb, hb + 1):
+        jj = ii + d
+        ok = (jj >= 0) & (jj < nb)
+        cand.update(zip(ii[ok].tolist(), jj[ok].tolist()))
+    for p, sz in dense:
+        r = range(p // bs, (p + sz - 1) // bs + 1)
+        cand.update((a, b) for a in r for b in r)
+    key = np.array(sorted(cand), dtype=np.int64).reshape(-1, 2)
+    a_in = np.arange(bs * bs) % bs  # row inside the leaf
+    b_in = np.arange(bs * bs) // bs  # column inside the leaf
+
+    def masks(t0, t1):
+        R = (key[t0:t1, 0:1] * bs).astype(np.int32) + a_in[None, :].astype(np.int32)
+        C = (key[t0:t1, 1:2] * bs).astype(np.int32) + b_in[None, :].astype(np.int32)
+        m = np.abs(R - C) <= h
+        for p, sz in dense:
+            m |= (R >= p) & (R < p + sz) & (C >= p) & (C < p + sz)
+        m &= (R < n) & (C < n)
+        return m
+
+    keep = np.zeros(key.shape[0], dtype=bool)
+    for t0 in range(0, key.shape[0], chunk):
+        keep[t0:t0 + chunk] = masks(t0, t0 + chunk).any(axis=1)
+    key = key[keep]
+    vals = rng.uniform(-1.0, 1.0, size=(key.shape[0], bs * bs))
+    for t0 in range(0, key.shape[0], chunk):
+        vals[t0:t0 + chunk] *= masks(t0, t0 + chunk)
+    return BlockMatrix(n, n, bs, key[:, 0].astype(np.int32), key[:, 1].astype(np.int32), vals,
+                       {"kind": f"paper-{kind}", "h": h, "dense_blocks": dense,
+                        "element_flops": 2 * _mults(_column_counts(n, h, dense))})

@@ -176,3 +176,45 @@ def test_config4_batched_full(q):
     for k in (0, 1, 2, 3, 100, 101):
         single = plans[k].numeric("f32")
         assert np.array_equal(values_np(single), values_np(batch.outs[k])), k
+
+
+@pytest.mark.parametrize("kind", ["banded", "growing", "random"])
+def test_paper_workloads_reduced(q, kind):
+    """The paper's three sequences (band half-width h plus dense diagonal
+    blocks by the doubling rule) at n = 6000, h = 300, 64x64 leaves: product
+    list and C pattern bit-exact, FP64 and BF16x3 values against the oracle."""
+    from tests.gpu_helpers import check_product, units
+    a = W.paper_workload(kind, 6000, 64, 300, seed=31)
+    for mode in ("f64", "bf16x3"):
+        for unit in units(64, mode):
+            check_product(q, a, a, mode, unit)
+
+
+def test_paper_random_blocks_full(q):
+    """Random blocks at the first Table 1 size (n = 1e5: the band plus one
+    dense 15716 block at a random diagonal position), 64x64 leaves: product
+    count from the block pattern, sampled C blocks in FP64 and BF16x3."""
+    a = W.paper_workload("random", 100000)
+    assert a.meta["dense_blocks"][0][1] == 15716
+    A = upload(q, a)
+    P = q.Plan(A, A)
+    info = P.info()
+    # A * A products: sum over block index K of (blocks in column K) * (blocks in row K)
+    ccnt = np.bincount(a.bcol, minlength=a.nbc).astype(np.int64)
+    rcnt = np.bincount(a.brow, minlength=a.nbr).astype(np.int64)
+    assert info["nprod"] == int((ccnt * rcnt).sum())
+    oa = O.from_workload(a)
+    rng = np.random.default_rng(41)
+    p0, sz = a.meta["dense_blocks"][0]
+    lo, hi = p0 // 64, (p0 + sz - 1) // 64
+    # samples inside the dense block's square, on the band, and at the band's edge
+    si = np.concatenate([rng.integers(lo, hi + 1, 12), rng.integers(0, a.nbr, 12), rng.integers(0, a.nbr - 200, 8)])
+    sj = np.concatenate([rng.integers(lo, hi + 1, 12), np.clip(si[12:24] + rng.integers(-90, 91, 12), 0, a.nbc - 1),
+                         si[24:] + 94])
+    key = np.unique(si * a.nbc + sj)
+    si, sj = key // a.nbc, key % a.nbc
+    ref = O.multiply_blocks(oa, oa, si, sj)
+    assert np.linalg.norm(ref) > 0
+    for mode in ("f64", "bf16x3"):
+        got = sampled_values(P.numeric(mode), si, sj)
+        assert O.rel_fro(got, ref) <= TOL[mode], (mode, O.rel_fro(got, ref))
