@@ -16,7 +16,9 @@ sparse-quadtree algorithms reach (no quadtree here):
 * Truncation (paper Sec. 2.2, block-level variant): a block is dropped iff its
   FP64 Frobenius norm is strictly below the tolerance (NaN norms are kept).
 * Matrix-matrix multiplication (paper Sec. 2.2): regular multiply; its masked
-  adjoints dA = (dC B^T) restricted to P_A and dB = (A^T dC) restricted to P_B.
+  adjoints dA = (dC B^T) restricted to P_A and dB = (A^T dC) restricted to P_B;
+  the sparse approximate multiply (Sec. 1 and 2.2) as the regular multiply
+  over the leaf products whose norm product is not below a tolerance.
 * Flop counts: element level ``2 * sum_k r(k) c(k)`` (the convention that
   reproduces the paper's Table 1) and block level ``2 * sum m_I k_K n_J`` over
   the nonzero leaf products with logical (unpadded) sizes.
@@ -239,14 +241,56 @@ def multiply(a: OMatrix, b: OMatrix, trans_a=False, trans_b=False) -> OProduct:
     return OProduct(ci, cj, vals, I, J, K, seg)
 
 
-def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j) -> np.ndarray:
+def spamm_keep(a: OMatrix, b: OMatrix, ia: np.ndarray, ib: np.ndarray, tau: float) -> np.ndarray:
+    """Leaf products kept by the sparse approximate multiply: not
+    (||A_IK||_F * ||B_KJ||_F < tau), both norms and their product in FP64.
+
+    Reading: the paper lists sparse approximate multiplication for matrices
+    with decay among the library's multiply task types (Sec. 1 and 2.2)
+    without a formula; the rule here is the norm-product test at leaf-block
+    granularity, with the same strict comparison as truncation.
+    """
+    if tau <= 0.0:
+        return np.ones(ia.shape[0], dtype=bool)
+    na, nb = block_fnorms(a.vals, a.bs), block_fnorms(b.vals, b.bs)
+    return ~(na[ia] * nb[ib] < tau)
+
+
+def multiply_spamm(a: OMatrix, b: OMatrix, tau: float) -> OProduct:
+    """Sparse approximate C = A B: the regular multiply over the kept leaf
+    products only; C holds the blocks with at least one kept product.
+    tau <= 0 is the regular multiply."""
+    if a.bs != b.bs:
+        raise ValueError("leaf sizes differ")
+    I, J, K, ia, ib = product_triples(a, b)
+    keep = spamm_keep(a, b, ia, ib, tau)
+    I, J, K, ia, ib = I[keep], J[keep], K[keep], ia[keep], ib[keep]
+    ci, cj, seg = c_pattern_from_triples(I, J)
+    vals = _segmented(a.bs, seg, ia, ib, a.vals, b.vals, False, False)
+    return OProduct(ci, cj, vals, I, J, K, seg)
+
+
+def spamm_borderline(a: OMatrix, b: OMatrix, tau: float, rel: float = 1e-9) -> int:
+    """Number of leaf products whose norm product lies within ``rel`` of tau
+    (their selection depends on the summation order of the norms)."""
+    if tau <= 0.0:
+        return 0
+    _, _, _, ia, ib = product_triples(a, b)
+    na, nb = block_fnorms(a.vals, a.bs), block_fnorms(b.vals, b.bs)
+    return int(np.count_nonzero(np.abs(na[ia] * nb[ib] / tau - 1.0) < rel))
+
+
+def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0) -> np.ndarray:
     """Values of selected C blocks only (for sampling very large products).
 
-    A selected (I, J) with no product gets a zero block.
+    A selected (I, J) with no product gets a zero block.  tau > 0 applies the
+    sparse approximate multiply's selection (spamm_keep).
     """
     sample_i = np.asarray(sample_i, dtype=np.int64)
     sample_j = np.asarray(sample_j, dtype=np.int64)
     bs = a.bs
+    if tau > 0.0:  # sparse approximate multiply: the norm-product test of spamm_keep
+        na, nb = block_fnorms(a.vals, bs), block_fnorms(b.vals, bs)
     # rows of A needed, columns of B needed
     segs = [0]
     lid, rid = [], []
@@ -260,9 +304,13 @@ def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j) -> np.ndarray:
         ks_a = a.bcol[ra]
         ks_b = b.brow[cb]
         common, xa, xb = np.intersect1d(ks_a, ks_b, assume_unique=True, return_indices=True)
-        lid.append(ra[xa])
-        rid.append(cb[xb])
-        segs.append(segs[-1] + common.size)
+        la, lb = ra[xa], cb[xb]
+        if tau > 0.0:
+            kept = ~(na[la] * nb[lb] < tau)
+            la, lb = la[kept], lb[kept]
+        lid.append(la)
+        rid.append(lb)
+        segs.append(segs[-1] + la.size)
     seg = np.asarray(segs, dtype=np.int64)
     lidx = np.concatenate(lid) if lid else np.zeros(0, np.int64)
     ridx = np.concatenate(rid) if rid else np.zeros(0, np.int64)

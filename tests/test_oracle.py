@@ -451,3 +451,95 @@ def test_ozaki_multiply_against_fp64():
     # a dropped term is visible: with 2 slices of 8 bits the error is ~2^-16
     r2 = O.ozaki_multiply(oa, ob, slices=2)
     assert 1e-7 < O.rel_fro(r2.vals, ref.vals) < 1e-3
+
+
+# ---------------------------------------------------------------- sparse approximate multiply
+def _decay_like(n, bs, seed):
+    """Small matrix with entries decaying away from the diagonal (block norms spread over decades)."""
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    dense = rng.uniform(-1, 1, (n, n)) * np.exp(-0.35 * np.abs(i - j))
+    nb = -(-n // bs)
+    blocks, br, bc = [], [], []
+    for I in range(nb):
+        for J in range(nb):
+            blk = np.zeros((bs, bs))
+            sub = dense[I * bs:(I + 1) * bs, J * bs:(J + 1) * bs]
+            blk[:sub.shape[0], :sub.shape[1]] = sub
+            br.append(I)
+            bc.append(J)
+            blocks.append(blk.T.ravel())  # column-major
+    return O.canonical(n, n, bs, np.array(br), np.array(bc), np.array(blocks))
+
+
+def test_spamm_zero_tolerance_is_the_multiply():
+    a = _decay_like(150, 16, 1)
+    b = _decay_like(150, 16, 2)
+    s, r = O.multiply_spamm(a, b, 0.0), O.multiply(a, b)
+    assert np.array_equal(s.brow, r.brow) and np.array_equal(s.bcol, r.bcol)
+    assert np.array_equal(s.vals, r.vals) and np.array_equal(s.K, r.K)
+
+
+def test_spamm_brute_force():
+    """Against explicit loops over (I, K, J) with norms summed element by element."""
+    bs, n = 8, 45
+    a, b = _decay_like(n, bs, 3), _decay_like(n, bs, 4)
+    tau = 0.05
+    nb = -(-n // bs)
+
+    def blk(m, I, J):
+        for t in range(m.nblk):
+            if m.brow[t] == I and m.bcol[t] == J:
+                return m.vals[t].reshape(bs, bs).T
+        return None
+
+    want = {}
+    kept = []
+    for I in range(nb):
+        for J in range(nb):
+            acc, any_ = np.zeros((bs, bs)), False
+            for K in range(nb):
+                x, y = blk(a, I, K), blk(b, K, J)
+                if x is None or y is None:
+                    continue
+                nx = sum(float(v) * float(v) for v in x.ravel()) ** 0.5
+                ny = sum(float(v) * float(v) for v in y.ravel()) ** 0.5
+                if nx * ny < tau:
+                    continue
+                kept.append((I, J, K))
+                acc += x @ y
+                any_ = True
+            if any_:
+                want[(I, J)] = acc
+    got = O.multiply_spamm(a, b, tau)
+    assert O.spamm_borderline(a, b, tau) == 0
+    assert list(zip(got.I.tolist(), got.J.tolist(), got.K.tolist())) == kept
+    assert list(zip(got.brow.tolist(), got.bcol.tolist())) == sorted(want)
+    for t, key in enumerate(zip(got.brow.tolist(), got.bcol.tolist())):
+        np.testing.assert_allclose(got.vals[t].reshape(bs, bs).T, want[key], rtol=0, atol=1e-13)
+    assert 0 < len(kept) < O.product_triples(a, b)[0].size  # the test really skips products
+
+
+def test_spamm_error_bound_and_monotone():
+    """||C_spamm - C||_F <= sum over skipped products of ||A_IK|| ||B_KJ|| (sub-
+    multiplicativity of the Frobenius norm); a larger tolerance keeps a subset."""
+    a, b = _decay_like(256, 16, 5), _decay_like(256, 16, 6)
+    exact = O.multiply(a, b)
+    na, nb = O.block_fnorms(a.vals, 16), O.block_fnorms(b.vals, 16)
+    _, _, _, ia, ib = O.product_triples(a, b)
+    prev = None
+    for tau in (1e-8, 1e-5, 1e-3, 1e-1):
+        s = O.multiply_spamm(a, b, tau)
+        # embed the approximate result in the exact pattern
+        pos = {(i, j): t for t, (i, j) in enumerate(zip(exact.brow.tolist(), exact.bcol.tolist()))}
+        full = np.zeros_like(exact.vals)
+        for t, (i, j) in enumerate(zip(s.brow.tolist(), s.bcol.tolist())):
+            full[pos[(i, j)]] = s.vals[t]
+        err = np.linalg.norm(full - exact.vals)
+        skipped = na[ia] * nb[ib]
+        bound = skipped[skipped < tau].sum()
+        assert err <= bound * (1 + 1e-12) + 1e-300
+        triples = set(zip(s.I.tolist(), s.J.tolist(), s.K.tolist()))
+        if prev is not None:
+            assert triples <= prev
+        prev = triples
