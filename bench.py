@@ -75,6 +75,9 @@ def parse():
                     help="decay: the 3-D decay matrix (headline); banded/growing/random: the paper's "
                          "weak-scaling sequences (Sec. 3, Table 1) at size --n")
     ap.add_argument("--n", type=int, default=100000, help="matrix size of the paper's sequences")
+    ap.add_argument("--spamm-tol", type=float, default=0.0,
+                    help="also time the sparse approximate multiply of the chosen mode with this tolerance "
+                         "(reported beside the headline, which is always the full multiply)")
     ap.add_argument("--modes", default="f64,f32", help="reference modes timed beside the chosen one")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (no error statement)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -194,23 +197,23 @@ def main():
 
     units, tuning = {}, {}
 
-    def step(mode):
+    def step(mode, spamm=0.0):
         A.set_blocks(brow, bcol, vals, tol)
         A.prepack(mode, 3)  # operand packing overlaps the symbolic phase (side stream)
-        P = qbsm.Plan(A, A, unit=units[mode])
+        P = qbsm.Plan(A, A, unit=units[mode] if spamm <= 0 else spamm_unit[mode], spamm_tol=spamm)
         P.numeric(mode, C)
         state["plan"] = P
 
-    def time_mode(mode, steps, warmup, profile):
+    def time_mode(mode, steps, warmup, profile, spamm=0.0):
         for _ in range(warmup):
-            step(mode)
+            step(mode, spamm)
         torch.cuda.synchronize()
         if profile:
             qbsm.profile_reset()
             qbsm.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            step(mode)
+            step(mode, spamm)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kern = None
@@ -261,6 +264,33 @@ def main():
               f"(kernel {kern:.3f} ms)", file=sys.stderr, flush=True)
         results[mode]["_vals"] = None
     info = state["plan"].info()
+    spamm = None
+    spamm_unit = {}
+    if args.spamm_tol > 0:
+        # the unit side for the approximate multiply: numeric phase timed per candidate
+        A.set_blocks(brow, bcol, vals, tol)
+        cand = {}
+        for u in (64, 128, 256):
+            if u % bs or u // bs > 4 or (u == 256 and args.mode == "f64") or (args.mode == "ozaki" and u != 64):
+                continue
+            P = qbsm.Plan(A, A, unit=u, spamm_tol=args.spamm_tol)
+            P.numeric(args.mode, C)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                P.numeric(args.mode, C)
+            torch.cuda.synchronize()
+            cand[u] = (time.perf_counter() - t0) / 2 * 1e3
+            del P
+        spamm_unit[args.mode] = min(cand, key=cand.get)
+        ms, kern, num_ms, sinfo = time_mode(args.mode, args.steps, args.warmup, profile=True, spamm=args.spamm_tol)
+        spamm = {"tol": args.spamm_tol, "mode": args.mode, "ms_per_step": round(ms, 4),
+                 "kernel_ms": round(kern, 4), "nprod_kept": sinfo["nprod"], "nprod_full": info["nprod"],
+                 "flops_kept": sinfo["flops"], "kept_gflops": round(sinfo["flops"] / (ms * 1e-3) / 1e9, 2),
+                 "speedup_vs_full": round(results[args.mode]["ms_per_step"] / ms, 3),
+                 "unit": spamm_unit[args.mode], "unit_ms": {str(u): round(t, 3) for u, t in cand.items()}}
+        print(f"[bench] spamm tol {args.spamm_tol:g} ({args.mode}): {ms:.3f} ms/step, "
+              f"{sinfo['nprod']}/{info['nprod']} products kept", file=sys.stderr, flush=True)
 
     # CPU oracle leg: baseline timing + reference values of sampled C blocks
     cpu = None
@@ -271,6 +301,10 @@ def main():
             got = C.extract(si, sj).cpu().numpy()
             err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
             results[mode]["rel_err_vs_fp64_oracle"] = float(f"{err:.3e}")
+        if spamm is not None:
+            step(args.mode, args.spamm_tol)
+            got = C.extract(si, sj).cpu().numpy()
+            spamm["rel_err_vs_exact_fp64_oracle"] = float(f"{np.linalg.norm(got - ref) / np.linalg.norm(ref):.3e}")
         print(f"[bench] cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
     for mode in modes:
@@ -322,6 +356,7 @@ def main():
         "modes": results,
         "vs_f64_gpu": round(ch["effective_gflops"] / f64["effective_gflops"], 3) if f64 else None,
         "cpu_baseline": cpu,
+        "spamm": spamm,
     }
     if args.workload != "decay":
         # the paper's own count (Table 1): element-level multiply-adds of the structure

@@ -188,7 +188,16 @@ qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *
  * QBSM_ERR_UNSUPPORTED otherwise. */
 typedef struct {
     int32_t unit;
-    int32_t reserved[7];
+    int32_t reserved0;
+    /* Sparse approximate multiply (Sec. 1 and 2.2 name it for matrices with
+     * decay): > 0 leaves out every leaf product A_IK * B_KJ whose FP64
+     * Frobenius norms satisfy ||A_IK|| * ||B_KJ|| < spamm_tol (the strict test
+     * of truncation), so C holds the blocks with at least one remaining
+     * product and its error is at most the sum of the left-out norm products.
+     * The norms are taken from the values current at the symbolic phase.
+     * 0 = the regular multiply.  Ignored by qbsm_multiply_backward. */
+    double spamm_tol;
+    int32_t reserved[4];
 } qbsm_plan_opts;
 
 /* Symbolic phase of C = A * B (Sec. 2 and 2.1: the recursive multiply over

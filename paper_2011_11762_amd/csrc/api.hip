@@ -2,6 +2,7 @@
 // batched launches with HIP graph replay, and the unit-size autotuner.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <numeric>
 
@@ -121,6 +122,9 @@ qbsm_status guard(F &&f) {
 }
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
+
+static_assert(sizeof(qbsm_plan_opts) == 32 && offsetof(qbsm_plan_opts, spamm_tol) == 8,
+              "plan options layout is part of the ABI");
 
 bool valid_mode(qbsm_mode m) {
     return m == QBSM_F64 || m == QBSM_F32 || m == QBSM_BF16 || m == QBSM_BF16X3 || m == QBSM_OZAKI_BF16;
@@ -246,7 +250,9 @@ qbsm_status qbsm_multiply_symbolic_ex(qbsm_matrix L, int32_t trans_l, qbsm_matri
     return guard([&] {
         QB_CHECK(L && R && plan, QBSM_ERR_ARG, "null argument");
         const int unit = opts ? opts->unit : 0;
-        auto p = plan_build(&L->m, trans_l ? 1 : 0, &R->m, trans_r ? 1 : 0, mask ? &mask->m : nullptr, unit,
+        const double tau = opts ? opts->spamm_tol : 0.0;
+        QB_CHECK(tau >= 0.0 && std::isfinite(tau), QBSM_ERR_ARG, "spamm_tol must be finite and >= 0");
+        auto p = plan_build(&L->m, trans_l ? 1 : 0, &R->m, trans_r ? 1 : 0, mask ? &mask->m : nullptr, unit, tau,
                             as_stream(stream));
         if (nblk_out) *nblk_out = p->nout;
         if (nprod) *nprod = p->nprod;
@@ -306,13 +312,13 @@ qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC,
         hipStream_t s = as_stream(stream);
         if (dA) {
             // dA = (dC * B^T) restricted to A's pattern
-            auto p = plan_build(&dC->m, 0, &B->m, 1, &A->m, unit, s);
+            auto p = plan_build(&dC->m, 0, &B->m, 1, &A->m, unit, 0.0, s);
             numeric_prepare_output(*p, mode, dA->m, s);
             numeric_launch(*p, mode, dA->m, s);
         }
         if (dB) {
             // dB = (A^T * dC) restricted to B's pattern
-            auto p = plan_build(&A->m, 1, &dC->m, 0, &B->m, unit, s);
+            auto p = plan_build(&A->m, 1, &dC->m, 0, &B->m, unit, 0.0, s);
             numeric_prepare_output(*p, mode, dB->m, s);
             numeric_launch(*p, mode, dB->m, s);
         }
@@ -454,7 +460,7 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
             const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64) &&
                             !(mode == QBSM_OZAKI_BF16 && u != 64);
             if (ok) {
-                auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, s);
+                auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, 0.0, s);
                 Matrix out;
                 out.nrows = p->out_rows;
                 out.ncols = p->out_cols;

@@ -159,6 +159,8 @@ struct Matrix {
     uint64_t version = 0;    // bumped on every value change
     uint64_t filled_by = 0;  // id of the plan that last wrote this matrix as an output
     uint64_t pattern_id = 0; // bumped on every pattern change
+    DArr<double> norms;      // leaf Frobenius norms, valid when norms_version == version
+    uint64_t norms_version = ~0ull;
     std::map<int, std::unique_ptr<Tree>> trees;         // by depth
     std::map<std::pair<int, int>, Pack> packs;          // (mode, role)
     hipStream_t stream = nullptr;                       // stream of the last allocation
@@ -172,6 +174,7 @@ struct Plan {
     int D = 0, s = 0, unit = 0, bs = 0, lpu = 1;
     int64_t out_rows = 0, out_cols = 0;
     int64_t nunits = 0, npairs = 0, nprod = 0, nout = 0, flops = 0;
+    double spamm_tol = 0.0;  // > 0: leaf products selected by the norm-product test
     DArr<int32_t> ustart;   // [nunits + 1] pair range of each unit
     DArr<uint32_t> ukey;    // [nunits] Morton key of the unit node
     DArr<int32_t> umask;    // [nunits] mask-tree node of the unit (masked plans)
@@ -202,8 +205,12 @@ void matrix_extract_blocks(Matrix &m, int64_t n, const int32_t *brow, const int3
                            hipStream_t s);
 void matrix_morton_to_rowmajor_rank(Matrix &m, int32_t *rank, hipStream_t s);
 
+// spamm_tol > 0: sparse approximate multiply (leaf products with
+// ||L leaf||_F * ||R leaf||_F < spamm_tol are left out).
 std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M,
-                                 int unit, hipStream_t s);
+                                 int unit, double spamm_tol, hipStream_t s);
+// FP64 Frobenius norm of every stored leaf (storage order), cached per value version.
+const double *matrix_norms(Matrix &m, hipStream_t s);
 void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t s);
 
 // Packs operand values for (mode, role); returns the device buffer and the
@@ -251,7 +258,9 @@ struct K5Member {
     int32_t lineStrideL, chunkStrideL, lineStrideR, chunkStrideR;
     const int32_t *nfL, *nfR;  // non-finite flags of the two packs (device)
     int64_t out_rows, out_cols;
-    int32_t nunits, bs, s, lpu, transL, transR, pad0, pad1;
+    int32_t nunits, bs, s, lpu, transL, transR;
+    int32_t select;  // 1: leaf products chosen one by one (sparse approximate multiply)
+    int32_t pad1;
 };
 
 struct Batch {

@@ -575,6 +575,43 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     return nk;
 }
 
+// FP64 Frobenius norm of each stored leaf (padding is zero, so the whole
+// block is summed): one workgroup per leaf.
+template <class T>
+__global__ void __launch_bounds__(256) k_block_norms(const T *__restrict__ vals, int64_t nblk, int32_t bs,
+                                                     double *out) {
+    const int64_t t = blockIdx.x;
+    if (t >= nblk) return;
+    const int64_t n2 = (int64_t)bs * bs;
+    const T *x = vals + t * n2;
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) {
+        const double v = (double)x[e];
+        s += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[t] = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+const double *matrix_norms(Matrix &m, hipStream_t s) {
+    QB_CHECK(m.has_blocks, QBSM_ERR_STATE, "matrix has no blocks yet");
+    if (m.norms.p && m.norms_version == m.version && m.norms.n == (size_t)(m.nblk ? m.nblk : 1))
+        return m.norms.p;
+    m.norms.alloc(m.nblk ? m.nblk : 1, s);
+    if (m.nblk) {
+        if (m.storage == ST_F64)
+            k_block_norms<double><<<(unsigned)m.nblk, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, m.norms.p);
+        else
+            k_block_norms<float><<<(unsigned)m.nblk, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, m.norms.p);
+        QB_LAUNCH_CHECK();
+    }
+    m.norms_version = m.version;
+    return m.norms.p;
+}
+
 void matrix_store_f32(Matrix &m, hipStream_t s) {
     if (m.storage != ST_F64) return;
     matrix_settle(m, s);

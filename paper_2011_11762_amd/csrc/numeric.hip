@@ -627,7 +627,9 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
 template <int MODE, int U, int BS>
 __device__ __forceinline__ void process_sel(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
     if constexpr (U >= 256) {
-        if ((*m.nfL | *m.nfR) == 0) {
+        // the branch-free path multiplies every pair of stored leaves of a
+        // step, so it serves only plans whose products are all such pairs
+        if ((*m.nfL | *m.nfR) == 0 && !m.select) {
             process_unit<MODE, U, BS, true>(m, u, st0, st1, meta);
             return;
         }
@@ -811,6 +813,7 @@ K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     m.lpu = p.lpu;
     m.transL = p.transL;
     m.transR = p.transR;
+    m.select = p.spamm_tol > 0.0 ? 1 : 0;
     return m;
 }
 

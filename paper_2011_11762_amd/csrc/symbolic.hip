@@ -36,9 +36,12 @@ __device__ __forceinline__ int slot_of(int rowbit, int colbit, int trans) {
 // level's scan total); the launch covers the level's capacity and the slots
 // beyond 4*np are zeroed, so that the scan over the whole capacity gives the
 // next level's count without a host round trip.
+// nL != nullptr (the step into the leaf level of a sparse approximate
+// multiply): a leaf pair is kept only when not nL[l] * nR[r] < tau.
 __global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl, const int32_t *pr,
                              const int32_t *gs, const int32_t *gm, const int32_t *pm, const int32_t *chL,
-                             const int32_t *chR, const int32_t *chM, int transL, int transR, int32_t *X) {
+                             const int32_t *chR, const int32_t *chM, int transL, int transR,
+                             const double *nL, const double *nR, double tau, int32_t *X) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t np = *npp;
     if (t >= cap4) return;
@@ -56,7 +59,7 @@ __global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl
         for (int kb = 0; kb < 2; ++kb) {
             const int32_t cl = chL[a + slot_of(ib, kb, transL)];
             const int32_t cr = chR[b + slot_of(kb, jb, transR)];
-            cnt += (cl >= 0 && cr >= 0) ? 1 : 0;
+            cnt += (cl >= 0 && cr >= 0 && (!nL || !(nL[cl] * nR[cr] < tau))) ? 1 : 0;
         }
     }
     const int64_t g = gs[p];
@@ -66,7 +69,7 @@ __global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl
 __global__ void k_walk_fill(const int64_t *npp, const int32_t *pl, const int32_t *pr, const int32_t *gs,
                             const int32_t *gm, const int32_t *pm, const uint32_t *ck, const int32_t *chL,
                             const int32_t *chR, const int32_t *chM, int transL, int transR,
-                            const int32_t *Y, int64_t ocap, int32_t *opl, int32_t *opr, int32_t *ogs,
+                            const double *nL, const double *nR, double tau, const int32_t *Y, int64_t ocap, int32_t *opl, int32_t *opr, int32_t *ogs,
                             int32_t *ogm, int32_t *opm, uint32_t *ock) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *npp * 4) return;
@@ -89,7 +92,7 @@ __global__ void k_walk_fill(const int64_t *npp, const int32_t *pl, const int32_t
     for (int kb = 0; kb < 2; ++kb) {
         const int32_t cl = chL[a + slot_of(ib, kb, transL)];
         const int32_t cr = chR[b + slot_of(kb, jb, transR)];
-        if (cl >= 0 && cr >= 0 && o < ocap) {  // o < ocap always; the host checks the count
+        if (cl >= 0 && cr >= 0 && (!nL || !(nL[cl] * nR[cr] < tau)) && o < ocap) {  // o < ocap always
             opl[o] = cl;
             opr[o] = cr;
             ogs[o] = ngs;
@@ -133,7 +136,8 @@ __global__ void k_level_dot(const int32_t *hL, const int32_t *hR, int64_t n, uns
 // be far above it, so a level whose bound exceeds kMaskedBoundPairs reads its
 // exact count back before its arrays are allocated.
 constexpr int64_t kMaskedBoundPairs = int64_t(1) << 20;
-Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int64_t *count, hipStream_t s) {
+Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int64_t *count, hipStream_t s,
+           const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0) {
     Pairs cur;
     const bool empty = tL.n[0] == 0 || tR.n[0] == 0 || (tM && tM->n[0] == 0);
     if (empty || target == 0) {
@@ -185,16 +189,19 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
             DArr<int32_t> X(capc * 4, s), Y(capc * 4 + 1, s);
             const unsigned g = grid_for(capc * 4, 256);
             const int32_t *chM = tM ? tM->child[l].p : nullptr;
+            // the norm test applies on the step into the leaf level only
+            const bool fl = nL && tau > 0.0 && l + 1 == tL.D;
+            const double *fL = fl ? nL : nullptr, *fR = fl ? nR : nullptr;
             k_walk_count<<<g, 256, 0, s>>>(counts.p + l, capc * 4, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
-                                          tL.child[l].p, tR.child[l].p, chM, transL, transR, X.p);
+                                          tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR, tau, X.p);
             QB_LAUNCH_CHECK();
             exclusive_scan_i32(X.p, Y.p, capc * 4, counts.p + l + 1, s);
-            if (tM && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
+            if ((tM || fl) && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
             nxt.alloc(capn, s);
             if (capn) {
                 k_walk_fill<<<g, 256, 0, s>>>(counts.p + l, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
-                                             cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, Y.p,
-                                             capn, nxt.pl.p, nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
+                                             cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR,
+                                             tau, Y.p, capn, nxt.pl.p, nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
                 QB_LAUNCH_CHECK();
             }
         } else {
@@ -212,9 +219,10 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
 }
 
 // The walk with its exact count read back.
-Pairs walk_exact(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s) {
+Pairs walk_exact(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s,
+                 const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0) {
     DArr<int64_t> cnt(1, s);
-    Pairs pr = walk(tL, transL, tR, transR, tM, target, cnt.p, s);
+    Pairs pr = walk(tL, transL, tR, transR, tM, target, cnt.p, s, nL, nR, tau);
     const int64_t n = read_back(cnt.p, s);
     QB_CHECK(n <= pr.n, QBSM_ERR_STATE, "pair count above its bound");
     pr.n = n;
@@ -280,7 +288,8 @@ template <int S>
 __global__ void k_pair_masks(int64_t np, const int32_t *pl, const int32_t *pr, const int32_t *pu,
                              const uint32_t *ukey, const int32_t *umask, const int32_t *descL,
                              const int32_t *descR, const int32_t *descM, int hasM, const uint32_t *keyL,
-                             Dims d, uint64_t *pmask, uint32_t *ucmask, unsigned long long *part) {
+                             Dims d, const double *nL, const double *nR, double tau, uint64_t *pmask,
+                             uint32_t *ucmask, unsigned long long *part) {
     constexpr int LPU = 1 << S, NSUB = LPU * LPU;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = p < np;
@@ -328,7 +337,8 @@ __global__ void k_pair_masks(int64_t np, const int32_t *pl, const int32_t *pr, c
 #pragma unroll
                 for (int jb = 0; jb < LPU; ++jb) {
                     const int32_t lb = d.transR ? dr[msub<S>(jb, kb)] : dr[msub<S>(kb, jb)];
-                    const bool on = la >= 0 && lb >= 0 && dm[msub<S>(ib, jb)] >= 0;
+                    const bool on = la >= 0 && lb >= 0 && dm[msub<S>(ib, jb)] >= 0 &&
+                                    (!nL || !(nL[la] * nR[lb] < tau));
                     if (on) {
                         bits |= 1ull << ((kb * LPU + ib) * LPU + jb);
                         cm |= 1u << (ib * LPU + jb);
@@ -469,6 +479,7 @@ __global__ void k_emit_products(int64_t np, const int32_t *gs, const int32_t *pl
 }  // namespace
 
 std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M, int unit,
+                                 double spamm_tol,
                                  hipStream_t s) {
     QB_CHECK(L && R, QBSM_ERR_ARG, "null matrix");
     QB_CHECK(L->has_blocks && R->has_blocks && (!M || M->has_blocks), QBSM_ERR_STATE,
@@ -510,7 +521,10 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     const int Lw = D - sl;
     // pair and unit counts come back together: meta = {pairs, units}
     DArr<int64_t> meta(2, s);
-    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, meta.p, s);
+    const double *nL = spamm_tol > 0.0 ? matrix_norms(*L, s) : nullptr;
+    const double *nR = spamm_tol > 0.0 ? matrix_norms(*R, s) : nullptr;
+    p->spamm_tol = spamm_tol;
+    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, meta.p, s, nL, nR, spamm_tol);
     const int64_t cap = pr.n;
     const int nsub = p->lpu * p->lpu;
 
@@ -554,8 +568,8 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
 #define QB_PAIR_MASKS(S_)                                                                                   \
     k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(np, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, dL, \
-                                                       dR, dM, M ? 1 : 0, tL.key[Lw].p, d, p->pmask.p,     \
-                                                       ucmask.p, part.p)
+                                                       dR, dM, M ? 1 : 0, tL.key[Lw].p, d, nL, nR,         \
+                                                       spamm_tol, p->pmask.p, ucmask.p, part.p)
         const int64_t nblk = grid_for(np, 256);
         DArr<unsigned long long> part(2 * nblk, s);
         if (sl == 0) QB_PAIR_MASKS(0);
@@ -603,7 +617,9 @@ void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t 
     Tree &tL = matrix_tree(*p.L, p.D, s);
     Tree &tR = matrix_tree(*p.R, p.D, s);
     Tree *tM = p.M ? &matrix_tree(*p.M, p.D, s) : nullptr;
-    Pairs lv = walk_exact(tL, p.transL, tR, p.transR, tM, p.D, s);
+    const double *nL = p.spamm_tol > 0.0 ? matrix_norms(*p.L, s) : nullptr;
+    const double *nR = p.spamm_tol > 0.0 ? matrix_norms(*p.R, s) : nullptr;
+    Pairs lv = walk_exact(tL, p.transL, tR, p.transR, tM, p.D, s, nL, nR, p.spamm_tol);
     const int64_t np = lv.n;
     QB_CHECK(np == p.nprod, QBSM_ERR_STATE, "leaf walk disagrees with the plan's product count");
     const int64_t nbc = (p.out_cols + p.bs - 1) / p.bs;

@@ -34,7 +34,7 @@ class QbsmError(RuntimeError):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("unit", c_int32), ("reserved", c_int32 * 7)]
+    _fields_ = [("unit", c_int32), ("reserved0", c_int32), ("spamm_tol", c_double), ("reserved", c_int32 * 4)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
@@ -215,11 +215,13 @@ class Plan:
     """Symbolic phase result (work list + output pattern) of op(L) op(R) [masked]."""
 
     def __init__(self, L: Matrix, R: Matrix, trans_l=False, trans_r=False, mask: Matrix | None = None,
-                 unit: int = 0):
+                 unit: int = 0, spamm_tol: float = 0.0):
+        """spamm_tol > 0: sparse approximate multiply (leaf products with
+        ||L_leaf|| * ||R_leaf|| < spamm_tol are left out)."""
         load()
         h = c_void_p()
         nout, nprod = c_int64(), c_int64()
-        opts = PlanOpts(unit=int(unit))
+        opts = PlanOpts(unit=int(unit), spamm_tol=float(spamm_tol))
         _check(_lib.qbsm_multiply_symbolic_ex(L.handle, int(trans_l), R.handle, int(trans_r),
                                               mask.handle if mask is not None else None, ctypes.byref(opts),
                                               _stream(), ctypes.byref(h), ctypes.byref(nout),
@@ -259,9 +261,9 @@ class Plan:
         return out
 
 
-def matmul(A: Matrix, B: Matrix, mode="f64", unit: int = 0) -> Matrix:
-    """C = A B (symbolic + numeric)."""
-    return Plan(A, B, unit=unit).numeric(mode)
+def matmul(A: Matrix, B: Matrix, mode="f64", unit: int = 0, spamm_tol: float = 0.0) -> Matrix:
+    """C = A B (symbolic + numeric); spamm_tol > 0 for the sparse approximate multiply."""
+    return Plan(A, B, unit=unit, spamm_tol=spamm_tol).numeric(mode)
 
 
 def backward(A: Matrix, B: Matrix, dC: Matrix, mode="f64", unit: int = 0, need_a=True, need_b=True):
