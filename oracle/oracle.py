@@ -270,6 +270,25 @@ def multiply_spamm(a: OMatrix, b: OMatrix, tau: float) -> OProduct:
     return OProduct(ci, cj, vals, I, J, K, seg)
 
 
+def multiply_upper(a: OMatrix, b: OMatrix) -> OProduct:
+    """The blocks I <= J of C = A B with their leaf products.
+
+    Reading: the paper lists symmetric multiplication and the symmetric
+    matrix square among the multiply task types (Sec. 2.2) without a storage
+    convention; for a symmetric A the square A A is symmetric, and here its
+    representation is the upper triangle of the regular product at block
+    granularity (diagonal blocks whole).
+    """
+    if a.bs != b.bs:
+        raise ValueError("leaf sizes differ")
+    I, J, K, ia, ib = product_triples(a, b)
+    keep = I <= J
+    I, J, K, ia, ib = I[keep], J[keep], K[keep], ia[keep], ib[keep]
+    ci, cj, seg = c_pattern_from_triples(I, J)
+    vals = _segmented(a.bs, seg, ia, ib, a.vals, b.vals, False, False)
+    return OProduct(ci, cj, vals, I, J, K, seg)
+
+
 def spamm_borderline(a: OMatrix, b: OMatrix, tau: float, rel: float = 1e-9) -> int:
     """Number of leaf products whose norm product lies within ``rel`` of tau
     (their selection depends on the summation order of the norms)."""

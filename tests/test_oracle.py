@@ -543,3 +543,56 @@ def test_spamm_error_bound_and_monotone():
         if prev is not None:
             assert triples <= prev
         prev = triples
+
+
+# ---------------------------------------------------------------- symmetric square
+def _symmetric(n, bs, p, seed):
+    """Block-sparse symmetric matrix (pattern and values mirrored)."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(-1, 1, (n, n))
+    nb = -(-n // bs)
+    keep = rng.random((nb, nb)) < p
+    keep = keep | keep.T
+    mask = np.kron(keep, np.ones((bs, bs), dtype=bool))[:n, :n]
+    dense = np.where(mask, x, 0.0)
+    dense = np.triu(dense) + np.triu(dense, 1).T
+    br, bc = np.nonzero(keep)
+    blocks = []
+    for I, J in zip(br, bc):
+        blk = np.zeros((bs, bs))
+        sub = dense[I * bs:(I + 1) * bs, J * bs:(J + 1) * bs]
+        blk[:sub.shape[0], :sub.shape[1]] = sub
+        blocks.append(blk.T.ravel())
+    return O.canonical(n, n, bs, br, bc, np.array(blocks)), dense
+
+
+def test_symmetric_square_reconstructs_the_product():
+    """For a symmetric A, the upper blocks with the mirror of the strictly
+    upper ones give the regular product, block for block (the product of a
+    symmetric matrix with itself is symmetric)."""
+    a, _ = _symmetric(300, 16, 0.3, 7)
+    up, full = O.multiply_upper(a, a), O.multiply(a, a)
+    assert np.all(up.brow <= up.bcol) and np.all(up.I <= up.J)
+    got = {}
+    for t, (i, j) in enumerate(zip(up.brow.tolist(), up.bcol.tolist())):
+        got[(i, j)] = up.vals[t].reshape(16, 16).T
+        if i < j:
+            got[(j, i)] = got[(i, j)].T
+    assert sorted(got) == list(zip(full.brow.tolist(), full.bcol.tolist()))
+    for t, (i, j) in enumerate(zip(full.brow.tolist(), full.bcol.tolist())):
+        np.testing.assert_allclose(got[(i, j)], full.vals[t].reshape(16, 16).T, rtol=0, atol=1e-12)
+
+
+def test_symmetric_square_against_dense():
+    a, dense = _symmetric(70, 8, 0.4, 8)
+    up = O.multiply_upper(a, a)
+    c = dense @ dense
+    for t, (i, j) in enumerate(zip(up.brow.tolist(), up.bcol.tolist())):
+        want = np.zeros((8, 8))
+        sub = c[i * 8:(i + 1) * 8, j * 8:(j + 1) * 8]
+        want[:sub.shape[0], :sub.shape[1]] = sub
+        np.testing.assert_allclose(up.vals[t].reshape(8, 8).T, want, rtol=0, atol=1e-12)
+    # every upper block of the boolean pattern product is present
+    bi, bj, _ = O.boolean_pattern_product(a, a)
+    sel = bi <= bj
+    assert np.array_equal(up.brow, bi[sel]) and np.array_equal(up.bcol, bj[sel])
