@@ -75,6 +75,8 @@ def parse():
                     help="decay: the 3-D decay matrix (headline); banded/growing/random: the paper's "
                          "weak-scaling sequences (Sec. 3, Table 1) at size --n")
     ap.add_argument("--n", type=int, default=100000, help="matrix size of the paper's sequences")
+    ap.add_argument("--sym-square", action="store_true",
+                    help="also time the symmetric square (upper-triangle blocks only) of the chosen mode")
     ap.add_argument("--spamm-tol", type=float, default=0.0,
                     help="also time the sparse approximate multiply of the chosen mode with this tolerance "
                          "(reported beside the headline, which is always the full multiply)")
@@ -197,23 +199,23 @@ def main():
 
     units, tuning = {}, {}
 
-    def step(mode, spamm=0.0):
+    def step(mode, spamm=0.0, upper=False):
         A.set_blocks(brow, bcol, vals, tol)
         A.prepack(mode, 3)  # operand packing overlaps the symbolic phase (side stream)
-        P = qbsm.Plan(A, A, unit=units[mode] if spamm <= 0 else spamm_unit[mode], spamm_tol=spamm)
+        P = qbsm.Plan(A, A, unit=units[mode] if spamm <= 0 else spamm_unit[mode], spamm_tol=spamm, upper=upper)
         P.numeric(mode, C)
         state["plan"] = P
 
-    def time_mode(mode, steps, warmup, profile, spamm=0.0):
+    def time_mode(mode, steps, warmup, profile, spamm=0.0, upper=False):
         for _ in range(warmup):
-            step(mode, spamm)
+            step(mode, spamm, upper)
         torch.cuda.synchronize()
         if profile:
             qbsm.profile_reset()
             qbsm.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            step(mode, spamm)
+            step(mode, spamm, upper)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kern = None
@@ -292,6 +294,16 @@ def main():
         print(f"[bench] spamm tol {args.spamm_tol:g} ({args.mode}): {ms:.3f} ms/step, "
               f"{sinfo['nprod']}/{info['nprod']} products kept", file=sys.stderr, flush=True)
 
+    sym = None
+    if args.sym_square:
+        ms, kern, num_ms, yinfo = time_mode(args.mode, args.steps, args.warmup, profile=True, upper=True)
+        sym = {"mode": args.mode, "ms_per_step": round(ms, 4), "kernel_ms": round(kern, 4),
+               "nblk_out": yinfo["nblk_out"], "nprod": yinfo["nprod"], "flops": yinfo["flops"],
+               "gflops": round(yinfo["flops"] / (ms * 1e-3) / 1e9, 2),
+               "speedup_vs_full": round(results[args.mode]["ms_per_step"] / ms, 3)}
+        print(f"[bench] symmetric square ({args.mode}): {ms:.3f} ms/step, {yinfo['nprod']} products",
+              file=sys.stderr, flush=True)
+
     # CPU oracle leg: baseline timing + reference values of sampled C blocks
     cpu = None
     if not args.no_cpu:
@@ -357,6 +369,7 @@ def main():
         "vs_f64_gpu": round(ch["effective_gflops"] / f64["effective_gflops"], 3) if f64 else None,
         "cpu_baseline": cpu,
         "spamm": spamm,
+        "symmetric_square": sym,
     }
     if args.workload != "decay":
         # the paper's own count (Table 1): element-level multiply-adds of the structure

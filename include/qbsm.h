@@ -188,7 +188,12 @@ qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *
  * QBSM_ERR_UNSUPPORTED otherwise. */
 typedef struct {
     int32_t unit;
-    int32_t reserved0;
+    /* 1: only the output blocks with I <= J are formed (the symmetric square
+     * of Sec. 2.2: for a symmetric A, A * A is symmetric and its upper
+     * triangle holds it all; about half the leaf products).  Needs a square
+     * product and no mask; the output's pattern is the upper triangle of the
+     * product's pattern.  0: every block. */
+    int32_t upper;
     /* Sparse approximate multiply (Sec. 1 and 2.2 name it for matrices with
      * decay): > 0 leaves out every leaf product A_IK * B_KJ whose FP64
      * Frobenius norms satisfy ||A_IK|| * ||B_KJ|| < spamm_tol (the strict test

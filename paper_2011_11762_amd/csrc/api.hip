@@ -123,7 +123,8 @@ qbsm_status guard(F &&f) {
 
 hipStream_t as_stream(void *s) { return static_cast<hipStream_t>(s); }
 
-static_assert(sizeof(qbsm_plan_opts) == 32 && offsetof(qbsm_plan_opts, spamm_tol) == 8,
+static_assert(sizeof(qbsm_plan_opts) == 32 && offsetof(qbsm_plan_opts, upper) == 4 &&
+                  offsetof(qbsm_plan_opts, spamm_tol) == 8,
               "plan options layout is part of the ABI");
 
 bool valid_mode(qbsm_mode m) {
@@ -252,8 +253,15 @@ qbsm_status qbsm_multiply_symbolic_ex(qbsm_matrix L, int32_t trans_l, qbsm_matri
         const int unit = opts ? opts->unit : 0;
         const double tau = opts ? opts->spamm_tol : 0.0;
         QB_CHECK(tau >= 0.0 && std::isfinite(tau), QBSM_ERR_ARG, "spamm_tol must be finite and >= 0");
+        const int upper = opts ? opts->upper : 0;
+        QB_CHECK(upper == 0 || upper == 1, QBSM_ERR_ARG, "upper must be 0 or 1");
+        if (upper) {
+            const int64_t rows = trans_l ? L->m.ncols : L->m.nrows, cols = trans_r ? R->m.nrows : R->m.ncols;
+            QB_CHECK(rows == cols, QBSM_ERR_SHAPE, "the upper triangle needs a square product");
+            QB_CHECK(!mask, QBSM_ERR_ARG, "upper and a mask do not combine");
+        }
         auto p = plan_build(&L->m, trans_l ? 1 : 0, &R->m, trans_r ? 1 : 0, mask ? &mask->m : nullptr, unit, tau,
-                            as_stream(stream));
+                            upper, as_stream(stream));
         if (nblk_out) *nblk_out = p->nout;
         if (nprod) *nprod = p->nprod;
         auto h = std::make_unique<qbsm_plan_>();
@@ -312,13 +320,13 @@ qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC,
         hipStream_t s = as_stream(stream);
         if (dA) {
             // dA = (dC * B^T) restricted to A's pattern
-            auto p = plan_build(&dC->m, 0, &B->m, 1, &A->m, unit, 0.0, s);
+            auto p = plan_build(&dC->m, 0, &B->m, 1, &A->m, unit, 0.0, 0, s);
             numeric_prepare_output(*p, mode, dA->m, s);
             numeric_launch(*p, mode, dA->m, s);
         }
         if (dB) {
             // dB = (A^T * dC) restricted to B's pattern
-            auto p = plan_build(&A->m, 1, &dC->m, 0, &B->m, unit, 0.0, s);
+            auto p = plan_build(&A->m, 1, &dC->m, 0, &B->m, unit, 0.0, 0, s);
             numeric_prepare_output(*p, mode, dB->m, s);
             numeric_launch(*p, mode, dB->m, s);
         }
@@ -460,7 +468,7 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
             const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64) &&
                             !(mode == QBSM_OZAKI_BF16 && u != 64);
             if (ok) {
-                auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, 0.0, s);
+                auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, 0.0, 0, s);
                 Matrix out;
                 out.nrows = p->out_rows;
                 out.ncols = p->out_cols;

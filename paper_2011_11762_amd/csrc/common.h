@@ -175,6 +175,7 @@ struct Plan {
     int64_t out_rows = 0, out_cols = 0;
     int64_t nunits = 0, npairs = 0, nprod = 0, nout = 0, flops = 0;
     double spamm_tol = 0.0;  // > 0: leaf products selected by the norm-product test
+    int upper = 0;           // 1: output blocks with I <= J only
     DArr<int32_t> ustart;   // [nunits + 1] pair range of each unit
     DArr<uint32_t> ukey;    // [nunits] Morton key of the unit node
     DArr<int32_t> umask;    // [nunits] mask-tree node of the unit (masked plans)
@@ -207,8 +208,10 @@ void matrix_morton_to_rowmajor_rank(Matrix &m, int32_t *rank, hipStream_t s);
 
 // spamm_tol > 0: sparse approximate multiply (leaf products with
 // ||L leaf||_F * ||R leaf||_F < spamm_tol are left out).
+// upper != 0: only the output blocks with I <= J (square outputs; the
+// symmetric square keeps the upper triangle of a symmetric product).
 std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M,
-                                 int unit, double spamm_tol, hipStream_t s);
+                                 int unit, double spamm_tol, int upper, hipStream_t s);
 // FP64 Frobenius norm of every stored leaf (storage order), cached per value version.
 const double *matrix_norms(Matrix &m, hipStream_t s);
 void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t s);

@@ -28,6 +28,12 @@ struct Pairs {
     }
 };
 
+// Node on the diagonal of C (row coordinate == column coordinate): in a
+// Morton key the row bits sit one place above the column bits.
+__device__ __forceinline__ bool on_diagonal(uint32_t key) {
+    return ((key >> 1) & 0x55555555u) == (key & 0x55555555u);
+}
+
 __device__ __forceinline__ int slot_of(int rowbit, int colbit, int trans) {
     return trans ? (colbit * 2 + rowbit) : (rowbit * 2 + colbit);
 }
@@ -39,9 +45,10 @@ __device__ __forceinline__ int slot_of(int rowbit, int colbit, int trans) {
 // nL != nullptr (the step into the leaf level of a sparse approximate
 // multiply): a leaf pair is kept only when not nL[l] * nR[r] < tau.
 __global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl, const int32_t *pr,
-                             const int32_t *gs, const int32_t *gm, const int32_t *pm, const int32_t *chL,
+                             const int32_t *gs, const int32_t *gm, const int32_t *pm, const uint32_t *ck,
+                             const int32_t *chL,
                              const int32_t *chR, const int32_t *chM, int transL, int transR,
-                             const double *nL, const double *nR, double tau, int32_t *X) {
+                             const double *nL, const double *nR, double tau, int upper, int32_t *X) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t np = *npp;
     if (t >= cap4) return;
@@ -53,7 +60,7 @@ __global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl
     const int q = (int)(t & 3);
     const int ib = q >> 1, jb = q & 1;
     int cnt = 0;
-    if (!chM || chM[(int64_t)pm[p] * 4 + q] >= 0) {
+    if ((!chM || chM[(int64_t)pm[p] * 4 + q] >= 0) && !(upper && ib > jb && on_diagonal(ck[p]))) {
         const int64_t a = (int64_t)pl[p] * 4, b = (int64_t)pr[p] * 4;
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
@@ -69,7 +76,8 @@ __global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl
 __global__ void k_walk_fill(const int64_t *npp, const int32_t *pl, const int32_t *pr, const int32_t *gs,
                             const int32_t *gm, const int32_t *pm, const uint32_t *ck, const int32_t *chL,
                             const int32_t *chR, const int32_t *chM, int transL, int transR,
-                            const double *nL, const double *nR, double tau, const int32_t *Y, int64_t ocap, int32_t *opl, int32_t *opr, int32_t *ogs,
+                            const double *nL, const double *nR, double tau, int upper, const int32_t *Y,
+                            int64_t ocap, int32_t *opl, int32_t *opr, int32_t *ogs,
                             int32_t *ogm, int32_t *opm, uint32_t *ock) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *npp * 4) return;
@@ -81,6 +89,7 @@ __global__ void k_walk_fill(const int64_t *npp, const int32_t *pl, const int32_t
         mchild = chM[(int64_t)pm[p] * 4 + q];
         if (mchild < 0) return;
     }
+    if (upper && ib > jb && on_diagonal(ck[p])) return;
     const int64_t g = gs[p], m = gm[p];
     const int64_t base = 4 * g + (int64_t)q * m;
     int32_t o = Y[base + (p - g)];
@@ -137,7 +146,7 @@ __global__ void k_level_dot(const int32_t *hL, const int32_t *hR, int64_t n, uns
 // exact count back before its arrays are allocated.
 constexpr int64_t kMaskedBoundPairs = int64_t(1) << 20;
 Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int64_t *count, hipStream_t s,
-           const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0) {
+           const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0, int upper = 0) {
     Pairs cur;
     const bool empty = tL.n[0] == 0 || tR.n[0] == 0 || (tM && tM->n[0] == 0);
     if (empty || target == 0) {
@@ -193,15 +202,16 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
             const bool fl = nL && tau > 0.0 && l + 1 == tL.D;
             const double *fL = fl ? nL : nullptr, *fR = fl ? nR : nullptr;
             k_walk_count<<<g, 256, 0, s>>>(counts.p + l, capc * 4, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
-                                          tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR, tau, X.p);
+                                          cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR, tau, upper,
+                                          X.p);
             QB_LAUNCH_CHECK();
             exclusive_scan_i32(X.p, Y.p, capc * 4, counts.p + l + 1, s);
-            if ((tM || fl) && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
+            if ((tM || fl || upper) && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
             nxt.alloc(capn, s);
             if (capn) {
                 k_walk_fill<<<g, 256, 0, s>>>(counts.p + l, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
                                              cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR,
-                                             tau, Y.p, capn, nxt.pl.p, nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
+                                             tau, upper, Y.p, capn, nxt.pl.p, nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
                 QB_LAUNCH_CHECK();
             }
         } else {
@@ -220,9 +230,9 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
 
 // The walk with its exact count read back.
 Pairs walk_exact(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s,
-                 const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0) {
+                 const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0, int upper = 0) {
     DArr<int64_t> cnt(1, s);
-    Pairs pr = walk(tL, transL, tR, transR, tM, target, cnt.p, s, nL, nR, tau);
+    Pairs pr = walk(tL, transL, tR, transR, tM, target, cnt.p, s, nL, nR, tau, upper);
     const int64_t n = read_back(cnt.p, s);
     QB_CHECK(n <= pr.n, QBSM_ERR_STATE, "pair count above its bound");
     pr.n = n;
@@ -288,8 +298,8 @@ template <int S>
 __global__ void k_pair_masks(int64_t np, const int32_t *pl, const int32_t *pr, const int32_t *pu,
                              const uint32_t *ukey, const int32_t *umask, const int32_t *descL,
                              const int32_t *descR, const int32_t *descM, int hasM, const uint32_t *keyL,
-                             Dims d, const double *nL, const double *nR, double tau, uint64_t *pmask,
-                             uint32_t *ucmask, unsigned long long *part) {
+                             Dims d, const double *nL, const double *nR, double tau, int upper,
+                             uint64_t *pmask, uint32_t *ucmask, unsigned long long *part) {
     constexpr int LPU = 1 << S, NSUB = LPU * LPU;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = p < np;
@@ -338,7 +348,7 @@ __global__ void k_pair_masks(int64_t np, const int32_t *pl, const int32_t *pr, c
                 for (int jb = 0; jb < LPU; ++jb) {
                     const int32_t lb = d.transR ? dr[msub<S>(jb, kb)] : dr[msub<S>(kb, jb)];
                     const bool on = la >= 0 && lb >= 0 && dm[msub<S>(ib, jb)] >= 0 &&
-                                    (!nL || !(nL[la] * nR[lb] < tau));
+                                    (!nL || !(nL[la] * nR[lb] < tau)) && !(upper && ui == uj && ib > jb);
                     if (on) {
                         bits |= 1ull << ((kb * LPU + ib) * LPU + jb);
                         cm |= 1u << (ib * LPU + jb);
@@ -479,7 +489,7 @@ __global__ void k_emit_products(int64_t np, const int32_t *gs, const int32_t *pl
 }  // namespace
 
 std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M, int unit,
-                                 double spamm_tol,
+                                 double spamm_tol, int upper,
                                  hipStream_t s) {
     QB_CHECK(L && R, QBSM_ERR_ARG, "null matrix");
     QB_CHECK(L->has_blocks && R->has_blocks && (!M || M->has_blocks), QBSM_ERR_STATE,
@@ -524,7 +534,8 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     const double *nL = spamm_tol > 0.0 ? matrix_norms(*L, s) : nullptr;
     const double *nR = spamm_tol > 0.0 ? matrix_norms(*R, s) : nullptr;
     p->spamm_tol = spamm_tol;
-    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, meta.p, s, nL, nR, spamm_tol);
+    p->upper = upper;
+    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, meta.p, s, nL, nR, spamm_tol, upper);
     const int64_t cap = pr.n;
     const int nsub = p->lpu * p->lpu;
 
@@ -569,7 +580,7 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
 #define QB_PAIR_MASKS(S_)                                                                                   \
     k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(np, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, dL, \
                                                        dR, dM, M ? 1 : 0, tL.key[Lw].p, d, nL, nR,         \
-                                                       spamm_tol, p->pmask.p, ucmask.p, part.p)
+                                                       spamm_tol, upper, p->pmask.p, ucmask.p, part.p)
         const int64_t nblk = grid_for(np, 256);
         DArr<unsigned long long> part(2 * nblk, s);
         if (sl == 0) QB_PAIR_MASKS(0);
@@ -619,7 +630,7 @@ void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t 
     Tree *tM = p.M ? &matrix_tree(*p.M, p.D, s) : nullptr;
     const double *nL = p.spamm_tol > 0.0 ? matrix_norms(*p.L, s) : nullptr;
     const double *nR = p.spamm_tol > 0.0 ? matrix_norms(*p.R, s) : nullptr;
-    Pairs lv = walk_exact(tL, p.transL, tR, p.transR, tM, p.D, s, nL, nR, p.spamm_tol);
+    Pairs lv = walk_exact(tL, p.transL, tR, p.transR, tM, p.D, s, nL, nR, p.spamm_tol, p.upper);
     const int64_t np = lv.n;
     QB_CHECK(np == p.nprod, QBSM_ERR_STATE, "leaf walk disagrees with the plan's product count");
     const int64_t nbc = (p.out_cols + p.bs - 1) / p.bs;

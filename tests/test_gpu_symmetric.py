@@ -1,0 +1,59 @@
+"""Symmetric square (only the output blocks with I <= J) on the GPU against the oracle.
+
+Product lists and patterns bit-exact, values within the per-mode tolerances;
+the upper blocks of an upper-only plan equal the same blocks of the full
+product bit for bit when both run the same kernel configuration.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_11762_amd import workloads as W
+from tests.gpu_helpers import TOL, pattern_np, units, upload, values_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2011_11762_amd import qbsm
+    assert torch.cuda.is_available()
+    qbsm.load()
+    return qbsm
+
+
+@pytest.mark.parametrize("npoints,bs", [(1500, 32), (3000, 64)])
+def test_symmetric_square_decay(q, npoints, bs):
+    c = W.config2(npoints=npoints, bs=bs, seed=14)
+    a, tol = c["A"], c["drop_tol"]
+    oa = O.from_workload(a, tol)
+    ref = O.multiply_upper(oa, oa)
+    A = upload(q, a, tol)
+    for mode in ("f64", "f32", "bf16x3"):
+        for unit in units(bs, mode):
+            P = q.Plan(A, A, unit=unit, upper=True)
+            info = P.info()
+            assert info["nprod"] == ref.I.size and info["nblk_out"] == ref.brow.size
+            assert info["flops"] == O.block_flops(ref.I, ref.J, ref.K, a.nrows, a.ncols, a.ncols, bs)
+            gI, gK, gJ = (t.cpu().numpy().astype(np.int64) for t in P.products())
+            assert np.array_equal(gI, ref.I) and np.array_equal(gJ, ref.J) and np.array_equal(gK, ref.K)
+            C = P.numeric(mode)
+            cr, cc = pattern_np(C)
+            assert np.array_equal(cr, ref.brow) and np.array_equal(cc, ref.bcol)
+            got = values_np(C)
+            assert O.rel_fro(got, ref.vals) <= TOL[mode], (mode, unit, O.rel_fro(got, ref.vals))
+            # the same blocks of the full product, same configuration: identical
+            full = q.Plan(A, A, unit=unit).numeric(mode)
+            assert np.array_equal(full.extract(cr, cc).cpu().numpy(), got), (mode, unit)
+
+
+def test_symmetric_square_rejections(q):
+    """A non-square product, or a mask, with the upper-triangle option is an error."""
+    a, b = W.small_random(200, 150, 120, 32, 0.5, 15)
+    A, B = upload(q, a), upload(q, b)
+    with pytest.raises(q.QbsmError):
+        q.Plan(A, B, upper=True)  # 200 x 120 output
+    S = upload(q, W.small_random(200, 200, 200, 32, 0.5, 17)[0])
+    with pytest.raises(q.QbsmError):
+        q.Plan(S, S, mask=S, upper=True)
