@@ -134,6 +134,76 @@ def canonical(nrows, ncols, bs, brow, bcol, vals, drop_tol=0.0) -> OMatrix:
     return OMatrix(nrows, ncols, bs, brow[keep], bcol[keep], np.ascontiguousarray(vals[keep]))
 
 
+def from_elements(nrows, ncols, bs, row, col, val) -> OMatrix:
+    """Assignment from vectors of row indices, column indices and values
+    (Sec. 2.2): the leaves are the blocks holding at least one given element;
+    every other element of a leaf is zero.  Reading: the paper does not say
+    what a repeated (row, col) means; it is rejected (as a repeated block is).
+    """
+    row = np.asarray(row, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    val = np.asarray(val, dtype=np.float64)
+    if row.size and (row.min() < 0 or col.min() < 0 or row.max() >= nrows or col.max() >= ncols):
+        raise ValueError("element index out of range")
+    key = row * ncols + col
+    if np.unique(key).size != key.size:
+        raise ValueError("repeated element")
+    nbc = -(-ncols // bs)
+    bkey = (row // bs) * nbc + col // bs
+    ub, inv = np.unique(bkey, return_inverse=True)
+    vals = np.zeros((ub.size, bs * bs))
+    vals[inv, (row % bs) + (col % bs) * bs] = val
+    return OMatrix(nrows, ncols, bs, ub // nbc, ub % nbc, vals)
+
+
+def get_elements(a: OMatrix, row, col) -> np.ndarray:
+    """Extraction of the elements given by row and column index vectors
+    (Sec. 2.2); zero where no leaf is stored."""
+    row = np.asarray(row, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    bs = a.bs
+    nbc = -(-a.ncols // bs)
+    pos = {int(k): t for t, k in enumerate((a.brow * nbc + a.bcol).tolist())}
+    out = np.zeros(row.size)
+    for q, (r, c) in enumerate(zip(row.tolist(), col.tolist())):
+        t = pos.get((r // bs) * nbc + c // bs)
+        if t is not None:
+            out[q] = a.vals[t, (r % bs) + (c % bs) * bs]
+    return out
+
+
+def truncate_error_control(a: OMatrix, eps: float) -> OMatrix:
+    """Truncation with error control (Sec. 2.2), at leaf-block granularity:
+    with the leaves ordered by FP64 Frobenius norm ascending (ties by storage
+    position), the longest leading run whose squared norms sum to at most
+    eps^2 is removed, so the removed part has Frobenius norm <= eps.  Leaves
+    with a NaN norm stay.  Reading: the paper names truncation with several
+    variants of error control without formulas; this is the Frobenius-norm
+    variant.
+    """
+    if a.nblk == 0:
+        return a
+    n = block_fnorms(a.vals, a.bs)
+    sq = n * n
+    order = np.lexsort((np.arange(a.nblk), sq))  # NaN last
+    csum = np.cumsum(sq[order])
+    k = int(np.count_nonzero(csum <= eps * eps))
+    keep = np.ones(a.nblk, dtype=bool)
+    keep[order[:k]] = False
+    return OMatrix(a.nrows, a.ncols, a.bs, a.brow[keep], a.bcol[keep], np.ascontiguousarray(a.vals[keep]))
+
+
+def truncate_borderline(a: OMatrix, eps: float, rel: float = 1e-9) -> int:
+    """Partial sums of the squared norms within ``rel`` of eps^2 (their
+    comparison depends on the summation order)."""
+    if a.nblk == 0:
+        return 0
+    n = block_fnorms(a.vals, a.bs)
+    sq = np.sort(n * n)
+    csum = np.cumsum(sq)
+    return int(np.count_nonzero(np.abs(csum / (eps * eps) - 1.0) < rel)) if eps > 0 else 0
+
+
 def from_workload(m, drop_tol=0.0) -> OMatrix:
     return canonical(m.nrows, m.ncols, m.bs, m.brow, m.bcol, m.vals, drop_tol)
 

@@ -596,3 +596,48 @@ def test_symmetric_square_against_dense():
     bi, bj, _ = O.boolean_pattern_product(a, a)
     sel = bi <= bj
     assert np.array_equal(up.brow, bi[sel]) and np.array_equal(up.bcol, bj[sel])
+
+
+# ---------------------------------------------------------------- elements and truncation
+def test_elements_round_trip_dense():
+    rng = np.random.default_rng(9)
+    n, m, bs = 70, 53, 16
+    dense = np.zeros((n, m))
+    pos = rng.choice(n * m, 400, replace=False)
+    r, c = pos // m, pos % m
+    v = rng.uniform(-1, 1, 400)
+    dense[r, c] = v
+    a = O.from_elements(n, m, bs, r, c, v)
+    full = np.zeros((-(-n // bs) * bs, -(-m // bs) * bs))
+    for t in range(a.nblk):
+        full[a.brow[t] * bs:(a.brow[t] + 1) * bs, a.bcol[t] * bs:(a.bcol[t] + 1) * bs] = a.vals[t].reshape(bs, bs).T
+    assert np.array_equal(full[:n, :m], dense) and not np.any(full[n:, :]) and not np.any(full[:, m:])
+    held = sorted(set(zip((r // bs).tolist(), (c // bs).tolist())))
+    assert list(zip(a.brow.tolist(), a.bcol.tolist())) == held
+    qr, qc = rng.integers(0, n, 300), rng.integers(0, m, 300)
+    assert np.array_equal(O.get_elements(a, qr, qc), dense[qr, qc])
+    with pytest.raises(ValueError):
+        O.from_elements(n, m, bs, np.append(r, r[0]), np.append(c, c[0]), np.append(v, 1.0))
+    with pytest.raises(ValueError):
+        O.from_elements(n, m, bs, np.array([n]), np.array([0]), np.array([1.0]))
+
+
+def test_truncation_error_control():
+    """The removed part is within eps in the Frobenius norm, removing one more
+    leaf (the next smallest) would exceed it, and the kept leaves are the
+    largest ones (brute force over the sorted norms)."""
+    rng = np.random.default_rng(10)
+    a = O.from_workload(W.random_blocks(300, 16, 0.5, rng))
+    a.vals *= np.exp(rng.uniform(-12, 0, a.nblk))[:, None]  # norms over many decades
+    norms = np.array([np.sqrt(np.sum(v * v)) for v in a.vals])
+    for eps in (1e-9, 1e-5, 1e-3, 0.1):
+        t = O.truncate_error_control(a, eps)
+        kept = set(zip(t.brow.tolist(), t.bcol.tolist()))
+        dropped = [i for i in range(a.nblk) if (a.brow[i], a.bcol[i]) not in kept]
+        err = np.sqrt(sum(norms[i] ** 2 for i in dropped))
+        assert err <= eps
+        rest = sorted(norms[i] for i in range(a.nblk) if (a.brow[i], a.bcol[i]) in kept)
+        if rest:
+            assert np.sqrt(err ** 2 + rest[0] ** 2) > eps
+            assert max((norms[i] for i in dropped), default=0.0) <= rest[0]
+    assert O.truncate_error_control(a, 0.0).nblk == a.nblk
