@@ -166,6 +166,36 @@ qbsm_status qbsm_matrix_get_pattern(qbsm_matrix m, int32_t *brow, int32_t *bcol,
  * widened exactly. */
 qbsm_status qbsm_matrix_get_values(qbsm_matrix m, double *vals, void *stream);
 
+/* Construction from elements (Sec. 2.2, assignment from vectors of row
+ * indices, column indices and values):
+ *   row, col : int64[n] element coordinates (device), any order.
+ *   val      : double[n] values (device).
+ *   nblk     : host out, number of stored leaves.
+ * The leaves are the blocks holding at least one given element (in storage
+ * order); their other elements, and the padding, are zero.  Replaces any
+ * previous content.  Errors: QBSM_ERR_PATTERN for a coordinate outside the
+ * matrix or a repeated (row, col) (checked on the device; the matrix is left
+ * unchanged).  Synchronises the stream. */
+qbsm_status qbsm_matrix_set_elements(qbsm_matrix m, int64_t n, const int64_t *row, const int64_t *col,
+                                     const double *val, void *stream, int64_t *nblk);
+
+/* Extraction of elements (Sec. 2.2, extraction of the elements given by
+ * vectors of row and column indices): val[q] = A(row[q], col[q]) as FP64
+ * (device arrays), zero where no leaf is stored.  Errors: QBSM_ERR_ARG for a
+ * coordinate outside the matrix (checked on the device; synchronises). */
+qbsm_status qbsm_matrix_get_elements(qbsm_matrix m, int64_t n, const int64_t *row, const int64_t *col,
+                                     double *val, void *stream);
+
+/* Truncation with error control (Sec. 2.2, removal of small matrix elements
+ * with control of the error), at leaf granularity in the Frobenius norm:
+ * with the leaves ordered by FP64 Frobenius norm ascending (ties in storage
+ * order), the longest leading run whose squared norms sum to at most eps^2
+ * is removed, so that ||A_before - A_after||_F <= eps.  Leaves with a NaN
+ * norm stay.  eps = 0 removes the identically zero leaves only.
+ *   nkept : host out, leaves left.  Synchronises the stream.
+ * Errors: QBSM_ERR_ARG for eps < 0 or NaN; QBSM_ERR_STATE without blocks. */
+qbsm_status qbsm_matrix_truncate(qbsm_matrix m, double eps, void *stream, int64_t *nkept);
+
 /* Extraction of selected blocks (Sec. 2.2, extraction of the elements given
  * by index vectors, at leaf-block granularity): for q in [0, n), block
  * (brow[q], bcol[q]) is written as an FP64 column-major bs x bs block to

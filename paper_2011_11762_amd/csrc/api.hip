@@ -203,6 +203,31 @@ qbsm_status qbsm_matrix_store_f32(qbsm_matrix m, void *stream) {
     });
 }
 
+qbsm_status qbsm_matrix_set_elements(qbsm_matrix m, int64_t n, const int64_t *row, const int64_t *col,
+                                     const double *val, void *stream, int64_t *nblk) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        const int64_t k = matrix_set_elements(m->m, n, row, col, val, as_stream(stream));
+        if (nblk) *nblk = k;
+    });
+}
+
+qbsm_status qbsm_matrix_get_elements(qbsm_matrix m, int64_t n, const int64_t *row, const int64_t *col,
+                                     double *val, void *stream) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        matrix_get_elements(m->m, n, row, col, val, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_matrix_truncate(qbsm_matrix m, double eps, void *stream, int64_t *nkept) {
+    return guard([&] {
+        QB_CHECK(m, QBSM_ERR_ARG, "null matrix");
+        const int64_t k = matrix_truncate(m->m, eps, as_stream(stream));
+        if (nkept) *nkept = k;
+    });
+}
+
 qbsm_status qbsm_matrix_prepack(qbsm_matrix m, qbsm_mode mode, int32_t roles, void *stream) {
     return guard([&] {
         QB_CHECK(m, QBSM_ERR_ARG, "null matrix");

@@ -214,6 +214,12 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
                                  int unit, double spamm_tol, int upper, hipStream_t s);
 // FP64 Frobenius norm of every stored leaf (storage order), cached per value version.
 const double *matrix_norms(Matrix &m, hipStream_t s);
+// Element-level assignment / extraction and error-controlled truncation.
+int64_t matrix_set_elements(Matrix &m, int64_t n, const int64_t *row, const int64_t *col, const double *val,
+                            hipStream_t s);
+void matrix_get_elements(Matrix &m, int64_t n, const int64_t *row, const int64_t *col, double *val,
+                         hipStream_t s);
+int64_t matrix_truncate(Matrix &m, double eps, hipStream_t s);
 void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t s);
 
 // Packs operand values for (mode, role); returns the device buffer and the

@@ -54,6 +54,9 @@ _SIGS = {
                                POINTER(c_int64)],
     "qbsm_matrix_store_f32": [c_void_p, c_void_p],
     "qbsm_matrix_prepack": [c_void_p, c_int32, c_int32, c_void_p],
+    "qbsm_matrix_set_elements": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int64)],
+    "qbsm_matrix_get_elements": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p],
+    "qbsm_matrix_truncate": [c_void_p, c_double, c_void_p, POINTER(c_int64)],
     "qbsm_matrix_info": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)],
     "qbsm_matrix_get_pattern": [c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_matrix_get_values": [c_void_p, c_void_p, c_void_p],
@@ -172,6 +175,30 @@ class Matrix:
     def store_f32(self):
         """Round stored values to binary32 and drop the FP64 copy (halves memory)."""
         _check(_lib.qbsm_matrix_store_f32(self._h, _stream()))
+
+    def set_elements(self, row: torch.Tensor, col: torch.Tensor, val: torch.Tensor) -> int:
+        """row/col: int64 cuda [n]; val: float64 cuda [n].  Returns the number of leaves."""
+        assert row.dtype == torch.int64 and col.dtype == torch.int64 and val.dtype == torch.float64
+        row, col, val = row.contiguous(), col.contiguous(), val.contiguous()
+        nb = c_int64()
+        _check(_lib.qbsm_matrix_set_elements(self._h, int(row.numel()), _ptr(row), _ptr(col), _ptr(val),
+                                             _stream(), ctypes.byref(nb)))
+        return nb.value
+
+    def get_elements(self, row, col) -> torch.Tensor:
+        """FP64 values at (row[q], col[q]) (zero where no leaf is stored)."""
+        row = torch.as_tensor(row, dtype=torch.int64).cuda().contiguous()
+        col = torch.as_tensor(col, dtype=torch.int64).cuda().contiguous()
+        out = torch.empty(row.numel(), dtype=torch.float64, device="cuda")
+        _check(_lib.qbsm_matrix_get_elements(self._h, int(row.numel()), _ptr(row), _ptr(col), _ptr(out),
+                                             _stream()))
+        return out
+
+    def truncate(self, eps: float) -> int:
+        """Removes the smallest leaves while their Frobenius norm stays <= eps; returns leaves kept."""
+        k = c_int64()
+        _check(_lib.qbsm_matrix_truncate(self._h, float(eps), _stream(), ctypes.byref(k)))
+        return k.value
 
     def prepack(self, mode="bf16x3", roles: int = 3):
         """Pack the values for `mode` ahead of use on the library's side stream.

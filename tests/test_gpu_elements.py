@@ -1,0 +1,108 @@
+"""Element-level assignment / extraction and error-controlled truncation on
+the GPU against the oracle: patterns bit-exact, values exact (they are
+copies), truncation's kept set bit-exact away from ties with eps."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2011_11762_amd import workloads as W
+from tests.gpu_helpers import TOL, pattern_np, upload, values_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def q():
+    from paper_2011_11762_amd import qbsm
+    assert torch.cuda.is_available()
+    qbsm.load()
+    return qbsm
+
+
+def _elements(n, m, count, seed):
+    rng = np.random.default_rng(seed)
+    pos = rng.choice(n * m, count, replace=False)
+    return pos // m, pos % m, rng.uniform(-1, 1, count)
+
+
+@pytest.mark.parametrize("n,m,bs", [(300, 250, 32), (1000, 700, 64), (513, 513, 128)])
+def test_set_and_get_elements(q, n, m, bs):
+    r, c, v = _elements(n, m, 5000, 40 + bs)
+    ref = O.from_elements(n, m, bs, r, c, v)
+    A = q.Matrix(n, m, bs)
+    nb = A.set_elements(torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), torch.from_numpy(v).cuda())
+    assert nb == ref.nblk
+    pr, pc = pattern_np(A)
+    assert np.array_equal(pr, ref.brow) and np.array_equal(pc, ref.bcol)
+    assert np.array_equal(values_np(A), ref.vals)
+    rng = np.random.default_rng(7)
+    qr = np.concatenate([r[:500], rng.integers(0, n, 500)])
+    qc = np.concatenate([c[:500], rng.integers(0, m, 500)])
+    assert np.array_equal(A.get_elements(qr, qc).cpu().numpy(), O.get_elements(ref, qr, qc))
+    # the element-built matrix multiplies like any other
+    b = W.random_blocks(m, bs, 0.4, np.random.default_rng(8), ncols=300)
+    B = upload(q, b)
+    got = values_np(q.matmul(A, B, "f64"))
+    want = O.multiply(ref, O.from_workload(b))
+    assert O.rel_fro(got, want.vals) <= TOL["f64"]
+
+
+def test_element_errors(q):
+    n, bs = 200, 32
+    A = q.Matrix(n, n, bs)
+    r, c, v = _elements(n, n, 100, 3)
+    T = lambda x, dt=torch.int64: torch.as_tensor(x, dtype=dt).cuda()
+    with pytest.raises(q.QbsmError):  # repeated (row, col)
+        A.set_elements(T(np.append(r, r[5])), T(np.append(c, c[5])), T(np.append(v, 2.0), torch.float64))
+    with pytest.raises(q.QbsmError):  # outside the matrix
+        A.set_elements(T([n]), T([0]), T([1.0], torch.float64))
+    A.set_elements(T(r), T(c), T(v, torch.float64))
+    with pytest.raises(q.QbsmError):
+        A.get_elements([0, n], [0, 0])
+    assert A.get_elements([int(r[0])], [int(c[0])]).item() == v[0]
+
+
+@pytest.mark.parametrize("store_f32", [False, True])
+def test_truncate_error_control(q, store_f32):
+    rng = np.random.default_rng(11)
+    a = W.random_blocks(900, 32, 0.4, rng)
+    a.vals *= np.exp(rng.uniform(-14, 0, a.nblk))[:, None]
+    a.vals[3] = 0.0                  # an identically zero leaf
+    a.vals[7, 5] = np.nan            # a NaN leaf stays
+    oa = O.from_workload(a)
+    if store_f32:
+        oa = O.OMatrix(oa.nrows, oa.ncols, oa.bs, oa.brow, oa.bcol, O.round_to_f32(oa.vals))
+    for eps in (0.0, 1e-9, 1e-6, 1e-3, 1e-1):
+        assert O.truncate_borderline(oa, eps) == 0
+        ref = O.truncate_error_control(oa, eps)
+        A = upload(q, a)
+        if store_f32:
+            A.store_f32()
+        assert A.truncate(eps) == ref.nblk
+        pr, pc = pattern_np(A)
+        assert np.array_equal(pr, ref.brow) and np.array_equal(pc, ref.bcol), eps
+        got = values_np(A)
+        assert np.array_equal(np.isnan(got), np.isnan(ref.vals))
+        assert np.array_equal(np.nan_to_num(got), np.nan_to_num(ref.vals))
+    with pytest.raises(q.QbsmError):
+        A.truncate(-1.0)
+
+
+def test_truncate_product(q):
+    """Truncation of a multiply's FP32 result, then a second multiply with it."""
+    c = W.config2(npoints=2000, bs=32, seed=19)
+    a, tol = c["A"], c["drop_tol"]
+    A = upload(q, a, tol)
+    C = q.matmul(A, A, "f32")
+    oc = O.OMatrix(C.nrows, C.ncols, 32, *pattern_np(C), values_np(C))
+    eps = 1e-4 * np.linalg.norm(oc.vals)
+    assert O.truncate_borderline(oc, eps) == 0
+    ref = O.truncate_error_control(oc, eps)
+    assert C.truncate(eps) == ref.nblk < oc.nblk
+    pr, pc = pattern_np(C)
+    assert np.array_equal(pr, ref.brow) and np.array_equal(pc, ref.bcol)
+    assert np.array_equal(values_np(C), ref.vals)
+    got = values_np(q.matmul(C, A, "f64"))
+    want = O.multiply(ref, O.from_workload(a, tol))
+    assert O.rel_fro(got, want.vals) <= TOL["f64"]
