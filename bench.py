@@ -47,17 +47,17 @@ KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "d6f3633e8fb19881",
+    "sources_sha256_16": "e54ff67eaf9853d5",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 119688991317,
-        "bf16x3@256": 41690477355,
-        "bf16x3@64": 340024201579,
-        "f32@128": 207989410539,
-        "f32@256": 76328000437,
-        "f32@64": 346352778133,
-        "f64@128": 281900051413,
-        "f64@64": 725625268053,
+        "bf16x3@128": 118978079104,
+        "bf16x3@256": 52111012224,
+        "bf16x3@64": 331969667627,
+        "f32@128": 208975380181,
+        "f32@256": 68142751829,
+        "f32@64": 337773168960,
+        "f64@128": 283733336811,
+        "f64@64": 729210711595,
     },
 }
 
