@@ -57,3 +57,29 @@ def test_symmetric_square_rejections(q):
     S = upload(q, W.small_random(200, 200, 200, 32, 0.5, 17)[0])
     with pytest.raises(q.QbsmError):
         q.Plan(S, S, mask=S, upper=True)
+
+
+def test_batched_upper_and_spamm_plans(q):
+    """Upper-triangle and sparse approximate plans in one persistent launch
+    equal their single launches bit for bit."""
+    c = W.config2(npoints=2500, bs=64, seed=18)
+    a, tol = c["A"], c["drop_tol"]
+    A = upload(q, a, tol)
+    plans = [q.Plan(A, A, unit=256, upper=True), q.Plan(A, A, unit=256, spamm_tol=1e-6),
+             q.Plan(A, A, unit=256), q.Plan(A, A, unit=256, upper=True, spamm_tol=1e-3)]
+    for mode in ("f32", "bf16x3"):
+        singles = [values_np(p.numeric(mode)) for p in plans]
+        batch = q.Batch(plans, mode)
+        batch.run()
+        torch.cuda.synchronize()
+        for o, s_ in zip(batch.outs, singles):
+            assert np.array_equal(values_np(o), s_), mode
+    # the combined options against the oracle: upper blocks of the approximate product
+    oa = O.from_workload(a, tol)
+    assert O.spamm_borderline(oa, oa, 1e-3) == 0 and O.spamm_borderline(oa, oa, 1e-6) == 0
+    sp = O.multiply_spamm(oa, oa, 1e-3)
+    keep = sp.brow <= sp.bcol
+    got = values_np(plans[3].numeric("f32"))
+    cr, cc = pattern_np(plans[3].numeric("f32"))
+    assert np.array_equal(cr, sp.brow[keep]) and np.array_equal(cc, sp.bcol[keep])
+    assert O.rel_fro(got, sp.vals[keep]) <= TOL["f32"]
