@@ -11,6 +11,8 @@
 // ascending keeps both orders at the next level, so no sort is needed: at
 // the leaves every output block's products come out contiguous with K
 // ascending.
+#include <algorithm>
+
 #include "common.h"
 
 namespace qbsm {
@@ -117,24 +119,42 @@ __global__ void k_walk_root(int32_t *pl, int32_t *pr, int32_t *gs, int32_t *gm, 
     pl[0] = 0; pr[0] = 0; gs[0] = 0; gm[0] = 1; pm[0] = 0; ck[0] = 0u;
 }
 
-// Histogram of the nodes of one tree level by their contraction coordinate
-// (column of a left operand, row of a right one; swapped when transposed).
-__global__ void k_level_hist(const uint32_t *key, int64_t n, int use_col, int32_t *hist) {
+// Node keys of levels 1..target of both operand trees, for the level sizing.
+struct LevelHistArgs {
+    const uint32_t *key[2][17];
+    int64_t n[2][17];
+    int use_col[2];   // contraction coordinate: column (1) or row (0) of the stored node
+    int64_t off[17];  // start of level l's histogram (2^l bins) in each operand's half
+    int64_t half;     // size of one operand's half
+};
+
+// Histograms of every level's nodes by their contraction coordinate (column
+// of a left operand, row of a right one; swapped when transposed): grid
+// (nodes, level, operand).
+__global__ void k_level_hist(LevelHistArgs a, int32_t *hist) {
+    const int l = (int)blockIdx.y + 1, op = (int)blockIdx.z;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    const uint32_t k = key[t];
+    if (t >= a.n[op][l]) return;
+    const uint32_t k = a.key[op][l][t];
     uint32_t c = 0;
-    for (int b = 0; b < 16; ++b) c |= ((k >> (2 * b + (use_col ? 0 : 1))) & 1u) << b;
-    atomicAdd(hist + c, 1);
+    for (int b = 0; b < 16; ++b) c |= ((k >> (2 * b + (a.use_col[op] ? 0 : 1))) & 1u) << b;
+    atomicAdd(hist + op * a.half + a.off[l] + c, 1);
 }
 
-// Pairs of one level without a mask: sum over the contraction coordinate of
-// (left nodes there) * (right nodes there); an upper bound under a mask.
-__global__ void k_level_dot(const int32_t *hL, const int32_t *hR, int64_t n, unsigned long long *cap) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long v = t < n ? (unsigned long long)hL[t] * (unsigned long long)hR[t] : 0ull;
+// Pairs of every level without a mask: sum over the contraction coordinate
+// of (left nodes there) * (right nodes there); an upper bound under a mask.
+// One workgroup per level.
+__global__ void __launch_bounds__(256) k_level_dot(const int32_t *hist, LevelHistArgs a, unsigned long long *cap) {
+    const int l = (int)blockIdx.x + 1;
+    const int32_t *hL = hist + a.off[l], *hR = hist + a.half + a.off[l];
+    unsigned long long v = 0;
+    for (int64_t t = threadIdx.x; t < ((int64_t)1 << l); t += 256)
+        v += (unsigned long long)hL[t] * (unsigned long long)hR[t];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(cap, v);
+    __shared__ unsigned long long red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) cap[l] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Runs the walk from the root to level `target`; returns the pair list there.
@@ -163,19 +183,26 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
     std::vector<int64_t> hoff(target + 1, 0);
     for (int l = 1; l <= target; ++l) hoff[l] = hoff[l - 1] + ((int64_t)1 << (l - 1));
     const int64_t hsize = hoff[target] + ((int64_t)1 << target);
-    DArr<int32_t> hL(hsize, s), hR(hsize, s);
+    DArr<int32_t> hist(2 * hsize, s);
     DArr<unsigned long long> capd(target + 1, s);
-    fill_bytes_zero(hL.p, hsize * sizeof(int32_t), s);
-    fill_bytes_zero(hR.p, hsize * sizeof(int32_t), s);
+    fill_bytes_zero(hist.p, 2 * hsize * sizeof(int32_t), s);
     fill_bytes_zero(capd.p, (target + 1) * sizeof(unsigned long long), s);
+    LevelHistArgs ha{};
+    ha.use_col[0] = transL ? 0 : 1;
+    ha.use_col[1] = transR ? 1 : 0;
+    ha.half = hsize;
+    int64_t nmax = 1;
     for (int l = 1; l <= target; ++l) {
-        if (tL.n[l])
-            k_level_hist<<<grid_for(tL.n[l], 256), 256, 0, s>>>(tL.key[l].p, tL.n[l], transL ? 0 : 1, hL.p + hoff[l]);
-        if (tR.n[l])
-            k_level_hist<<<grid_for(tR.n[l], 256), 256, 0, s>>>(tR.key[l].p, tR.n[l], transR ? 1 : 0, hR.p + hoff[l]);
-        const int64_t w = (int64_t)1 << l;
-        k_level_dot<<<grid_for(w, 256), 256, 0, s>>>(hL.p + hoff[l], hR.p + hoff[l], w, capd.p + l);
+        ha.key[0][l] = tL.key[l].p;
+        ha.key[1][l] = tR.key[l].p;
+        ha.n[0][l] = tL.n[l];
+        ha.n[1][l] = tR.n[l];
+        ha.off[l] = hoff[l];
+        nmax = std::max(nmax, std::max(tL.n[l], tR.n[l]));
     }
+    k_level_hist<<<dim3(grid_for(nmax, 256), (unsigned)target, 2), 256, 0, s>>>(ha, hist.p);
+    QB_LAUNCH_CHECK();
+    k_level_dot<<<(unsigned)target, 256, 0, s>>>(hist.p, ha, capd.p);
     QB_LAUNCH_CHECK();
     std::vector<unsigned long long> cap(target + 1, 0);
     QB_HIP(hipMemcpyAsync(cap.data(), capd.p, (target + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
