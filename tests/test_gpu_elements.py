@@ -106,3 +106,37 @@ def test_truncate_product(q):
     got = values_np(q.matmul(C, A, "f64"))
     want = O.multiply(ref, O.from_workload(a, tol))
     assert O.rel_fro(got, want.vals) <= TOL["f64"]
+
+
+def test_empty_and_degenerate_new_operations(q):
+    """Zero elements, truncation of an empty matrix, empty queries, packing an
+    empty matrix ahead, and a tolerance that leaves out every product."""
+    bs = 32
+    E = q.Matrix(100, 90, bs)
+    T = lambda x, dt=torch.int64: torch.as_tensor(x, dtype=dt).cuda()
+    assert E.set_elements(T([]), T([]), T([], torch.float64)) == 0
+    assert E.nblk == 0 and E.truncate(1.0) == 0
+    assert E.get_elements([], []).numel() == 0
+    E.prepack("bf16x3", 3)
+    b = W.random_blocks(90, bs, 0.5, np.random.default_rng(3), ncols=70)
+    B = upload(q, b)
+    C = q.matmul(E, B, "f32")
+    assert C.nblk == 0
+    # one element: one leaf; squares and products of it
+    one = q.Matrix(40, 40, bs)
+    assert one.set_elements(T([33]), T([5]), T([2.0], torch.float64)) == 1
+    assert one.get_elements([33, 0], [5, 0]).cpu().numpy().tolist() == [2.0, 0.0]
+    sq = q.matmul(one, one, "f64")   # (33,5) * (33,5): no product (5 != 33 // 32 block)
+    assert sq.nblk == (1 if 33 // bs == 5 // bs else 0)
+    # every product left out: empty output, zero units
+    c = W.config2(npoints=1200, bs=32, seed=21)
+    A = upload(q, c["A"], c["drop_tol"])
+    P = q.Plan(A, A, spamm_tol=1e30)
+    assert P.info()["nprod"] == 0 and P.info()["nblk_out"] == 0
+    assert P.numeric("bf16x3").nblk == 0
+    # the upper triangle of a single-leaf product is that leaf
+    s1 = W.small_random(30, 30, 30, bs, 1.0, 22)[0]
+    S1 = upload(q, s1)
+    U1 = q.Plan(S1, S1, upper=True).numeric("f64")
+    full = q.matmul(S1, S1, "f64")
+    assert np.array_equal(values_np(U1), values_np(full))
