@@ -161,7 +161,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not built "
-                                   "(the sharding design is described in DESIGN.md)", "n_gpus": args.gpus}))
+                                   "(the library has no cross-GPU path)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
