@@ -33,7 +33,10 @@
  *     once, and keep a plan's matrices alive (and their patterns unchanged)
  *     for the plan's lifetime.
  *   - Device memory comes from the allocator set by qbsm_set_allocator
- *     (default: hipMallocAsync / hipFreeAsync on the call's stream).
+ *     (default: hipMallocAsync / hipFreeAsync on the call's stream, from the
+ *     device's default memory pool; the library raises that pool's release
+ *     threshold so that memory freed by one call is reused by the next
+ *     instead of returning to the driver at each synchronisation).
  */
 #ifndef QBSM_H
 #define QBSM_H

@@ -1,6 +1,7 @@
 // The C ABI of libqbsm: argument checks, error mapping, handle lifetimes,
 // batched launches with HIP graph replay, and the unit-size autotuner.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstddef>
 #include <cstring>
@@ -31,12 +32,34 @@ Allocator g_alloc;
 
 Allocator &allocator() { return g_alloc; }
 
+namespace {
+// Without a hook, memory comes from the device's default stream-ordered pool.
+// Its release threshold is raised once per device so that the temporaries a
+// call frees stay in the pool for the next call instead of going back to the
+// driver at every synchronisation.
+std::atomic<bool> g_pool_tuned[64];
+
+void keep_pool_memory() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+    if (g_pool_tuned[dev].load(std::memory_order_acquire)) return;
+    hipMemPool_t pool = nullptr;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess && pool) {
+        uint64_t keep = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    g_pool_tuned[dev].store(true, std::memory_order_release);
+}
+}  // namespace
+
 void *dalloc(size_t bytes, hipStream_t s) {
     if (!bytes) return nullptr;
     void *p = nullptr;
     if (g_alloc.alloc) {
         p = g_alloc.alloc(bytes, (void *)s, g_alloc.ctx);
     } else {
+        keep_pool_memory();
         hipError_t e = hipMallocAsync(&p, bytes, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
