@@ -186,6 +186,22 @@ def main():
     print(f"[bench] workload generated and resident in HBM in {time.perf_counter() - t_gen:.1f} s",
           file=sys.stderr, flush=True)
 
+    # device-to-device copy bandwidth (read + write bytes / time) for scale;
+    # left out of counter runs, whose only large copy is the calibration copy
+    copy_gbps = None
+    if not args.calibrate_copy:
+        src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t_copy = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_gbps = round(2 * (1 << 31) * 5 / (time.perf_counter() - t_copy) / 1e9, 1)
+        del src, dst
+        torch.cuda.empty_cache()
+
     if args.calibrate_copy:
         src = torch.empty(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
@@ -234,6 +250,15 @@ def main():
             P.numeric(mode, C)
         torch.cuda.synchronize()
         num_ms = (time.perf_counter() - t1) / steps * 1e3
+        # spread of single steps (each bracketed by a synchronisation), after the timed run
+        single = []
+        for _ in range(steps):
+            t2 = time.perf_counter()
+            step(mode, spamm, upper)
+            torch.cuda.synchronize()
+            single.append((time.perf_counter() - t2) * 1e3)
+        state["spread"] = {"median": round(float(np.median(single)), 4), "min": round(min(single), 4),
+                           "max": round(max(single), 4)}
         return el / steps * 1e3, kern, num_ms, info
 
     modes = [m for m in args.modes.split(",") if m and m != args.mode] + [args.mode]
@@ -259,6 +284,7 @@ def main():
             "kernel_ms": round(kern, 4),
             "kernel_mfma_tflops": round(MFMA_TERMS[mode] * flops / (kern * 1e-3) / 1e12, 2),
             "unit": units[mode],
+            "single_step_ms": state["spread"],
         }
         if mode in tuning:
             results[mode]["autotune_ms"] = tuning[mode]
@@ -368,6 +394,7 @@ def main():
         "modes": results,
         "vs_f64_gpu": round(ch["effective_gflops"] / f64["effective_gflops"], 3) if f64 else None,
         "cpu_baseline": cpu,
+        "copy_gbps": copy_gbps,
         "spamm": spamm,
         "symmetric_square": sym,
     }
