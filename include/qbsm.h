@@ -223,9 +223,10 @@ typedef struct {
     int32_t unit;
     /* 1: only the output blocks with I <= J are formed (the symmetric square
      * of Sec. 2.2: for a symmetric A, A * A is symmetric and its upper
-     * triangle holds it all; about half the leaf products).  Needs a square
-     * product and no mask; the output's pattern is the upper triangle of the
-     * product's pattern.  0: every block. */
+     * triangle holds it all; with a transposed right operand, A * A^T is the
+     * symmetric rank-k construction of the same section; about half the leaf
+     * products).  Needs a square product and no mask; the output's pattern is
+     * the upper triangle of the product's pattern.  0: every block. */
     int32_t upper;
     /* Sparse approximate multiply (Sec. 1 and 2.2 name it for matrices with
      * decay): > 0 leaves out every leaf product A_IK * B_KJ whose FP64

@@ -83,3 +83,26 @@ def test_batched_upper_and_spamm_plans(q):
     cr, cc = pattern_np(plans[3].numeric("f32"))
     assert np.array_equal(cr, sp.brow[keep]) and np.array_equal(cc, sp.bcol[keep])
     assert O.rel_fro(got, sp.vals[keep]) <= TOL["f32"]
+
+
+@pytest.mark.parametrize("bs", [32, 64])
+def test_symmetric_rank_k(q, bs):
+    """Symmetric rank-k construction (Sec. 2.2): C = A A^T is symmetric for any
+    A, and the upper-triangle option with a transposed right operand forms
+    exactly its blocks I <= J."""
+    a, _ = W.small_random(9 * bs + 5, 6 * bs + 7, 10, bs, 0.4, 60 + bs)  # tall A, m x k
+    oa = O.from_workload(a)
+    full = O.multiply(oa, oa, trans_b=True)
+    keep = full.brow <= full.bcol
+    I, J, K, _, _ = O.product_triples(oa, oa, trans_b=True)
+    sel = I <= J
+    A = upload(q, a)
+    for mode in ("f64", "f32", "bf16x3"):
+        for unit in units(bs, mode):
+            P = q.Plan(A, A, trans_r=True, unit=unit, upper=True)
+            gI, gK, gJ = (t.cpu().numpy().astype(np.int64) for t in P.products())
+            assert np.array_equal(gI, I[sel]) and np.array_equal(gJ, J[sel]) and np.array_equal(gK, K[sel])
+            C = P.numeric(mode)
+            cr, cc = pattern_np(C)
+            assert np.array_equal(cr, full.brow[keep]) and np.array_equal(cc, full.bcol[keep])
+            assert O.rel_fro(values_np(C), full.vals[keep]) <= TOL[mode], (mode, unit)
