@@ -204,6 +204,39 @@ def truncate_borderline(a: OMatrix, eps: float, rel: float = 1e-9) -> int:
     return int(np.count_nonzero(np.abs(csum / (eps * eps) - 1.0) < rel)) if eps > 0 else 0
 
 
+def add(alpha: float, a: OMatrix, beta: float, b: OMatrix) -> OMatrix:
+    """Matrix addition (Sec. 2.2): alpha A + beta B on the union of the two
+    leaf patterns, each block alpha*A_IJ + beta*B_IJ in FP64 (a missing block
+    is zero).  Reading: the paper lists regular addition without a rule for
+    the pattern; every leaf of either operand is kept, none is dropped."""
+    if (a.nrows, a.ncols, a.bs) != (b.nrows, b.ncols, b.bs):
+        raise ValueError("shapes differ")
+    nbc = -(-a.ncols // a.bs)
+    ka, kb = a.brow * nbc + a.bcol, b.brow * nbc + b.bcol
+    keys = np.union1d(ka, kb)
+    vals = np.zeros((keys.size, a.bs * a.bs))
+    ia, ib = np.searchsorted(keys, ka), np.searchsorted(keys, kb)
+    vals[ia] += alpha * a.vals
+    vals[ib] += beta * b.vals
+    return OMatrix(a.nrows, a.ncols, a.bs, keys // nbc, keys % nbc, vals)
+
+
+def add_identity(a: OMatrix, sigma: float) -> OMatrix:
+    """A + sigma I (Sec. 2.2, addition of a scaled identity): sigma is added to
+    the diagonal elements (r, r), r < min(nrows, ncols); diagonal leaves that
+    are not stored are created."""
+    bs = a.bs
+    nd = min(a.nrows, a.ncols)
+    nb = -(-nd // bs)
+    diag = np.zeros((nb, bs * bs))
+    for t in range(nb):
+        for r in range(bs):
+            if t * bs + r < nd:
+                diag[t, r + r * bs] = sigma
+    d = OMatrix(a.nrows, a.ncols, bs, np.arange(nb, dtype=np.int64), np.arange(nb, dtype=np.int64), diag)
+    return add(1.0, a, 1.0, d)
+
+
 def from_workload(m, drop_tol=0.0) -> OMatrix:
     return canonical(m.nrows, m.ncols, m.bs, m.brow, m.bcol, m.vals, drop_tol)
 

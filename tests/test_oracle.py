@@ -641,3 +641,36 @@ def test_truncation_error_control():
             assert np.sqrt(err ** 2 + rest[0] ** 2) > eps
             assert max((norms[i] for i in dropped), default=0.0) <= rest[0]
     assert O.truncate_error_control(a, 0.0).nblk == a.nblk
+
+
+# ---------------------------------------------------------------- addition
+def test_addition_against_dense():
+    rng = np.random.default_rng(12)
+    a = W.random_blocks(150, 16, 0.3, rng, ncols=130)
+    b = W.random_blocks(150, 16, 0.3, rng, ncols=130)
+    A, B = om(a), om(b)
+    c = O.add(0.5, A, -2.0, B)
+    dense = 0.5 * a.to_dense() - 2.0 * b.to_dense()
+    got = W.BlockMatrix(150, 130, 16, c.brow.astype(np.int32), c.bcol.astype(np.int32), c.vals).to_dense()
+    assert np.array_equal(got, dense)
+    pat = set(zip(A.brow.tolist(), A.bcol.tolist())) | set(zip(B.brow.tolist(), B.bcol.tolist()))
+    assert list(zip(c.brow.tolist(), c.bcol.tolist())) == sorted(pat)
+    # the multiply distributes over the sum: (A + B) X = A X + B X within rounding
+    X = om(W.random_blocks(130, 16, 0.4, rng, ncols=90))
+    left = O.multiply(O.add(1.0, A, 1.0, B), X)
+    ax, bx = O.multiply(A, X), O.multiply(B, X)
+    right = O.add(1.0, O.OMatrix(150, 90, 16, ax.brow, ax.bcol, ax.vals), 1.0,
+                  O.OMatrix(150, 90, 16, bx.brow, bx.bcol, bx.vals))
+    assert np.array_equal(left.brow, right.brow) and np.array_equal(left.bcol, right.bcol)
+    assert O.rel_fro(left.vals, right.vals) < 1e-14
+
+
+def test_add_identity_against_dense():
+    rng = np.random.default_rng(13)
+    a = W.random_blocks(100, 16, 0.2, rng, ncols=90)
+    A = om(a)
+    c = O.add_identity(A, 3.5)
+    dense = a.to_dense()[:100, :90].copy()
+    dense[np.arange(90), np.arange(90)] += 3.5
+    got = W.BlockMatrix(100, 90, 16, c.brow.astype(np.int32), c.bcol.astype(np.int32), c.vals).to_dense()
+    assert np.array_equal(got[:100, :90], dense) and not np.any(got[100:, :]) and not np.any(got[:, 90:])
