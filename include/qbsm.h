@@ -199,6 +199,22 @@ qbsm_status qbsm_matrix_get_elements(qbsm_matrix m, int64_t n, const int64_t *ro
  * Errors: QBSM_ERR_ARG for eps < 0 or NaN; QBSM_ERR_STATE without blocks. */
 qbsm_status qbsm_matrix_truncate(qbsm_matrix m, double eps, void *stream, int64_t *nkept);
 
+/* Matrix addition (Sec. 2.2, regular addition): C = alpha*A + beta*B on the
+ * union of the two leaf patterns (no leaf is dropped; a missing block counts
+ * as zero).  Each element is rounded as alpha*a, beta*b and their sum, in
+ * FP64; the result is stored in FP64.  C must have A's shape and leaf size
+ * and must not be A or B; its previous content is replaced.  Errors:
+ * QBSM_ERR_SHAPE for differing shapes, QBSM_ERR_ARG for aliasing or a
+ * non-finite coefficient, QBSM_ERR_STATE without blocks.  Synchronises. */
+qbsm_status qbsm_matrix_add(double alpha, qbsm_matrix A, double beta, qbsm_matrix B, qbsm_matrix C,
+                            void *stream);
+
+/* Addition of a scaled identity (Sec. 2.2), in place: A += sigma*I, sigma
+ * added to the elements (r, r), r < min(nrows, ncols); missing diagonal
+ * leaves are created.  The result is stored in FP64.  Errors: QBSM_ERR_ARG
+ * for a non-finite sigma, QBSM_ERR_STATE without blocks.  Synchronises. */
+qbsm_status qbsm_matrix_add_identity(qbsm_matrix A, double sigma, void *stream);
+
 /* Extraction of selected blocks (Sec. 2.2, extraction of the elements given
  * by index vectors, at leaf-block granularity): for q in [0, n), block
  * (brow[q], bcol[q]) is written as an FP64 column-major bs x bs block to

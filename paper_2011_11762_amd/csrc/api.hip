@@ -251,6 +251,21 @@ qbsm_status qbsm_matrix_truncate(qbsm_matrix m, double eps, void *stream, int64_
     });
 }
 
+qbsm_status qbsm_matrix_add(double alpha, qbsm_matrix A, double beta, qbsm_matrix B, qbsm_matrix C,
+                            void *stream) {
+    return guard([&] {
+        QB_CHECK(A && B && C, QBSM_ERR_ARG, "null matrix");
+        matrix_add(alpha, A->m, beta, B->m, C->m, as_stream(stream));
+    });
+}
+
+qbsm_status qbsm_matrix_add_identity(qbsm_matrix A, double sigma, void *stream) {
+    return guard([&] {
+        QB_CHECK(A, QBSM_ERR_ARG, "null matrix");
+        matrix_add_identity(A->m, sigma, as_stream(stream));
+    });
+}
+
 qbsm_status qbsm_matrix_prepack(qbsm_matrix m, qbsm_mode mode, int32_t roles, void *stream) {
     return guard([&] {
         QB_CHECK(m, QBSM_ERR_ARG, "null matrix");

@@ -220,6 +220,8 @@ int64_t matrix_set_elements(Matrix &m, int64_t n, const int64_t *row, const int6
 void matrix_get_elements(Matrix &m, int64_t n, const int64_t *row, const int64_t *col, double *val,
                          hipStream_t s);
 int64_t matrix_truncate(Matrix &m, double eps, hipStream_t s);
+void matrix_add(double alpha, Matrix &A, double beta, Matrix &B, Matrix &C, hipStream_t s);
+void matrix_add_identity(Matrix &A, double sigma, hipStream_t s);
 void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t s);
 
 // Packs operand values for (mode, role); returns the device buffer and the

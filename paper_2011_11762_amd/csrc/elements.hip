@@ -1,6 +1,7 @@
-// Element-level assignment and extraction, and truncation with error control
-// (the construction, extraction and truncation task types of Sec. 2.2), on
-// the block-sparse storage: Morton-ordered leaves, column-major inside.
+// Element-level assignment and extraction, truncation with error control and
+// matrix addition (the construction, extraction, truncation and addition task
+// types of Sec. 2.2), on the block-sparse storage: Morton-ordered leaves,
+// column-major inside.
 #include <cmath>
 
 #include <hipcub/hipcub.hpp>
@@ -226,6 +227,141 @@ int64_t matrix_truncate(Matrix &m, double eps, hipStream_t s) {
     m.nblk = nk;
     commit_new_pattern(m, s);
     return nk;
+}
+
+}  // namespace qbsm
+
+// ------------------------------------------------------------------ addition
+namespace qbsm {
+
+namespace {
+
+// Diagonal block keys 0 .. nbd-1 appended after the first operand's keys.
+__global__ void k_diag_keys(int64_t nbd, uint32_t *keys) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nbd) keys[t] = block_key((uint32_t)t, (uint32_t)t);
+}
+
+__global__ void k_union_keys(const uint32_t *keys, const int32_t *rank, int64_t n, uint32_t *okeys) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) okeys[rank[t]] = keys[t];  // equal keys write equal values
+}
+
+// out[rank[t]] += coef * src[t], block by block; one workgroup per block.
+// Products and sums are rounded separately (contraction off), so that
+// alpha*a + beta*b is rounded as two products and one sum.
+template <class T>
+__global__ void __launch_bounds__(256) k_add_scaled(const T *src, const int32_t *rank, int64_t n, int64_t n2,
+                                                    double coef, double *out) {
+    const int64_t t = blockIdx.x;
+    if (t >= n) return;
+    double *o = out + (int64_t)rank[t] * n2;
+    const T *x = src + t * n2;
+    for (int64_t e = threadIdx.x; e < n2; e += 256) {
+#pragma clang fp contract(off)
+        const double p = coef * (double)x[e];
+        o[e] = o[e] + p;
+    }
+}
+
+// sigma on the diagonal elements (r, r), r < nd, of the diagonal blocks.
+__global__ void k_add_diag(const int32_t *rank, int64_t nbd, int32_t bs, int64_t nd, double sigma, double *out) {
+    const int64_t t = blockIdx.x;
+    if (t >= nbd) return;
+    const int64_t n2 = (int64_t)bs * bs;
+    for (int r = threadIdx.x; r < bs; r += blockDim.x) {
+        if (t * bs + r >= nd) continue;
+        double *o = out + (int64_t)rank[t] * n2 + r + (int64_t)r * bs;
+        *o = *o + sigma;
+    }
+}
+
+void add_operand(const Matrix &m, const int32_t *rank, double coef, double *pool, hipStream_t s) {
+    const int64_t n2 = (int64_t)m.bs * m.bs;
+    if (!m.nblk) return;
+    if (m.storage == ST_F32)
+        k_add_scaled<float><<<(unsigned)m.nblk, 256, 0, s>>>(m.v32.p, rank, m.nblk, n2, coef, pool);
+    else
+        k_add_scaled<double><<<(unsigned)m.nblk, 256, 0, s>>>(m.v64.p, rank, m.nblk, n2, coef, pool);
+    QB_LAUNCH_CHECK();
+}
+
+// Union of the stored keys of a (and of b, or of the diagonal blocks), ranked
+// in Morton order; returns the number of distinct leaves (host read).
+int64_t union_rank(const Matrix &a, const Matrix *b, int64_t nbd, DArr<uint32_t> &keys, DArr<int32_t> &rank,
+                   DArr<uint32_t> &okeys, hipStream_t s) {
+    const int64_t na = a.nblk, nb = b ? b->nblk : nbd;
+    const int64_t n = na + nb;
+    keys.alloc(n ? n : 1, s);
+    rank.alloc(n ? n : 1, s);
+    if (na) QB_HIP(hipMemcpyAsync(keys.p, a.keys.p, na * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (b && nb) QB_HIP(hipMemcpyAsync(keys.p + na, b->keys.p, nb * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (!b && nb) {
+        k_diag_keys<<<grid_for(nb, 256), 256, 0, s>>>(nb, keys.p + na);
+        QB_LAUNCH_CHECK();
+    }
+    const uint64_t range = (uint64_t)1 << (2 * ceil_log2(a.nbr > a.nbc ? a.nbr : a.nbc));
+    DArr<int32_t> dummy(1, s);
+    DArr<int64_t> cnt(1, s);
+    bitmap_rank(keys.p, nullptr, n, range, rank.p, dummy.p, cnt.p, s);
+    const int64_t nu = n ? read_back(cnt.p, s) : 0;
+    okeys.alloc(nu ? nu : 1, s);
+    if (n) {
+        k_union_keys<<<grid_for(n, 256), 256, 0, s>>>(keys.p, rank.p, n, okeys.p);
+        QB_LAUNCH_CHECK();
+    }
+    return nu;
+}
+
+void commit_values(Matrix &m, DArr<uint32_t> &okeys, DArr<double> &pool, int64_t nblk, hipStream_t s) {
+    m.keys = std::move(okeys);
+    m.v64 = std::move(pool);
+    m.v32.reset();
+    m.nblk = nblk;
+    m.storage = ST_F64;
+    commit_new_pattern(m, s);
+}
+
+}  // namespace
+
+void matrix_add(double alpha, Matrix &A, double beta, Matrix &B, Matrix &C, hipStream_t s) {
+    QB_CHECK(A.has_blocks && B.has_blocks, QBSM_ERR_STATE, "matrix has no blocks yet");
+    QB_CHECK(A.nrows == B.nrows && A.ncols == B.ncols && A.bs == B.bs, QBSM_ERR_SHAPE, "operands differ in shape");
+    QB_CHECK(C.nrows == A.nrows && C.ncols == A.ncols && C.bs == A.bs, QBSM_ERR_SHAPE, "output shape differs");
+    QB_CHECK(&C != &A && &C != &B, QBSM_ERR_ARG, "output aliases an operand");
+    QB_CHECK(std::isfinite(alpha) && std::isfinite(beta), QBSM_ERR_ARG, "alpha and beta must be finite");
+    matrix_settle(A, s);
+    matrix_settle(B, s);
+    matrix_settle(C, s);
+    DArr<uint32_t> keys, okeys;
+    DArr<int32_t> rank;
+    const int64_t nu = union_rank(A, &B, 0, keys, rank, okeys, s);
+    const int64_t n2 = (int64_t)A.bs * A.bs;
+    DArr<double> pool(nu ? nu * n2 : 1, s);
+    if (nu) fill_bytes_zero(pool.p, nu * n2 * sizeof(double), s);
+    add_operand(A, rank.p, alpha, pool.p, s);
+    add_operand(B, rank.p + A.nblk, beta, pool.p, s);
+    commit_values(C, okeys, pool, nu, s);
+}
+
+void matrix_add_identity(Matrix &A, double sigma, hipStream_t s) {
+    QB_CHECK(A.has_blocks, QBSM_ERR_STATE, "matrix has no blocks yet");
+    QB_CHECK(std::isfinite(sigma), QBSM_ERR_ARG, "sigma must be finite");
+    matrix_settle(A, s);
+    const int64_t nd = A.nrows < A.ncols ? A.nrows : A.ncols;
+    const int64_t nbd = (nd + A.bs - 1) / A.bs;
+    DArr<uint32_t> keys, okeys;
+    DArr<int32_t> rank;
+    const int64_t nu = union_rank(A, nullptr, nbd, keys, rank, okeys, s);
+    const int64_t n2 = (int64_t)A.bs * A.bs;
+    DArr<double> pool(nu ? nu * n2 : 1, s);
+    if (nu) fill_bytes_zero(pool.p, nu * n2 * sizeof(double), s);
+    add_operand(A, rank.p, 1.0, pool.p, s);
+    if (nbd) {
+        k_add_diag<<<(unsigned)nbd, 64, 0, s>>>(rank.p + A.nblk, nbd, A.bs, nd, sigma, pool.p);
+        QB_LAUNCH_CHECK();
+    }
+    commit_values(A, okeys, pool, nu, s);
 }
 
 }  // namespace qbsm

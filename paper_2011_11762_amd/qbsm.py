@@ -57,6 +57,8 @@ _SIGS = {
     "qbsm_matrix_set_elements": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int64)],
     "qbsm_matrix_get_elements": [c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_matrix_truncate": [c_void_p, c_double, c_void_p, POINTER(c_int64)],
+    "qbsm_matrix_add": [c_double, c_void_p, c_double, c_void_p, c_void_p, c_void_p],
+    "qbsm_matrix_add_identity": [c_void_p, c_double, c_void_p],
     "qbsm_matrix_info": [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)],
     "qbsm_matrix_get_pattern": [c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_matrix_get_values": [c_void_p, c_void_p, c_void_p],
@@ -200,6 +202,10 @@ class Matrix:
         _check(_lib.qbsm_matrix_truncate(self._h, float(eps), _stream(), ctypes.byref(k)))
         return k.value
 
+    def add_identity(self, sigma: float):
+        """In place: self += sigma * I."""
+        _check(_lib.qbsm_matrix_add_identity(self._h, float(sigma), _stream()))
+
     def prepack(self, mode="bf16x3", roles: int = 3):
         """Pack the values for `mode` ahead of use on the library's side stream.
 
@@ -287,6 +293,13 @@ class Plan:
             out = Matrix(self.nrows, self.ncols, self.bs)
         _check(_lib.qbsm_multiply_numeric(self._h, mode_id(mode), out.handle, _stream()))
         return out
+
+
+def add(alpha: float, A: Matrix, beta: float, B: Matrix) -> Matrix:
+    """alpha A + beta B on the union of the leaf patterns (FP64)."""
+    C = Matrix(A.nrows, A.ncols, A.bs)
+    _check(_lib.qbsm_matrix_add(float(alpha), A.handle, float(beta), B.handle, C.handle, _stream()))
+    return C
 
 
 def matmul(A: Matrix, B: Matrix, mode="f64", unit: int = 0, spamm_tol: float = 0.0) -> Matrix:

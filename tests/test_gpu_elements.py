@@ -140,3 +140,39 @@ def test_empty_and_degenerate_new_operations(q):
     U1 = q.Plan(S1, S1, upper=True).numeric("f64")
     full = q.matmul(S1, S1, "f64")
     assert np.array_equal(values_np(U1), values_np(full))
+
+
+@pytest.mark.parametrize("bs", [32, 64])
+def test_matrix_addition(q, bs):
+    """alpha A + beta B and A + sigma I against the oracle, bit for bit (each
+    element is two rounded products and one rounded sum on both sides);
+    FP32-stored operands; the sum then feeds a multiply."""
+    rng = np.random.default_rng(30 + bs)
+    n, m = 9 * bs + 3, 7 * bs + 11
+    a = W.random_blocks(n, bs, 0.3, rng, ncols=m)
+    b = W.random_blocks(n, bs, 0.3, rng, ncols=m)
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    A, B = upload(q, a), upload(q, b)
+    C = q.add(0.75, A, -1.5, B)
+    ref = O.add(0.75, oa, -1.5, ob)
+    cr, cc = pattern_np(C)
+    assert np.array_equal(cr, ref.brow) and np.array_equal(cc, ref.bcol)
+    assert np.array_equal(values_np(C), ref.vals)
+    # FP32 storage of one operand: its values widened exactly
+    B.store_f32()
+    ob32 = O.OMatrix(ob.nrows, ob.ncols, bs, ob.brow, ob.bcol, O.round_to_f32(ob.vals))
+    assert np.array_equal(values_np(q.add(2.0, A, 1.0, B)), O.add(2.0, oa, 1.0, ob32).vals)
+    # scaled identity, in place, creating missing diagonal leaves
+    S = upload(q, a)
+    S.add_identity(-3.25)
+    refi = O.add_identity(oa, -3.25)
+    sr, sc = pattern_np(S)
+    assert np.array_equal(sr, refi.brow) and np.array_equal(sc, refi.bcol)
+    assert np.array_equal(values_np(S), refi.vals)
+    # (A + B) X through the multiply
+    x = W.random_blocks(m, bs, 0.4, rng, ncols=5 * bs)
+    got = values_np(q.matmul(q.add(1.0, A, 1.0, upload(q, b)), upload(q, x), "f64"))
+    want = O.multiply(O.add(1.0, oa, 1.0, ob), O.from_workload(x))
+    assert O.rel_fro(got, want.vals) <= TOL["f64"]
+    with pytest.raises(q.QbsmError):
+        q.add(1.0, A, 1.0, upload(q, W.random_blocks(n, bs, 0.3, rng, ncols=m + bs)))
