@@ -325,7 +325,12 @@ qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC,
 qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode,
                               qbsm_matrix *outs, void *stream, qbsm_batch *batch);
 /* Launch-only part (operand packing + the persistent kernel); no allocation
- * and no synchronisation, so it may be captured into a HIP graph. */
+ * and no synchronisation, so it may be captured into a HIP graph.  Before any
+ * launch it checks that the batch still matches its matrices: errors
+ * QBSM_ERR_STATE if a member plan is stale (an operand's pattern changed), an
+ * operand's values were stored again (new pack buffers) or an output was
+ * filled by another plan since qbsm_batch_create; create the batch again.
+ * The batch's outputs and operands must outlive it. */
 qbsm_status qbsm_batch_run(qbsm_batch batch, void *stream);
 /* Captures qbsm_batch_run into a HIP graph on first use, then replays it. */
 qbsm_status qbsm_batch_run_graph(qbsm_batch batch, void *stream);

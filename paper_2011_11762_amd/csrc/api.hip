@@ -420,13 +420,19 @@ qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode,
             hm[i] = make_member(p, mode, outs[i]->m, s);
             b.plans.push_back(&p);
             b.outs.push_back(&outs[i]->m);
+            b.out_vals.push_back(outs[i]->m.storage == ST_F64 ? (const void *)outs[i]->m.v64.p
+                                                              : (const void *)outs[i]->m.v32.p);
+            b.out_pattern.push_back(outs[i]->m.pattern_id);
             // operand packs replayed on each run
             for (int side = 0; side < 2; ++side) {
                 Matrix *mm = side == 0 ? p.L : p.R;
                 Role role = side == 0 ? (p.transL ? ROLE_COL : ROLE_ROW) : (p.transR ? ROLE_ROW : ROLE_COL);
                 bool seen = false;
                 for (auto &j : b.packs) seen |= (j.m == mm && j.mode == mode && j.role == role);
-                if (!seen) b.packs.push_back({mm, mode, role});
+                if (!seen) {
+                    const Pack &pk = mm->packs[std::make_pair((int)mode, (int)role)];
+                    b.packs.push_back({mm, mode, role, pk.buf.p, pk.buf.n});
+                }
             }
             // per-unit cost: number of node pairs (read back for ordering)
             std::vector<int32_t> us(p.nunits + 1);

@@ -290,12 +290,19 @@ struct Batch {
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
     // packing jobs replayed on every run
-    struct PackJob { Matrix *m; qbsm_mode mode; Role role; };
+    // buf / bytes: the pack buffer the member records point to; out_vals /
+    // out_pattern: each output's value buffer and pattern id.  A run checks
+    // that all are still in place.
+    struct PackJob { Matrix *m; qbsm_mode mode; Role role; const void *buf; size_t bytes; };
     std::vector<PackJob> packs;
+    std::vector<const void *> out_vals;
+    std::vector<uint64_t> out_pattern;
 };
 
 void batch_launch(Batch &b, hipStream_t s);
-// Orders s after pending packs of the batch's operands (call outside capture).
+// Checks that the batch's plans, packs and outputs are still the ones its
+// member records point to (QBSM_ERR_STATE otherwise), then orders s after
+// pending packs of its operands (call outside capture).
 void batch_settle(Batch &b, hipStream_t s);
 void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s);
 void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t nmembers_host_unused,

@@ -873,7 +873,19 @@ void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
 
 // ------------------------------------------------------------------ batched
 void batch_settle(Batch &b, hipStream_t s) {
-    for (auto &j : b.packs) j.m->packs[std::make_pair((int)j.mode, (int)j.role)].settle(s);
+    for (Plan *p : b.plans) plan_check_current(*p);
+    for (size_t i = 0; i < b.outs.size(); ++i) {
+        const Matrix &o = *b.outs[i];
+        const void *v = o.storage == ST_F64 ? (const void *)o.v64.p : (const void *)o.v32.p;
+        QB_CHECK(v == b.out_vals[i] && o.pattern_id == b.out_pattern[i], QBSM_ERR_STATE,
+                 "a batch output was replaced after the batch was created");
+    }
+    for (auto &j : b.packs) {
+        Pack &pk = j.m->packs[std::make_pair((int)j.mode, (int)j.role)];
+        QB_CHECK(pk.buf.p == j.buf && pk.buf.n == j.bytes, QBSM_ERR_STATE,
+                 "an operand's values were re-stored after the batch was created (create the batch again)");
+        pk.settle(s);
+    }
 }
 
 void batch_launch(Batch &b, hipStream_t s) {

@@ -106,3 +106,33 @@ def test_symmetric_rank_k(q, bs):
             cr, cc = pattern_np(C)
             assert np.array_equal(cr, full.brow[keep]) and np.array_equal(cc, full.bcol[keep])
             assert O.rel_fro(values_np(C), full.vals[keep]) <= TOL[mode], (mode, unit)
+
+
+def test_batch_rejects_replaced_operands_and_outputs(q):
+    """A batch run after an operand's values were re-stored (new pack
+    buffers) or after an output was refilled by another plan is an error
+    raised before anything is launched; a fresh batch works."""
+    c = W.config2(npoints=1500, bs=64, seed=24)
+    A = upload(q, c["A"], c["drop_tol"])
+    P = q.Plan(A, A, unit=128)
+    batch = q.Batch([P], "f32")
+    batch.run()
+    torch.cuda.synchronize()
+    first = values_np(batch.outs[0])
+    A.store_f32()  # same pattern, new value storage: the batch's packs are gone
+    with pytest.raises(q.QbsmError):
+        batch.run()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with pytest.raises(q.QbsmError):
+            batch.run_graph()
+    stream.synchronize()
+    fresh = q.Batch([P], "f32")
+    fresh.run()
+    torch.cuda.synchronize()
+    assert np.array_equal(values_np(fresh.outs[0]), first)  # f32 packs of rounded values are the same
+    # an output refilled by a different plan
+    P2 = q.Plan(A, A, unit=128)
+    P2.numeric("f32", fresh.outs[0])
+    with pytest.raises(q.QbsmError):
+        fresh.run()
