@@ -47,17 +47,17 @@ KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "e54ff67eaf9853d5",
+    "sources_sha256_16": "165440bee26585f8",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 118978079104,
-        "bf16x3@256": 52111012224,
-        "bf16x3@64": 331969667627,
-        "f32@128": 208975380181,
-        "f32@256": 68142751829,
-        "f32@64": 337773168960,
-        "f64@128": 283733336811,
-        "f64@64": 729210711595,
+        "bf16x3@128": 122565018261,
+        "bf16x3@256": 51160638281,
+        "bf16x3@64": 330987160405,
+        "f32@128": 207369210304,
+        "f32@256": 68168690432,
+        "f32@64": 337169398656,
+        "f64@128": 296951149678,
+        "f64@64": 735571384021,
     },
 }
 
