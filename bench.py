@@ -47,17 +47,17 @@ KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "165440bee26585f8",
+    "sources_sha256_16": "bac98c7bb5542313",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 122565018261,
-        "bf16x3@256": 51160638281,
-        "bf16x3@64": 330987160405,
-        "f32@128": 207369210304,
-        "f32@256": 68168690432,
-        "f32@64": 337169398656,
-        "f64@128": 296951149678,
-        "f64@64": 735571384021,
+        "bf16x3@128": 121539910955,
+        "bf16x3@256": 50052018725,
+        "bf16x3@64": 330812222613,
+        "f32@128": 208178071189,
+        "f32@256": 68106300517,
+        "f32@64": 337558545301,
+        "f64@128": 285042906898,
+        "f64@64": 715585925632,
     },
 }
 

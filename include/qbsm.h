@@ -77,9 +77,10 @@ typedef enum {
  *               slices of 8-bit digits on the grid 2^(e - 8t), t = 1..6, each
  *               exact in bfloat16 (the 48 leading bits of the element below
  *               e).  The 21 slice pairs with t + u <= 7 are multiplied; the
- *               products of one pair group (t + u fixed) over a 32-element K
- *               chunk sum exactly in FP32 and are accumulated in FP64; FP64
- *               result.  Needs a plan with unit 64 (see qbsm_plan_opts).
+ *               products of one pair group (t + u fixed) over one leaf sum in
+ *               FP32 (exactly for t + u <= 5; groups 6 and 7 share one sum)
+ *               and are accumulated in FP64; FP64 result.  Needs a plan with
+ *               unit 64 (see qbsm_plan_opts).
  *               An infinite input gives a non-finite result where reached.
  * In every mode a product exists only where both leaf blocks are stored: an
  * Inf or NaN never meets the implicit zeros of a nil block. */

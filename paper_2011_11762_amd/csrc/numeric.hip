@@ -48,6 +48,8 @@ struct MT<QBSM_F64> {
     using Acc = d4;
     using Out = double;
     static constexpr int BK = 16, PARTS = 1, LBMAX = 128, KPG = 16, PPG = 8, SUBS = 2;
+    static constexpr bool LEAF_SUMS = false;
+    struct Part {};
     struct Frag { uint4 q[2]; };
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
         const double2 a0 = __builtin_bit_cast(double2, a[0].q[0]), a1 = __builtin_bit_cast(double2, a[0].q[1]);
@@ -67,6 +69,8 @@ struct MT<QBSM_F32> {
     using Acc = f4;
     using Out = float;
     static constexpr int BK = 32, PARTS = 1, LBMAX = 128, KPG = 16, PPG = 4, SUBS = 1;
+    static constexpr bool LEAF_SUMS = false;
+    struct Part {};
     struct Frag { uint4 q[1]; };
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
         const f4 x = __builtin_bit_cast(f4, a[0].q[0]), y = __builtin_bit_cast(f4, b[0].q[0]);
@@ -85,6 +89,8 @@ struct MT<QBSM_BF16> {
     using Acc = f4;
     using Out = float;
     static constexpr int BK = 64, PARTS = 1, LBMAX = 128, KPG = 32, PPG = 4, SUBS = 1;
+    static constexpr bool LEAF_SUMS = false;
+    struct Part {};
     struct Frag { uint4 q[1]; };
     __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[0].q[0]),
@@ -99,6 +105,8 @@ struct MT<QBSM_BF16X3> {
     using Acc = f4;
     using Out = float;
     static constexpr int BK = 32, PARTS = 2, LBMAX = 64, KPG = 32, PPG = 4, SUBS = 1;
+    static constexpr bool LEAF_SUMS = false;
+    struct Part {};
     struct Frag { uint4 q[1]; };
     // a*b ~ hi*lo + lo*hi + hi*hi (the lo*lo term is below FP32 resolution);
     // a[0]/b[0] are the hi parts, a[1]/b[1] the lo parts
@@ -116,28 +124,41 @@ struct MT<QBSM_BF16X3> {
 // then hold zeros, so the products of a nil leaf add exact zeros.
 __device__ __attribute__((aligned(1024))) uint8_t g_zero_page[1024] = {};
 
-// Ozaki slices (6 per operand, each exact in bfloat16): for every pair group
-// g = t + u (2..7) the products of slice pairs (t, u) over one 32-element K
-// chunk are summed by one MFMA chain in FP32, exactly (each product has at
-// most 16 significant bits on the group's common exponent grid and the chain
-// at most 6 * 32 of them), then added to the FP64 accumulator.
+// Ozaki slices (6 per operand, each exact in bfloat16).  The products of
+// slice pairs (t, u) of one pair group g = t + u (2..7) lie on one exponent
+// grid per leaf (the line exponents are per leaf row / column), each an
+// integer below 2^16 on that grid.  Over one leaf of at most 64 K, groups
+// 2..5 hold at most 4 * 64 such products, so their FP32 MFMA sums are exact
+// (below 2^24 units); groups 6 and 7 share one FP32 sum, whose rounding lies
+// near 2^-48 of the leading group.  At the end of every leaf the five sums
+// are added to the FP64 accumulator and cleared.
 template <>
 struct MT<QBSM_OZAKI_BF16> {
     using T = uint16_t;
     using Acc = d4;
     using Out = double;
     static constexpr int BK = 32, PARTS = 6, LBMAX = 64, KPG = 32, PPG = 4, SUBS = 1;
+    static constexpr bool LEAF_SUMS = true;
+    static constexpr int NSUMS = 5;
+    struct Part { f4 s[NSUMS]; };
     struct Frag { uint4 q[1]; };
-    __device__ static void mma(Acc &c, const Frag *a, const Frag *b) {
+    __device__ static void mma_part(Part &p, const Frag *a, const Frag *b) {
 #pragma unroll
         for (int g = 2; g <= PARTS + 1; ++g) {
-            f4 t = {0.f, 0.f, 0.f, 0.f};
+            const int k = g <= 5 ? g - 2 : 4;
 #pragma unroll
             for (int ta = 1; ta < g; ++ta)
-                t = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[ta - 1].q[0]),
-                                                            __builtin_bit_cast(bf8, b[g - ta - 1].q[0]), t, 0, 0, 0);
+                p.s[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[ta - 1].q[0]),
+                                                                 __builtin_bit_cast(bf8, b[g - ta - 1].q[0]), p.s[k],
+                                                                 0, 0, 0);
+        }
+    }
+    __device__ static void flush(Acc &c, Part &p) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) c[i] += (double)t[i];
+        for (int k = 0; k < NSUMS; ++k) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i] += (double)p.s[k][i];
+            p.s[k] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
     // the FP32 MFMA layout: element i of a lane holds row 4*(lane/16) + i
@@ -434,6 +455,7 @@ __device__ __forceinline__ Advance advance(const Meta &mt, int nb, const Step &s
 template <int MODE, int U, int BS, bool DENSE>
 __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                         typename MT<MODE>::Part (&part)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
                                          Step &st, Advance &nxa, const CopyLane &cl, uint32_t chunk_bytes, int w,
                                          int wr, int wc) {
     using G = Geo<MODE, U, BS>;
@@ -497,7 +519,23 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
                 if (tn + 1 < TPW) read_b(tn + 1, fb[(tn + 1) & 1]);
 #pragma unroll
                 for (int tm = 0; tm < TPW; ++tm)
-                    if (DENSE || ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u)) M::mma(acc[tm][tn], fa[tm], fb[tn & 1]);
+                    if (DENSE || ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u)) {
+                        if constexpr (M::LEAF_SUMS)
+                            M::mma_part(part[tm][tn], fa[tm], fb[tn & 1]);
+                        else
+                            M::mma(acc[tm][tn], fa[tm], fb[tn & 1]);
+                    }
+            }
+        }
+        if constexpr (M::LEAF_SUMS) {
+            // the last chunk of the leaf column: its sums are complete (a
+            // tile without products adds zeros; a wave without leaves in
+            // this column skips the whole block and its sums stay zero)
+            if (st.c == G::NCHUNK - 1) {
+#pragma unroll
+                for (int tm = 0; tm < TPW; ++tm)
+#pragma unroll
+                    for (int tn = 0; tn < TPW; ++tn) M::flush(acc[tm][tn], part[tm][tn]);
             }
         }
     } else if (SPREAD) {
@@ -530,6 +568,15 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
     for (int a = 0; a < TPW; ++a)
 #pragma unroll
         for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
+    typename M::Part part[TPW][TPW];
+    if constexpr (M::LEAF_SUMS) {
+#pragma unroll
+        for (int a = 0; a < TPW; ++a)
+#pragma unroll
+            for (int b = 0; b < TPW; ++b)
+#pragma unroll
+                for (int k = 0; k < M::NSUMS; ++k) part[a][b].s[k] = f4{0.f, 0.f, 0.f, 0.f};
+    }
 
     // (loaded values are not known to be wave-uniform: say so, or every
     // comparison with the batch size makes the step iterator divergent)
@@ -575,9 +622,9 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         // steps alternate between the two stages; unrolled by two so that
         // every access names its stage array at compile time
         while (st.i < nb) {
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, st, nxa, cl, chunk_bytes, w, wr, wc);
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc);
             if (st.i >= nb) break;
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, st, nxa, cl, chunk_bytes, w, wr, wc);
+            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc);
         }
     }
 
