@@ -195,7 +195,9 @@ qbsm_status qbsm_matrix_get_elements(qbsm_matrix m, int64_t n, const int64_t *ro
  * with the leaves ordered by FP64 Frobenius norm ascending (ties in storage
  * order), the longest leading run whose squared norms sum to at most eps^2
  * is removed, so that ||A_before - A_after||_F <= eps.  Leaves with a NaN
- * norm stay.  eps = 0 removes the identically zero leaves only.
+ * norm stay, and so does every leaf from the first at which the running sum
+ * of squared norms is no longer finite (an infinite norm is never within
+ * eps, however large).  eps = 0 removes the identically zero leaves only.
  *   nkept : host out, leaves left.  Synchronises the stream.
  * Errors: QBSM_ERR_ARG for eps < 0 or NaN; QBSM_ERR_STATE without blocks. */
 qbsm_status qbsm_matrix_truncate(qbsm_matrix m, double eps, void *stream, int64_t *nkept);

@@ -177,9 +177,11 @@ def truncate_error_control(a: OMatrix, eps: float) -> OMatrix:
     with the leaves ordered by FP64 Frobenius norm ascending (ties by storage
     position), the longest leading run whose squared norms sum to at most
     eps^2 is removed, so the removed part has Frobenius norm <= eps.  Leaves
-    with a NaN norm stay.  Reading: the paper names truncation with several
-    variants of error control without formulas; this is the Frobenius-norm
-    variant.
+    with a NaN norm stay, and so does every leaf from the first one at which
+    the running sum of squared norms stops being finite (an infinite norm is
+    never within eps; a sum that overflows only makes the cut conservative).
+    Reading: the paper names truncation with several variants of error
+    control without formulas; this is the Frobenius-norm variant.
     """
     if a.nblk == 0:
         return a
@@ -187,7 +189,7 @@ def truncate_error_control(a: OMatrix, eps: float) -> OMatrix:
     sq = n * n
     order = np.lexsort((np.arange(a.nblk), sq))  # NaN last
     csum = np.cumsum(sq[order])
-    k = int(np.count_nonzero(csum <= eps * eps))
+    k = int(np.count_nonzero((csum <= eps * eps) & np.isfinite(csum)))
     keep = np.ones(a.nblk, dtype=bool)
     keep[order[:k]] = False
     return OMatrix(a.nrows, a.ncols, a.bs, a.brow[keep], a.bcol[keep], np.ascontiguousarray(a.vals[keep]))

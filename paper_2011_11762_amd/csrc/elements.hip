@@ -81,12 +81,14 @@ __global__ void k_sq_norms(const double *norms, int64_t n, double *sq, int32_t *
     idx[t] = (int32_t)t;
 }
 
-// Number of leading partial sums <= lim (the sums do not decrease).
+// Number of leading partial sums that are finite and <= lim (the sums do
+// not decrease, and stay infinite or NaN once they are): an infinite norm is
+// never within the bound, also where lim itself overflows.
 __global__ void k_cut(const double *csum, int64_t n, double lim, int64_t *k) {
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         const int64_t mid = (lo + hi) >> 1;
-        if (csum[mid] <= lim) lo = mid + 1;
+        if (csum[mid] <= lim && isfinite(csum[mid])) lo = mid + 1;
         else hi = mid;
     }
     *k = lo;

@@ -89,6 +89,25 @@ def test_truncate_error_control(q, store_f32):
         A.truncate(-1.0)
 
 
+def test_truncate_keeps_infinite_norms(q):
+    """A leaf with an infinite norm stays for every eps, also where eps^2
+    overflows; so does a leaf whose squared norm overflows."""
+    rng = np.random.default_rng(12)
+    a = W.random_blocks(600, 32, 0.4, rng)
+    a.vals[4, 9] = np.inf
+    a.vals[8] *= 1e170
+    oa = O.from_workload(a)
+    with np.errstate(over="ignore"):
+        for eps in (1e-3, 1e200, np.finfo(np.float64).max):
+            ref = O.truncate_error_control(oa, eps)
+            A = upload(q, a)
+            assert A.truncate(eps) == ref.nblk
+            pr, pc = pattern_np(A)
+            assert np.array_equal(pr, ref.brow) and np.array_equal(pc, ref.bcol), eps
+            assert np.array_equal(values_np(A), ref.vals)
+    assert ref.nblk == 2
+
+
 def test_truncate_product(q):
     """Truncation of a multiply's FP32 result, then a second multiply with it."""
     c = W.config2(npoints=2000, bs=32, seed=19)

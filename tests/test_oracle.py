@@ -643,6 +643,27 @@ def test_truncation_error_control():
     assert O.truncate_error_control(a, 0.0).nblk == a.nblk
 
 
+def test_truncation_keeps_infinite_norms():
+    """A leaf with an infinite element has an infinite norm, which no eps
+    bounds: it stays even where eps^2 overflows, while the finite small
+    leaves still go.  Leaves whose squared norms overflow are kept too (the
+    removed part must be shown to be within eps)."""
+    rng = np.random.default_rng(11)
+    a = O.from_workload(W.random_blocks(96, 16, 0.6, rng))
+    a.vals[3, 5] = np.inf
+    a.vals[7] *= 1e170                       # squared norm overflows
+    for eps in (1e-3, 1e200, np.finfo(np.float64).max):
+        with np.errstate(over="ignore"):
+            t = O.truncate_error_control(a, eps)
+        kept = set(zip(t.brow.tolist(), t.bcol.tolist()))
+        assert (a.brow[3], a.bcol[3]) in kept and (a.brow[7], a.bcol[7]) in kept
+        dropped = [i for i in range(a.nblk) if (a.brow[i], a.bcol[i]) not in kept]
+        err = np.sqrt(sum(float(np.sum(a.vals[i] ** 2)) for i in dropped))
+        assert err <= eps
+        if eps >= 1e200:                     # every finite, non-overflowing leaf goes
+            assert t.nblk == 2
+
+
 # ---------------------------------------------------------------- addition
 def test_addition_against_dense():
     rng = np.random.default_rng(12)
