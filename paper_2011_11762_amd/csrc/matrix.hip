@@ -438,6 +438,30 @@ __global__ void __launch_bounds__(256) k_oz_exp(const Src *src, int64_t nblk, in
     ex[t] = e;
 }
 
+// The same exponents for the columns of the leaves (right operand): one wave
+// per column, lane r reading row r (a column is contiguous, so the wave's
+// reads are coalesced), then a maximum over the wave.
+template <class Src>
+__global__ void __launch_bounds__(256) k_oz_exp_col(const Src *src, int64_t nblk, int32_t bs, int32_t *ex) {
+    const int64_t line = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int r = (int)(threadIdx.x & 63);
+    if (line >= nblk * bs) return;  // the same for every lane of the wave
+    const int64_t leaf = line / bs;
+    const int64_t c = line - leaf * bs;
+    double m = 0.0;
+    if (r < bs) {
+        const double v = fabs((double)src[leaf * (int64_t)bs * bs + c * bs + r]);
+        if (isfinite(v)) m = v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if (r == 0) {
+        int e = 0;
+        if (m > 0.0) (void)frexp(m, &e);
+        ex[line] = e;
+    }
+}
+
 // One 16-byte piece (8 elements) of one packed line, all 6 slices: element x
 // with line exponent e is cut into N = floor(|x| 2^(48 - e)) < 2^48 and slice
 // t holds sign(x) * digit_t(N) * 2^(e - 8t), digit t being bits
@@ -755,11 +779,18 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) 
     fill_i32(pk.nonfinite.p, 0, 1, s);
     if (mode == QBSM_OZAKI_BF16) {
         const unsigned ge = grid_for(m.nblk * m.bs, 256);
+        const unsigned gc = grid_for(m.nblk * m.bs * 64, 256);
         if (m.storage == ST_F64) {
-            k_oz_exp<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, (int)role, pk.aux.p);
+            if (role == ROLE_COL)
+                k_oz_exp_col<double><<<gc, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, pk.aux.p);
+            else
+                k_oz_exp<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, (int)role, pk.aux.p);
             k_pack_oz<double><<<g, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, bk, (int)role, pk.aux.p, dst, pk.nonfinite.p);
         } else {
-            k_oz_exp<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, (int)role, pk.aux.p);
+            if (role == ROLE_COL)
+                k_oz_exp_col<float><<<gc, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, pk.aux.p);
+            else
+                k_oz_exp<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, (int)role, pk.aux.p);
             k_pack_oz<float><<<g, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, bk, (int)role, pk.aux.p, dst, pk.nonfinite.p);
         }
         QB_LAUNCH_CHECK();
