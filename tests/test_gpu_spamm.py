@@ -51,7 +51,7 @@ def test_spamm_decay_against_oracle(q, npoints, bs):
         bound = prodn[prodn < tau].sum()
         if tau == 1e-1:  # here leaving a product in would show at every mode's tolerance
             assert O.rel_fro(_embed(ref, exact), exact.vals) > 10 * TOL["bf16x3"]
-        for mode in ("f64", "bf16x3"):
+        for mode in ("f64", "bf16x3", "ozaki"):
             for unit in units(bs, mode):
                 P = q.Plan(A, A, unit=unit, spamm_tol=tau)
                 info = P.info()

@@ -30,7 +30,7 @@ def test_symmetric_square_decay(q, npoints, bs):
     oa = O.from_workload(a, tol)
     ref = O.multiply_upper(oa, oa)
     A = upload(q, a, tol)
-    for mode in ("f64", "f32", "bf16x3"):
+    for mode in ("f64", "f32", "bf16x3", "ozaki"):
         for unit in units(bs, mode):
             P = q.Plan(A, A, unit=unit, upper=True)
             info = P.info()
@@ -97,7 +97,7 @@ def test_symmetric_rank_k(q, bs):
     I, J, K, _, _ = O.product_triples(oa, oa, trans_b=True)
     sel = I <= J
     A = upload(q, a)
-    for mode in ("f64", "f32", "bf16x3"):
+    for mode in ("f64", "f32", "bf16x3", "ozaki"):
         for unit in units(bs, mode):
             P = q.Plan(A, A, trans_r=True, unit=unit, upper=True)
             gI, gK, gJ = (t.cpu().numpy().astype(np.int64) for t in P.products())
