@@ -71,10 +71,11 @@ def parse():
     ap.add_argument("--unit", type=int, default=0,
                     help="work-unit side; 0 = chosen per mode by the library's autotuner before timing")
     ap.add_argument("--npoints", type=int, default=16384)
-    ap.add_argument("--workload", default="decay", choices=["decay", "banded", "growing", "random", "batched"],
+    ap.add_argument("--workload", default="decay", choices=["decay", "banded", "growing", "random", "batched", "backward"],
                     help="decay: the 3-D decay matrix (headline); banded/growing/random: the paper's "
                          "weak-scaling sequences (Sec. 3, Table 1) at size --n; batched: 256 FP32 "
-                         "multiplies of uneven sizes in one persistent launch replayed as a HIP graph")
+                         "multiplies of uneven sizes in one persistent launch replayed as a HIP graph; "
+                         "backward: forward and masked backward on banded N 16384 with FP32 entries")
     ap.add_argument("--n", type=int, default=100000, help="matrix size of the paper's sequences")
     ap.add_argument("--sym-square", action="store_true",
                     help="also time the symmetric square (upper-triangle blocks only) of the chosen mode")
@@ -245,6 +246,74 @@ def batched_main(args, torch, qbsm, W):
     print(json.dumps(out), flush=True)
 
 
+def backward_main(args, torch, qbsm, W):
+    """Forward C = A*B and the masked backward (dA on A's pattern, dB on B's)
+    on the banded workload with FP32 entries (N 16384, 64x64 leaves, block
+    half-bandwidth 6, dC on C's pattern).  A step is one backward call: the
+    two masked symbolic walks and both numeric phases, with the inputs in
+    HBM; the forward (symbolic + numeric) is timed beside it.  The backward
+    reuses every forward leaf product once for dA and once for dB."""
+    c = W.config5()
+    A, B, dC = qbsm.from_host(c["A"]), qbsm.from_host(c["B"]), qbsm.from_host(c["dC"])
+    info = qbsm.Plan(A, B).info()
+    fwd_flops, bwd_flops = info["flops"], 2 * info["flops"]
+
+    def timed(fn):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps * 1e3
+
+    modes = [m for m in args.modes.split(",") if m and m != args.mode] + [args.mode]
+    results = {}
+    for mode in modes:
+        fwd = timed(lambda: qbsm.matmul(A, B, mode))
+        bwd = timed(lambda: qbsm.backward(A, B, dC, mode))
+        results[mode] = {"forward_ms": round(fwd, 4), "forward_gflops": round(fwd_flops / (fwd * 1e-3) / 1e9, 2),
+                         "backward_ms": round(bwd, 4), "backward_gflops": round(bwd_flops / (bwd * 1e-3) / 1e9, 2)}
+        print(f"[bench] {mode}: forward {fwd:.3f} ms, backward {bwd:.3f} ms "
+              f"({results[mode]['backward_gflops']} GFLOP/s)", file=sys.stderr, flush=True)
+    ch = results[args.mode]
+    achieved = MFMA_TERMS[args.mode] * bwd_flops / (ch["backward_ms"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": ch["backward_gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(args.warmup, 1),
+        "ms_per_step": ch["backward_ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.mode],
+        "data": "synthetic",
+        "config": {
+            "workload": f"banded-n16384-bs64-h6-fp32-entries masked backward ({info['nprod']} forward leaf "
+                        f"products, each used for dA and for dB)",
+            "mode": args.mode,
+            "flops_per_step": bwd_flops,
+            "step": "one backward call: masked symbolic walks for dA and dB + both numeric phases",
+        },
+        "roofline": {
+            "bound": "mfma",
+            "achieved": round(achieved, 2),
+            "peak": PEAK_TFLOPS[args.mode],
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[args.mode], 4),
+            "traffic": None,
+            "kernel": "whole backward call (symbolic walks included): a small, launch-bound workload",
+        },
+        "modes": results,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -260,6 +329,9 @@ def main():
     qbsm.load()
     if args.workload == "batched":
         batched_main(args, torch, qbsm, W)
+        return
+    if args.workload == "backward":
+        backward_main(args, torch, qbsm, W)
         return
     bs = 64
     t_gen = time.perf_counter()
