@@ -165,9 +165,13 @@ qbsm_status qbsm_matrix_info(qbsm_matrix m, int64_t *nrows, int64_t *ncols, int3
  * canonical row-major (I, J) order into device int32[nblk] arrays. */
 qbsm_status qbsm_matrix_get_pattern(qbsm_matrix m, int32_t *brow, int32_t *bcol, void *stream);
 
-/* Values of the stored blocks, same canonical order, as FP64 column-major
- * blocks into device double[nblk * bs * bs].  Results of an FP32 mode are
- * widened exactly. */
+/* Extraction (Sec. 2.2; leaf matrices are stored column-wise, Sec. 2.1):
+ * the values of the stored blocks, in the canonical order of
+ * qbsm_matrix_get_pattern, as FP64 column-major blocks into device
+ * double[nblk * bs * bs] (caller-owned).  Results of an FP32 mode are
+ * widened exactly; padding beyond the logical size reads as zero.
+ * Errors: QBSM_ERR_ARG for a null array when blocks are stored.  Does not
+ * synchronise. */
 qbsm_status qbsm_matrix_get_values(qbsm_matrix m, double *vals, void *stream);
 
 /* Construction from elements (Sec. 2.2, assignment from vectors of row
@@ -297,14 +301,26 @@ qbsm_status qbsm_plan_get_products(qbsm_plan p, int32_t *I, int32_t *K, int32_t 
 
 qbsm_status qbsm_plan_destroy(qbsm_plan p);
 
-/* Numeric phase: leaf-block products on the matrix cores with a segmented,
- * atomic-free accumulation -- every output block is owned by one workgroup,
- * which sums its products with the contraction index ascending and writes
- * the block once.  `out` receives the plan's output pattern and values
- * (result storage FP64 for QBSM_F64, FP32 otherwise); its shape must be
- * rows(op(L)) x cols(op(R)) with the same bs.  Does not synchronise.
+/* Numeric phase of the regular multiply (Sec. 2.2), the part the paper
+ * leaves to its leaf library (Sec. 2.1: a leaf is a small dense matrix whose
+ * product is one dense kernel call; Sec. 3 runs that call on 64 x 64 blocks
+ * inside larger leaves): every nonzero leaf-block product of the plan on
+ * the matrix cores, with a segmented, atomic-free accumulation -- every
+ * output block is owned by one workgroup, which sums its products with the
+ * contraction index ascending and writes the block once, so C_IJ is the sum
+ * over K of L_IK R_KJ with exactly the plan's products.
+ *   p    : plan from the symbolic phase; its operands must still have the
+ *          patterns they had then (QBSM_ERR_STATE otherwise).
+ *   mode : arithmetic of the leaf products (qbsm_mode).
+ *   out  : receives the plan's output pattern and values, stored FP64 for
+ *          QBSM_F64 and QBSM_OZAKI_BF16, FP32 otherwise; its shape must be
+ *          rows(op(L)) x cols(op(R)) with the same bs (QBSM_ERR_SHAPE) and it
+ *          must not be an operand (QBSM_ERR_ARG).  Its memory is taken from
+ *          the allocator unless it already holds this plan's result layout.
  * The operands' current values are used (they may change between calls as
- * long as their patterns do not). */
+ * long as their patterns do not); operand packs are made or refreshed as
+ * needed.  QBSM_ERR_UNSUPPORTED for a unit side the mode does not run at.
+ * Does not synchronise. */
 qbsm_status qbsm_multiply_numeric(qbsm_plan p, qbsm_mode mode, qbsm_matrix out, void *stream);
 
 /* Masked backward of C = A * B for an upstream gradient dC given on C's

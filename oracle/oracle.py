@@ -357,7 +357,12 @@ def spamm_keep(a: OMatrix, b: OMatrix, ia: np.ndarray, ib: np.ndarray, tau: floa
     """
     if tau <= 0.0:
         return np.ones(ia.shape[0], dtype=bool)
-    na, nb = block_fnorms(a.vals, a.bs), block_fnorms(b.vals, b.bs)
+    return _spamm_test(block_fnorms(a.vals, a.bs), block_fnorms(b.vals, b.bs), ia, ib, tau)
+
+
+def _spamm_test(na: np.ndarray, nb: np.ndarray, ia: np.ndarray, ib: np.ndarray, tau: float) -> np.ndarray:
+    """The norm-product test itself: product (ia, ib) is kept unless
+    na[ia] * nb[ib] < tau (FP64, strict)."""
     return ~(na[ia] * nb[ib] < tau)
 
 
@@ -404,18 +409,20 @@ def spamm_borderline(a: OMatrix, b: OMatrix, tau: float, rel: float = 1e-9) -> i
     return int(np.count_nonzero(np.abs(na[ia] * nb[ib] / tau - 1.0) < rel))
 
 
-def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0) -> np.ndarray:
-    """Values of selected C blocks only (for sampling very large products).
+def sampled_products(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0):
+    """The leaf products of selected C blocks (I, J) = (sample_i[q], sample_j[q]).
 
-    A selected (I, J) with no product gets a zero block.  tau > 0 applies the
-    sparse approximate multiply's selection (spamm_keep).
+    Returns (seg, lidx, ridx): the products of selected block q are the
+    stored-block pairs (lidx[t], ridx[t]) for t in [seg[q], seg[q+1]), with
+    the contraction index K ascending -- the same products, in the same
+    order, that ``multiply`` (tau = 0) or ``multiply_spamm`` (tau > 0) uses
+    for that block.  A selected block with no product has an empty range.
     """
     sample_i = np.asarray(sample_i, dtype=np.int64)
     sample_j = np.asarray(sample_j, dtype=np.int64)
     bs = a.bs
-    if tau > 0.0:  # sparse approximate multiply: the norm-product test of spamm_keep
+    if tau > 0.0:
         na, nb = block_fnorms(a.vals, bs), block_fnorms(b.vals, bs)
-    # rows of A needed, columns of B needed
     segs = [0]
     lid, rid = [], []
     a_rowptr = _row_index(a.brow, -(-a.nrows // bs))
@@ -425,12 +432,10 @@ def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0
     for i, j in zip(sample_i.tolist(), sample_j.tolist()):
         ra = np.arange(a_rowptr[i], a_rowptr[i + 1])
         cb = bt_order[b_colptr[j]:b_colptr[j + 1]]
-        ks_a = a.bcol[ra]
-        ks_b = b.brow[cb]
-        common, xa, xb = np.intersect1d(ks_a, ks_b, assume_unique=True, return_indices=True)
+        common, xa, xb = np.intersect1d(a.bcol[ra], b.brow[cb], assume_unique=True, return_indices=True)
         la, lb = ra[xa], cb[xb]
         if tau > 0.0:
-            kept = ~(na[la] * nb[lb] < tau)
+            kept = _spamm_test(na, nb, la, lb, tau)
             la, lb = la[kept], lb[kept]
         lid.append(la)
         rid.append(lb)
@@ -438,7 +443,52 @@ def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0
     seg = np.asarray(segs, dtype=np.int64)
     lidx = np.concatenate(lid) if lid else np.zeros(0, np.int64)
     ridx = np.concatenate(rid) if rid else np.zeros(0, np.int64)
-    return _segmented(bs, seg, lidx, ridx, a.vals, b.vals, False, False)
+    return seg, lidx, ridx
+
+
+def multiply_blocks(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0) -> np.ndarray:
+    """Values of selected C blocks only (for sampling very large products).
+
+    A selected (I, J) with no product gets a zero block.  tau > 0 applies the
+    sparse approximate multiply's selection (the norm-product test of
+    ``spamm_keep``).
+    """
+    seg, lidx, ridx = sampled_products(a, b, sample_i, sample_j, tau)
+    return _segmented(a.bs, seg, lidx, ridx, a.vals, b.vals, False, False)
+
+
+def _norm_product_sums(na, nb, seg, lidx, ridx):
+    """Per segment: (sum of na[l] * nb[r] over its products, product count)."""
+    terms = na[lidx] * nb[ridx]
+    out = np.zeros(seg.size - 1)
+    nz = np.nonzero(np.diff(seg))[0]  # reduceat needs non-empty segments
+    if nz.size:
+        out[nz] = np.add.reduceat(terms, seg[nz])
+    return out, np.diff(seg).astype(np.int64)
+
+
+def block_bound_terms(a: OMatrix, b: OMatrix, trans_a=False, trans_b=False, tau: float = 0.0):
+    """For every block of C = op(A) op(B) (canonical order of ``multiply``,
+    or of ``multiply_spamm`` when tau > 0): S_IJ = sum over its leaf products
+    of ||op(A)_IK||_F ||op(B)_KJ||_F, and the number of those products.
+
+    S_IJ bounds the block: ||C_IJ||_F <= S_IJ, and ||(|A| |B|)_IJ||_F <= S_IJ
+    (triangle inequality and submultiplicativity of the Frobenius norm), which
+    is the scale of every rounding-error bound of the block.
+    """
+    I, J, K, ia, ib = product_triples(a, b, trans_a, trans_b)
+    if tau > 0.0:
+        keep = spamm_keep(a, b, ia, ib, tau)
+        I, J, ia, ib = I[keep], J[keep], ia[keep], ib[keep]
+    _, _, seg = c_pattern_from_triples(I, J)
+    return _norm_product_sums(block_fnorms(a.vals, a.bs), block_fnorms(b.vals, b.bs), seg, ia, ib)
+
+
+def sampled_bound_terms(a: OMatrix, b: OMatrix, sample_i, sample_j, tau: float = 0.0):
+    """``block_bound_terms`` of selected C blocks (zero and 0 where a block has
+    no product)."""
+    seg, lidx, ridx = sampled_products(a, b, sample_i, sample_j, tau)
+    return _norm_product_sums(block_fnorms(a.vals, a.bs), block_fnorms(b.vals, b.bs), seg, lidx, ridx)
 
 
 def _restrict(prod: OProduct, mask: OMatrix) -> np.ndarray:

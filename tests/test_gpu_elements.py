@@ -7,7 +7,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_11762_amd import workloads as W
-from tests.gpu_helpers import TOL, pattern_np, upload, values_np
+from tests.gpu_helpers import assert_product, pattern_np, upload, values_np
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,8 @@ def test_set_and_get_elements(q, n, m, bs):
     b = W.random_blocks(m, bs, 0.4, np.random.default_rng(8), ncols=300)
     B = upload(q, b)
     got = values_np(q.matmul(A, B, "f64"))
-    want = O.multiply(ref, O.from_workload(b))
-    assert O.rel_fro(got, want.vals) <= TOL["f64"]
+    ob = O.from_workload(b)
+    assert_product(got, ref, ob, O.multiply(ref, ob).vals, "f64", what="element-built operand")
 
 
 def test_element_errors(q):
@@ -123,8 +123,8 @@ def test_truncate_product(q):
     assert np.array_equal(pr, ref.brow) and np.array_equal(pc, ref.bcol)
     assert np.array_equal(values_np(C), ref.vals)
     got = values_np(q.matmul(C, A, "f64"))
-    want = O.multiply(ref, O.from_workload(a, tol))
-    assert O.rel_fro(got, want.vals) <= TOL["f64"]
+    oa2 = O.from_workload(a, tol)
+    assert_product(got, ref, oa2, O.multiply(ref, oa2).vals, "f64", what="truncated operand")
 
 
 def test_empty_and_degenerate_new_operations(q):
@@ -191,7 +191,7 @@ def test_matrix_addition(q, bs):
     # (A + B) X through the multiply
     x = W.random_blocks(m, bs, 0.4, rng, ncols=5 * bs)
     got = values_np(q.matmul(q.add(1.0, A, 1.0, upload(q, b)), upload(q, x), "f64"))
-    want = O.multiply(O.add(1.0, oa, 1.0, ob), O.from_workload(x))
-    assert O.rel_fro(got, want.vals) <= TOL["f64"]
+    osum, ox = O.add(1.0, oa, 1.0, ob), O.from_workload(x)
+    assert_product(got, osum, ox, O.multiply(osum, ox).vals, "f64", what="sum operand")
     with pytest.raises(q.QbsmError):
         q.add(1.0, A, 1.0, upload(q, W.random_blocks(n, bs, 0.3, rng, ncols=m + bs)))

@@ -12,7 +12,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_11762_amd import workloads as W
-from tests.gpu_helpers import TOL, pattern_np, units, upload, values_np
+from tests.gpu_helpers import TOL, assert_product, assert_sampled, pattern_np, units, upload, values_np
 
 pytestmark = pytest.mark.gpu
 
@@ -63,7 +63,7 @@ def test_spamm_decay_against_oracle(q, npoints, bs):
                 cr, cc = pattern_np(C)
                 assert np.array_equal(cr, ref.brow) and np.array_equal(cc, ref.bcol), (tau, mode, unit)
                 got = values_np(C)
-                assert O.rel_fro(got, ref.vals) <= TOL[mode], (tau, mode, unit, O.rel_fro(got, ref.vals))
+                assert_product(got, oa, oa, ref.vals, mode, tau=tau, what=f"spamm tau={tau} unit={unit}")
                 if mode == "f64":
                     err = np.linalg.norm(_embed(type(ref)(cr, cc, got, ref.I, ref.J, ref.K, ref.seg), exact)
                                          - exact.vals)
@@ -104,4 +104,4 @@ def test_spamm_decay_full_sampled(q):
     ref = O.multiply_blocks(oa, oa, si, sj, tau=tau)
     for mode in ("f64", "bf16x3"):
         got = P.numeric(mode).extract(si, sj).cpu().numpy()
-        assert O.rel_fro(got, ref) <= TOL[mode], (mode, O.rel_fro(got, ref))
+        assert_sampled(got, oa, oa, si, sj, ref, mode, tau=tau, what="spamm decay sampled")

@@ -10,7 +10,7 @@ import torch
 
 from oracle import oracle as O
 from paper_2011_11762_amd import workloads as W
-from tests.gpu_helpers import TOL, pattern_np, units, upload, values_np
+from tests.gpu_helpers import assert_values, pattern_np, units, upload, values_np
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +29,9 @@ def test_symmetric_square_decay(q, npoints, bs):
     a, tol = c["A"], c["drop_tol"]
     oa = O.from_workload(a, tol)
     ref = O.multiply_upper(oa, oa)
+    fI, fJ, _, _, _ = O.product_triples(oa, oa)
+    fr, fc, _ = O.c_pattern_from_triples(fI, fJ)
+    S, npr = (x[fr <= fc] for x in O.block_bound_terms(oa, oa))  # upper blocks of the full product
     A = upload(q, a, tol)
     for mode in ("f64", "f32", "bf16x3", "ozaki"):
         for unit in units(bs, mode):
@@ -42,7 +45,7 @@ def test_symmetric_square_decay(q, npoints, bs):
             cr, cc = pattern_np(C)
             assert np.array_equal(cr, ref.brow) and np.array_equal(cc, ref.bcol)
             got = values_np(C)
-            assert O.rel_fro(got, ref.vals) <= TOL[mode], (mode, unit, O.rel_fro(got, ref.vals))
+            assert_values(got, ref.vals, S, npr, mode, bs, f"upper unit={unit}")
             # the same blocks of the full product, same configuration: identical
             full = q.Plan(A, A, unit=unit).numeric(mode)
             assert np.array_equal(full.extract(cr, cc).cpu().numpy(), got), (mode, unit)
@@ -82,7 +85,8 @@ def test_batched_upper_and_spamm_plans(q):
     got = values_np(plans[3].numeric("f32"))
     cr, cc = pattern_np(plans[3].numeric("f32"))
     assert np.array_equal(cr, sp.brow[keep]) and np.array_equal(cc, sp.bcol[keep])
-    assert O.rel_fro(got, sp.vals[keep]) <= TOL["f32"]
+    S, npr = (x[keep] for x in O.block_bound_terms(oa, oa, tau=1e-3))
+    assert_values(got, sp.vals[keep], S, npr, "f32", 64, "upper spamm")
 
 
 @pytest.mark.parametrize("bs", [32, 64])
@@ -96,6 +100,7 @@ def test_symmetric_rank_k(q, bs):
     keep = full.brow <= full.bcol
     I, J, K, _, _ = O.product_triples(oa, oa, trans_b=True)
     sel = I <= J
+    S, npr = (x[keep] for x in O.block_bound_terms(oa, oa, trans_b=True))
     A = upload(q, a)
     for mode in ("f64", "f32", "bf16x3", "ozaki"):
         for unit in units(bs, mode):
@@ -105,7 +110,7 @@ def test_symmetric_rank_k(q, bs):
             C = P.numeric(mode)
             cr, cc = pattern_np(C)
             assert np.array_equal(cr, full.brow[keep]) and np.array_equal(cc, full.bcol[keep])
-            assert O.rel_fro(values_np(C), full.vals[keep]) <= TOL[mode], (mode, unit)
+            assert_values(values_np(C), full.vals[keep], S, npr, mode, bs, f"rank-k unit={unit}")
 
 
 def test_batch_rejects_replaced_operands_and_outputs(q):

@@ -545,6 +545,176 @@ def test_spamm_error_bound_and_monotone():
         prev = triples
 
 
+def _decay_rect(m, n, bs, rate, seed, shift=0):
+    """Rectangular block matrix whose entries decay away from the line i = j + shift."""
+    rng = np.random.default_rng(seed)
+    i, j = np.meshgrid(np.arange(m), np.arange(n), indexing="ij")
+    dense = rng.uniform(-1, 1, (m, n)) * np.exp(-rate * np.abs(i - j - shift))
+    nbr, nbc = -(-m // bs), -(-n // bs)
+    br, bc, blocks = [], [], []
+    for I in range(nbr):
+        for J in range(nbc):
+            blk = np.zeros((bs, bs))
+            sub = dense[I * bs:(I + 1) * bs, J * bs:(J + 1) * bs]
+            blk[:sub.shape[0], :sub.shape[1]] = sub
+            br.append(I)
+            bc.append(J)
+            blocks.append(blk.T.ravel())
+    return O.canonical(m, n, bs, np.array(br), np.array(bc), np.array(blocks))
+
+
+def test_sampled_spamm_blocks_match_the_approximate_product():
+    """multiply_blocks with tau > 0 (the sampled path of the sparse
+    approximate multiply) gives exactly the blocks of multiply_spamm, and its
+    bound terms those of block_bound_terms.  A and B differ in shape, decay
+    rate and offset, so a norm taken from the wrong operand or index changes
+    the kept set."""
+    bs = 16
+    a = _decay_rect(200, 120, bs, 0.30, 21, shift=40)
+    b = _decay_rect(120, 168, bs, 0.08, 22, shift=-25)
+    tau = 0.5
+    full = O.multiply_spamm(a, b, tau)
+    exact = O.multiply(a, b)
+    assert 0 < full.I.size < exact.I.size  # the test really leaves products out
+    nbr, nbc = -(-200 // bs), -(-168 // bs)
+    si, sj = np.meshgrid(np.arange(nbr), np.arange(nbc), indexing="ij")
+    si, sj = si.ravel(), sj.ravel()
+    got = O.multiply_blocks(a, b, si, sj, tau)
+    pos = {(i, j): t for t, (i, j) in enumerate(zip(full.brow.tolist(), full.bcol.tolist()))}
+    for q, (i, j) in enumerate(zip(si.tolist(), sj.tolist())):
+        t = pos.get((i, j))
+        if t is None:
+            assert not np.any(got[q])
+        else:
+            assert np.array_equal(got[q], full.vals[t]), (i, j)
+    # selected blocks whose products are all left out exist and come back zero
+    assert any((i, j) not in pos for i, j in zip(exact.brow.tolist(), exact.bcol.tolist()))
+    S, npr = O.block_bound_terms(a, b, tau=tau)
+    sS, snpr = O.sampled_bound_terms(a, b, si, sj, tau)
+    for q, (i, j) in enumerate(zip(si.tolist(), sj.tolist())):
+        t = pos.get((i, j))
+        assert (snpr[q], sS[q]) == ((npr[t], S[t]) if t is not None else (0, 0.0))
+
+
+def test_block_bound_terms_brute_force():
+    """S_IJ and the product count per C block against explicit loops with
+    norms summed element by element, also for transposed operands."""
+    bs = 8
+    a = _decay_rect(40, 56, bs, 0.2, 23)
+    b = _decay_rect(40, 33, bs, 0.1, 24, shift=5)
+    S, npr = O.block_bound_terms(a, b, trans_a=True)
+    c = O.multiply(a, b, trans_a=True)
+
+    def nrm(m, t):
+        return sum(float(v) * float(v) for v in m.vals[t]) ** 0.5
+
+    ia = {(int(i), int(j)): t for t, (i, j) in enumerate(zip(a.brow, a.bcol))}
+    ib = {(int(i), int(j)): t for t, (i, j) in enumerate(zip(b.brow, b.bcol))}
+    want = {}
+    for (k, i), ta in ia.items():          # op(A) = A^T: block (i, k) of op(A) is A's (k, i)
+        for (k2, j), tb in ib.items():
+            if k2 == k:
+                s0, n0 = want.get((i, j), (0.0, 0))
+                want[(i, j)] = (s0 + nrm(a, ta) * nrm(b, tb), n0 + 1)
+    assert sorted(want) == list(zip(c.brow.tolist(), c.bcol.tolist()))
+    for t, key in enumerate(zip(c.brow.tolist(), c.bcol.tolist())):
+        assert npr[t] == want[key][1]
+        assert abs(S[t] - want[key][0]) <= 1e-13 * want[key][0]
+    # the scale bounds the block itself
+    assert np.all(np.linalg.norm(c.vals, axis=1) <= S * (1 + 1e-13))
+
+
+def _emulate(mode, a, b):
+    """Plain numpy emulation of a precision mode, block by block (each leaf
+    product one float32 GEMM, summed over K in float32; the Ozaki mode is the
+    oracle's own splitting), in C's canonical order."""
+    from tests.bounds import SAFETY  # noqa: F401  (same module as the GPU checks)
+    bs = a.bs
+    if mode == "ozaki":
+        return O.ozaki_multiply(a, b).vals
+    I, J, K, ia, ib = O.product_triples(a, b)
+    _, _, seg = O.c_pattern_from_triples(I, J)
+
+    def mats(vals, fn):
+        return np.ascontiguousarray(fn(vals).reshape(-1, bs, bs).transpose(0, 2, 1))
+
+    out = np.zeros((seg.size - 1, bs * bs))
+    if mode == "f64":
+        A, B = mats(a.vals, lambda x: x), mats(b.vals, lambda x: x)
+        for q in range(seg.size - 1):  # K descending: another order than the oracle's
+            acc = np.zeros((bs, bs))
+            for t in range(seg[q + 1] - 1, seg[q] - 1, -1):
+                acc = acc + A[ia[t]] @ B[ib[t]]
+            out[q] = acc.T.ravel()
+        return out
+    if mode == "bf16x3":
+        ah, al = (mats(x, lambda v: v).astype(np.float32) for x in O.split_bf16(a.vals))
+        bh, bl = (mats(x, lambda v: v).astype(np.float32) for x in O.split_bf16(b.vals))
+        for q in range(seg.size - 1):
+            acc = np.zeros((bs, bs), np.float32)
+            for t in range(seg[q], seg[q + 1]):
+                x, y = ia[t], ib[t]
+                acc = acc + ah[x] @ bl[y]
+                acc = acc + al[x] @ bh[y]
+                acc = acc + ah[x] @ bh[y]
+            out[q] = acc.astype(np.float64).T.ravel()
+        return out
+    rnd = O.round_to_f32 if mode == "f32" else O.round_to_bf16
+    A = mats(a.vals, rnd).astype(np.float32)
+    B = mats(b.vals, rnd).astype(np.float32)
+    for q in range(seg.size - 1):
+        acc = np.zeros((bs, bs), np.float32)
+        for t in range(seg[q], seg[q + 1]):
+            acc = acc + A[ia[t]] @ B[ib[t]]
+        out[q] = acc.astype(np.float64).T.ravel()
+    return out
+
+
+@pytest.mark.parametrize("mode", ["f64", "f32", "bf16", "bf16x3", "ozaki"])
+def test_blockwise_bound_holds_and_catches_mistakes(mode):
+    """The per-block bound of every mode holds for a plain emulation of that
+    mode's arithmetic on block norms spread over many decades, and it catches
+    a zeroed block and a dropped leaf product that a relative Frobenius norm
+    over the whole C lets through."""
+    from tests.bounds import rel_bound, violations
+    bs = 16
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-2, "bf16x3": 1e-4, "ozaki": 1e-11}[mode]
+    for case, (a, b) in enumerate(((_decay_rect(192, 160, bs, 0.25, 25), _decay_rect(160, 176, bs, 0.2, 26, shift=8)),
+                                   W_small_pair(bs))):
+        ref = O.multiply(a, b)
+        S, npr = O.block_bound_terms(a, b)
+        got = _emulate(mode, a, b)
+        bad, err, lim = violations(got, ref.vals, S, npr, mode, bs)
+        assert bad.size == 0, (mode, bad[:5], err[bad[:5]], lim[bad[:5]])
+        # planted mistake 1: the block with the smallest norm relative to the total comes back zero
+        nrm = np.linalg.norm(ref.vals, axis=1)
+        k = int(np.argmin(np.where(nrm > 0, nrm, np.inf)))
+        wrong = got.copy()
+        wrong[k] = 0.0
+        assert k in violations(wrong, ref.vals, S, npr, mode, bs)[0]
+        if case == 0:  # decaying blocks: the mistake passes the global check at the mode's tolerance
+            assert O.rel_fro(wrong, ref.vals) <= tol
+        # planted mistake 2: one block misses its largest leaf product
+        I, J, K, ia, ib = O.product_triples(a, b)
+        _, _, seg = O.c_pattern_from_triples(I, J)
+        na, nb = O.block_fnorms(a.vals, bs), O.block_fnorms(b.vals, bs)
+        q = int(np.argmax(npr))
+        ts = np.arange(seg[q], seg[q + 1])
+        t = ts[np.argmax(na[ia[ts]] * nb[ib[ts]])]
+        lo = O.OMatrix(a.nrows, a.ncols, bs, a.brow[[ia[t]]], a.bcol[[ia[t]]], a.vals[[ia[t]]])
+        hi = O.OMatrix(b.nrows, b.ncols, bs, b.brow[[ib[t]]], b.bcol[[ib[t]]], b.vals[[ib[t]]])
+        term = O.multiply(lo, hi).vals[0]
+        wrong = got.copy()
+        wrong[q] -= term
+        if np.linalg.norm(term) > 4 * rel_bound(mode, npr[q], bs) * S[q]:
+            assert q in violations(wrong, ref.vals, S, npr, mode, bs)[0]
+
+
+def W_small_pair(bs):
+    a, b = W.small_random(150, 130, 120, bs, 0.4, 27)
+    return O.from_workload(a), O.from_workload(b)
+
+
 # ---------------------------------------------------------------- symmetric square
 def _symmetric(n, bs, p, seed):
     """Block-sparse symmetric matrix (pattern and values mirrored)."""
