@@ -323,6 +323,40 @@ qbsm_status qbsm_plan_destroy(qbsm_plan p);
  * Does not synchronise. */
 qbsm_status qbsm_multiply_numeric(qbsm_plan p, qbsm_mode mode, qbsm_matrix out, void *stream);
 
+/* Bytes of the library's per-device scratch array used by
+ * qbsm_multiply_numeric_noalloc (64 MiB). */
+#define QBSM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  The
+ * numeric phase of qbsm_multiply_numeric (same kernels, same results bit for
+ * bit) with two differences:
+ *   - the operand packs (with their non-finite flags and, in the Ozaki mode,
+ *     the line exponents) go to a file-scope device array of
+ *     QBSM_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ *     the process ends, instead of allocator memory;
+ *   - the result goes to the caller's array out_vals instead of a matrix
+ *     handle: device memory of nblk_out * bs * bs elements, double for
+ *     QBSM_F64 and QBSM_OZAKI_BF16 and float otherwise.  Block t of the
+ *     plan's output pattern is written column-major at t * bs * bs, the blocks
+ *     taken in ascending Morton (Z) order of (I, J) -- the bits of I and J
+ *     interleaved, I's bit above J's at every level -- which is the storage
+ *     order of the matrix qbsm_multiply_numeric fills.  Padding beyond the
+ *     logical size is written as zero; with a masked plan the mask's blocks
+ *     without products are written as zero.
+ * Nothing is allocated (no hipMalloc, no allocator hook) and nothing is
+ * synchronised: launches only.  The plan's quadtree tables must be the ones
+ * its symbolic phase made (QBSM_ERR_STATE otherwise).
+ * The scratch array is shared by every call on one GPU and keeps the last
+ * call's contents; each call writes what it reads first.  Calls that overlap
+ * on one GPU (different streams or host threads) race on it: order them.
+ * Errors: as qbsm_multiply_numeric; QBSM_ERR_UNSUPPORTED, before any launch,
+ * when the two operand packs need more than QBSM_NOALLOC_SCRATCH_BYTES (bytes
+ * per stored leaf and operand: bs*bs times 8 for F64, 4 for F32 and BF16X3,
+ * 2 for BF16, 12 for the Ozaki mode, plus 4*bs for the Ozaki exponents,
+ * each operand's total rounded up to 256). */
+qbsm_status qbsm_multiply_numeric_noalloc(qbsm_plan p, qbsm_mode mode, void *out_vals, void *stream);
+
 /* Masked backward of C = A * B for an upstream gradient dC given on C's
  * pattern (dC may hold any subset of C's blocks):
  *   dA = (dC * B^T) restricted to A's pattern,

@@ -9,16 +9,6 @@
 
 #include "common.h"
 
-struct qbsm_matrix_ {
-    qbsm::Matrix m;
-};
-struct qbsm_plan_ {
-    std::unique_ptr<qbsm::Plan> p;
-};
-struct qbsm_batch_ {
-    qbsm::Batch b;
-};
-
 namespace qbsm {
 
 K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
@@ -31,6 +21,8 @@ Allocator g_alloc;
 }  // namespace
 
 Allocator &allocator() { return g_alloc; }
+
+void set_last_error(const char *msg) { g_last_error = msg; }
 
 namespace {
 // Without a hook, memory comes from the device's default stream-ordered pool.

@@ -235,6 +235,17 @@ struct PackView {
     const int32_t *nonfinite = nullptr;  // device flag of the pack
 };
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s);
+// Bytes of one (mode, role) pack of m, and the number of int32 line
+// exponents that go with it (Ozaki mode; 0 otherwise).
+size_t pack_bytes(const Matrix &m, qbsm_mode mode);
+size_t pack_aux_count(const Matrix &m, qbsm_mode mode);
+// Strides of a pack of m for `mode` stored at buf.
+PackView pack_view(const Matrix &m, qbsm_mode mode, const void *buf, const int32_t *nonfinite);
+// Packs m's current values for (mode, role) into caller-provided device
+// memory: dst (pack_bytes), nonfinite (one int32 flag, cleared first) and aux
+// (pack_aux_count int32, Ozaki mode only).  Launches only.
+void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonfinite, int32_t *aux,
+               hipStream_t s);
 // Brings both packs (row and column lines) of m up to date in one pass when
 // both are stale; otherwise leaves them to matrix_pack.
 void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s);
@@ -250,6 +261,8 @@ hipStream_t side_stream();
 int mode_bk(qbsm_mode mode, int bs);
 
 void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
+// Checks that a plan is still current and runs at unit p.unit in `mode`.
+void numeric_check(const Plan &p, qbsm_mode mode);
 void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
 
 // Kernel-side member description (also used by the batched launch).
@@ -299,6 +312,9 @@ struct Batch {
     std::vector<uint64_t> out_pattern;
 };
 
+K5Member member_from_views(const Plan &p, const int32_t *descL, const int32_t *descR, const PackView &vL,
+                           const PackView &vR, void *C);
+
 void batch_launch(Batch &b, hipStream_t s);
 // Checks that the batch's plans, packs and outputs are still the ones its
 // member records point to (QBSM_ERR_STATE otherwise), then orders s after
@@ -310,6 +326,8 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t nmembe
                const K5Member &single, hipStream_t s);
 
 int device_cu_count();
+// Text returned by qbsm_last_error() on this thread.
+void set_last_error(const char *msg);
 
 // Optional event timing around kernel launches (kernel classes below).
 enum ProfClass { PROF_NUMERIC = 0, PROF_PACK = 1, PROF_NCLASS = 2 };
@@ -322,3 +340,14 @@ struct ProfScope {
 };
 
 }  // namespace qbsm
+
+// Opaque handles of the C ABI.
+struct qbsm_matrix_ {
+    qbsm::Matrix m;
+};
+struct qbsm_plan_ {
+    std::unique_ptr<qbsm::Plan> p;
+};
+struct qbsm_batch_ {
+    qbsm::Batch b;
+};

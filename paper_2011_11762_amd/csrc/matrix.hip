@@ -766,38 +766,42 @@ void matrix_extract_blocks(Matrix &m, int64_t n, const int32_t *brow, const int3
 }
 
 void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) {
+    pack_into(m, mode, role, pk.buf.p, pk.nonfinite.p, pk.aux.p, s);
+}
+
+void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonfinite, int32_t *aux,
+               hipStream_t s) {
     const int bk = mode_bk(mode, m.bs);
     const int ppl = bk * (int)mode_elem_bytes(mode) / 16;
     const int64_t work = m.nblk * (m.bs / bk) * (int64_t)m.bs * ppl;
     if (!work) {
-        fill_i32(pk.nonfinite.p, 0, 1, s);
+        fill_i32(nonfinite, 0, 1, s);
         return;
     }
     const unsigned g = grid_for(work, 256);
-    uint8_t *dst = pk.buf.p;
     ProfScope prof(PROF_PACK, s);
-    fill_i32(pk.nonfinite.p, 0, 1, s);
+    fill_i32(nonfinite, 0, 1, s);
     if (mode == QBSM_OZAKI_BF16) {
         const unsigned ge = grid_for(m.nblk * m.bs, 256);
         const unsigned gc = grid_for(m.nblk * m.bs * 64, 256);
         if (m.storage == ST_F64) {
             if (role == ROLE_COL)
-                k_oz_exp_col<double><<<gc, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, pk.aux.p);
+                k_oz_exp_col<double><<<gc, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, aux);
             else
-                k_oz_exp<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, (int)role, pk.aux.p);
-            k_pack_oz<double><<<g, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, bk, (int)role, pk.aux.p, dst, pk.nonfinite.p);
+                k_oz_exp<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, (int)role, aux);
+            k_pack_oz<double><<<g, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, bk, (int)role, aux, dst, nonfinite);
         } else {
             if (role == ROLE_COL)
-                k_oz_exp_col<float><<<gc, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, pk.aux.p);
+                k_oz_exp_col<float><<<gc, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, aux);
             else
-                k_oz_exp<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, (int)role, pk.aux.p);
-            k_pack_oz<float><<<g, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, bk, (int)role, pk.aux.p, dst, pk.nonfinite.p);
+                k_oz_exp<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, (int)role, aux);
+            k_pack_oz<float><<<g, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, bk, (int)role, aux, dst, nonfinite);
         }
         QB_LAUNCH_CHECK();
         return;
     }
 #define QB_PACK(SRC, PTR, MODE) \
-    k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst, pk.nonfinite.p)
+    k_pack<SRC, MODE><<<g, 256, 0, s>>>(PTR, m.nblk, m.bs, bk, (int)role, dst, nonfinite)
     if (m.storage == ST_F64) {
         switch (mode) {
             case QBSM_F64: QB_PACK(double, m.v64.p, QBSM_F64); break;
@@ -853,10 +857,29 @@ void pack2_launch(Matrix &m, qbsm_mode mode, Pack &pr, Pack &pc, hipStream_t ks)
     QB_LAUNCH_CHECK();
 }
 
-namespace {
 size_t pack_bytes(const Matrix &m, qbsm_mode mode) {
     return (size_t)m.nblk * m.bs * m.bs * mode_elem_bytes(mode) * mode_parts(mode);
 }
+
+size_t pack_aux_count(const Matrix &m, qbsm_mode mode) {
+    return mode == QBSM_OZAKI_BF16 ? (size_t)m.nblk * m.bs : 0;
+}
+
+PackView pack_view(const Matrix &m, qbsm_mode mode, const void *buf, const int32_t *nonfinite) {
+    const int bs = m.bs;
+    const int bk = mode_bk(mode, bs);
+    const int64_t n2 = (int64_t)bs * bs;
+    PackView v;
+    v.ptr = buf;
+    v.leaf_stride = n2 * mode_parts(mode);
+    v.part_stride = n2;
+    v.line_stride = bk;
+    v.chunk_stride = (int32_t)((int64_t)bs * bk);
+    v.nonfinite = nonfinite;
+    return v;
+}
+
+namespace {
 bool pack_stale(const Matrix &m, qbsm_mode mode, const Pack &pk) {
     return pk.buf.n != pack_bytes(m, mode) || pk.version != m.version || !pk.buf.p;
 }
@@ -868,8 +891,8 @@ void pack_size(const Matrix &m, qbsm_mode mode, Pack &pk, hipStream_t s) {
     const size_t bytes = pack_bytes(m, mode);
     if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
     if (!pk.nonfinite.p) pk.nonfinite.alloc(1, s);
-    if (mode == QBSM_OZAKI_BF16 && pk.aux.n != (size_t)(m.nblk * m.bs))
-        pk.aux.alloc(m.nblk * m.bs ? m.nblk * m.bs : 1, s);
+    const size_t naux = pack_aux_count(m, mode);
+    if (naux && pk.aux.n != naux) pk.aux.alloc(naux, s);
 }
 }  // namespace
 
@@ -966,10 +989,6 @@ void matrix_prepack(Matrix &m, qbsm_mode mode, int roles, hipStream_t s) {
 }
 
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
-    const int bs = m.bs;
-    const int bk = mode_bk(mode, bs);
-    const int64_t n2 = (int64_t)bs * bs;
-    PackView v;
     auto key = std::make_pair((int)mode, (int)role);
     Pack &pk = m.packs[key];
     pk.settle(s);
@@ -978,13 +997,7 @@ PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s) {
         pack_launch(m, mode, role, pk, s);
         pk.version = m.version;
     }
-    v.ptr = pk.buf.p;
-    v.leaf_stride = n2 * mode_parts(mode);
-    v.part_stride = n2;
-    v.line_stride = bk;
-    v.chunk_stride = (int32_t)((int64_t)bs * bk);
-    v.nonfinite = pk.nonfinite.p;
-    return v;
+    return pack_view(m, mode, pk.buf.p, pk.nonfinite.p);
 }
 
 }  // namespace qbsm

@@ -821,25 +821,22 @@ int k5_occupancy(qbsm_mode mode, int unit, int bs) {
     return nb < 1 ? 1 : nb;
 }
 
-K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
-    Tree &tL = matrix_tree(*p.L, p.D, s);
-    Tree &tR = matrix_tree(*p.R, p.D, s);
-    const Role roleL = p.transL ? ROLE_COL : ROLE_ROW, roleR = p.transR ? ROLE_ROW : ROLE_COL;
-    if (p.L == p.R && roleL != roleR) matrix_pack_pair(*p.L, mode, s);
-    const PackView vL = matrix_pack(*p.L, mode, roleL, s);
-    const PackView vR = matrix_pack(*p.R, mode, roleR, s);
+// The kernel's record of one multiply: the plan's work lists, the operands'
+// unit-level descriptor tables and packs, and the output values.
+K5Member member_from_views(const Plan &p, const int32_t *descL, const int32_t *descR, const PackView &vL,
+                           const PackView &vR, void *C) {
     K5Member m{};
     m.ustart = p.ustart.p;
     m.ukey = p.ukey.p;
     m.pl = p.pl.p;
     m.pr = p.pr.p;
     m.pmask = p.pmask.p;
-    m.descL = tree_desc(*p.L, tL, p.s, s);
-    m.descR = tree_desc(*p.R, tR, p.s, s);
+    m.descL = descL;
+    m.descR = descR;
     m.cdesc = p.cdesc.p;
     m.packL = vL.ptr;
     m.packR = vR.ptr;
-    m.C = out.storage == ST_F64 ? (void *)out.v64.p : (void *)out.v32.p;
+    m.C = C;
     m.leafStrideL = vL.leaf_stride;
     m.partStrideL = vL.part_stride;
     m.lineStrideL = vL.line_stride;
@@ -864,16 +861,31 @@ K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     return m;
 }
 
+K5Member make_member(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
+    Tree &tL = matrix_tree(*p.L, p.D, s);
+    Tree &tR = matrix_tree(*p.R, p.D, s);
+    const Role roleL = p.transL ? ROLE_COL : ROLE_ROW, roleR = p.transR ? ROLE_ROW : ROLE_COL;
+    if (p.L == p.R && roleL != roleR) matrix_pack_pair(*p.L, mode, s);
+    const PackView vL = matrix_pack(*p.L, mode, roleL, s);
+    const PackView vR = matrix_pack(*p.R, mode, roleR, s);
+    return member_from_views(p, tree_desc(*p.L, tL, p.s, s), tree_desc(*p.R, tR, p.s, s), vL, vR,
+                             out.storage == ST_F64 ? (void *)out.v64.p : (void *)out.v32.p);
+}
+
 void plan_check_current(const Plan &p) {
     QB_CHECK(p.L->pattern_id == p.patL && p.R->pattern_id == p.patR && (!p.M || p.M->pattern_id == p.patM),
              QBSM_ERR_STATE, "an operand's pattern changed after the symbolic phase");
 }
 
-void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
+void numeric_check(const Plan &p, qbsm_mode mode) {
     plan_check_current(p);
     QB_CHECK(!(mode == QBSM_F64 && p.unit >= 256), QBSM_ERR_UNSUPPORTED,
              "unit 256 serves the FP32-accumulating modes only");
     QB_CHECK(mode != QBSM_OZAKI_BF16 || p.unit == 64, QBSM_ERR_UNSUPPORTED, "the Ozaki mode runs at unit 64");
+}
+
+void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
+    numeric_check(p, mode);
     QB_CHECK(&out != p.L && &out != p.R && &out != p.M, QBSM_ERR_ARG, "output aliases an operand");
     QB_CHECK(out.nrows == p.out_rows && out.ncols == p.out_cols && out.bs == p.bs, QBSM_ERR_SHAPE,
              "output shape or leaf size differs from the product");

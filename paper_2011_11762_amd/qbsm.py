@@ -72,6 +72,7 @@ _SIGS = {
     "qbsm_plan_get_products": [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
     "qbsm_plan_destroy": [c_void_p],
     "qbsm_multiply_numeric": [c_void_p, c_int32, c_void_p, c_void_p],
+    "qbsm_multiply_numeric_noalloc": [c_void_p, c_int32, c_void_p, c_void_p],
     "qbsm_multiply_backward": [c_void_p, c_void_p, c_void_p, c_int32, POINTER(PlanOpts), c_void_p, c_void_p,
                                c_void_p],
     "qbsm_batch_create": [c_int32, POINTER(c_void_p), c_int32, POINTER(c_void_p), c_void_p, POINTER(c_void_p)],
@@ -293,6 +294,18 @@ class Plan:
             out = Matrix(self.nrows, self.ncols, self.bs)
         _check(_lib.qbsm_multiply_numeric(self._h, mode_id(mode), out.handle, _stream()))
         return out
+
+
+    def numeric_noalloc(self, mode, out: torch.Tensor) -> torch.Tensor:
+        """Numeric phase into a caller-owned tensor (float64 for f64/ozaki,
+        float32 otherwise; [nblk_out, bs*bs], blocks in ascending Morton order
+        of (I, J)); the library allocates nothing."""
+        assert out.is_cuda and out.is_contiguous()
+        _check(_lib.qbsm_multiply_numeric_noalloc(self._h, mode_id(mode), _ptr(out), _stream()))
+        return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def add(alpha: float, A: Matrix, beta: float, B: Matrix) -> Matrix:
