@@ -48,7 +48,16 @@
 extern "C" {
 #endif
 
-typedef enum {
+/* C++ sees the enumerations with a fixed 32-bit underlying type, so that any
+ * int32 value a C caller passes is a valid value on the library's side (the
+ * library rejects unknown ones); C sees plain int-sized enumerations. */
+#ifdef __cplusplus
+#define QBSM_ENUM(name) enum name : int32_t
+#else
+#define QBSM_ENUM(name) enum name
+#endif
+
+typedef QBSM_ENUM(qbsm_status_e) {
     QBSM_OK = 0,
     QBSM_ERR_ARG = 1,         /* null pointer, negative size, bad enum value        */
     QBSM_ERR_SHAPE = 2,       /* inner dimensions / leaf sizes do not agree         */
@@ -84,7 +93,7 @@ typedef enum {
  *               An infinite input gives a non-finite result where reached.
  * In every mode a product exists only where both leaf blocks are stored: an
  * Inf or NaN never meets the implicit zeros of a nil block. */
-typedef enum {
+typedef QBSM_ENUM(qbsm_mode_e) {
     QBSM_F64 = 0,
     QBSM_F32 = 1,
     QBSM_BF16 = 2,
