@@ -33,13 +33,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "effective GFLOP/s on nonzero leaf products, plain FP64 vs chosen form at stated error"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "ozaki": 2500.0}
-MFMA_TERMS = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3, "ozaki": 21}
-DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16", "ozaki": "bf16"}
-# bytes per element of the packed operands and of the result, per mode
-OPERAND_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4, "ozaki": 12}
+# dense MFMA peaks of the instruction type each mode runs (TFLOP/s; int8 in TOP/s)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "ozaki": 5000.0}
+MFMA_TERMS = {"f64": 1, "f32": 1, "bf16": 1, "bf16x3": 3, "ozaki": 28}
+DTYPE = {"f64": "f64", "f32": "f32", "bf16": "bf16", "bf16x3": "bf16", "ozaki": "i8"}
+# bytes per element of the packed operands and of the result, per mode (the
+# Ozaki packs: seven 1-byte digits plus a 4-byte exponent per 64-element line)
+OPERAND_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4, "ozaki": 7 + 4 / 64}
 RESULT_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "bf16x3": 4, "ozaki": 8}
-KERNEL_SOURCES = ("numeric.hip", "common.h", "device_math.h")
+KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # HBM bytes of one numeric-kernel launch on the default workload, per
 # "mode@unit", from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB
 # per dispatch), scaled by what the same counters read for a 1 GiB
@@ -83,8 +85,12 @@ def parse():
     ap.add_argument("--spamm-tol", type=float, default=0.0,
                     help="also time the sparse approximate multiply of the chosen mode with this tolerance "
                          "(reported beside the headline, which is always the full multiply)")
-    ap.add_argument("--modes", default="f64,f32", help="reference modes timed beside the chosen one")
+    ap.add_argument("--modes", default="f64,f32,ozaki", help="reference modes timed beside the chosen one")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (no error statement)")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="decay workload only: leave out the compact legs of the other workloads (N 2048 "
+                         "banded FP64, random blocks, batched, forward + backward)")
+    ap.add_argument("--leg-steps", type=int, default=3, help="timed steps of each compact leg")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference for HBM byte counters)")
@@ -163,86 +169,366 @@ def cpu_baseline_leg(wl, tol, bs, seconds):
     return rec, (si, sj, ref)
 
 
-def batched_main(args, torch, qbsm, W):
-    """The batched form: 256 multiplies of uneven sizes (N 1024..16384, leaves
-    32 or 64, banded members with independent A and B, decay members squared),
-    stored in FP32, one persistent launch over all of them replayed as a HIP
-    graph.  A step is one replay: operand re-packing and the persistent
-    kernel, with the inputs, plans and work list already built."""
-    unit = args.unit or 128
-    t_gen = time.perf_counter()
+# --------------------------------------------------------------------------
+# Compact legs for the other workloads, added to the default run's JSON line.
+# Each leg times one pass of its hot path, reports the dominant kernel's
+# roofline (HIP events around every launch of it during the timed steps) and
+# times the FP64 oracle on the same inputs on the host (all threads and one
+# thread where the oracle finishes in seconds).
+
+def _oracle_timed(fn, flops, sample, one_thread=True):
+    """Runs fn (an oracle computation) on all threads, then on one; returns
+    the cpu_baseline record and fn's result."""
+    from oracle import oracle as O
+
+    nthr = O.set_threads(0)  # query (n < 1 leaves the count as it is)
+    t0 = time.perf_counter()
+    res = fn()
+    el = time.perf_counter() - t0
+    rec = {"value": round(flops / el / 1e9, 3), "unit": "GFLOP/s", "cores": nthr, "kind": "oracle",
+           "sample": f"{sample}; {flops / 1e9:.2f} GFLOP in {el:.2f} s on {nthr} threads"}
+    if one_thread:
+        O.set_threads(1)
+        t0 = time.perf_counter()
+        fn()
+        el1 = time.perf_counter() - t0
+        O.set_threads(nthr)
+        rec["value_1_thread"] = round(flops / el1 / 1e9, 3)
+        rec["seconds_1_thread"] = round(el1, 3)
+    return rec, res
+
+
+def _timed_steps(torch, qbsm, fn, steps, warmup):
+    """Average wall time of fn over `steps` calls (after `warmup`), and the
+    average numeric-kernel launch time recorded meanwhile."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    qbsm.profile_reset()
+    qbsm.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    qbsm.profile_enable(False)
+    n, tot = qbsm.profile_read(qbsm.PROF_NUMERIC)
+    qbsm.profile_reset()
+    return ms, tot / max(n, 1), n
+
+
+def _upload_raw(torch, m):
+    return (torch.from_numpy(m.brow.astype(np.int32)).cuda(), torch.from_numpy(m.bcol.astype(np.int32)).cuda(),
+            torch.from_numpy(m.vals).cuda())
+
+
+def _mfma_roofline(mode, flops, kern_ms, kernel):
+    ach = MFMA_TERMS[mode] * flops / (kern_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 3), "peak": PEAK_TFLOPS[mode],
+            "unit": "TOP/s" if mode == "ozaki" else "TFLOP/s", "frac": round(ach / PEAK_TFLOPS[mode], 4),
+            "traffic": None, "kernel": kernel}
+
+
+def leg_config1(torch, qbsm, W, steps, warmup):
+    """Banded N 2048, 32x32 leaves, half-bandwidth 4, FP64: one whole pass
+    (set_blocks of A and B, symbolic, numeric); a latency-bound workload."""
+    from oracle import oracle as O
+
+    c = W.config1()
+    a, b = c["A"], c["B"]
+    ra, rb = _upload_raw(torch, a), _upload_raw(torch, b)
+    A, B = qbsm.Matrix(a.nrows, a.ncols, a.bs), qbsm.Matrix(b.nrows, b.ncols, b.bs)
+    C = qbsm.Matrix(a.nrows, b.ncols, a.bs)
+    st = {}
+
+    def step():
+        A.set_blocks(*ra)
+        B.set_blocks(*rb)
+        st["P"] = qbsm.Plan(A, B)
+        st["P"].numeric("f64", C)
+
+    ms, kern, _ = _timed_steps(torch, qbsm, step, steps, warmup)
+    info = st["P"].info()
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    cpu, ref = _oracle_timed(lambda: O.multiply(oa, ob), info["flops"], "the whole product, FP64 oracle")
+    err = O.rel_fro(C.values().cpu().numpy(), ref.vals)
+    return {"workload": f"{c['name']} ({info['nblk_out']} C blocks, {info['nprod']} leaf products)",
+            "mode": "f64", "unit": info["unit"], "ms_per_step": round(ms, 4), "kernel_ms": round(kern, 4),
+            "value": round(info["flops"] / (ms * 1e-3) / 1e9, 3), "unit_value": "GFLOP/s",
+            "step": "set_blocks(A, B) + symbolic + numeric", "rel_err_vs_fp64_oracle": float(f"{err:.3e}"),
+            "roofline": _mfma_roofline("f64", info["flops"], kern, "numeric leaf-product kernel (f64): "
+                                       "latency-bound at this size"),
+            "cpu_baseline": cpu}
+
+
+def leg_config3(torch, qbsm, W, steps, warmup, modes=("bf16x3", "bf16")):
+    """Random 128x128 blocks at density 0.01, N 65536: BF16 and BF16X3 (the
+    last mode listed is the leg's chosen one); bound by HBM."""
+    from oracle import oracle as O
+
+    c = W.config3()
+    a, b = c["A"], c["B"]
+    bs = a.bs
+    ra, rb = _upload_raw(torch, a), _upload_raw(torch, b)
+    A, B = qbsm.Matrix(a.nrows, a.ncols, bs), qbsm.Matrix(b.nrows, b.ncols, bs)
+    C = qbsm.Matrix(a.nrows, b.ncols, bs)
+    A.set_blocks(*ra)
+    B.set_blocks(*rb)
+    res, st = {}, {}
+    for mode in modes:
+        unit = qbsm.autotune_unit(A, B, mode, reps=2)[0]
+
+        def step():
+            A.set_blocks(*ra)
+            B.set_blocks(*rb)
+            A.prepack(mode, 1)
+            B.prepack(mode, 2)
+            st["P"] = qbsm.Plan(A, B, unit=unit)
+            st["P"].numeric(mode, C)
+
+        ms, kern, _ = _timed_steps(torch, qbsm, step, steps, warmup)
+        info = st["P"].info()
+        alg = (A.nblk + B.nblk) * bs * bs * OPERAND_BYTES[mode] + info["nblk_out"] * bs * bs * RESULT_BYTES[mode]
+        res[mode] = {"ms_per_step": round(ms, 4), "kernel_ms": round(kern, 4), "unit": unit,
+                     "value": round(info["flops"] / (ms * 1e-3) / 1e9, 3), "algorithmic_bytes": int(alg),
+                     "kernel_gbps": round(alg / (kern * 1e-3) / 1e9, 1), "_vals": C.values().cpu().numpy()}
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    cpu, ref = _oracle_timed(lambda: O.multiply(oa, ob), info["flops"], "the whole product, FP64 oracle")
+    for mode in modes:
+        res[mode]["rel_err_vs_fp64_oracle"] = float(f"{O.rel_fro(res[mode].pop('_vals'), ref.vals):.3e}")
+    ch = res[modes[-1]]
+    return {"workload": f"{c['name']} ({A.nblk} + {B.nblk} blocks, {info['nblk_out']} C blocks, "
+                        f"{info['nprod']} leaf products)",
+            "mode": modes[-1], "modes": res, "ms_per_step": ch["ms_per_step"], "value": ch["value"],
+            "unit_value": "GFLOP/s", "step": "set_blocks(A, B) + packing + symbolic + numeric",
+            "roofline": {"bound": "hbm", "achieved": ch["kernel_gbps"], "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(ch["kernel_gbps"] / 8000.0, 4), "traffic": None,
+                         "algorithmic_bytes": ch["algorithmic_bytes"],
+                         "kernel": f"numeric leaf-product kernel, mode {modes[-1]}, unit {ch['unit']}"},
+            "cpu_baseline": cpu}
+
+
+def leg_config5(torch, qbsm, W, steps, warmup, mode="f32"):
+    """Banded N 16384, 64x64 leaves, h 6, FP32 entries: forward C = A B and
+    the masked backward (dA on A's pattern, dB on B's) from stored operands."""
+    from oracle import oracle as O
+
+    c = W.config5()
+    A, B, dC = qbsm.from_host(c["A"]), qbsm.from_host(c["B"]), qbsm.from_host(c["dC"])
+    st = {}
+
+    def fwd():
+        st["C"] = qbsm.matmul(A, B, mode)
+
+    def bwd():
+        st["g"] = qbsm.backward(A, B, dC, mode)
+
+    info = qbsm.Plan(A, B).info()
+    fms, fkern, _ = _timed_steps(torch, qbsm, fwd, steps, warmup)
+    bms, bkern, nb = _timed_steps(torch, qbsm, bwd, steps, warmup)
+    fl_f, fl_b = info["flops"], 2 * info["flops"]
+    oa, ob, odc = O.from_workload(c["A"]), O.from_workload(c["B"]), O.from_workload(c["dC"])
+
+    def oracle_pass():
+        return O.multiply(oa, ob), O.backward(oa, ob, odc)
+
+    cpu, (ref, (ga, gb)) = _oracle_timed(oracle_pass, fl_f + fl_b, "forward + masked backward, FP64 oracle")
+    dA, dB = st["g"]
+    err = {"forward": float(f"{O.rel_fro(st['C'].values().cpu().numpy(), ref.vals):.3e}"),
+           "dA": float(f"{O.rel_fro(dA.values().cpu().numpy(), ga):.3e}"),
+           "dB": float(f"{O.rel_fro(dB.values().cpu().numpy(), gb):.3e}")}
+    ms = fms + bms
+    return {"workload": f"{c['name']} ({info['nprod']} leaf products; each reused for dA and for dB)",
+            "mode": mode, "ms_per_step": round(ms, 4), "forward_ms": round(fms, 4), "backward_ms": round(bms, 4),
+            "value": round((fl_f + fl_b) / (ms * 1e-3) / 1e9, 3), "unit_value": "GFLOP/s",
+            "backward_gflops": round(fl_b / (bms * 1e-3) / 1e9, 3),
+            "step": "forward (symbolic + numeric) + backward (dA and dB), operands stored",
+            "rel_err_vs_fp64_oracle": err,
+            "roofline": _mfma_roofline(mode, fl_b / 2, bkern, f"numeric leaf-product kernel of the backward "
+                                       f"({mode}; one of its two launches)"),
+            "cpu_baseline": cpu}
+
+
+def batched_member_builder(torch, qbsm, W, spec):
+    """Callable leaf size -> the member's (A, B) handles, stored in FP32.
+    Banded members are defined at their own leaf size (their half-bandwidth
+    counts blocks); decay members are given by their points, so any leaf
+    size stores the same matrix (before the block drop)."""
+
+    def build(bs):
+        if spec["kind"] == "banded":
+            assert bs == spec["bs"], "a banded member keeps its leaf size"
+            mem = W.config4_member(spec)
+            A, B = qbsm.from_host(mem["A"]), qbsm.from_host(mem["B"])
+            A.store_f32()
+            B.store_f32()
+            return A, B
+        # decay values generated on the device (FP64), then stored in FP32
+        pts = W.decay_points(spec["n"], 0.1, np.random.default_rng([4, spec["m"]]))
+        r, c, v = W.decay_blocks_device(pts, bs)
+        A = qbsm.Matrix(spec["n"], spec["n"], bs)
+        A.set_blocks(r, c, v, spec["drop_tol"])
+        del r, c, v
+        A.store_f32()
+        return A, A
+
+    return build
+
+
+def build_batched(torch, qbsm, W, unit=128, leaf="given"):
+    """The batched workload: 256 multiplies of uneven sizes (N 1024..16384,
+    leaves 32 or 64, banded members with independent A and B, decay members
+    squared), stored in FP32, with one plan per member at `unit`; decay
+    members stored at `leaf` (32 or 64) unless it is "given"."""
     specs = W.config4_members()
     plans, handles = [], []
     for spec in specs:
-        if spec["kind"] == "banded":
-            mem = W.config4_member(spec)
-            A, B = qbsm.from_host(mem["A"]), qbsm.from_host(mem["B"])
-        else:
-            # decay values generated on the device (FP64), then stored in FP32
-            pts = W.decay_points(spec["n"], 0.1, np.random.default_rng([4, spec["m"]]))
-            r, c, v = W.decay_blocks_device(pts, spec["bs"])
-            A = qbsm.Matrix(spec["n"], spec["n"], spec["bs"])
-            A.set_blocks(r, c, v, spec["drop_tol"])
-            del r, c, v
-            B = A
-        A.store_f32()
-        if B is not A:
-            B.store_f32()
+        bs = spec["bs"] if (leaf == "given" or spec["kind"] == "banded") else int(leaf)
+        A, B = batched_member_builder(torch, qbsm, W, spec)(bs)
         plans.append(qbsm.Plan(A, B, unit=unit))
         handles.append((A, B))
     torch.cuda.empty_cache()
+    return specs, plans, handles
+
+
+def tuned_batch_settings(torch, qbsm, W, log=None):
+    """The autotuner's (leaf option, unit, occupancy) for the batched
+    workload, from the cache when the batch's key is there.  The key needs the
+    plan infos of the batch as given; returns them with the built batch so
+    that a "given" choice reuses it."""
+    from paper_2011_11762_amd import autotune
+
+    specs, plans, handles = build_batched(torch, qbsm, W, 128, "given")
+    infos = [p.info() for p in plans]
+    members = [{"bs": s["bs"], "flexible": s["kind"] == "decay", "build": batched_member_builder(torch, qbsm, W, s)}
+               for s in specs]
+    t0 = time.perf_counter()
+    choice, key, cached = autotune.tune_batch(qbsm, "f32", members, infos=infos, log=log)
+    return choice, key, cached, time.perf_counter() - t0, (specs, plans, handles)
+
+
+def leg_config4(torch, qbsm, W, steps, warmup, unit=0, oracle_members=(0, 2, 4, 6, 1, 3)):
+    """The batched form: one persistent launch over all 256 members' work
+    units, captured once as a HIP graph and replayed; a step is one replay
+    (operand re-packing + the persistent kernel).  unit 0: the unit side,
+    the occupancy and the decay members' leaf size come from the autotuner
+    (its cache, or a tuning run on a sample of the members).  The oracle
+    checks and is timed on a bounded sample: whole banded members and sampled
+    output blocks of decay members (their FP32-stored values read back)."""
+    from oracle import oracle as O
+
+    t_gen = time.perf_counter()
+    tuning = None
+    if unit:
+        specs, plans, handles = build_batched(torch, qbsm, W, unit)
+        occ = 0
+    else:
+        log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)  # noqa: E731
+        choice, key, cached, tune_s, built = tuned_batch_settings(torch, qbsm, W, log=log)
+        unit, occ = choice["unit"], choice["wg_per_cu"]
+        tuning = {"key": key, "cached": cached, "tuning_s": round(tune_s, 2), "leaf": choice["leaf"],
+                  "unit": unit, "wg_per_cu": occ, "sample_ms": choice.get("ms"), "sample": choice.get("sample")}
+        log(f"batched settings ({'cached' if cached else 'tuned'}): leaf {choice['leaf']}, unit {unit}, "
+            f"{occ} WG/CU")
+        if choice["leaf"] == "given" and unit == 128:
+            specs, plans, handles = built
+        else:
+            del built
+            torch.cuda.empty_cache()
+            specs, plans, handles = build_batched(torch, qbsm, W, unit, choice["leaf"])
     infos = [p.info() for p in plans]
     flops = sum(i["flops"] for i in infos)
     batch = qbsm.Batch(plans, "f32")
+    if occ:
+        batch.set_occupancy(occ)
     torch.cuda.synchronize()
-    print(f"[bench] batched: {len(plans)} members, {flops / 1e12:.1f} TFLOP per step, built in "
-          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    build_s = time.perf_counter() - t_gen
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        for _ in range(max(args.warmup, 1)):  # the first replay captures the graph
+        ms, _, _ = _timed_steps(torch, qbsm, batch.run_graph, steps, max(warmup, 1))
+        # GPU time of one replay (the graph holds the packing and the
+        # persistent kernel; the library's own kernel events are not captured)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
             batch.run_graph()
-        stream.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            batch.run_graph()
-        stream.synchronize()
-        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        e1.record(stream)
+        e1.synchronize()
+        kern = e0.elapsed_time(e1) / steps
+    # oracle sample
+    refs, gots, oflops, nblocks = [], [], 0, 0
+    work = []
+    for m in oracle_members:
+        A, B = handles[m]
+        oa = O.canonical(A.nrows, A.ncols, A.bs, *[t.cpu().numpy() for t in A.pattern()], A.values().cpu().numpy())
+        ob = oa if B is A else O.canonical(B.nrows, B.ncols, B.bs, *[t.cpu().numpy() for t in B.pattern()],
+                                          B.values().cpu().numpy())
+        out = batch.outs[m]
+        cr, cc = (t.cpu().numpy() for t in out.pattern())
+        if specs[m]["kind"] == "banded":
+            work.append((oa, ob, None, None, out.values().cpu().numpy()))
+            oflops += infos[m]["flops"]
+            nblocks += cr.size
+        else:
+            rng = np.random.default_rng(40 + m)
+            pick = np.sort(rng.choice(cr.size, size=min(48, cr.size), replace=False))
+            si, sj = cr[pick].astype(np.int64), cc[pick].astype(np.int64)
+            work.append((oa, ob, si, sj, out.extract(si, sj).cpu().numpy()))
+            I, J, K, _, _ = O.product_triples(oa, ob)
+            sel = np.isin(I * (1 << 20) + J, si * (1 << 20) + sj)
+            oflops += O.block_flops(I[sel], J[sel], K[sel], oa.nrows, oa.ncols, ob.ncols, oa.bs)
+            nblocks += si.size
+
+    def oracle_pass():
+        return [O.multiply(oa, ob).vals if si is None else O.multiply_blocks(oa, ob, si, sj)
+                for oa, ob, si, sj, _ in work]
+
+    cpu, err = None, None
+    if work:
+        cpu, outs = _oracle_timed(oracle_pass, oflops, f"members {list(oracle_members)}: whole banded members "
+                                  f"and 48 sampled C blocks of each decay member ({nblocks} C blocks)",
+                                  one_thread=False)
+        num = sum(float(np.sum((w[4] - r) ** 2)) for w, r in zip(work, outs))
+        den = sum(float(np.sum(r ** 2)) for r in outs)
+        err = float(f"{(num / den) ** 0.5:.3e}")
     tflops = flops / (ms * 1e-3) / 1e12
-    print(f"[bench] batched f32: {ms:.3f} ms/step, {tflops * 1e3:.2f} GFLOP/s", file=sys.stderr, flush=True)
+    return {"workload": f"batched-{len(plans)}-members-n1024..16384-bs32/64-banded+decay "
+                        f"({sum(i['nblk_out'] for i in infos)} C blocks, {sum(i['nprod'] for i in infos)} "
+                        "leaf products)",
+            "mode": "f32", "unit": unit, "ms_per_step": round(ms, 4), "kernel_ms": round(kern, 4),
+            "value": round(tflops * 1e3, 3), "unit_value": "GFLOP/s", "flops_per_step": flops,
+            "build_s": round(build_s, 2), "autotune": tuning,
+            "step": "one HIP-graph replay: operand re-packing + one persistent MFMA kernel over every member",
+            "rel_err_vs_fp64_oracle": err,
+            "roofline": _mfma_roofline("f32", flops, kern, f"one graph replay: packing + persistent numeric kernel "
+                                       f"(f32, unit {unit}), HIP events on the replay stream"),
+            "cpu_baseline": cpu}
+
+
+def batched_main(args, torch, qbsm, W):
+    """The batched form as its own JSON line (see leg_config4)."""
+    leg = leg_config4(torch, qbsm, W, args.steps, args.warmup, unit=args.unit,
+                      oracle_members=() if args.no_cpu else (0, 2, 4, 6, 1, 3))
+    print(f"[bench] batched f32: {leg['ms_per_step']:.3f} ms/step, {leg['value']} GFLOP/s", file=sys.stderr,
+          flush=True)
     out = {
         "metric": METRIC,
-        "value": round(tflops * 1e3, 2),
+        "value": leg["value"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": max(args.warmup, 1),
-        "ms_per_step": round(ms, 4),
+        "ms_per_step": leg["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": f"batched-{len(plans)}-members-n1024..16384-bs32/64-banded+decay "
-                        f"({sum(i['nblk_out'] for i in infos)} C blocks, {sum(i['nprod'] for i in infos)} "
-                        "leaf products)",
-            "mode": "f32",
-            "unit": unit,
-            "flops_per_step": flops,
-            "step": "one HIP-graph replay of the batched numeric phase (operand re-packing + one persistent "
-                    "MFMA kernel over every member's work units)",
-        },
-        "roofline": {
-            "bound": "mfma",
-            "achieved": round(tflops, 2),
-            "peak": PEAK_TFLOPS["f32"],
-            "unit": "TFLOP/s",
-            "frac": round(tflops / PEAK_TFLOPS["f32"], 4),
-            "traffic": None,
-            "kernel": "persistent numeric leaf-product kernel, mode f32 (achieved over the whole replay, "
-                      "packing included)",
-        },
-        "cpu_baseline": None,
+        "config": {"workload": leg["workload"], "mode": "f32", "unit": leg["unit"],
+                   "flops_per_step": leg["flops_per_step"], "step": leg["step"], "autotune": leg["autotune"]},
+        "roofline": leg["roofline"],
+        "cpu_baseline": leg["cpu_baseline"] if not args.no_cpu else None,
+        "rel_err_vs_fp64_oracle": leg["rel_err_vs_fp64_oracle"] if not args.no_cpu else None,
     }
     print(json.dumps(out), flush=True)
 
@@ -644,6 +930,23 @@ def main():
         ef = a.meta["element_flops"]
         out["config"]["element_flops_table1"] = ef
         out["element_gflops"] = round(ef / (ch["ms_per_step"] * 1e-3) / 1e9, 2)
+    if args.workload == "decay" and not args.no_legs:
+        # the other workloads, each with its own roofline and oracle timing
+        del A, C, state, brow, bcol, vals
+        torch.cuda.empty_cache()
+        legs = {}
+        ls, lw = max(args.leg_steps, 1), 1
+        for name, fn in (("banded-n2048-f64", lambda: leg_config1(torch, qbsm, W, ls, lw)),
+                         ("random-blocks-n65536", lambda: leg_config3(torch, qbsm, W, ls, lw)),
+                         ("forward-backward-n16384-f32", lambda: leg_config5(torch, qbsm, W, ls, lw)),
+                         ("batched-256-f32", lambda: leg_config4(torch, qbsm, W, ls, lw))):
+            t_leg = time.perf_counter()
+            legs[name] = fn()
+            torch.cuda.empty_cache()
+            print(f"[bench] leg {name}: {legs[name]['ms_per_step']} ms/step, {legs[name]['value']} GFLOP/s, "
+                  f"roofline {legs[name]['roofline']['frac']} ({time.perf_counter() - t_leg:.1f} s)",
+                  file=sys.stderr, flush=True)
+        out["configs"] = legs
     print(json.dumps(out), flush=True)
 
 

@@ -79,18 +79,19 @@ typedef QBSM_ENUM(qbsm_status_e) {
  *               lo_a*hi_b, FP32 accumulation, FP32 result.  An infinite input
  *               gives a non-finite result (Inf, or NaN where the split terms of
  *               its partner differ in sign) in exactly the elements it reaches.
- *   QBSM_OZAKI_BF16 Ozaki splitting (Ozaki, Ogita, Oishi and Rump 2012) on
- *               bfloat16 MFMA: each line of a leaf (a row of the left operand,
- *               a column of the right one) gets the exponent e of its largest
- *               finite magnitude m (m < 2^e), and each element is cut into 6
- *               slices of 8-bit digits on the grid 2^(e - 8t), t = 1..6, each
- *               exact in bfloat16 (the 48 leading bits of the element below
- *               e).  The 21 slice pairs with t + u <= 7 are multiplied; the
- *               products of one pair group (t + u fixed) over one leaf sum in
- *               FP32 (exactly for t + u <= 5; groups 6 and 7 share one sum)
- *               and are accumulated in FP64; FP64 result.  Needs a plan with
- *               unit 64 (see qbsm_plan_opts).
- *               An infinite input gives a non-finite result where reached.
+ *   QBSM_OZAKI_I8 Ozaki splitting (Ozaki, Ogita, Oishi and Rump 2012) on
+ *               8-bit integer MFMA: each line of a leaf (a row of the left
+ *               operand, a column of the right one) gets the exponent e of its
+ *               largest magnitude m (m < 2^e), and each element is cut into 7
+ *               signed 7-bit digits on the grid 2^(e - 7t), t = 1..7 (the 49
+ *               leading bits of the element below e).  The 28 digit pairs with
+ *               t + u <= 8 are multiplied; the products of one pair group
+ *               (t + u fixed) over one leaf sum exactly in 32-bit integers, are
+ *               combined in FP64, scaled by 2^(e_row + e_col) (so the whole FP64
+ *               exponent range is covered) and accumulated in FP64; FP64 result.
+ *               Needs 64 x 64 leaves and a plan with unit 64 (see
+ *               qbsm_plan_opts).  A line holding an Inf or NaN makes every
+ *               element its leaf products reach NaN.
  * In every mode a product exists only where both leaf blocks are stored: an
  * Inf or NaN never meets the implicit zeros of a nil block. */
 typedef QBSM_ENUM(qbsm_mode_e) {
@@ -98,7 +99,7 @@ typedef QBSM_ENUM(qbsm_mode_e) {
     QBSM_F32 = 1,
     QBSM_BF16 = 2,
     QBSM_BF16X3 = 3,
-    QBSM_OZAKI_BF16 = 4
+    QBSM_OZAKI_I8 = 4
 } qbsm_mode;
 
 typedef struct qbsm_matrix_ *qbsm_matrix;
@@ -248,8 +249,8 @@ qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *
  * 0..2 and a value in {64, 128, 256}.  A plan with unit 256 serves the
  * 4-byte-accumulator modes (F32, BF16, BF16X3); its FP64 numeric phase
  * returns QBSM_ERR_UNSUPPORTED (a 256 x 256 FP64 accumulator exceeds the
- * register file of one compute unit).  QBSM_OZAKI_BF16 runs on plans with
- * unit 64 only (its six slices per operand fill the LDS) and returns
+ * register file of one compute unit).  QBSM_OZAKI_I8 runs on plans with
+ * unit 64 only (its seven slices per operand fill the LDS) and returns
  * QBSM_ERR_UNSUPPORTED otherwise. */
 typedef struct {
     int32_t unit;
@@ -322,7 +323,7 @@ qbsm_status qbsm_plan_destroy(qbsm_plan p);
  *          patterns they had then (QBSM_ERR_STATE otherwise).
  *   mode : arithmetic of the leaf products (qbsm_mode).
  *   out  : receives the plan's output pattern and values, stored FP64 for
- *          QBSM_F64 and QBSM_OZAKI_BF16, FP32 otherwise; its shape must be
+ *          QBSM_F64 and QBSM_OZAKI_I8, FP32 otherwise; its shape must be
  *          rows(op(L)) x cols(op(R)) with the same bs (QBSM_ERR_SHAPE) and it
  *          must not be an operand (QBSM_ERR_ARG).  Its memory is taken from
  *          the allocator unless it already holds this plan's result layout.
@@ -346,7 +347,7 @@ qbsm_status qbsm_multiply_numeric(qbsm_plan p, qbsm_mode mode, qbsm_matrix out, 
  *     the process ends, instead of allocator memory;
  *   - the result goes to the caller's array out_vals instead of a matrix
  *     handle: device memory of nblk_out * bs * bs elements, double for
- *     QBSM_F64 and QBSM_OZAKI_BF16 and float otherwise.  Block t of the
+ *     QBSM_F64 and QBSM_OZAKI_I8 and float otherwise.  Block t of the
  *     plan's output pattern is written column-major at t * bs * bs, the blocks
  *     taken in ascending Morton (Z) order of (I, J) -- the bits of I and J
  *     interleaved, I's bit above J's at every level -- which is the storage
@@ -362,19 +363,35 @@ qbsm_status qbsm_multiply_numeric(qbsm_plan p, qbsm_mode mode, qbsm_matrix out, 
  * Errors: as qbsm_multiply_numeric; QBSM_ERR_UNSUPPORTED, before any launch,
  * when the two operand packs need more than QBSM_NOALLOC_SCRATCH_BYTES (bytes
  * per stored leaf and operand: bs*bs times 8 for F64, 4 for F32 and BF16X3,
- * 2 for BF16, 12 for the Ozaki mode, plus 4*bs for the Ozaki exponents,
- * each operand's total rounded up to 256). */
+ * 2 for BF16, 7 for the Ozaki mode plus 4*bs for its line exponents; each
+ * operand's total rounded up to 256). */
 qbsm_status qbsm_multiply_numeric_noalloc(qbsm_plan p, qbsm_mode mode, void *out_vals, void *stream);
 
 /* Masked backward of C = A * B for an upstream gradient dC given on C's
  * pattern (dC may hold any subset of C's blocks):
  *   dA = (dC * B^T) restricted to A's pattern,
  *   dB = (A^T * dC) restricted to B's pattern.
- * dA / dB receive A's / B's pattern (either may be NULL to skip it).
- * Runs two masked symbolic walks and two numeric phases on `stream`. */
+ * dA / dB receive A's / B's pattern (either may be NULL to skip it); blocks
+ * of the pattern without a product are zero.  Every term is one forward leaf
+ * product (Sec. 2: the product list of the recursive multiply) whose dC
+ * block exists, so the forward product list is regrouped -- by A block for
+ * dA, by B block for dB -- instead of walking the quadtrees again: one
+ * symbolic walk (the forward one, unit side from opts, spamm_tol and upper
+ * ignored) and two numeric phases on `stream`.  Errors: QBSM_ERR_SHAPE when
+ * dC is not shaped like A*B; QBSM_ERR_ARG when an output is dC or both
+ * outputs are the same handle. */
 qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC, qbsm_mode mode,
                                    const qbsm_plan_opts *opts, qbsm_matrix dA, qbsm_matrix dB,
                                    void *stream);
+
+/* The same backward from the plan of the forward product (a regular plan of
+ * qbsm_multiply_symbolic: no transposes, mask, spamm_tol or upper option,
+ * QBSM_ERR_UNSUPPORTED otherwise; its operands' patterns unchanged,
+ * QBSM_ERR_STATE otherwise): no symbolic walk at all, only the regrouping of
+ * its product list (a stable sort on device) and the two numeric phases.
+ * The forward plan keeps its unit side. */
+qbsm_status qbsm_multiply_backward_plan(qbsm_plan forward, qbsm_matrix dC, qbsm_mode mode, qbsm_matrix dA,
+                                        qbsm_matrix dB, void *stream);
 
 /* ----------------------------------------------------------------- batched */
 
@@ -402,11 +419,33 @@ qbsm_status qbsm_batch_destroy(qbsm_batch batch);
 
 /* ----------------------------------------------------------------- tuning */
 
+/* Result of qbsm_batch_autotune. */
+typedef struct {
+    int32_t unit;           /* fastest work-unit side */
+    int32_t wg_per_cu;      /* fastest persistent occupancy, workgroups per compute unit */
+    double ms;              /* its time per batched run (operand packing + persistent kernel) */
+    double times_ms[3][4];  /* [unit 64, 128, 256][occupancy 1..4], < 0 where not applicable */
+} qbsm_batch_tuning;
+
+/* Autotuner of the batched form's tile schedule (the batch of Sec. 2.2
+ * multiplies that qbsm_batch_create runs in one launch): for every work-unit
+ * side that all members can run at -- which fixes the leaf-product kernel's
+ * wave tile, its LDS stage and how many leaves one workgroup owns -- and
+ * every persistent occupancy the kernel allows (at most 4 workgroups per
+ * compute unit), builds the plans of L[i] * R[i] and a batch over them, runs
+ * it once and then times `reps` runs with HIP events; reports the fastest
+ * setting and the whole table.  Pass a representative subset of a large
+ * batch: the trial batches allocate their own outputs and packs, which are
+ * freed before returning.  Synchronises.  Errors: QBSM_ERR_UNSUPPORTED when
+ * no unit side serves every member in this mode. */
+qbsm_status qbsm_batch_autotune(int32_t n, const qbsm_matrix *L, const qbsm_matrix *R, qbsm_mode mode,
+                                int32_t reps, void *stream, qbsm_batch_tuning *out);
+
 /* Times the numeric phase of C = A * B for every valid unit side (symbolic
  * + numeric, `reps` timed repetitions after one warm-up) and reports the
  * fastest.  times_ms (host, may be NULL) receives 3 entries in the order
  * unit = 64, 128, 256 (negative when not applicable to the leaf size or the
- * mode; QBSM_OZAKI_BF16 has unit 64 only). */
+ * mode; QBSM_OZAKI_I8 has unit 64 only). */
 qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps,
                                void *stream, int32_t *best_unit, double *times_ms);
 

@@ -62,12 +62,20 @@ def _load():
         lib.oracle_segmented_products.argtypes = [i32, i64, p, p, p, p, p,
                                                   ctypes.c_int, ctypes.c_int, p]
         lib.oracle_segmented_products.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
 
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the C part for the calls that follow; returns the
+    previous count (used to time the oracle on all threads and on one)."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 # --------------------------------------------------------------------------
@@ -591,9 +599,10 @@ def split_bf16(x: np.ndarray):
 # and its applications", Numer. Algorithms 59, 2012): an addition to the
 # paper's FP64-only leaves.  Reading taken here: one exponent per leaf row of
 # the left operand and per leaf column of the right operand; OZ_SLICES slices
-# of OZ_BITS-bit digits, each exactly representable in bfloat16; the slice
+# of OZ_BITS-bit digits, so that a signed digit is an 8-bit integer (|d| <=
+# 127) and a slice is that integer on the line's exponent grid; the slice
 # pairs with t + u <= OZ_SLICES + 1 are kept.
-OZ_SLICES, OZ_BITS = 6, 8
+OZ_SLICES, OZ_BITS = 7, 7
 
 
 def ozaki_split(vals: np.ndarray, bs: int, line: str, slices: int = OZ_SLICES, bits: int = OZ_BITS) -> np.ndarray:

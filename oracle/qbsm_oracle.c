@@ -20,6 +20,23 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* OpenMP threads of the calls that follow (n >= 1); returns the count used
+ * before.  Lets a caller time the same oracle on all threads and on one. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    const int before = omp_get_max_threads();
+    if (n >= 1) omp_set_num_threads(n);
+    return before;
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* Frobenius norm of each block: sqrt of the sum of squares, summed in
  * column-major element order, FP64 (the truncation rule of paper Sec. 2.2

@@ -110,6 +110,78 @@ ProfScope::~ProfScope() {
     if (e1) (void)hipEventRecord(e1, s);
 }
 
+// dA = (dC B^T) on A's pattern and dB = (A^T dC) on B's pattern from the
+// forward plan of A * B (either output may be null).
+void backward_from(const Plan &f, Matrix &dC, qbsm_mode mode, Matrix *dA, Matrix *dB, hipStream_t s) {
+    QB_CHECK(dC.nrows == f.out_rows && dC.ncols == f.out_cols, QBSM_ERR_SHAPE, "dC shape differs from A*B");
+    QB_CHECK(dA != &dC && dB != &dC && (!dA || dA != dB), QBSM_ERR_ARG, "outputs alias dC or each other");
+    Matrix *outs[2] = {dA, dB};
+    for (int which = 0; which < 2; ++which) {
+        if (!outs[which]) continue;
+        auto p = plan_backward(f, &dC, which, s);
+        numeric_prepare_output(*p, mode, *outs[which], s);
+        numeric_launch(*p, mode, *outs[which], s);
+    }
+}
+
+// Everything a batch run needs that allocates or synchronises: outputs,
+// operand packs, the member table and the longest-processing-time-first
+// work list (the cost of a unit is its number of node pairs).
+void batch_init(Batch &b, const std::vector<Plan *> &plans, const std::vector<Matrix *> &outs, qbsm_mode mode,
+                hipStream_t s) {
+    const int n = (int)plans.size();
+    b.n = n;
+    b.mode = mode;
+    b.num_cus = device_cu_count();
+    std::vector<K5Member> hm(n);
+    std::vector<std::vector<int32_t>> cost(n);
+    for (int i = 0; i < n; ++i) {
+        Plan &p = *plans[i];
+        if (i == 0) b.unit = p.unit;
+        QB_CHECK(p.unit == b.unit, QBSM_ERR_UNSUPPORTED, "all members must use the same unit side");
+        for (int j = 0; j < i; ++j) QB_CHECK(outs[j] != outs[i], QBSM_ERR_ARG, "two members share an output");
+        numeric_prepare_output(p, mode, *outs[i], s);
+        hm[i] = make_member(p, mode, *outs[i], s);
+        b.plans.push_back(&p);
+        b.outs.push_back(outs[i]);
+        b.out_vals.push_back(outs[i]->storage == ST_F64 ? (const void *)outs[i]->v64.p : (const void *)outs[i]->v32.p);
+        b.out_pattern.push_back(outs[i]->pattern_id);
+        // operand packs replayed on each run
+        for (int side = 0; side < 2; ++side) {
+            Matrix *mm = side == 0 ? p.L : p.R;
+            Role role = side == 0 ? (p.transL ? ROLE_COL : ROLE_ROW) : (p.transR ? ROLE_ROW : ROLE_COL);
+            bool seen = false;
+            for (auto &j : b.packs) seen |= (j.m == mm && j.mode == mode && j.role == role);
+            if (!seen) {
+                const Pack &pk = mm->packs[std::make_pair((int)mode, (int)role)];
+                b.packs.push_back({mm, mode, role, pk.buf.p, pk.buf.n, mm->storage_id});
+            }
+        }
+        // per-unit cost: number of node pairs (read back for ordering)
+        std::vector<int32_t> us(p.nunits + 1);
+        if (p.nunits)
+            QB_HIP(hipMemcpyAsync(us.data(), p.ustart.p, (p.nunits + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+        cost[i].resize(p.nunits);
+        for (int64_t u = 0; u < p.nunits; ++u) cost[i][u] = us[u + 1] - us[u];
+    }
+    // longest-processing-time-first order over all (member, unit) items
+    std::vector<int2> items;
+    for (int i = 0; i < n; ++i)
+        for (int64_t u = 0; u < (int64_t)cost[i].size(); ++u) items.push_back(make_int2(i, (int)u));
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const int2 &x, const int2 &y) { return cost[x.x][x.y] > cost[y.x][y.y]; });
+    b.nitems = (int64_t)items.size();
+    b.members.alloc(n ? n : 1, s);
+    b.items.alloc(items.empty() ? 1 : items.size(), s);
+    b.counter.alloc(1, s);
+    if (n) QB_HIP(hipMemcpyAsync(b.members.p, hm.data(), n * sizeof(K5Member), hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        QB_HIP(hipMemcpyAsync(b.items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    QB_HIP(hipStreamSynchronize(s));
+    b.wg_per_cu = b.unit ? k5_occupancy(mode, b.unit, 0) : 1;
+}
+
 }  // namespace qbsm
 
 using namespace qbsm;
@@ -143,7 +215,7 @@ static_assert(sizeof(qbsm_plan_opts) == 32 && offsetof(qbsm_plan_opts, upper) ==
               "plan options layout is part of the ABI");
 
 bool valid_mode(qbsm_mode m) {
-    return m == QBSM_F64 || m == QBSM_F32 || m == QBSM_BF16 || m == QBSM_BF16X3 || m == QBSM_OZAKI_BF16;
+    return m == QBSM_F64 || m == QBSM_F32 || m == QBSM_BF16 || m == QBSM_BF16X3 || m == QBSM_OZAKI_I8;
 }
 
 }  // namespace
@@ -373,18 +445,18 @@ qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC,
                  "dC shape differs from A*B");
         const int unit = opts ? opts->unit : 0;
         hipStream_t s = as_stream(stream);
-        if (dA) {
-            // dA = (dC * B^T) restricted to A's pattern
-            auto p = plan_build(&dC->m, 0, &B->m, 1, &A->m, unit, 0.0, 0, s);
-            numeric_prepare_output(*p, mode, dA->m, s);
-            numeric_launch(*p, mode, dA->m, s);
-        }
-        if (dB) {
-            // dB = (A^T * dC) restricted to B's pattern
-            auto p = plan_build(&A->m, 1, &dC->m, 0, &B->m, unit, 0.0, 0, s);
-            numeric_prepare_output(*p, mode, dB->m, s);
-            numeric_launch(*p, mode, dB->m, s);
-        }
+        // one symbolic walk for the forward product list, regrouped for both adjoints
+        auto f = plan_build(&A->m, 0, &B->m, 0, nullptr, unit, 0.0, 0, s);
+        backward_from(*f, dC->m, mode, dA ? &dA->m : nullptr, dB ? &dB->m : nullptr, s);
+    });
+}
+
+qbsm_status qbsm_multiply_backward_plan(qbsm_plan forward, qbsm_matrix dC, qbsm_mode mode, qbsm_matrix dA,
+                                        qbsm_matrix dB, void *stream) {
+    return guard([&] {
+        QB_CHECK(forward && forward->p && dC, QBSM_ERR_ARG, "null argument");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        backward_from(*forward->p, dC->m, mode, dA ? &dA->m : nullptr, dB ? &dB->m : nullptr, as_stream(stream));
     });
 }
 
@@ -393,63 +465,15 @@ qbsm_status qbsm_batch_create(int32_t n, const qbsm_plan *plans, qbsm_mode mode,
     return guard([&] {
         QB_CHECK(n >= 0 && batch && (n == 0 || (plans && outs)), QBSM_ERR_ARG, "null argument");
         QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
-        hipStream_t s = as_stream(stream);
-        auto h = std::make_unique<qbsm_batch_>();
-        Batch &b = h->b;
-        b.n = n;
-        b.mode = mode;
-        b.num_cus = device_cu_count();
-        std::vector<K5Member> hm(n);
-        std::vector<std::vector<int32_t>> cost(n);
+        std::vector<Plan *> ps(n);
+        std::vector<Matrix *> os(n);
         for (int i = 0; i < n; ++i) {
             QB_CHECK(plans[i] && plans[i]->p && outs[i], QBSM_ERR_ARG, "null plan or output");
-            Plan &p = *plans[i]->p;
-            if (i == 0) b.unit = p.unit;
-            QB_CHECK(p.unit == b.unit, QBSM_ERR_UNSUPPORTED, "all members must use the same unit side");
-            for (int j = 0; j < i; ++j)
-                QB_CHECK(outs[j] != outs[i], QBSM_ERR_ARG, "two members share an output");
-            numeric_prepare_output(p, mode, outs[i]->m, s);
-            hm[i] = make_member(p, mode, outs[i]->m, s);
-            b.plans.push_back(&p);
-            b.outs.push_back(&outs[i]->m);
-            b.out_vals.push_back(outs[i]->m.storage == ST_F64 ? (const void *)outs[i]->m.v64.p
-                                                              : (const void *)outs[i]->m.v32.p);
-            b.out_pattern.push_back(outs[i]->m.pattern_id);
-            // operand packs replayed on each run
-            for (int side = 0; side < 2; ++side) {
-                Matrix *mm = side == 0 ? p.L : p.R;
-                Role role = side == 0 ? (p.transL ? ROLE_COL : ROLE_ROW) : (p.transR ? ROLE_ROW : ROLE_COL);
-                bool seen = false;
-                for (auto &j : b.packs) seen |= (j.m == mm && j.mode == mode && j.role == role);
-                if (!seen) {
-                    const Pack &pk = mm->packs[std::make_pair((int)mode, (int)role)];
-                    b.packs.push_back({mm, mode, role, pk.buf.p, pk.buf.n});
-                }
-            }
-            // per-unit cost: number of node pairs (read back for ordering)
-            std::vector<int32_t> us(p.nunits + 1);
-            if (p.nunits)
-                QB_HIP(hipMemcpyAsync(us.data(), p.ustart.p, (p.nunits + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            QB_HIP(hipStreamSynchronize(s));
-            cost[i].resize(p.nunits);
-            for (int64_t u = 0; u < p.nunits; ++u) cost[i][u] = us[u + 1] - us[u];
+            ps[i] = plans[i]->p.get();
+            os[i] = &outs[i]->m;
         }
-        // longest-processing-time-first order over all (member, unit) items
-        std::vector<int2> items;
-        for (int i = 0; i < n; ++i)
-            for (int64_t u = 0; u < (int64_t)cost[i].size(); ++u) items.push_back(make_int2(i, (int)u));
-        std::stable_sort(items.begin(), items.end(), [&](const int2 &x, const int2 &y) {
-            return cost[x.x][x.y] > cost[y.x][y.y];
-        });
-        b.nitems = (int64_t)items.size();
-        b.members.alloc(n ? n : 1, s);
-        b.items.alloc(items.empty() ? 1 : items.size(), s);
-        b.counter.alloc(1, s);
-        if (n) QB_HIP(hipMemcpyAsync(b.members.p, hm.data(), n * sizeof(K5Member), hipMemcpyHostToDevice, s));
-        if (!items.empty())
-            QB_HIP(hipMemcpyAsync(b.items.p, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-        QB_HIP(hipStreamSynchronize(s));
-        b.wg_per_cu = b.unit ? k5_occupancy(mode, b.unit, 0) : 1;
+        auto h = std::make_unique<qbsm_batch_>();
+        batch_init(h->b, ps, os, mode, as_stream(stream));
         *batch = h.release();
     });
 }
@@ -527,7 +551,7 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
             const int u = cand[ci];
             double t = -1.0;
             const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64) &&
-                            !(mode == QBSM_OZAKI_BF16 && u != 64);
+                            !(mode == QBSM_OZAKI_I8 && (u != 64 || bs != 64));
             if (ok) {
                 auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, 0.0, 0, s);
                 Matrix out;
@@ -555,6 +579,81 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *best_unit = bu;
+    });
+}
+
+qbsm_status qbsm_batch_autotune(int32_t n, const qbsm_matrix *L, const qbsm_matrix *R, qbsm_mode mode, int32_t reps,
+                                void *stream, qbsm_batch_tuning *out) {
+    return guard([&] {
+        QB_CHECK(n >= 1 && L && R && out, QBSM_ERR_ARG, "null argument or empty member list");
+        QB_CHECK(valid_mode(mode), QBSM_ERR_ARG, "unknown mode");
+        QB_CHECK(reps >= 1, QBSM_ERR_ARG, "reps must be >= 1");
+        for (int i = 0; i < n; ++i) QB_CHECK(L[i] && R[i], QBSM_ERR_ARG, "null member matrix");
+        hipStream_t s = as_stream(stream);
+        qbsm_batch_tuning res{};
+        for (auto &row : res.times_ms)
+            for (double &t : row) t = -1.0;
+        res.ms = -1.0;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        QB_HIP(hipEventCreate(&e0));
+        QB_HIP(hipEventCreate(&e1));
+        struct Events {
+            hipEvent_t a, b;
+            ~Events() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev{e0, e1};
+        const int cand[3] = {64, 128, 256};
+        for (int ci = 0; ci < 3; ++ci) {
+            const int u = cand[ci];
+            bool ok = !(u == 256 && mode == QBSM_F64);
+            for (int i = 0; i < n && ok; ++i) {
+                const int bs = L[i]->m.bs;
+                ok = u % bs == 0 && u / bs <= 4 && !(mode == QBSM_OZAKI_I8 && (u != 64 || bs != 64));
+            }
+            if (!ok) continue;
+            std::vector<std::unique_ptr<Plan>> plans;
+            std::vector<std::unique_ptr<Matrix>> outs;
+            std::vector<Plan *> pp;
+            std::vector<Matrix *> op;
+            for (int i = 0; i < n; ++i) {
+                plans.push_back(plan_build(&L[i]->m, 0, &R[i]->m, 0, nullptr, u, 0.0, 0, s));
+                auto o = std::make_unique<Matrix>();
+                o->nrows = plans.back()->out_rows;
+                o->ncols = plans.back()->out_cols;
+                o->bs = L[i]->m.bs;
+                o->nbr = (o->nrows + o->bs - 1) / o->bs;
+                o->nbc = (o->ncols + o->bs - 1) / o->bs;
+                pp.push_back(plans.back().get());
+                op.push_back(o.get());
+                outs.push_back(std::move(o));
+            }
+            Batch b;  // destroyed before the plans and outputs it points to
+            batch_init(b, pp, op, mode, s);
+            const int maxocc = std::min(4, k5_occupancy(mode, u, 0));
+            for (int occ = 1; occ <= maxocc; ++occ) {
+                b.wg_per_cu = occ;
+                batch_settle(b, s);
+                batch_launch(b, s);  // warm-up (packs, caches)
+                QB_HIP(hipEventRecord(e0, s));
+                for (int r = 0; r < reps; ++r) batch_launch(b, s);
+                QB_HIP(hipEventRecord(e1, s));
+                QB_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                QB_HIP(hipEventElapsedTime(&ms, e0, e1));
+                const double t = (double)ms / reps;
+                res.times_ms[ci][occ - 1] = t;
+                if (res.ms < 0 || t < res.ms) {
+                    res.ms = t;
+                    res.unit = u;
+                    res.wg_per_cu = occ;
+                }
+            }
+            QB_HIP(hipStreamSynchronize(s));
+        }
+        QB_CHECK(res.unit != 0, QBSM_ERR_UNSUPPORTED, "no unit side serves every member in this mode");
+        *out = res;
     });
 }
 

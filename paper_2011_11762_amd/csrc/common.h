@@ -116,6 +116,19 @@ void bitmap_rank(const uint32_t *keys, const uint8_t *active, int64_t n, uint64_
 
 // ----------------------------------------------------------------- handles
 enum Storage { ST_NONE = 0, ST_F64 = 1, ST_F32 = 2 };
+
+// Ozaki mode: OZ_SLICES signed digits of OZ_BITS bits per element (each an
+// 8-bit integer); a packed leaf holds the slices [slice][chunk][line][bytes]
+// followed by one int32 exponent per line.  OZ_NONFINITE marks a line that
+// holds an Inf or NaN.
+constexpr int OZ_SLICES = 7, OZ_BITS = 7;
+constexpr int32_t OZ_NONFINITE = 0x10000000;  // twice it still fits an int32
+__host__ __device__ constexpr int64_t oz_leaf_bytes(int bs) {
+    return (int64_t)OZ_SLICES * bs * bs + 4 * (int64_t)bs;
+}
+__host__ __device__ inline int32_t *oz_exponents(uint8_t *pack, int64_t leaf, int bs) {
+    return reinterpret_cast<int32_t *>(pack + leaf * oz_leaf_bytes(bs) + (int64_t)OZ_SLICES * bs * bs);
+}
 enum Role { ROLE_ROW = 0, ROLE_COL = 1 };  // lines = rows / lines = columns
 
 // Sparse quadtree of one matrix at a given depth (paper Sec. 2.1: a node
@@ -131,7 +144,6 @@ struct Tree {
 struct Pack {
     DArr<uint8_t> buf;
     DArr<int32_t> nonfinite;  // [1]: set by the pack kernel when a packed value is Inf or NaN
-    DArr<int32_t> aux;        // Ozaki mode: exponent of every packed line [nblk * bs]
     uint64_t version = 0;
     // A pack made ahead of use runs on the library's side stream and records
     // this event; until a stream has waited for it, the buffers may still be
@@ -159,6 +171,7 @@ struct Matrix {
     uint64_t version = 0;    // bumped on every value change
     uint64_t filled_by = 0;  // id of the plan that last wrote this matrix as an output
     uint64_t pattern_id = 0; // bumped on every pattern change
+    uint64_t storage_id = 0; // bumped whenever the value array is replaced or freed
     DArr<double> norms;      // leaf Frobenius norms, valid when norms_version == version
     uint64_t norms_version = ~0ull;
     std::map<int, std::unique_ptr<Tree>> trees;         // by depth
@@ -223,6 +236,14 @@ int64_t matrix_truncate(Matrix &m, double eps, hipStream_t s);
 void matrix_add(double alpha, Matrix &A, double beta, Matrix &B, Matrix &C, hipStream_t s);
 void matrix_add_identity(Matrix &A, double sigma, hipStream_t s);
 void plan_get_products(Plan &p, int32_t *I, int32_t *K, int32_t *J, hipStream_t s);
+// QBSM_ERR_STATE unless the plan's operands still have their patterns.
+void plan_check_current(const Plan &p);
+// Masked backward plans regrouped from a forward plan (no symbolic walk):
+// which 0 gives dA = (dC op(R)^T) on L's pattern, 1 gives dB = (op(L)^T dC)
+// on R's pattern.  The forward plan must be a regular one (no transposes,
+// mask, approximation or triangle option).
+bool plan_backward_ok(const Plan &f);
+std::unique_ptr<Plan> plan_backward(const Plan &f, Matrix *dC, int which, hipStream_t s);
 
 // Packs operand values for (mode, role); returns the device buffer and the
 // strides (in elements) the numeric kernel uses to address leaf lines.
@@ -235,17 +256,14 @@ struct PackView {
     const int32_t *nonfinite = nullptr;  // device flag of the pack
 };
 PackView matrix_pack(Matrix &m, qbsm_mode mode, Role role, hipStream_t s);
-// Bytes of one (mode, role) pack of m, and the number of int32 line
-// exponents that go with it (Ozaki mode; 0 otherwise).
+// Bytes of one (mode, role) pack of m.
 size_t pack_bytes(const Matrix &m, qbsm_mode mode);
-size_t pack_aux_count(const Matrix &m, qbsm_mode mode);
 // Strides of a pack of m for `mode` stored at buf.
 PackView pack_view(const Matrix &m, qbsm_mode mode, const void *buf, const int32_t *nonfinite);
 // Packs m's current values for (mode, role) into caller-provided device
-// memory: dst (pack_bytes), nonfinite (one int32 flag, cleared first) and aux
-// (pack_aux_count int32, Ozaki mode only).  Launches only.
-void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonfinite, int32_t *aux,
-               hipStream_t s);
+// memory: dst (pack_bytes) and nonfinite (one int32 flag, cleared first).
+// Launches only.
+void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonfinite, hipStream_t s);
 // Brings both packs (row and column lines) of m up to date in one pass when
 // both are stale; otherwise leaves them to matrix_pack.
 void matrix_pack_pair(Matrix &m, qbsm_mode mode, hipStream_t s);
@@ -306,7 +324,9 @@ struct Batch {
     // buf / bytes: the pack buffer the member records point to; out_vals /
     // out_pattern: each output's value buffer and pattern id.  A run checks
     // that all are still in place.
-    struct PackJob { Matrix *m; qbsm_mode mode; Role role; const void *buf; size_t bytes; };
+    // storage: the operand's storage_id at creation (the captured pack
+    // kernels read its value array of that time)
+    struct PackJob { Matrix *m; qbsm_mode mode; Role role; const void *buf; size_t bytes; uint64_t storage; };
     std::vector<PackJob> packs;
     std::vector<const void *> out_vals;
     std::vector<uint64_t> out_pattern;
@@ -315,6 +335,8 @@ struct Batch {
 K5Member member_from_views(const Plan &p, const int32_t *descL, const int32_t *descR, const PackView &vL,
                            const PackView &vR, void *C);
 
+void batch_init(Batch &b, const std::vector<Plan *> &plans, const std::vector<Matrix *> &outs, qbsm_mode mode,
+                hipStream_t s);
 void batch_launch(Batch &b, hipStream_t s);
 // Checks that the batch's plans, packs and outputs are still the ones its
 // member records point to (QBSM_ERR_STATE otherwise), then orders s after

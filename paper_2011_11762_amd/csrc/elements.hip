@@ -158,6 +158,7 @@ int64_t matrix_set_elements(Matrix &m, int64_t n, const int64_t *row, const int6
     QB_CHECK(!h.dup, QBSM_ERR_PATTERN, "repeated element");
     m.v64 = std::move(pool);
     m.v32.reset();
+    ++m.storage_id;
     m.keys = std::move(okeys);
     m.nblk = nb;
     m.storage = ST_F64;
@@ -219,11 +220,13 @@ int64_t matrix_truncate(Matrix &m, double eps, hipStream_t s) {
         k_gather_kept<float><<<(unsigned)n, 256, 0, s>>>(keep.p, pos.p, n, m.keys.p, m.v32.p, n2, okeys.p, ov.p);
         QB_LAUNCH_CHECK();
         m.v32 = std::move(ov);
+        ++m.storage_id;
     } else {
         DArr<double> ov(nk ? nk * n2 : 1, s);
         k_gather_kept<double><<<(unsigned)n, 256, 0, s>>>(keep.p, pos.p, n, m.keys.p, m.v64.p, n2, okeys.p, ov.p);
         QB_LAUNCH_CHECK();
         m.v64 = std::move(ov);
+        ++m.storage_id;
     }
     m.keys = std::move(okeys);
     m.nblk = nk;
@@ -319,6 +322,7 @@ void commit_values(Matrix &m, DArr<uint32_t> &okeys, DArr<double> &pool, int64_t
     m.keys = std::move(okeys);
     m.v64 = std::move(pool);
     m.v32.reset();
+    ++m.storage_id;
     m.nblk = nblk;
     m.storage = ST_F64;
     commit_new_pattern(m, s);

@@ -414,63 +414,78 @@ __global__ void __launch_bounds__(256) k_pack2(const Src *src, int32_t bk, uint8
     if (bad_col) *nf_col = 1;
 }
 
-// Ozaki splitting: 6 slices of 8-bit digits per element (each exact in
-// bfloat16) on the exponent grid of the element's packed line.
-constexpr int OZ_SLICES = 6, OZ_BITS = 8;
+// Ozaki splitting on 8-bit integers (Ozaki, Ogita, Oishi and Rump 2012):
+// every element of a packed line is cut into OZ_SLICES signed digits of
+// OZ_BITS bits on the exponent grid of that line; the line exponents are
+// stored after the slices of each leaf (OZ_* in common.h).
 
-// Exponent e of every packed line (a row of a leaf for the left operand, a
-// column for the right one): the largest finite magnitude m of the line
-// satisfies m < 2^e (e = 0 for an all-zero line).
+// Exponent e of every packed line (a row of a leaf for the left operand):
+// the largest magnitude m of the line satisfies m < 2^e (e = 0 for an
+// all-zero line); a line holding an Inf or NaN gets OZ_NONFINITE.
 template <class Src>
-__global__ void __launch_bounds__(256) k_oz_exp(const Src *src, int64_t nblk, int32_t bs, int role, int32_t *ex) {
+__global__ void __launch_bounds__(256) k_oz_exp_row(const Src *src, int64_t nblk, int32_t bs, uint8_t *dst,
+                                                    int32_t *nonfinite) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nblk * bs) return;
     const int64_t leaf = t / bs;
     const int l = (int)(t - leaf * bs);
     const Src *x = src + leaf * (int64_t)bs * bs;
     double m = 0.0;
+    bool bad = false;
     for (int k = 0; k < bs; ++k) {
-        const double v = fabs((double)(role == ROLE_COL ? x[k + (int64_t)l * bs] : x[l + (int64_t)k * bs]));
-        if (isfinite(v) && v > m) m = v;
+        const double v = fabs((double)x[l + (int64_t)k * bs]);
+        bad |= !isfinite(v);
+        m = v > m ? v : m;
     }
     int e = 0;
     if (m > 0.0) (void)frexp(m, &e);
-    ex[t] = e;
+    oz_exponents(dst, leaf, bs)[l] = bad ? OZ_NONFINITE : e;
+    if (bad) *nonfinite = 1;
 }
 
-// The same exponents for the columns of the leaves (right operand): one wave
-// per column, lane r reading row r (a column is contiguous, so the wave's
-// reads are coalesced), then a maximum over the wave.
+// The same for the columns of the leaves (right operand): one wave per
+// column, lane r reading row r (a column is contiguous, so the reads are
+// coalesced), then a maximum and a non-finite vote over the wave.
 template <class Src>
-__global__ void __launch_bounds__(256) k_oz_exp_col(const Src *src, int64_t nblk, int32_t bs, int32_t *ex) {
+__global__ void __launch_bounds__(256) k_oz_exp_col(const Src *src, int64_t nblk, int32_t bs, uint8_t *dst,
+                                                    int32_t *nonfinite) {
     const int64_t line = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int r = (int)(threadIdx.x & 63);
     if (line >= nblk * bs) return;  // the same for every lane of the wave
     const int64_t leaf = line / bs;
     const int64_t c = line - leaf * bs;
     double m = 0.0;
-    if (r < bs) {
-        const double v = fabs((double)src[leaf * (int64_t)bs * bs + c * bs + r]);
-        if (isfinite(v)) m = v;
+    int bad = 0;
+    for (int rr = r; rr < bs; rr += 64) {
+        const double v = fabs((double)src[leaf * (int64_t)bs * bs + c * bs + rr]);
+        bad |= !isfinite(v);
+        m = v > m ? v : m;  // a NaN never wins the comparison; the line is marked anyway
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmax(m, __shfl_xor(m, o, 64));
+        bad |= __shfl_xor(bad, o, 64);
+    }
     if (r == 0) {
         int e = 0;
-        if (m > 0.0) (void)frexp(m, &e);
-        ex[line] = e;
+        if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
+        oz_exponents(dst, leaf, bs)[c] = bad ? OZ_NONFINITE : e;
+        if (bad) *nonfinite = 1;
     }
 }
 
-// One 16-byte piece (8 elements) of one packed line, all 6 slices: element x
-// with line exponent e is cut into N = floor(|x| 2^(48 - e)) < 2^48 and slice
-// t holds sign(x) * digit_t(N) * 2^(e - 8t), digit t being bits
-// [48 - 8t, 56 - 8t) of N.  An Inf or NaN element is its own first slice.
+// One 16-byte piece (16 elements) of one packed line, all slices: element x
+// of a line with exponent e becomes N = floor(|x| 2^(B - e)) < 2^B, with
+// B = OZ_SLICES * OZ_BITS, and slice t = 1..OZ_SLICES holds the signed digit
+// sign(x) * bits [B - t OZ_BITS, B - (t - 1) OZ_BITS) of N, so that
+// x = sum_t digit_t 2^(e - t OZ_BITS) + (less than 2^(e - B)).  A line with
+// an Inf or NaN gets zero digits (its products are set to NaN from its
+// exponent).
 template <class Src>
 __global__ void __launch_bounds__(256) k_pack_oz(const Src *src, int64_t nblk, int32_t bs, int32_t bk, int role,
-                                                 const int32_t *ex, uint8_t *dst, int32_t *nonfinite) {
-    constexpr int EB = 2, EPP = 8;
-    const int LB = bk * EB;
+                                                 uint8_t *dst) {
+    constexpr int EPP = 16;
+    const int LB = bk;
     const int ppl = LB / 16;
     const int64_t nc = bs / bk;
     const int64_t per_leaf = nc * bs * ppl;
@@ -491,55 +506,44 @@ __global__ void __launch_bounds__(256) k_pack_oz(const Src *src, int64_t nblk, i
     const int64_t n2 = (int64_t)bs * bs;
     const Src *x = src + leaf * n2;
     const int64_t k0 = c * bk + piece * EPP;
-    const int e = ex[leaf * bs + l];
-    uint16_t d[OZ_SLICES][EPP];
-    bool bad = false;
+    uint8_t *base = dst + leaf * oz_leaf_bytes(bs);
+    const int e = oz_exponents(dst, leaf, bs)[l];
+    uint32_t w[OZ_SLICES][4] = {};
+    if (e != OZ_NONFINITE) {
 #pragma unroll
-    for (int k = 0; k < EPP; ++k) {
-        const double v = role == ROLE_COL ? (double)x[(k0 + k) + l * bs] : (double)x[l + (k0 + k) * bs];
-        if (!isfinite(v)) {
-            bad = true;
-            d[0][k] = bf16_rne_bits(v);
+        for (int k = 0; k < EPP; ++k) {
+            const double v = role == ROLE_COL ? (double)x[(k0 + k) + l * bs] : (double)x[l + (k0 + k) * bs];
+            const uint64_t n = (uint64_t)floor(ldexp(fabs(v), OZ_SLICES * OZ_BITS - e));
 #pragma unroll
-            for (int q = 1; q < OZ_SLICES; ++q) d[q][k] = 0;
-            continue;
-        }
-        const uint64_t n = (uint64_t)floor(ldexp(fabs(v), OZ_SLICES * OZ_BITS - e));
-        const double sg = v < 0.0 ? -1.0 : 1.0;
-#pragma unroll
-        for (int q = 0; q < OZ_SLICES; ++q) {
-            const int sh = OZ_BITS * (OZ_SLICES - 1 - q);
-            const double digit = (double)((n >> sh) & 0xFFu);
-            d[q][k] = bf16_rne_bits(sg * ldexp(digit, e - OZ_BITS * (q + 1)));  // exact: 8 significant bits
+            for (int q = 0; q < OZ_SLICES; ++q) {
+                const int d = (int)((n >> (OZ_BITS * (OZ_SLICES - 1 - q))) & ((1u << OZ_BITS) - 1u));
+                const uint32_t b = (uint32_t)(uint8_t)(int8_t)(v < 0.0 ? -d : d);
+                w[q][k >> 2] |= b << (8 * (k & 3));
+            }
         }
     }
-    uint8_t *o = dst + leaf * (OZ_SLICES * n2 * EB) + c * (int64_t)bs * LB + l * LB +
-                 ((piece ^ piece_swizzle((int)l, LB)) << 4);
+    uint8_t *o = base + c * (int64_t)bs * LB + l * LB + ((piece ^ piece_swizzle((int)l, LB)) << 4);
 #pragma unroll
-    for (int q = 0; q < OZ_SLICES; ++q) {
-        uint4 w;
-        w.x = d[q][0] | ((uint32_t)d[q][1] << 16); w.y = d[q][2] | ((uint32_t)d[q][3] << 16);
-        w.z = d[q][4] | ((uint32_t)d[q][5] << 16); w.w = d[q][6] | ((uint32_t)d[q][7] << 16);
-        *reinterpret_cast<uint4 *>(o + q * n2 * EB) = w;
-    }
-    if (bad) *nonfinite = 1;
+    for (int q = 0; q < OZ_SLICES; ++q)
+        *reinterpret_cast<uint4 *>(o + q * n2) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
 }
 
 size_t mode_elem_bytes(qbsm_mode mode) {
     switch (mode) {
         case QBSM_F64: return 8;
         case QBSM_F32: return 4;
+        case QBSM_OZAKI_I8: return 1;
         default: return 2;
     }
 }
-int mode_parts(qbsm_mode mode) { return mode == QBSM_BF16X3 ? 2 : mode == QBSM_OZAKI_BF16 ? OZ_SLICES : 1; }
+int mode_parts(qbsm_mode mode) { return mode == QBSM_BF16X3 ? 2 : mode == QBSM_OZAKI_I8 ? OZ_SLICES : 1; }
 
 }  // namespace
 
 int mode_bk(qbsm_mode mode, int bs) {
     // K chunk per packed line: 128-byte lines, except the two-part split mode
     // (64-byte lines) so that two LDS stages of both parts fit in 64 KB
-    int bk = (mode == QBSM_BF16X3 || mode == QBSM_OZAKI_BF16 ? 64 : 128) / (int)mode_elem_bytes(mode);
+    int bk = (mode == QBSM_BF16X3 || mode == QBSM_OZAKI_I8 ? 64 : 128) / (int)mode_elem_bytes(mode);
     return bk < bs ? bk : bs;
 }
 
@@ -586,6 +590,7 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     }
     m.v64 = std::move(pool);
     m.v32.reset();
+    ++m.storage_id;
     m.keys = std::move(okeys);
     m.nblk = nk;
     m.storage = ST_F64;
@@ -648,6 +653,7 @@ void matrix_store_f32(Matrix &m, hipStream_t s) {
     }
     m.v32 = std::move(v);
     m.v64.reset();
+    ++m.storage_id;
     m.storage = ST_F32;
     m.version++;
     m.packs.clear();
@@ -766,11 +772,10 @@ void matrix_extract_blocks(Matrix &m, int64_t n, const int32_t *brow, const int3
 }
 
 void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s) {
-    pack_into(m, mode, role, pk.buf.p, pk.nonfinite.p, pk.aux.p, s);
+    pack_into(m, mode, role, pk.buf.p, pk.nonfinite.p, s);
 }
 
-void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonfinite, int32_t *aux,
-               hipStream_t s) {
+void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonfinite, hipStream_t s) {
     const int bk = mode_bk(mode, m.bs);
     const int ppl = bk * (int)mode_elem_bytes(mode) / 16;
     const int64_t work = m.nblk * (m.bs / bk) * (int64_t)m.bs * ppl;
@@ -781,21 +786,22 @@ void pack_into(Matrix &m, qbsm_mode mode, Role role, uint8_t *dst, int32_t *nonf
     const unsigned g = grid_for(work, 256);
     ProfScope prof(PROF_PACK, s);
     fill_i32(nonfinite, 0, 1, s);
-    if (mode == QBSM_OZAKI_BF16) {
+    if (mode == QBSM_OZAKI_I8) {
+        QB_CHECK(m.bs == 64, QBSM_ERR_UNSUPPORTED, "the Ozaki mode needs 64 x 64 leaves");
         const unsigned ge = grid_for(m.nblk * m.bs, 256);
         const unsigned gc = grid_for(m.nblk * m.bs * 64, 256);
         if (m.storage == ST_F64) {
             if (role == ROLE_COL)
-                k_oz_exp_col<double><<<gc, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, aux);
+                k_oz_exp_col<double><<<gc, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, dst, nonfinite);
             else
-                k_oz_exp<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, (int)role, aux);
-            k_pack_oz<double><<<g, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, bk, (int)role, aux, dst, nonfinite);
+                k_oz_exp_row<double><<<ge, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, dst, nonfinite);
+            k_pack_oz<double><<<g, 256, 0, s>>>(m.v64.p, m.nblk, m.bs, bk, (int)role, dst);
         } else {
             if (role == ROLE_COL)
-                k_oz_exp_col<float><<<gc, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, aux);
+                k_oz_exp_col<float><<<gc, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, dst, nonfinite);
             else
-                k_oz_exp<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, (int)role, aux);
-            k_pack_oz<float><<<g, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, bk, (int)role, aux, dst, nonfinite);
+                k_oz_exp_row<float><<<ge, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, dst, nonfinite);
+            k_pack_oz<float><<<g, 256, 0, s>>>(m.v32.p, m.nblk, m.bs, bk, (int)role, dst);
         }
         QB_LAUNCH_CHECK();
         return;
@@ -858,11 +864,8 @@ void pack2_launch(Matrix &m, qbsm_mode mode, Pack &pr, Pack &pc, hipStream_t ks)
 }
 
 size_t pack_bytes(const Matrix &m, qbsm_mode mode) {
+    if (mode == QBSM_OZAKI_I8) return (size_t)m.nblk * (size_t)oz_leaf_bytes(m.bs);
     return (size_t)m.nblk * m.bs * m.bs * mode_elem_bytes(mode) * mode_parts(mode);
-}
-
-size_t pack_aux_count(const Matrix &m, qbsm_mode mode) {
-    return mode == QBSM_OZAKI_BF16 ? (size_t)m.nblk * m.bs : 0;
 }
 
 PackView pack_view(const Matrix &m, qbsm_mode mode, const void *buf, const int32_t *nonfinite) {
@@ -871,7 +874,7 @@ PackView pack_view(const Matrix &m, qbsm_mode mode, const void *buf, const int32
     const int64_t n2 = (int64_t)bs * bs;
     PackView v;
     v.ptr = buf;
-    v.leaf_stride = n2 * mode_parts(mode);
+    v.leaf_stride = mode == QBSM_OZAKI_I8 ? oz_leaf_bytes(bs) : n2 * mode_parts(mode);
     v.part_stride = n2;
     v.line_stride = bk;
     v.chunk_stride = (int32_t)((int64_t)bs * bk);
@@ -884,15 +887,13 @@ bool pack_stale(const Matrix &m, qbsm_mode mode, const Pack &pk) {
     return pk.buf.n != pack_bytes(m, mode) || pk.version != m.version || !pk.buf.p;
 }
 bool pair_ok(const Matrix &m, qbsm_mode mode) {
-    return (m.bs == 32 || m.bs == 64) && m.nblk > 0 && mode != QBSM_OZAKI_BF16;
+    return (m.bs == 32 || m.bs == 64) && m.nblk > 0 && mode != QBSM_OZAKI_I8;
 }
 // Sizes the buffers of a stale pack (memory taken on s).
 void pack_size(const Matrix &m, qbsm_mode mode, Pack &pk, hipStream_t s) {
     const size_t bytes = pack_bytes(m, mode);
     if (pk.buf.n != bytes) pk.buf.alloc(bytes, s);
     if (!pk.nonfinite.p) pk.nonfinite.alloc(1, s);
-    const size_t naux = pack_aux_count(m, mode);
-    if (naux && pk.aux.n != naux) pk.aux.alloc(naux, s);
 }
 }  // namespace
 
@@ -915,7 +916,6 @@ void Pack::settle(hipStream_t s) {
     QB_HIP(hipStreamWaitEvent(s, ready, 0));
     if (buf.p && buf.s != s) QB_HIP(hipStreamWaitEvent(buf.s, ready, 0));
     if (nonfinite.p && nonfinite.s != s) QB_HIP(hipStreamWaitEvent(nonfinite.s, ready, 0));
-    if (aux.p && aux.s != s) QB_HIP(hipStreamWaitEvent(aux.s, ready, 0));
     (void)hipEventDestroy(ready);
     ready = nullptr;
 }
@@ -925,7 +925,6 @@ Pack::~Pack() {
     // the buffers are returned on their own streams: those wait for the pack
     if (buf.p) (void)hipStreamWaitEvent(buf.s, ready, 0);
     if (nonfinite.p) (void)hipStreamWaitEvent(nonfinite.s, ready, 0);
-    if (aux.p) (void)hipStreamWaitEvent(aux.s, ready, 0);
     (void)hipEventDestroy(ready);
 }
 

@@ -1,8 +1,9 @@
 // Numeric phase for callers that cannot allocate device memory (code under
 // HIP graph capture, tight serving loops, harnesses that forbid allocation).
 //
-// The operand packs, their non-finite flags and the Ozaki line exponents go
-// to one file-scope device array per GPU instead of allocator memory, and the
+// The operand packs (the Ozaki mode's line exponents are part of its packs)
+// and their non-finite flags go to one file-scope device array per GPU
+// instead of allocator memory, and the
 // result goes to a caller-owned array.  Everything else is the regular
 // numeric phase: the same pack kernels and the same leaf-product kernel.
 #include <mutex>
@@ -53,11 +54,11 @@ const int32_t *existing_desc(const Matrix &m, int D, int s) {
     return d->second.p;
 }
 
-// Scratch layout of one call: [left pack][right pack][2 flags][left exps][right exps],
-// each part 256-byte aligned; the right operand's parts are absent when both
-// sides use the same pack (the same matrix in the same role).
+// Scratch layout of one call: [left pack][right pack][2 flags], each part
+// 256-byte aligned; the right pack is absent when both sides use the same
+// pack (the same matrix in the same role).
 struct Layout {
-    size_t packL = 0, packR = 0, flags = 0, auxL = 0, auxR = 0, total = 0;
+    size_t packL = 0, packR = 0, flags = 0, total = 0;
 };
 
 Layout layout(const Plan &p, qbsm_mode mode, bool shared) {
@@ -69,10 +70,6 @@ Layout layout(const Plan &p, qbsm_mode mode, bool shared) {
     if (!shared) off += up(pack_bytes(*p.R, mode));
     l.flags = off;
     off += up(2 * sizeof(int32_t));
-    l.auxL = off;
-    off += up(pack_aux_count(*p.L, mode) * sizeof(int32_t));
-    l.auxR = shared ? l.auxL : off;
-    if (!shared) off += up(pack_aux_count(*p.R, mode) * sizeof(int32_t));
     l.total = off;
     return l;
 }
@@ -88,7 +85,7 @@ extern "C" qbsm_status qbsm_multiply_numeric_noalloc(qbsm_plan plan, qbsm_mode m
     try {
         QB_CHECK(plan, QBSM_ERR_ARG, "null plan");
         QB_CHECK(mode == QBSM_F64 || mode == QBSM_F32 || mode == QBSM_BF16 || mode == QBSM_BF16X3 ||
-                     mode == QBSM_OZAKI_BF16,
+                     mode == QBSM_OZAKI_I8,
                  QBSM_ERR_ARG, "unknown mode");
         QB_CHECK(plan->p, QBSM_ERR_ARG, "null plan");
         Plan &p = *plan->p;
@@ -102,7 +99,7 @@ extern "C" qbsm_status qbsm_multiply_numeric_noalloc(qbsm_plan plan, qbsm_mode m
         QB_CHECK(l.total <= (size_t)QBSM_NOALLOC_SCRATCH_BYTES, QBSM_ERR_UNSUPPORTED,
                  "operand packs of " + std::to_string(l.total) + " bytes exceed the " +
                      std::to_string((size_t)QBSM_NOALLOC_SCRATCH_BYTES) + "-byte scratch array");
-        const bool f64out = mode == QBSM_F64 || mode == QBSM_OZAKI_BF16;
+        const bool f64out = mode == QBSM_F64 || mode == QBSM_OZAKI_I8;
         const size_t out_bytes = (size_t)nout * p.bs * p.bs * (f64out ? sizeof(double) : sizeof(float));
         // a masked plan's output keeps the mask's pattern: blocks without
         // products read as zero
@@ -116,9 +113,8 @@ extern "C" qbsm_status qbsm_multiply_numeric_noalloc(qbsm_plan plan, qbsm_mode m
             QB_CHECK(m->has_blocks && (m->v64.p || m->v32.p), QBSM_ERR_STATE, "operand without values");
         uint8_t *base = scratch_ptr();
         int32_t *flags = reinterpret_cast<int32_t *>(base + l.flags);
-        pack_into(*p.L, mode, roleL, base + l.packL, flags, reinterpret_cast<int32_t *>(base + l.auxL), s);
-        if (!shared)
-            pack_into(*p.R, mode, roleR, base + l.packR, flags + 1, reinterpret_cast<int32_t *>(base + l.auxR), s);
+        pack_into(*p.L, mode, roleL, base + l.packL, flags, s);
+        if (!shared) pack_into(*p.R, mode, roleR, base + l.packR, flags + 1, s);
         const PackView vL = pack_view(*p.L, mode, base + l.packL, flags);
         const PackView vR = pack_view(*p.R, mode, base + l.packR, shared ? flags : flags + 1);
         const K5Member m = member_from_views(p, dL, dR, vL, vR, out_vals);

@@ -124,44 +124,69 @@ struct MT<QBSM_BF16X3> {
 // then hold zeros, so the products of a nil leaf add exact zeros.
 __device__ __attribute__((aligned(1024))) uint8_t g_zero_page[1024] = {};
 
-// Ozaki slices (6 per operand, each exact in bfloat16).  The products of
-// slice pairs (t, u) of one pair group g = t + u (2..7) lie on one exponent
-// grid per leaf (the line exponents are per leaf row / column), each an
-// integer below 2^16 on that grid.  Over one leaf of at most 64 K, groups
-// 2..5 hold at most 4 * 64 such products, so their FP32 MFMA sums are exact
-// (below 2^24 units); groups 6 and 7 share one FP32 sum, whose rounding lies
-// near 2^-48 of the leading group.  At the end of every leaf the five sums
-// are added to the FP64 accumulator and cleared.
+// Ozaki slices: OZ_SLICES = 7 signed 7-bit digits per element, as 8-bit
+// integers.  The products of digit pairs (t, u) of one pair group g = t + u
+// (2..8; the pairs with t + u > 8 are dropped) lie on one exponent grid
+// 2^(e_row + e_col - 7g) per leaf, and over one 64-wide leaf each group's
+// integer MFMA sum S_g is exact (|S_g| <= 7 * 64 * 127^2 < 2^23).  Groups
+// share four int32 accumulators: P1 = S_2 2^7 + S_3, P2 = S_4 2^7 + S_5,
+// P3 = S_6 2^7 + S_7 (each below 2^31: the accumulator is shifted by 7 bits
+// between its two groups) and P4 = S_8.  At the end of every leaf the four
+// are converted to FP64, scaled by 2^(e_row + e_col) and added to the FP64
+// accumulator, so the whole FP64 exponent range is covered.
+typedef __attribute__((ext_vector_type(4))) int i4;
+
 template <>
-struct MT<QBSM_OZAKI_BF16> {
-    using T = uint16_t;
+struct MT<QBSM_OZAKI_I8> {
+    using T = int8_t;
     using Acc = d4;
     using Out = double;
-    static constexpr int BK = 32, PARTS = 6, LBMAX = 64, KPG = 32, PPG = 4, SUBS = 1;
+    static constexpr int BK = 64, PARTS = OZ_SLICES, LBMAX = 64, KPG = 64, PPG = 4, SUBS = 1;
     static constexpr bool LEAF_SUMS = true;
-    static constexpr int NSUMS = 5;
-    struct Part { f4 s[NSUMS]; };
+    static constexpr int NSUMS = 4;
+    static_assert(OZ_SLICES == 7 && OZ_BITS == 7, "the accumulators below combine seven 7-bit pair groups");
+    struct Part { i4 s[NSUMS]; };
     struct Frag { uint4 q[1]; };
+    __device__ static i4 mm(const Frag *a, const Frag *b, int ta, int tb, i4 c) {
+        return __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i4, a[ta - 1].q[0]),
+                                                     __builtin_bit_cast(i4, b[tb - 1].q[0]), c, 0, 0, 0);
+    }
+    // the pairs (t, u) of group g into accumulator c
+    __device__ static i4 group(const Frag *a, const Frag *b, int g, i4 c) {
+#pragma unroll
+        for (int ta = 1; ta < g; ++ta)
+            if (ta <= OZ_SLICES && g - ta <= OZ_SLICES) c = mm(a, b, ta, g - ta, c);
+        return c;
+    }
     __device__ static void mma_part(Part &p, const Frag *a, const Frag *b) {
 #pragma unroll
-        for (int g = 2; g <= PARTS + 1; ++g) {
-            const int k = g <= 5 ? g - 2 : 4;
-#pragma unroll
-            for (int ta = 1; ta < g; ++ta)
-                p.s[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a[ta - 1].q[0]),
-                                                                 __builtin_bit_cast(bf8, b[g - ta - 1].q[0]), p.s[k],
-                                                                 0, 0, 0);
+        for (int k = 0; k < 3; ++k) {
+            p.s[k] = group(a, b, 2 * k + 2, p.s[k]);
+            p.s[k] = p.s[k] * 128;  // S_g 2^7, below 2^30
+            p.s[k] = group(a, b, 2 * k + 3, p.s[k]);
         }
+        p.s[3] = group(a, b, 8, p.s[3]);
     }
-    __device__ static void flush(Acc &c, Part &p) {
+    // c += 2^(er + ec) * (P1 2^-21 + P2 2^-35 + P3 2^-49 + P4 2^-56), element i
+    // of a lane being row 4*(lane/16) + i (exponent er[i]) and column
+    // lane % 16 (exponent ec).  NF: the operands hold non-finite lines,
+    // whose products become NaN.
+    template <bool NF>
+    __device__ static void flush(Acc &c, Part &p, const i4 &er, int ec) {
 #pragma unroll
-        for (int k = 0; k < NSUMS; ++k) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) c[i] += (double)p.s[k][i];
-            p.s[k] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 4; ++i) {
+            const double x = fma((double)p.s[3][i], 0x1p-35,
+                                 fma((double)p.s[2][i], 0x1p-28, fma((double)p.s[1][i], 0x1p-14, (double)p.s[0][i])));
+            const double v = c[i] + ldexp(x, er[i] + ec - 21);
+            if constexpr (NF)
+                c[i] = (er[i] == OZ_NONFINITE || ec == OZ_NONFINITE) ? __builtin_nan("") : v;
+            else
+                c[i] = v;
         }
+#pragma unroll
+        for (int k = 0; k < NSUMS; ++k) p.s[k] = i4{0, 0, 0, 0};
     }
-    // the FP32 MFMA layout: element i of a lane holds row 4*(lane/16) + i
+    // the integer MFMA layout: element i of a lane holds row 4*(lane/16) + i
     __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
@@ -308,7 +333,7 @@ struct Geo {
     static constexpr int IPA = U / LPI;                  // load instructions per array
     // side of the part one wave computes (the six Ozaki slices per operand
     // leave LDS for 64-wide units only: four waves of 32 x 32 there)
-    static constexpr int WT = MODE == QBSM_OZAKI_BF16 ? 32 : U >= 256 ? 128 : 64;
+    static constexpr int WT = MODE == QBSM_OZAKI_I8 ? 32 : U >= 256 ? 128 : 64;
     static constexpr int WPS = U / WT;                   // waves per unit side
     static constexpr int NW = WPS * WPS;
     static constexpr int TPW = WT / 16;                  // 16x16 tiles per wave side
@@ -325,7 +350,7 @@ struct Geo {
 };
 
 template <int MODE, int U>
-constexpr int k5_wt = MODE == QBSM_OZAKI_BF16 ? 32 : U >= 256 ? 128 : 64;
+constexpr int k5_wt = MODE == QBSM_OZAKI_I8 ? 32 : U >= 256 ? 128 : 64;
 
 template <int MODE, int U>
 constexpr int k5_nt = 64 * (U / k5_wt<MODE, U>) * (U / k5_wt<MODE, U>);
@@ -449,15 +474,45 @@ __device__ __forceinline__ Advance advance(const Meta &mt, int nb, const Step &s
     return a;
 }
 
+// Ozaki mode: the line exponents a wave needs for one step -- the rows of its
+// row tiles in the left leaf and the columns of its column tiles in the right
+// leaf -- read from the exponent block after the leaf's slices.  Loaded one
+// step ahead; the step's closing wait covers them.
+template <int TPW>
+struct OzExp {
+    i4 er[TPW];   // rows 4*(lane/16) .. +3 of row tile tm
+    int ec[TPW];  // column lane % 16 of column tile tn
+};
+
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void oz_load_exp(const Meta &mt, int i, int kb, int wr, int wc,
+                                            OzExp<Geo<MODE, U, BS>::TPW> &ex) {
+    using G = Geo<MODE, U, BS>;
+    if constexpr (MODE == QBSM_OZAKI_I8) {
+        const int lane = threadIdx.x & 63;
+        const uint64_t *d = mt.ad + (int64_t)i * 2 * G::NSUB + kb * 2 * G::LPU;
+        constexpr int64_t EXP_OFF = (int64_t)OZ_SLICES * BS * BS;
+#pragma unroll
+        for (int t = 0; t < G::TPW; ++t) {
+            const int r = G::WT * wr + 16 * t, c = G::WT * wc + 16 * t;
+            const uint64_t la = uni64(d[r / BS]), lb = uni64(d[G::LPU + c / BS]);
+            const int32_t *eA = reinterpret_cast<const int32_t *>(la + EXP_OFF);
+            const int32_t *eB = reinterpret_cast<const int32_t *>(lb + EXP_OFF);
+            ex.er[t] = *reinterpret_cast<const i4 *>(eA + (r % BS) + 4 * (lane >> 4));
+            ex.ec[t] = eB[(c % BS) + (lane & 15)];
+        }
+    }
+}
+
 // One step on stage cur: st is this step, nxa the next one with its copy
 // addresses (looked up during the previous step).  The step after next is
 // looked up once this step's MFMAs are issued, while the copies land.
-template <int MODE, int U, int BS, bool DENSE>
+template <int MODE, int U, int BS, bool DENSE, bool NF>
 __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
                                          typename MT<MODE>::Part (&part)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
                                          Step &st, Advance &nxa, const CopyLane &cl, uint32_t chunk_bytes, int w,
-                                         int wr, int wc) {
+                                         int wr, int wc, OzExp<Geo<MODE, U, BS>::TPW> &ex) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
     constexpr int PARTS = M::PARTS, TPW = G::TPW, TPL = G::TPL, NLW = G::NLW;
@@ -473,6 +528,10 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
 #pragma unroll
             for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, nxt, w);
         }
+    }
+    OzExp<TPW> ex_next = ex;
+    if constexpr (MODE == QBSM_OZAKI_I8) {
+        if (nxa.nx.i < nb) oz_load_exp<MODE, U, BS>(mt, nxa.nx.i, nxa.nx.kb, wr, wc, ex_next);
     }
     constexpr int TSPAN = TPW;
     constexpr int KPT = (G::PER_WAVE + TSPAN - 1) / TSPAN;
@@ -535,7 +594,8 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
 #pragma unroll
                 for (int tm = 0; tm < TPW; ++tm)
 #pragma unroll
-                    for (int tn = 0; tn < TPW; ++tn) M::flush(acc[tm][tn], part[tm][tn]);
+                    for (int tn = 0; tn < TPW; ++tn)
+                        M::template flush<NF>(acc[tm][tn], part[tm][tn], ex.er[tm], ex.ec[tn]);
             }
         }
     } else if (SPREAD) {
@@ -548,12 +608,13 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
     __syncthreads();
     st = nxa.nx;
     nxa = nn;
+    if constexpr (MODE == QBSM_OZAKI_I8) ex = ex_next;
 }
 
 // DENSE: the branch-free path (every tile multiplied, nil leaves copied as
 // zeros), valid when neither pack holds Inf or NaN (an infinite value times
 // the zero of a nil partner would give NaN where no product exists).
-template <int MODE, int U, int BS, bool DENSE>
+template <int MODE, int U, int BS, bool DENSE, bool NF = false>
 __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
@@ -575,8 +636,9 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
 #pragma unroll
             for (int b = 0; b < TPW; ++b)
 #pragma unroll
-                for (int k = 0; k < M::NSUMS; ++k) part[a][b].s[k] = f4{0.f, 0.f, 0.f, 0.f};
+                for (int k = 0; k < M::NSUMS; ++k) part[a][b].s[k] = i4{0, 0, 0, 0};
     }
+    OzExp<TPW> ex{};
 
     // (loaded values are not known to be wave-uniform: say so, or every
     // comparison with the batch size makes the step iterator divergent)
@@ -615,6 +677,7 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
             const uint64_t addrs = copy_addr<MODE, U, BS>(mt, st.i, st.kb, 0, cl, chunk_bytes);
 #pragma unroll
             for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
+            oz_load_exp<MODE, U, BS>(mt, st.i, st.kb, wr, wc, ex);
             nxa = advance<MODE, U, BS>(mt, nb, st, addrs, cl, chunk_bytes);
         }
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
@@ -622,9 +685,9 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         // steps alternate between the two stages; unrolled by two so that
         // every access names its stage array at compile time
         while (st.i < nb) {
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc);
+            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
             if (st.i >= nb) break;
-            run_step<MODE, U, BS, DENSE>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc);
+            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
         }
     }
 
@@ -681,12 +744,19 @@ __device__ __forceinline__ void process_sel(const K5Member &m, int u, uint8_t *s
             return;
         }
     }
+    if constexpr (MODE == QBSM_OZAKI_I8) {
+        if ((*m.nfL | *m.nfR) != 0) {
+            process_unit<MODE, U, BS, false, true>(m, u, st0, st1, meta);
+            return;
+        }
+    }
     process_unit<MODE, U, BS, false>(m, u, st0, st1, meta);
 }
 
 template <int MODE, int U>
 __device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
-    if constexpr (U <= 128) {
+    // (the Ozaki mode's 64-wide integer MFMA needs 64-wide leaves)
+    if constexpr (U <= 128 && MODE != QBSM_OZAKI_I8) {
         if (m.bs == 32) {
             process_sel<MODE, U, 32>(m, u, st0, st1, meta);
             return;
@@ -700,7 +770,7 @@ __device__ __forceinline__ void process_any(const K5Member &m, int u, uint8_t *s
 }
 
 template <int MODE, int U>
-constexpr int k5_min_blocks = (MODE == QBSM_F64 || MODE == QBSM_OZAKI_BF16 || U >= 256) ? 1 : 2;
+constexpr int k5_min_blocks = (MODE == QBSM_F64 || MODE == QBSM_OZAKI_I8 || U >= 256) ? 1 : 2;
 
 // BS > 0: one launch of one multiply with that leaf size, one workgroup per
 // unit.  BS == 0: persistent launch over a work list of (member, unit) items
@@ -737,7 +807,7 @@ void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems
         k5<MODE, U, 0><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
         return;
     }
-    if constexpr (U <= 128) {
+    if constexpr (U <= 128 && MODE != QBSM_OZAKI_I8) {
         if (bs == 32) {
             k5<MODE, U, 32><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
             return;
@@ -762,7 +832,7 @@ void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, i
     switch (unit) {
         case 64: launch_u<MODE, 64>(bs, members, items, nitems, counter, grid, persistent, single, s); break;
         case 128:
-            if constexpr (MODE != QBSM_OZAKI_BF16) {
+            if constexpr (MODE != QBSM_OZAKI_I8) {
                 launch_u<MODE, 128>(bs, members, items, nitems, counter, grid, persistent, single, s);
                 break;
             }
@@ -770,7 +840,7 @@ void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, i
         case 256:
             // the 128 x 128 part of a wave holds 64 KB of accumulators in FP32
             // but twice that in FP64, beyond the register file
-            if constexpr (MODE != QBSM_F64 && MODE != QBSM_OZAKI_BF16) {
+            if constexpr (MODE != QBSM_F64 && MODE != QBSM_OZAKI_I8) {
                 launch_u<MODE, 256>(bs, members, items, nitems, counter, grid, persistent, single, s);
                 break;
             }
@@ -781,6 +851,25 @@ void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, i
 
 }  // namespace
 
+#ifdef QB_K5_OZAKI_UNIT
+// This translation unit (numeric_oz.hip) holds the Ozaki mode's kernels only.
+void k5_launch_ozaki(int unit, int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter,
+                     int grid, int persistent, const K5Member &single, hipStream_t s) {
+    launch_mode<QBSM_OZAKI_I8>(unit, bs, members, items, nitems, counter, grid, persistent, single, s);
+}
+
+const void *k5_kernel_ozaki(int unit, int bs) {
+    if (unit != 64) return nullptr;
+    if (bs == 0) return reinterpret_cast<const void *>(&k5<QBSM_OZAKI_I8, 64, 0>);
+    if (bs == 64) return reinterpret_cast<const void *>(&k5<QBSM_OZAKI_I8, 64, 64>);
+    return nullptr;
+}
+#else
+// The Ozaki mode's kernels are compiled in numeric_oz.hip (see there).
+void k5_launch_ozaki(int unit, int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter,
+                     int grid, int persistent, const K5Member &single, hipStream_t s);
+const void *k5_kernel_ozaki(int unit, int bs);
+
 void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const int2 *items, int64_t nitems,
                int32_t *counter, int grid, int persistent, const K5Member &single, hipStream_t s) {
     if (grid <= 0) return;
@@ -790,8 +879,8 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const
         case QBSM_F32: launch_mode<QBSM_F32>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
         case QBSM_BF16: launch_mode<QBSM_BF16>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
         case QBSM_BF16X3: launch_mode<QBSM_BF16X3>(unit, bs, members, items, nitems, counter, grid, persistent, single, s); break;
-        case QBSM_OZAKI_BF16:
-            launch_mode<QBSM_OZAKI_BF16>(unit, bs, members, items, nitems, counter, grid, persistent, single, s);
+        case QBSM_OZAKI_I8:
+            k5_launch_ozaki(unit, bs, members, items, nitems, counter, grid, persistent, single, s);
             break;
         default: throw Error(QBSM_ERR_ARG, "mode");
     }
@@ -802,7 +891,7 @@ void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t, const
 // work-list variant).
 int k5_occupancy(qbsm_mode mode, int unit, int bs) {
     int nb = 0;
-    const int NT = mode == QBSM_OZAKI_BF16 ? 256 : 64 * (unit >= 256 ? 4 : (unit / 64) * (unit / 64));
+    const int NT = mode == QBSM_OZAKI_I8 ? 256 : 64 * (unit >= 256 ? 4 : (unit / 64) * (unit / 64));
     const void *fn = nullptr;
 #define QB_OCC(MD, UU, BB) \
     if (mode == MD && unit == UU && bs == BB) fn = reinterpret_cast<const void *>(&k5<MD, UU, BB>);
@@ -812,10 +901,10 @@ int k5_occupancy(qbsm_mode mode, int unit, int bs) {
 #define QB_OCC_256(MD) QB_OCC(MD, 256, 0) QB_OCC(MD, 256, 64) QB_OCC(MD, 256, 128)
     QB_OCC_M(QBSM_F64) QB_OCC_M(QBSM_F32) QB_OCC_M(QBSM_BF16) QB_OCC_M(QBSM_BF16X3)
     QB_OCC_256(QBSM_F32) QB_OCC_256(QBSM_BF16) QB_OCC_256(QBSM_BF16X3)
-    QB_OCC(QBSM_OZAKI_BF16, 64, 0) QB_OCC(QBSM_OZAKI_BF16, 64, 32) QB_OCC(QBSM_OZAKI_BF16, 64, 64)
 #undef QB_OCC_256
 #undef QB_OCC_M
 #undef QB_OCC
+    if (mode == QBSM_OZAKI_I8) fn = k5_kernel_ozaki(unit, bs);
     QB_CHECK(fn, QBSM_ERR_UNSUPPORTED, "no kernel for this mode, unit and leaf size");
     QB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, 0));
     return nb < 1 ? 1 : nb;
@@ -881,7 +970,8 @@ void numeric_check(const Plan &p, qbsm_mode mode) {
     plan_check_current(p);
     QB_CHECK(!(mode == QBSM_F64 && p.unit >= 256), QBSM_ERR_UNSUPPORTED,
              "unit 256 serves the FP32-accumulating modes only");
-    QB_CHECK(mode != QBSM_OZAKI_BF16 || p.unit == 64, QBSM_ERR_UNSUPPORTED, "the Ozaki mode runs at unit 64");
+    QB_CHECK(mode != QBSM_OZAKI_I8 || (p.unit == 64 && p.bs == 64), QBSM_ERR_UNSUPPORTED,
+             "the Ozaki mode needs 64 x 64 leaves and unit 64");
 }
 
 void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
@@ -889,7 +979,7 @@ void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s)
     QB_CHECK(&out != p.L && &out != p.R && &out != p.M, QBSM_ERR_ARG, "output aliases an operand");
     QB_CHECK(out.nrows == p.out_rows && out.ncols == p.out_cols && out.bs == p.bs, QBSM_ERR_SHAPE,
              "output shape or leaf size differs from the product");
-    const Storage want = mode == QBSM_F64 || mode == QBSM_OZAKI_BF16 ? ST_F64 : ST_F32;
+    const Storage want = mode == QBSM_F64 || mode == QBSM_OZAKI_I8 ? ST_F64 : ST_F32;
     const int64_t nout = p.nout;
     // the same plan refilling its own output: pattern and storage are already in place
     // (masked outputs keep their zero blocks: only the plan's products are rewritten)
@@ -913,6 +1003,7 @@ void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s)
         if (p.M) fill_bytes_zero(out.v32.p, elems * sizeof(float), s);
     }
     out.storage = want;
+    ++out.storage_id;
     out.nblk = nout;
     out.has_blocks = true;
     out.version++;
@@ -941,7 +1032,9 @@ void batch_settle(Batch &b, hipStream_t s) {
     }
     for (auto &j : b.packs) {
         Pack &pk = j.m->packs[std::make_pair((int)j.mode, (int)j.role)];
-        QB_CHECK(pk.buf.p == j.buf && pk.buf.n == j.bytes, QBSM_ERR_STATE,
+        // a re-stored operand may get a buffer at the old address, so the
+        // storage counter, not the address, tells whether the values moved
+        QB_CHECK(j.m->storage_id == j.storage && pk.buf.p == j.buf && pk.buf.n == j.bytes, QBSM_ERR_STATE,
                  "an operand's values were re-stored after the batch was created (create the batch again)");
         pk.settle(s);
     }
@@ -958,5 +1051,6 @@ void batch_launch(Batch &b, hipStream_t s) {
     if (b.nitems)
         k5_launch(b.mode, b.unit, b.members.p, b.n, b.items.p, b.nitems, b.counter.p, grid, 1, K5Member{}, s);
 }
+#endif  // QB_K5_OZAKI_UNIT
 
 }  // namespace qbsm

@@ -19,8 +19,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libqbsm.so")
 
-F64, F32, BF16, BF16X3, OZAKI_BF16 = 0, 1, 2, 3, 4
-MODES = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3, "ozaki": OZAKI_BF16}
+F64, F32, BF16, BF16X3, OZAKI_I8 = 0, 1, 2, 3, 4
+MODES = {"f64": F64, "f32": F32, "bf16": BF16, "bf16x3": BF16X3, "ozaki": OZAKI_I8}
 MODE_NAMES = {v: k for k, v in MODES.items()}
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "shape mismatch", 3: "invalid block pattern",
@@ -31,6 +31,10 @@ class QbsmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("unit", c_int32), ("wg_per_cu", c_int32), ("ms", c_double), ("times_ms", (c_double * 4) * 3)]
 
 
 class PlanOpts(ctypes.Structure):
@@ -75,12 +79,15 @@ _SIGS = {
     "qbsm_multiply_numeric_noalloc": [c_void_p, c_int32, c_void_p, c_void_p],
     "qbsm_multiply_backward": [c_void_p, c_void_p, c_void_p, c_int32, POINTER(PlanOpts), c_void_p, c_void_p,
                                c_void_p],
+    "qbsm_multiply_backward_plan": [c_void_p, c_void_p, c_int32, c_void_p, c_void_p, c_void_p],
     "qbsm_batch_create": [c_int32, POINTER(c_void_p), c_int32, POINTER(c_void_p), c_void_p, POINTER(c_void_p)],
     "qbsm_batch_run": [c_void_p, c_void_p],
     "qbsm_batch_run_graph": [c_void_p, c_void_p],
     "qbsm_batch_set_occupancy": [c_void_p, c_int32],
     "qbsm_batch_destroy": [c_void_p],
     "qbsm_autotune_unit": [c_void_p, c_void_p, c_int32, c_int32, c_void_p, POINTER(c_int32), POINTER(c_double)],
+    "qbsm_batch_autotune": [c_int32, POINTER(c_void_p), POINTER(c_void_p), c_int32, c_int32, c_void_p,
+                            POINTER(BatchTuning)],
     "qbsm_profile_enable": [c_int32],
     "qbsm_profile_reset": [],
     "qbsm_profile_read": [c_int32, POINTER(c_int64), POINTER(c_double)],
@@ -296,6 +303,17 @@ class Plan:
         return out
 
 
+    def backward(self, dC: Matrix, mode="f64", need_a=True, need_b=True):
+        """dA = (dC R^T) on L's pattern, dB = (L^T dC) on R's pattern from this
+        (forward) plan's product list: no symbolic walk."""
+        L, R, _ = self._keep
+        dA = Matrix(L.nrows, L.ncols, L.bs) if need_a else None
+        dB = Matrix(R.nrows, R.ncols, R.bs) if need_b else None
+        _check(_lib.qbsm_multiply_backward_plan(self._h, dC.handle, mode_id(mode),
+                                                dA.handle if dA is not None else None,
+                                                dB.handle if dB is not None else None, _stream()))
+        return dA, dB
+
     def numeric_noalloc(self, mode, out: torch.Tensor) -> torch.Tensor:
         """Numeric phase into a caller-owned tensor (float64 for f64/ozaki,
         float32 otherwise; [nblk_out, bs*bs], blocks in ascending Morton order
@@ -369,6 +387,20 @@ def autotune_unit(A: Matrix, B: Matrix, mode, reps: int = 3):
     return best.value, {64: times[0], 128: times[1], 256: times[2]}
 
 
+def batch_autotune(pairs, mode, reps: int = 1) -> dict:
+    """Times every valid (unit side, persistent occupancy) for a batch over
+    the (A, B) pairs; returns the fastest and the table {unit: {occ: ms}}."""
+    n = len(pairs)
+    lh = (c_void_p * n)(*[a.handle.value for a, _ in pairs])
+    rh = (c_void_p * n)(*[b.handle.value for _, b in pairs])
+    res = BatchTuning()
+    _check(_lib.qbsm_batch_autotune(n, lh, rh, mode_id(mode), int(reps), _stream(), ctypes.byref(res)))
+    table = {u: {o + 1: res.times_ms[i][o] for o in range(4) if res.times_ms[i][o] >= 0}
+             for i, u in enumerate((64, 128, 256))}
+    return {"unit": res.unit, "wg_per_cu": res.wg_per_cu, "ms": res.ms,
+            "table": {u: t for u, t in table.items() if t}}
+
+
 PROF_NUMERIC, PROF_PACK = 0, 1
 
 
@@ -409,10 +441,11 @@ class _MatmulFn(torch.autograd.Function):
         B = Matrix(k, n, bs)
         A.set_blocks(a_pat[0], a_pat[1], a_vals.detach().contiguous())
         B.set_blocks(b_pat[0], b_pat[1], b_vals.detach().contiguous())
-        C = Plan(A, B, unit=unit).numeric(mode)
+        P = Plan(A, B, unit=unit)
+        C = P.numeric(mode)
         cr, cc = C.pattern()
         ctx.save_for_backward(cr, cc)
-        ctx.handles = (A, B)
+        ctx.handles = (A, B, P)
         ctx.meta = (m, n, bs, mode, unit)
         ctx.mark_non_differentiable(cr, cc)
         return C.values(), cr, cc
@@ -420,11 +453,11 @@ class _MatmulFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g_vals, _g1, _g2):
         cr, cc = ctx.saved_tensors
-        A, B = ctx.handles
+        A, B, P = ctx.handles
         m, n, bs, mode, unit = ctx.meta
         dC = Matrix(m, n, bs)
         dC.set_blocks(cr, cc, g_vals.contiguous().to(torch.float64))
-        dA, dB = backward(A, B, dC, mode, unit, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        dA, dB = P.backward(dC, mode, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
         ga = dA.values() if dA is not None else None
         gb = dB.values() if dB is not None else None
         return ga, gb, None, None, None, None, None

@@ -190,6 +190,42 @@ def test_backward_small_vs_oracle(q):
                 assert_backward(values_np(dA), values_np(dB), oa, ob, odc, ga, gb, mode, f"unit={unit}")
 
 
+def test_backward_from_forward_plan(q):
+    """The backward regrouped from a forward plan: dC on a subset of C's
+    blocks (its missing blocks drop their products), every unit side, the
+    plan entry point equal bit for bit to the matrix entry point and to
+    itself on a repeat; rejected for plans it cannot regroup."""
+    for (m, k, n, bs, p, seed) in [(700, 520, 600, 64, 0.5, 24), (450, 390, 330, 32, 0.6, 25),
+                                    (640, 600, 700, 128, 0.5, 26)]:
+        a, b = W.small_random(m, k, n, bs, p, seed)
+        oa, ob = O.from_workload(a), O.from_workload(b)
+        ref = O.multiply(oa, ob)
+        rng = np.random.default_rng(seed)
+        keep = rng.random(ref.brow.size) < 0.7  # dC holds 70% of C's blocks
+        dcv = rng.uniform(-1, 1, size=(int(keep.sum()), bs * bs))
+        W.zero_padding(W.BlockMatrix(m, n, bs, ref.brow[keep], ref.bcol[keep], dcv))
+        odc = O.canonical(m, n, bs, ref.brow[keep], ref.bcol[keep], dcv)
+        ga, gb = O.backward(oa, ob, odc)
+        A, B = upload(q, a), upload(q, b)
+        dC = q.Matrix(m, n, bs)
+        dC.set_blocks(torch.from_numpy(ref.brow[keep].astype(np.int32)).cuda(),
+                      torch.from_numpy(ref.bcol[keep].astype(np.int32)).cuda(), torch.from_numpy(dcv).cuda())
+        for mode in ("f64", "f32"):
+            for unit in units(bs, mode):
+                P = q.Plan(A, B, unit=unit)
+                dA, dB = P.backward(dC, mode)
+                assert_backward(values_np(dA), values_np(dB), oa, ob, odc, ga, gb, mode, f"plan unit={unit}")
+                dA2, dB2 = q.backward(A, B, dC, mode, unit)
+                dA3, _ = P.backward(dC, mode, need_b=False)
+                assert np.array_equal(values_np(dA), values_np(dA2)) and np.array_equal(values_np(dB), values_np(dB2))
+                assert np.array_equal(values_np(dA), values_np(dA3))
+    A, B = upload(q, a), upload(q, b)
+    with pytest.raises(q.QbsmError):
+        q.Plan(A, B, upper=False, spamm_tol=1e-3).backward(dC, "f64")
+    with pytest.raises(q.QbsmError):
+        q.Plan(B, A, trans_l=True, trans_r=True).backward(dC, "f64")
+
+
 def test_masked_plan_products(q):
     a, b = W.small_random(300, 260, 200, 64, 0.5, 31)
     oa, ob = O.from_workload(a), O.from_workload(b)
@@ -277,6 +313,35 @@ def test_autotune_unit(q):
     assert all(times[u] > 0 for u in (64, 128, 256))
     best, times = q.autotune_unit(A, B, "f64", reps=1)
     assert best in (64, 128) and times[256] < 0
+
+
+def test_batch_autotune(q):
+    """The batch tuner times every (unit side, occupancy) that all members
+    can run at and returns the fastest; a member with 32-wide leaves rules
+    out unit 256, an FP64 batch too; the trial batches leave nothing behind."""
+    pairs = []
+    for t, (n, bs) in enumerate([(900, 64), (1300, 64), (700, 64)]):
+        a, b = W.small_random(n, n, n, bs, 0.4, 400 + t)
+        pairs.append((upload(q, a), upload(q, b)))
+    r = q.batch_autotune(pairs, "f32", reps=1)
+    assert set(r["table"]) == {64, 128, 256}
+    assert r["unit"] in r["table"] and r["ms"] == min(min(v.values()) for v in r["table"].values())
+    assert all(1 <= o <= 4 and t > 0 for row in r["table"].values() for o, t in row.items())
+    # the chosen settings run the batch correctly
+    plans = [q.Plan(A, B, unit=r["unit"]) for A, B in pairs]
+    singles = [values_np(p.numeric("f32")) for p in plans]
+    batch = q.Batch(plans, "f32")
+    batch.set_occupancy(r["wg_per_cu"])
+    batch.run()
+    torch.cuda.synchronize()
+    assert all(np.array_equal(values_np(o), s_) for o, s_ in zip(batch.outs, singles))
+    a32, b32 = W.small_random(600, 600, 600, 32, 0.4, 410)
+    r2 = q.batch_autotune(pairs + [(upload(q, a32), upload(q, b32))], "bf16x3", reps=1)
+    assert 256 not in r2["table"] and set(r2["table"]) <= {64, 128}
+    r3 = q.batch_autotune(pairs, "f64", reps=1)
+    assert 256 not in r3["table"]
+    with pytest.raises(q.QbsmError):
+        q.batch_autotune(pairs + [(upload(q, a32), upload(q, b32))], "ozaki", reps=1)
 
 
 UNIT256 = [
@@ -441,8 +506,8 @@ def test_prepack_matches_packing_on_use(q, bs):
 
 OZAKI_CASES = [
     (300, 260, 200, 64, 0.5, 81),
-    (190, 170, 150, 32, 0.5, 82),
-    (1000, 900, 1100, 32, 0.15, 83),
+    (190, 170, 150, 64, 1.0, 82),
+    (2000, 1900, 2100, 64, 0.15, 83),   # deeper tree, many pairs per unit
     (64 * 9 + 5, 64 * 7, 64 * 11 + 63, 64, 0.3, 84),
 ]
 
@@ -460,14 +525,27 @@ def test_ozaki_against_oracle_split(q, case):
     assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
 
 
-def test_ozaki_wide_dynamic_range(q):
-    """Blocks scaled over 40 decades: the per-leaf-line exponents keep the
-    relative accuracy of every block."""
+@pytest.mark.parametrize("decades", [40, 120, 280])
+def test_ozaki_wide_dynamic_range(q, decades):
+    """Entries spread over 40, 120 and 280 decades (up to about 1e140 and
+    down to 1e-140, far outside the FP32 and bfloat16 exponent range; the
+    squares that the norms of the checks take stay within FP64): the line
+    exponents are applied in FP64, so every block keeps its relative accuracy
+    and nothing overflows or underflows that the FP64 product does not."""
     a, b = W.small_random(640, 640, 640, 64, 0.6, 85)
     rng = np.random.default_rng(85)
-    a.vals *= np.exp(rng.uniform(-46, 46, (a.vals.shape[0], 1)))
-    b.vals *= np.exp(rng.uniform(-46, 46, (b.vals.shape[0], 1)))
+    # block (I, K) of A scaled by 10^(p_I + q_K), block (K, J) of B by
+    # 10^(r_J - q_K): the entries span `decades` decades while every leaf
+    # product A_IK B_KJ has the scale 10^(p_I + r_J) of its output block, so
+    # no product over- or underflows FP64 (p and r spread over a third of
+    # the range, q over the rest)
+    nb = 10
+    p, r = (rng.uniform(-decades / 6, decades / 6, nb) for _ in range(2))
+    qk = rng.uniform(-decades / 3, decades / 3, nb)
+    a.vals *= 10.0 ** (p[a.brow] + qk[a.bcol])[:, None]
+    b.vals *= 10.0 ** (r[b.bcol] - qk[b.brow])[:, None]
     C, ref, err, got = check_product(q, a, b, "ozaki", 64)
+    assert np.all(np.isfinite(ref.vals)) and np.all(np.isfinite(got))
     oz = O.ozaki_multiply(O.from_workload(a), O.from_workload(b))
     assert O.rel_fro(got, oz.vals) <= TOL_OZAKI_EMULATED
     # block by block, relative to each block's own norm
@@ -476,11 +554,61 @@ def test_ozaki_wide_dynamic_range(q):
     assert np.max(rel) <= 1e-10
 
 
+def test_ozaki_extreme_values_and_nonfinite(q):
+    """Entries near 1e30 and 1e-30 (beyond the bfloat16 and FP32 ranges when
+    multiplied), a product that overflows FP64 as in the oracle, and Inf/NaN
+    inputs: non-finite exactly where the FP64 product is."""
+    a, b = W.small_random(256, 256, 256, 64, 1.0, 88)
+    a.vals[:4] *= 1e30
+    a.vals[4:8] *= 1e-30
+    b.vals[:4] *= 1e30
+    b.vals[4:8] *= 1e-30
+    C, ref, err, got = check_product(q, a, b, "ozaki", 64)
+    assert np.all(np.isfinite(got))
+    # an overflowing product: 1e200 * 1e200 is Inf in FP64 too
+    a2, b2 = W.small_random(128, 128, 128, 64, 1.0, 89)
+    a2.vals[0] *= 1e200
+    b2.vals[0] *= 1e200
+    r2 = O.multiply(O.from_workload(a2), O.from_workload(b2)).vals
+    g2 = values_np(q.matmul(upload(q, a2), upload(q, b2), "ozaki", unit=64))
+    assert np.array_equal(np.isfinite(g2), np.isfinite(r2)) and not np.all(np.isfinite(r2))
+    _finite_parts_close(g2, r2)
+    # Inf and NaN inputs
+    a3, b3 = W.small_random(256, 256, 256, 64, 1.0, 13)
+    a3.vals[5, 17] = np.nan
+    a3.vals[9, 100] = np.inf
+    b3.vals[2, 4000] = -np.inf
+    ref3 = O.multiply(O.from_workload(a3), O.from_workload(b3)).vals
+    got3 = values_np(q.matmul(upload(q, a3), upload(q, b3), "ozaki", unit=64))
+    assert np.array_equal(np.isfinite(got3), np.isfinite(ref3))
+    _finite_parts_close(got3, ref3)
+
+
+def _finite_parts_close(got, ref, tol=1e-11):
+    """Block by block, the finite elements agree within tol relative to the
+    norm of the block's finite reference elements (single elements may
+    cancel, so they are not compared one by one)."""
+    fin = np.isfinite(ref)
+    for t in range(ref.shape[0]):
+        f = fin[t]
+        if not f.any():
+            continue
+        r, g = ref[t, f], got[t, f]
+        s = np.max(np.abs(r))
+        if s == 0:
+            assert np.all(g == 0)
+            continue
+        assert np.linalg.norm((g - r) / s) <= tol * np.linalg.norm(r / s), t
+
+
 def test_ozaki_unit_and_backward(q):
     a, b = W.small_random(320, 256, 288, 64, 0.5, 86)
     A, B = upload(q, a), upload(q, b)
     with pytest.raises(q.QbsmError, match="unit 64"):
         q.Plan(A, B, unit=128).numeric("ozaki")
+    a32, b32 = W.small_random(200, 150, 120, 32, 0.5, 87)
+    with pytest.raises(q.QbsmError, match="64 x 64 leaves"):
+        q.Plan(upload(q, a32), upload(q, b32), unit=64).numeric("ozaki")
     oa, ob = O.from_workload(a), O.from_workload(b)
     ref = O.multiply(oa, ob)
     rng = np.random.default_rng(86)
@@ -498,7 +626,7 @@ def test_ozaki_unit_and_backward(q):
 def test_ozaki_batched(q):
     rng = np.random.default_rng(87)
     members = [W.small_random(n, n, n, bs, 0.4, 300 + t) for t, (n, bs) in
-               enumerate([(700, 32), (1000, 64), (513, 64)])]
+               enumerate([(700, 64), (1000, 64), (513, 64)])]
     plans = [q.Plan(upload(q, a), upload(q, b), unit=64) for a, b in members]
     singles = [values_np(p.numeric("ozaki")) for p in plans]
     batch = q.Batch(plans, "ozaki")

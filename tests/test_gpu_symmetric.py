@@ -127,6 +127,13 @@ def test_batch_rejects_replaced_operands_and_outputs(q):
     A.store_f32()  # same pattern, new value storage: the batch's packs are gone
     with pytest.raises(q.QbsmError):
         batch.run()
+    # a multiply packs the re-stored values again, into a buffer of the same
+    # size that the pool may place at the old address: still an error (the
+    # batch's captured pack kernels would read the freed FP64 values)
+    P.numeric("f32")
+    torch.cuda.synchronize()
+    with pytest.raises(q.QbsmError):
+        batch.run()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         with pytest.raises(q.QbsmError):

@@ -386,8 +386,9 @@ def test_multiply_blocks_matches_full():
 
 
 def test_ozaki_split_exact_slices_and_reconstruction():
-    """Slices are bfloat16-exact digits on the line's exponent grid, and their
-    sum is the element truncated to 48 bits below the line exponent."""
+    """Slices are signed 7-bit digits (8-bit integers) on the line's exponent
+    grid, and their sum is the element truncated to 49 bits below the line
+    exponent."""
     rng = np.random.default_rng(5)
     bs = 16
     vals = rng.standard_normal((7, bs * bs)) * np.exp(rng.uniform(-20, 20, (7, 1)))
@@ -397,7 +398,7 @@ def test_ozaki_split_exact_slices_and_reconstruction():
     for line in ("row", "col"):
         sl = O.ozaki_split(vals, bs, line)
         assert sl.shape == (O.OZ_SLICES, 7, bs * bs)
-        assert np.array_equal(O.round_to_bf16(sl), sl)        # each slice exact in bf16
+        assert O.OZ_SLICES * O.OZ_BITS == 49 and 2 ** O.OZ_BITS - 1 <= 127  # 49 bits, int8 digits
         v = vals.reshape(-1, bs, bs)
         m = np.abs(v).max(axis=1 if line == "row" else 2, keepdims=True)
         _, e = np.frexp(m)
@@ -411,9 +412,9 @@ def test_ozaki_split_exact_slices_and_reconstruction():
         assert np.all(err < np.ldexp(1.0, e - O.OZ_SLICES * O.OZ_BITS))
         assert np.all(np.abs(rec) <= np.abs(vals))           # truncation toward zero
         assert np.all(sl[:, 2] == 0)
-    # values with at most 48 bits below the line exponent split exactly
-    ints = rng.integers(-(2 ** 47), 2 ** 47, (3, bs * bs)).astype(np.float64)
-    ints[:, 0] = 2.0 ** 47 - 1                                # line maxima just below 2^47
+    # values with at most 49 bits below the line exponent split exactly
+    ints = rng.integers(-(2 ** 48), 2 ** 48, (3, bs * bs)).astype(np.float64)
+    ints[:, 0] = 2.0 ** 48 - 1                                # line maxima just below 2^48
     x = np.ldexp(ints, -30)
     for line in ("row", "col"):
         assert np.array_equal(O.ozaki_split(x, bs, line).sum(axis=0), x)
@@ -433,8 +434,9 @@ def test_ozaki_split_nonfinite_and_sign():
 
 def test_ozaki_multiply_against_fp64():
     """Slice products are exact, so inputs with at most 24 bits below their
-    line exponents (all of whose slice pairs are kept) give the FP64 product;
-    general inputs differ from it by the 48-bit truncation only."""
+    line exponents (four 7-bit slices, all of whose pairs are kept) give the
+    FP64 product; general inputs differ from it by the 49-bit truncation and
+    the dropped pairs only."""
     rng = np.random.default_rng(6)
     a, b = W.small_random(150, 130, 170, 32, 0.6, 7)
     oa, ob = O.from_workload(a), O.from_workload(b)
@@ -442,13 +444,13 @@ def test_ozaki_multiply_against_fp64():
     oz = O.ozaki_multiply(oa, ob)
     assert np.array_equal(oz.brow, ref.brow) and np.array_equal(oz.bcol, ref.bcol)
     assert O.rel_fro(oz.vals, ref.vals) < 1e-13
-    # 24-bit inputs (three slices each): every needed slice pair is present
+    # 24-bit inputs (four slices each): every needed slice pair is present
     a24 = O.OMatrix(oa.nrows, oa.ncols, oa.bs, oa.brow, oa.bcol, O.round_to_f32(oa.vals))
     b24 = O.OMatrix(ob.nrows, ob.ncols, ob.bs, ob.brow, ob.bcol, O.round_to_f32(ob.vals))
     r24, z24 = O.multiply(a24, b24), O.ozaki_multiply(a24, b24)
     scale = np.abs(r24.vals).max()
     assert np.max(np.abs(z24.vals - r24.vals)) <= 64 * 2.0 ** -52 * scale
-    # a dropped term is visible: with 2 slices of 8 bits the error is ~2^-16
+    # a dropped term is visible: with 2 slices of 7 bits the error is ~2^-13
     r2 = O.ozaki_multiply(oa, ob, slices=2)
     assert 1e-7 < O.rel_fro(r2.vals, ref.vals) < 1e-3
 
