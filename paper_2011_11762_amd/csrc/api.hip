@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
 
 #include "common.h"
@@ -45,8 +47,8 @@ void keep_pool_memory() {
 }
 }  // namespace
 
-void *dalloc(size_t bytes, hipStream_t s) {
-    if (!bytes) return nullptr;
+namespace {
+void *raw_alloc(size_t bytes, hipStream_t s) {
     void *p = nullptr;
     if (g_alloc.alloc) {
         p = g_alloc.alloc(bytes, (void *)s, g_alloc.ctx);
@@ -58,16 +60,86 @@ void *dalloc(size_t bytes, hipStream_t s) {
             p = nullptr;
         }
     }
+    return p;
+}
+
+void raw_free(void *p, hipStream_t s) {
+    if (g_alloc.release)
+        g_alloc.release(p, (void *)s, g_alloc.ctx);
+    else
+        (void)hipFreeAsync(p, s);
+}
+
+// Small temporaries (the symbolic phase takes and returns dozens per call)
+// are kept for reuse instead of going back to the allocator, which may be a
+// call into another runtime: power-of-two size classes up to 1 MiB, one free
+// list per class.  Only blocks of the null stream are cached: it lives as long
+// as the process, and a block freed on it is only handed out again on it, so
+// stream order covers its last use (a user stream could be destroyed and its
+// handle reused).  At most kSmallCacheBytes stay cached; qbsm_set_allocator
+// returns them to the allocator they came from first.
+constexpr size_t kSmallMax = size_t(1) << 20, kSmallMin = 256, kSmallCacheBytes = size_t(256) << 20;
+struct SmallCache {
+    std::mutex mu;
+    std::map<std::pair<hipStream_t, size_t>, std::vector<void *>> free;
+    std::map<void *, size_t> live;  // cached-class blocks handed out: size class
+    size_t cached = 0;
+};
+SmallCache g_small;
+
+size_t small_class(size_t bytes) {
+    size_t c = kSmallMin;
+    while (c < bytes) c <<= 1;
+    return c;
+}
+
+void small_trim() {
+    std::lock_guard<std::mutex> lock(g_small.mu);
+    for (auto &kv : g_small.free)
+        for (void *p : kv.second) raw_free(p, kv.first.first);
+    g_small.free.clear();
+    g_small.cached = 0;
+}
+}  // namespace
+
+void *dalloc(size_t bytes, hipStream_t s) {
+    if (!bytes) return nullptr;
+    void *p = nullptr;
+    if (bytes <= kSmallMax && s == nullptr) {
+        const size_t c = small_class(bytes);
+        std::lock_guard<std::mutex> lock(g_small.mu);
+        auto it = g_small.free.find({s, c});
+        if (it != g_small.free.end() && !it->second.empty()) {
+            p = it->second.back();
+            it->second.pop_back();
+            g_small.cached -= c;
+        } else {
+            p = raw_alloc(c, s);
+        }
+        if (p) g_small.live[p] = c;
+    } else {
+        p = raw_alloc(bytes, s);
+    }
     if (!p) throw Error(QBSM_ERR_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     return p;
 }
 
 void dfree(void *p, hipStream_t s) {
     if (!p) return;
-    if (g_alloc.release)
-        g_alloc.release(p, (void *)s, g_alloc.ctx);
-    else
-        (void)hipFreeAsync(p, s);
+    {
+        std::lock_guard<std::mutex> lock(g_small.mu);
+        auto it = g_small.live.find(p);
+        if (it != g_small.live.end()) {
+            const size_t c = it->second;
+            g_small.live.erase(it);
+            if (g_small.cached + c <= kSmallCacheBytes) {
+                g_small.free[{s, c}].push_back(p);
+                g_small.cached += c;
+                return;
+            }
+        }
+    }
+    raw_free(p, s);
 }
 
 int device_cu_count() {
@@ -225,6 +297,7 @@ extern "C" {
 qbsm_status qbsm_set_allocator(qbsm_alloc_fn alloc, qbsm_release_fn release, void *ctx) {
     return guard([&] {
         QB_CHECK((alloc == nullptr) == (release == nullptr), QBSM_ERR_ARG, "set both hooks or neither");
+        small_trim();  // cached blocks go back to the allocator they came from
         g_alloc.alloc = alloc;
         g_alloc.release = release;
         g_alloc.ctx = ctx;

@@ -91,10 +91,40 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const Tin *in, Tout *
     }
 }
 
+// The whole scan in one workgroup, for at most SCAN_TILE values (the small
+// levels of the symbolic walk): one launch and no scratch array.
+template <class Tin, class Tout>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_small(const Tin *in, Tout *out, int64_t n, int64_t *total64) {
+    int64_t vals[SCAN_ITEMS];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t idx = (int64_t)threadIdx.x * SCAN_ITEMS + i;
+        vals[i] = idx < n ? (int64_t)in[idx] : 0;
+        s += vals[i];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan<int64_t>(s, &tot);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        const int64_t idx = (int64_t)threadIdx.x * SCAN_ITEMS + i;
+        if (idx < n) out[idx] = (Tout)ex;
+        ex += vals[i];
+    }
+    if (threadIdx.x == 0) {
+        out[n] = (Tout)tot;
+        if (total64) *total64 = tot;
+    }
+}
+
 template <class Tin, class Tout>
 void scan_impl(const Tin *in, Tout *out, int64_t n, int64_t *total64, hipStream_t s) {
-    int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
-    if (nb < 1) nb = 1;
+    if (n <= SCAN_TILE) {
+        k_scan_small<Tin, Tout><<<1, SCAN_BLOCK, 0, s>>>(in, out, n, total64);
+        QB_LAUNCH_CHECK();
+        return;
+    }
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     DArr<int64_t> partial(nb + 1, s);
     k_scan_reduce<Tin, int64_t><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, n, partial.p);
     QB_LAUNCH_CHECK();
