@@ -349,6 +349,11 @@ struct Geo {
     static_assert(NSUB * LPU <= 64, "leaf-product bits of a pair must fit 64 bits");
 };
 
+// s_waitcnt immediate for vmcnt(N), other counters left alone (gfx9 layout:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+constexpr int k5_vmcnt = 0x0F70 | (N & 15) | ((N >> 4) << 14);
+
 template <int MODE, int U>
 constexpr int k5_wt = MODE == QBSM_OZAKI_I8 ? 32 : U >= 256 ? 128 : 64;
 
@@ -375,7 +380,7 @@ __device__ __forceinline__ CopyLane copy_lane(const K5Member &m, int w) {
     using T = typename G::T;
     constexpr int IPW = G::IPA / G::NW;
     static_assert(G::IPA % G::NW == 0, "copy blocks of an array must split evenly over the waves");
-    static_assert(G::PER_WAVE <= 64, "one lane per copy instruction");
+    static_assert(G::PER_WAVE <= 63, "one lane per copy instruction; vmcnt counts to 63");
     const int k = (threadIdx.x & 63) < G::PER_WAVE ? (threadIdx.x & 63) : 0;
     const int arr = k / IPW;
     const int op = arr / MT<MODE>::PARTS, part = arr - op * MT<MODE>::PARTS;
@@ -507,7 +512,9 @@ __device__ __forceinline__ void oz_load_exp(const Meta &mt, int i, int kb, int w
 // One step on stage cur: st is this step, nxa the next one with its copy
 // addresses (looked up during the previous step).  The step after next is
 // looked up once this step's MFMAs are issued, while the copies land.
-template <int MODE, int U, int BS, bool DENSE, bool NF>
+// FIRST: the unit's first step, whose successor's copy was issued with the
+// step's own copy at the start of the unit; nothing is copied during it.
+template <int MODE, int U, int BS, bool DENSE, bool NF, bool FIRST = false>
 __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int nb, const uint8_t *cur, uint8_t *nxt,
                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
                                          typename MT<MODE>::Part (&part)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
@@ -522,8 +529,8 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
     // this step for 64-wide wave parts and on the branch-free path; with
     // 128 x 128 per wave and tile skipping the register file has no room for
     // that schedule and the copy is issued in one go
-    constexpr bool SPREAD = G::WT <= 64 || DENSE;
-    if constexpr (!SPREAD) {
+    constexpr bool SPREAD = (G::WT <= 64 || DENSE) && !FIRST;
+    if constexpr (!SPREAD && !FIRST) {
         if (nxa.nx.i < nb) {
 #pragma unroll
             for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, nxt, w);
@@ -598,7 +605,7 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
                         M::template flush<NF>(acc[tm][tn], part[tm][tn], ex.er[tm], ex.ec[tn]);
             }
         }
-    } else if (SPREAD) {
+    } else if constexpr (SPREAD) {
 #pragma unroll
         for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, nxt, w);
     }
@@ -673,21 +680,56 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         Advance nxa;
         nxa.nx = st;
         nxa.addrs = 0;
+        // the first step's copy and, right behind it, the second step's: a
+        // unit of two steps (one leaf product of two K chunks) waits for one
+        // copy latency instead of two.  Only below unit 256: those units are
+        // short on sparse inputs, while the 256-wide kernels run long units
+        // and have no registers to spare for a third copy of the step body.
+        constexpr bool PRE2 = U <= 128;
+        bool pre = false;
         if (st.i < nb) {
             const uint64_t addrs = copy_addr<MODE, U, BS>(mt, st.i, st.kb, 0, cl, chunk_bytes);
 #pragma unroll
             for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
             oz_load_exp<MODE, U, BS>(mt, st.i, st.kb, wr, wc, ex);
             nxa = advance<MODE, U, BS>(mt, nb, st, addrs, cl, chunk_bytes);
+            pre = PRE2 && nxa.nx.i < nb;
+            if (pre) {
+#pragma unroll
+                for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, st1, w);
+            }
         }
-        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        if (pre)
+            __builtin_amdgcn_s_waitcnt(k5_vmcnt<G::PER_WAVE>);  // the first step's copies (and exponents)
+        else
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
         __syncthreads();
         // steps alternate between the two stages; unrolled by two so that
         // every access names its stage array at compile time
-        while (st.i < nb) {
-            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
-            if (st.i >= nb) break;
-            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
+        if constexpr (PRE2) {
+            if (st.i < nb) {
+                if (pre)
+                    run_step<MODE, U, BS, DENSE, NF, true>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes,
+                                                           w, wr, wc, ex);
+                else
+                    run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr,
+                                                     wc, ex);
+            }
+            while (st.i < nb) {
+                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
+                                                 ex);
+                if (st.i >= nb) break;
+                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
+                                                 ex);
+            }
+        } else {
+            while (st.i < nb) {
+                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
+                                                 ex);
+                if (st.i >= nb) break;
+                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
+                                                 ex);
+            }
         }
     }
 
