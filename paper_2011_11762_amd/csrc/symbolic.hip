@@ -40,78 +40,163 @@ __device__ __forceinline__ int slot_of(int rowbit, int colbit, int trans) {
     return trans ? (colbit * 2 + rowbit) : (rowbit * 2 + colbit);
 }
 
-// The pair count np of the level is read from device memory (the previous
-// level's scan total); the launch covers the level's capacity and the slots
-// beyond 4*np are zeroed, so that the scan over the whole capacity gives the
-// next level's count without a host round trip.
-// nL != nullptr (the step into the leaf level of a sparse approximate
-// multiply): a leaf pair is kept only when not nL[l] * nR[r] < tau.
-__global__ void k_walk_count(const int64_t *npp, int64_t cap4, const int32_t *pl, const int32_t *pr,
-                             const int32_t *gs, const int32_t *gm, const int32_t *pm, const uint32_t *ck,
-                             const int32_t *chL,
-                             const int32_t *chR, const int32_t *chM, int transL, int transR,
-                             const double *nL, const double *nR, double tau, int upper, int32_t *X) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t np = *npp;
-    if (t >= cap4) return;
-    if (t >= np * 4) {
-        X[t] = 0;  // the layout below covers exactly [0, 4*np)
-        return;
-    }
+// One walk level: the inputs of item t = 4 p + q (pair p, output quadrant q).
+struct WalkLevel {
+    const int32_t *pl, *pr, *gs, *gm, *pm;
+    const uint32_t *ck;
+    const int32_t *chL, *chR, *chM;
+    int transL, transR;
+    const double *nL, *nR;  // non-null on the step into the leaf level of a sparse approximate multiply
+    double tau;
+    int upper;
+};
+
+struct WalkOut {
+    int32_t *pl, *pr, *gs, *gm, *pm;
+    uint32_t *ck;
+};
+
+// Child pairs of item t (0..2), written to its slot of the count layout
+// 4 g + q m + (p - g) (g the first pair of p's group, m the group size), so
+// that the exclusive scan of the counts gives every child its position with
+// groups kept together, quadrants in order and pairs in order inside them.
+// A nL test keeps a leaf pair only when not nL[l] * nR[r] < tau.
+__device__ __forceinline__ void walk_count_item(const WalkLevel &w, int64_t t, int32_t *X) {
     const int64_t p = t >> 2;
     const int q = (int)(t & 3);
     const int ib = q >> 1, jb = q & 1;
     int cnt = 0;
-    if ((!chM || chM[(int64_t)pm[p] * 4 + q] >= 0) && !(upper && ib > jb && on_diagonal(ck[p]))) {
-        const int64_t a = (int64_t)pl[p] * 4, b = (int64_t)pr[p] * 4;
+    if ((!w.chM || w.chM[(int64_t)w.pm[p] * 4 + q] >= 0) && !(w.upper && ib > jb && on_diagonal(w.ck[p]))) {
+        const int64_t a = (int64_t)w.pl[p] * 4, b = (int64_t)w.pr[p] * 4;
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb) {
-            const int32_t cl = chL[a + slot_of(ib, kb, transL)];
-            const int32_t cr = chR[b + slot_of(kb, jb, transR)];
-            cnt += (cl >= 0 && cr >= 0 && (!nL || !(nL[cl] * nR[cr] < tau))) ? 1 : 0;
+            const int32_t cl = w.chL[a + slot_of(ib, kb, w.transL)];
+            const int32_t cr = w.chR[b + slot_of(kb, jb, w.transR)];
+            cnt += (cl >= 0 && cr >= 0 && (!w.nL || !(w.nL[cl] * w.nR[cr] < w.tau))) ? 1 : 0;
         }
     }
-    const int64_t g = gs[p];
-    X[4 * g + (int64_t)q * gm[p] + (p - g)] = cnt;
+    const int64_t g = w.gs[p];
+    X[4 * g + (int64_t)q * w.gm[p] + (p - g)] = cnt;
 }
 
-__global__ void k_walk_fill(const int64_t *npp, const int32_t *pl, const int32_t *pr, const int32_t *gs,
-                            const int32_t *gm, const int32_t *pm, const uint32_t *ck, const int32_t *chL,
-                            const int32_t *chR, const int32_t *chM, int transL, int transR,
-                            const double *nL, const double *nR, double tau, int upper, const int32_t *Y,
-                            int64_t ocap, int32_t *opl, int32_t *opr, int32_t *ogs,
-                            int32_t *ogm, int32_t *opm, uint32_t *ock) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= *npp * 4) return;
+// Writes the child pairs of item t at their scanned positions Y.
+__device__ __forceinline__ void walk_fill_item(const WalkLevel &w, int64_t t, const int32_t *Y, int64_t ocap,
+                                               const WalkOut &o) {
     const int64_t p = t >> 2;
     const int q = (int)(t & 3);
     const int ib = q >> 1, jb = q & 1;
     int32_t mchild = -1;
-    if (chM) {
-        mchild = chM[(int64_t)pm[p] * 4 + q];
+    if (w.chM) {
+        mchild = w.chM[(int64_t)w.pm[p] * 4 + q];
         if (mchild < 0) return;
     }
-    if (upper && ib > jb && on_diagonal(ck[p])) return;
-    const int64_t g = gs[p], m = gm[p];
+    if (w.upper && ib > jb && on_diagonal(w.ck[p])) return;
+    const int64_t g = w.gs[p], m = w.gm[p];
     const int64_t base = 4 * g + (int64_t)q * m;
-    int32_t o = Y[base + (p - g)];
+    int32_t pos = Y[base + (p - g)];
     const int32_t ngs = Y[base];
     const int32_t nge = Y[base + m];
-    const int64_t a = (int64_t)pl[p] * 4, b = (int64_t)pr[p] * 4;
-    const uint32_t key = ck[p] * 4u + (uint32_t)q;
+    const int64_t a = (int64_t)w.pl[p] * 4, b = (int64_t)w.pr[p] * 4;
+    const uint32_t key = w.ck[p] * 4u + (uint32_t)q;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
-        const int32_t cl = chL[a + slot_of(ib, kb, transL)];
-        const int32_t cr = chR[b + slot_of(kb, jb, transR)];
-        if (cl >= 0 && cr >= 0 && (!nL || !(nL[cl] * nR[cr] < tau)) && o < ocap) {  // o < ocap always
-            opl[o] = cl;
-            opr[o] = cr;
-            ogs[o] = ngs;
-            ogm[o] = nge - ngs;
-            opm[o] = mchild;
-            ock[o] = key;
-            ++o;
+        const int32_t cl = w.chL[a + slot_of(ib, kb, w.transL)];
+        const int32_t cr = w.chR[b + slot_of(kb, jb, w.transR)];
+        if (cl >= 0 && cr >= 0 && (!w.nL || !(w.nL[cl] * w.nR[cr] < w.tau)) && pos < ocap) {  // pos < ocap always
+            o.pl[pos] = cl;
+            o.pr[pos] = cr;
+            o.gs[pos] = ngs;
+            o.gm[pos] = nge - ngs;
+            o.pm[pos] = mchild;
+            o.ck[pos] = key;
+            ++pos;
         }
+    }
+}
+
+// The pair count np of the level is read from device memory (the previous
+// level's scan total); the launch covers the level's capacity and the slots
+// beyond 4*np are zeroed, so that the scan over the whole capacity gives the
+// next level's count without a host round trip.
+__global__ void k_walk_count(const int64_t *npp, int64_t cap4, WalkLevel w, int32_t *X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cap4) return;
+    if (t >= *npp * 4) {
+        X[t] = 0;  // the layout covers exactly [0, 4*np)
+        return;
+    }
+    walk_count_item(w, t, X);
+}
+
+__global__ void k_walk_fill(const int64_t *npp, WalkLevel w, const int32_t *Y, int64_t ocap, WalkOut o) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *npp * 4) return;
+    walk_fill_item(w, t, Y, ocap, o);
+}
+
+// The small top levels of the walk in one workgroup: for each level, counts
+// into LDS, a workgroup scan, then the fill, with the level's count kept in
+// counts[l + 1] as the separate launches do.  Every level's input holds at
+// most kTopItems / 4 pairs.
+constexpr int kTopThreads = 1024, kTopItems = 4096;
+struct TopLevels {
+    int n;                    // levels processed: l0 .. l0 + n - 1
+    WalkLevel lv[8];          // level inputs (the first one's pair arrays given; the rest filled here)
+    WalkOut out[8];           // level outputs (out[i] is the input pairs of lv[i + 1])
+    int64_t ocap[8];          // output capacities
+};
+
+__global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t *counts) {
+    __shared__ int32_t X[kTopItems + 1];
+    __shared__ int32_t wsum[kTopThreads / 64];
+    const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int IPT = kTopItems / kTopThreads;  // items per thread
+    for (int i = 0; i < tl.n; ++i) {
+        const WalkLevel &w = tl.lv[i];
+        const int64_t n4 = counts[i] * 4;  // this level's pairs (written by the previous round)
+        // counts: thread tid owns items tid*IPT .. +IPT-1
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            const int t = tid * IPT + k;
+            if (t < n4) walk_count_item(w, t, X);
+            else X[t] = 0;
+        }
+        __syncthreads();
+        // exclusive scan of X[0 .. kTopItems)
+        int32_t v[IPT], s = 0;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            v[k] = X[tid * IPT + k];
+            s += v[k];
+        }
+        int32_t x = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int32_t base = 0, tot = 0;
+        for (int k = 0; k < kTopThreads / 64; ++k) {
+            base += k < wid ? wsum[k] : 0;
+            tot += wsum[k];
+        }
+        int32_t e = base + x - s;
+#pragma unroll
+        for (int k = 0; k < IPT; ++k) {
+            X[tid * IPT + k] = e;
+            e += v[k];
+        }
+        if (tid == 0) X[kTopItems] = tot;
+        __syncthreads();
+        for (int k = 0; k < IPT; ++k) {
+            const int t = tid * IPT + k;
+            if (t < n4) walk_fill_item(w, t, X, tl.ocap[i], tl.out[i]);
+        }
+        if (tid == 0) counts[i + 1] = tot;
+        __syncthreads();  // the next level reads this level's output and count
+        __threadfence_block();
     }
 }
 
@@ -217,28 +302,69 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
     cur.alloc(1, s);
     k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p);
     QB_LAUNCH_CHECK();
+    auto level_in = [&](const Pairs &p, int l) {
+        WalkLevel w{};
+        w.pl = p.pl.p; w.pr = p.pr.p; w.gs = p.gs.p; w.gm = p.gm.p; w.pm = p.pm.p; w.ck = p.ck.p;
+        w.chL = tL.child[l].p;
+        w.chR = tR.child[l].p;
+        w.chM = tM ? tM->child[l].p : nullptr;
+        w.transL = transL;
+        w.transR = transR;
+        // the norm test applies on the step into the leaf level only
+        const bool fl = nL && tau > 0.0 && l + 1 == tL.D;
+        w.nL = fl ? nL : nullptr;
+        w.nR = fl ? nR : nullptr;
+        w.tau = tau;
+        w.upper = upper;
+        return w;
+    };
+    auto level_out = [](const Pairs &p) {
+        WalkOut o{p.pl.p, p.pr.p, p.gs.p, p.gm.p, p.pm.p, p.ck.p};
+        return o;
+    };
     int64_t capc = 1;  // capacity of the current level
-    for (int l = 0; l < target; ++l) {
+    int l = 0;
+    // the top levels whose inputs are small run in one launch (their output
+    // capacities are the exact or bounding pair counts from the histograms)
+    {
+        TopLevels tl{};
+        std::vector<Pairs> outs;
+        int64_t c = 1;
+        while (l + tl.n < target && tl.n < 8 && c * 4 <= kTopItems && cap[l + tl.n + 1] > 0 &&
+               (int64_t)cap[l + tl.n + 1] <= kMaskedBoundPairs) {
+            outs.emplace_back();
+            outs.back().alloc((int64_t)cap[l + tl.n + 1], s);
+            c = (int64_t)cap[l + tl.n + 1];
+            ++tl.n;
+        }
+        if (tl.n >= 2) {
+            for (int i = 0; i < tl.n; ++i) {
+                tl.lv[i] = level_in(i == 0 ? cur : outs[i - 1], l + i);
+                tl.out[i] = level_out(outs[i]);
+                tl.ocap[i] = outs[i].n;
+            }
+            k_walk_top<<<1, kTopThreads, 0, s>>>(tl, counts.p + l);
+            QB_LAUNCH_CHECK();
+            capc = outs.back().n;
+            cur = std::move(outs.back());
+            l += tl.n;
+        }
+    }
+    for (; l < target; ++l) {
         int64_t capn = (int64_t)cap[l + 1];
         Pairs nxt;
         if (capc && capn) {
             DArr<int32_t> X(capc * 4, s), Y(capc * 4 + 1, s);
             const unsigned g = grid_for(capc * 4, 256);
-            const int32_t *chM = tM ? tM->child[l].p : nullptr;
-            // the norm test applies on the step into the leaf level only
-            const bool fl = nL && tau > 0.0 && l + 1 == tL.D;
-            const double *fL = fl ? nL : nullptr, *fR = fl ? nR : nullptr;
-            k_walk_count<<<g, 256, 0, s>>>(counts.p + l, capc * 4, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
-                                          cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR, tau, upper,
-                                          X.p);
+            const WalkLevel w = level_in(cur, l);
+            const bool bounded = w.chM || w.nL || upper;
+            k_walk_count<<<g, 256, 0, s>>>(counts.p + l, capc * 4, w, X.p);
             QB_LAUNCH_CHECK();
             exclusive_scan_i32(X.p, Y.p, capc * 4, counts.p + l + 1, s);
-            if ((tM || fl || upper) && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
+            if (bounded && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
             nxt.alloc(capn, s);
             if (capn) {
-                k_walk_fill<<<g, 256, 0, s>>>(counts.p + l, cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p,
-                                             cur.ck.p, tL.child[l].p, tR.child[l].p, chM, transL, transR, fL, fR,
-                                             tau, upper, Y.p, capn, nxt.pl.p, nxt.pr.p, nxt.gs.p, nxt.gm.p, nxt.pm.p, nxt.ck.p);
+                k_walk_fill<<<g, 256, 0, s>>>(counts.p + l, w, Y.p, capn, level_out(nxt));
                 QB_LAUNCH_CHECK();
             }
         } else {
@@ -281,11 +407,12 @@ __global__ void k_unit_flags(const int64_t *npp, int64_t cap, const int32_t *gs,
     if (p < cap) flags[p] = (p < *npp && gs[p] == (int32_t)p) ? 1 : 0;
 }
 
-__global__ void k_unit_fill(int64_t np, const int32_t *gs, const int32_t *pm, const uint32_t *ck,
+// meta = {pairs, units} on the device; launches cover host-side bounds.
+__global__ void k_unit_fill(const int64_t *meta, const int32_t *gs, const int32_t *pm, const uint32_t *ck,
                             const int32_t *uscan, int32_t *ustart, uint32_t *ukey, int32_t *umask,
                             int32_t *pu) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
+    if (p >= meta[0]) return;
     const bool start = gs[p] == (int32_t)p;
     const int32_t u = uscan[p] + (start ? 1 : 0) - 1;
     pu[p] = u;
@@ -296,7 +423,7 @@ __global__ void k_unit_fill(int64_t np, const int32_t *gs, const int32_t *pm, co
     }
 }
 
-__global__ void k_unit_end(int32_t *ustart, int64_t nunits, int64_t np) { ustart[nunits] = (int32_t)np; }
+__global__ void k_unit_end(int32_t *ustart, const int64_t *meta) { ustart[meta[1]] = (int32_t)meta[0]; }
 
 struct Dims {
     int64_t out_rows, inner, out_cols;
@@ -322,14 +449,14 @@ __device__ __forceinline__ constexpr int msub(int r, int c) {
 // both nodes (and of the mask node) are loaded first; the 2^(3S) candidate
 // products are then tested with compile-time indexes.
 template <int S>
-__global__ void k_pair_masks(int64_t np, const int32_t *pl, const int32_t *pr, const int32_t *pu,
+__global__ void k_pair_masks(const int64_t *meta, const int32_t *pl, const int32_t *pr, const int32_t *pu,
                              const uint32_t *ukey, const int32_t *umask, const int32_t *descL,
                              const int32_t *descR, const int32_t *descM, int hasM, const uint32_t *keyL,
                              Dims d, const double *nL, const double *nR, double tau, int upper,
                              uint64_t *pmask, uint32_t *ucmask, unsigned long long *part) {
     constexpr int LPU = 1 << S, NSUB = LPU * LPU;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = p < np;
+    const bool live = p < meta[0];
     const int32_t a = live ? pl[p] : 0, b = live ? pr[p] : 0;  // node 0 exists whenever np > 0
     const int32_t u = live ? pu[p] : -1;
     const int32_t us = live ? u : 0;
@@ -436,18 +563,19 @@ __global__ void __launch_bounds__(256) k_sum_parts(const unsigned long long *par
         out[threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
-__global__ void k_unit_count(int64_t nu, const uint32_t *ucmask, int32_t *cnt) {
+// Output leaves per unit; zero beyond the units (the scan covers the bound).
+__global__ void k_unit_count(const int64_t *meta, int64_t cap, const uint32_t *ucmask, int32_t *cnt) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < nu) cnt[u] = __popc(ucmask[u]);
+    if (u < cap) cnt[u] = u < meta[1] ? __popc(ucmask[u]) : 0;
 }
 
 // Output leaves of each unit: numbered in Morton order inside the unit
 // (unmasked plans), or taken from the mask's leaves (masked plans).
-__global__ void k_unit_cdesc(int64_t nu, const uint32_t *ucmask, const int32_t *cbase, const uint32_t *ukey,
+__global__ void k_unit_cdesc(const int64_t *meta, const uint32_t *ucmask, const int32_t *cbase, const uint32_t *ukey,
                              const int32_t *umask, const int32_t *descM, int hasM, int s, int lpu,
                              int32_t *cdesc, uint32_t *okeys) {
     int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= nu) return;
+    if (u >= meta[1]) return;
     const uint32_t cm = ucmask[u];
     const int nsub = lpu * lpu;
     int32_t next = hasM ? 0 : cbase[u];
@@ -515,6 +643,10 @@ __global__ void k_emit_products(int64_t np, const int32_t *gs, const int32_t *pl
 
 }  // namespace
 
+// Plans with at most this many unit-level pairs size their unit arrays by the
+// pair count and skip the host read of the unit count.
+constexpr int64_t kBoundedUnitPairs = int64_t(1) << 20;
+
 std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, Matrix *M, int unit,
                                  double spamm_tol, int upper,
                                  hipStream_t s) {
@@ -575,13 +707,19 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     } else {
         fill_bytes_zero(meta.p + 1, sizeof(int64_t), s);
     }
-    int64_t hm[2];
-    QB_HIP(hipMemcpyAsync(hm, meta.p, sizeof(hm), hipMemcpyDeviceToHost, s));
-    QB_HIP(hipStreamSynchronize(s));
-    const int64_t np = hm[0], nu = hm[1];
-    QB_CHECK(np <= cap && nu <= np, QBSM_ERR_STATE, "pair count above its bound");
-    p->npairs = np;
-    p->nunits = nu;
+    // Small plans size their unit arrays by the pair bound (units <= pairs)
+    // and read the exact counts back with the totals, in one host read;
+    // large ones read the counts first and allocate exactly.
+    int64_t np = cap, nu = cap;
+    const bool bound = cap <= kBoundedUnitPairs;
+    if (!bound) {
+        int64_t hm[2];
+        QB_HIP(hipMemcpyAsync(hm, meta.p, sizeof(hm), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+        np = hm[0];
+        nu = hm[1];
+        QB_CHECK(np <= cap && nu <= np, QBSM_ERR_STATE, "pair count above its bound");
+    }
     p->ustart.alloc(nu + 1, s);
     p->ukey.alloc(nu ? nu : 1, s);
     p->umask.alloc(nu ? nu : 1, s);
@@ -595,18 +733,18 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     DArr<uint32_t> ucmask(nu ? nu : 1, s);
     fill_u32(ucmask.p, 0u, nu ? nu : 1, s);
     if (np) {
-        k_unit_fill<<<grid_for(np, 256), 256, 0, s>>>(np, pr.gs.p, pr.pm.p, pr.ck.p, uscan.p, p->ustart.p,
+        k_unit_fill<<<grid_for(np, 256), 256, 0, s>>>(meta.p, pr.gs.p, pr.pm.p, pr.ck.p, uscan.p, p->ustart.p,
                                                      p->ukey.p, p->umask.p, pu.p);
         QB_LAUNCH_CHECK();
-        k_unit_end<<<1, 1, 0, s>>>(p->ustart.p, nu, np);
+        k_unit_end<<<1, 1, 0, s>>>(p->ustart.p, meta.p);
         QB_LAUNCH_CHECK();
         Dims d{rows, inner, cols, bs, sl, p->lpu, transL, transR};
         const int32_t *dL = tree_desc(*L, tL, sl, s);
         const int32_t *dR = tree_desc(*R, tR, sl, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
 #define QB_PAIR_MASKS(S_)                                                                                   \
-    k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(np, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, dL, \
-                                                       dR, dM, M ? 1 : 0, tL.key[Lw].p, d, nL, nR,         \
+    k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(meta.p, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, \
+                                                       dL, dR, dM, M ? 1 : 0, tL.key[Lw].p, d, nL, nR,     \
                                                        spamm_tol, upper, p->pmask.p, ucmask.p, part.p)
         const int64_t nblk = grid_for(np, 256);
         DArr<unsigned long long> part(2 * nblk, s);
@@ -626,17 +764,24 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     DArr<uint32_t> okeys_b;
     if (nu) {
         DArr<int32_t> cnt(nu, s), cbase(nu + 1, s);
-        k_unit_count<<<grid_for(nu, 256), 256, 0, s>>>(nu, ucmask.p, cnt.p);
+        k_unit_count<<<grid_for(nu, 256), 256, 0, s>>>(meta.p, nu, ucmask.p, cnt.p);
         QB_LAUNCH_CHECK();
         exclusive_scan_i32(cnt.p, cbase.p, nu, &totals.p->nout, s);
         if (!M) okeys_b.alloc(nu * nsub, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
-        k_unit_cdesc<<<grid_for(nu, 256), 256, 0, s>>>(nu, ucmask.p, cbase.p, p->ukey.p, p->umask.p, dM,
+        k_unit_cdesc<<<grid_for(nu, 256), 256, 0, s>>>(meta.p, ucmask.p, cbase.p, p->ukey.p, p->umask.p, dM,
                                                       M ? 1 : 0, sl, p->lpu, p->cdesc.p,
                                                       M ? nullptr : okeys_b.p);
         QB_LAUNCH_CHECK();
     }
+    int64_t hm[2];
+    QB_HIP(hipMemcpyAsync(hm, meta.p, sizeof(hm), hipMemcpyDeviceToHost, s));
     Tot h = read_back(totals.p, s);
+    QB_CHECK(hm[0] <= np && hm[1] <= hm[0], QBSM_ERR_STATE, "pair count above its bound");
+    np = hm[0];
+    nu = hm[1];
+    p->npairs = np;
+    p->nunits = nu;
     const int64_t nout = nu ? h.nout : 0;
     QB_CHECK(nout <= nu * nsub, QBSM_ERR_STATE, "output leaf count above its bound");
     if (!M) {
