@@ -624,7 +624,7 @@ qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int
             const int u = cand[ci];
             double t = -1.0;
             const bool ok = (u % bs == 0) && (u / bs) <= 4 && (u / bs) >= 1 && !(u == 256 && mode == QBSM_F64) &&
-                            !(mode == QBSM_OZAKI_I8 && (u != 64 || bs != 64));
+                            !(mode == QBSM_OZAKI_I8 && ((u != 64 && u != 128) || bs != 64));
             if (ok) {
                 auto p = plan_build(&A->m, 0, &B->m, 0, nullptr, u, 0.0, 0, s);
                 Matrix out;
@@ -683,7 +683,7 @@ qbsm_status qbsm_batch_autotune(int32_t n, const qbsm_matrix *L, const qbsm_matr
             bool ok = !(u == 256 && mode == QBSM_F64);
             for (int i = 0; i < n && ok; ++i) {
                 const int bs = L[i]->m.bs;
-                ok = u % bs == 0 && u / bs <= 4 && !(mode == QBSM_OZAKI_I8 && (u != 64 || bs != 64));
+                ok = u % bs == 0 && u / bs <= 4 && !(mode == QBSM_OZAKI_I8 && ((u != 64 && u != 128) || bs != 64));
             }
             if (!ok) continue;
             std::vector<std::unique_ptr<Plan>> plans;

@@ -331,9 +331,9 @@ struct Geo {
     static constexpr int NGROUPS = BK / M::KPG;
     static constexpr int LPI = 1024 / LB;                // lines per 1 KB load instruction
     static constexpr int IPA = U / LPI;                  // load instructions per array
-    // side of the part one wave computes (the six Ozaki slices per operand
-    // leave LDS for 64-wide units only: four waves of 32 x 32 there)
-    static constexpr int WT = MODE == QBSM_OZAKI_I8 ? 32 : U >= 256 ? 128 : 64;
+    // side of the part one wave computes (Ozaki: four waves of 32 x 32 at
+    // unit 64, of one 64 x 64 leaf each at unit 128)
+    static constexpr int WT = MODE == QBSM_OZAKI_I8 ? (U >= 128 ? 64 : 32) : U >= 256 ? 128 : 64;
     static constexpr int WPS = U / WT;                   // waves per unit side
     static constexpr int NW = WPS * WPS;
     static constexpr int TPW = WT / 16;                  // 16x16 tiles per wave side
@@ -355,7 +355,7 @@ template <int N>
 constexpr int k5_vmcnt = 0x0F70 | (N & 15) | ((N >> 4) << 14);
 
 template <int MODE, int U>
-constexpr int k5_wt = MODE == QBSM_OZAKI_I8 ? 32 : U >= 256 ? 128 : 64;
+constexpr int k5_wt = MODE == QBSM_OZAKI_I8 ? (U >= 128 ? 64 : 32) : U >= 256 ? 128 : 64;
 
 template <int MODE, int U>
 constexpr int k5_nt = 64 * (U / k5_wt<MODE, U>) * (U / k5_wt<MODE, U>);
@@ -618,6 +618,99 @@ __device__ __forceinline__ void run_step(const K5Member &m, const Meta &mt, int 
     if constexpr (MODE == QBSM_OZAKI_I8) ex = ex_next;
 }
 
+// Fills the LDS metadata of pairs b0 .. b0 + nb - 1 of a unit: product bits
+// and the packed address of every leaf the pair's steps copy.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void load_meta(const K5Member &m, const Meta &mt, int b0, int nb) {
+    using G = Geo<MODE, U, BS>;
+    constexpr int NT = 64 * G::NW;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB, S = G::S;
+    for (int i = threadIdx.x; i < nb; i += NT) {
+        const int p = b0 + i;
+        const int a = m.pl[p], b = m.pr[p];
+        mt.pm[i] = m.pmask[p];
+#pragma unroll
+        for (int kb = 0; kb < LPU; ++kb)
+#pragma unroll
+            for (int q = 0; q < LPU; ++q) {
+                const int qa = m.transL ? morton_sub(kb, q, S) : morton_sub(q, kb, S);
+                const int qb = m.transR ? morton_sub(q, kb, S) : morton_sub(kb, q, S);
+                const int la = m.descL ? m.descL[(int64_t)a * NSUB + qa] : a;
+                const int lb = m.descR ? m.descR[(int64_t)b * NSUB + qb] : b;
+                uint64_t *d = mt.ad + (int64_t)i * 2 * NSUB + kb * 2 * LPU;
+                d[q] = la < 0 ? 0 : reinterpret_cast<uint64_t>(static_cast<const uint8_t *>(m.packL) +
+                                                               (int64_t)la * m.leafStrideL * (int64_t)sizeof(typename G::T));
+                d[LPU + q] = lb < 0 ? 0 : reinterpret_cast<uint64_t>(static_cast<const uint8_t *>(m.packR) +
+                                                                     (int64_t)lb * m.leafStrideR * (int64_t)sizeof(typename G::T));
+            }
+    }
+}
+
+// Writes a unit's owned output blocks once (padding beyond the logical size
+// = 0) from the wave's accumulators.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void store_unit(const K5Member &m, int u,
+                                           const typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                           int wr, int wc) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB;
+    const int tid = threadIdx.x;
+    // leaf by leaf: the wave's NLW x NLW leaves have their output indices
+    // looked up together, then each stored leaf writes its TPL x TPL tiles
+    const int lane = tid & 63;
+    uint32_t ui, uj;
+    demorton(m.ukey[u], ui, uj);
+    typename M::Out *C = static_cast<typename M::Out *>(m.C);
+    constexpr int64_t N2 = (int64_t)BS * BS;
+    constexpr int NLW = G::NLW, TPL = G::TPL;
+    const int ib0 = (G::WT * wr) / BS, jb0 = (G::WT * wc) / BS;
+    int32_t leaves[NLW][NLW];
+#pragma unroll
+    for (int a = 0; a < NLW; ++a)
+#pragma unroll
+        for (int b = 0; b < NLW; ++b) leaves[a][b] = uni(m.cdesc[(int64_t)u * NSUB + (ib0 + a) * LPU + jb0 + b]);
+#pragma unroll
+    for (int a = 0; a < NLW; ++a)
+#pragma unroll
+        for (int b = 0; b < NLW; ++b) {
+            const int32_t leaf = leaves[a][b];
+            if (leaf < 0) continue;
+            const int ib = ib0 + a, jb = jb0 + b;
+            const int64_t I = (int64_t)ui * LPU + ib, J = (int64_t)uj * LPU + jb;
+            const bool interior = (I + 1) * BS <= m.out_rows && (J + 1) * BS <= m.out_cols;
+            typename M::Out *Cl = C + (int64_t)leaf * N2;
+#pragma unroll
+            for (int ta = 0; ta < TPL; ++ta)
+#pragma unroll
+                for (int tb = 0; tb < TPL; ++tb) {
+                    const int tm = a * TPL + ta, tn = b * TPL + tb;
+                    // tile origin inside the leaf
+                    const int r0 = G::WT * wr + 16 * tm - ib * BS, c0 = G::WT * wc + 16 * tn - jb * BS;
+                    const int cc = c0 + (lane & 15);
+                    typename M::Out *dst = Cl + (int64_t)cc * BS + r0;
+                    if (M::row_of(0, 1) == 1 && interior) {
+                        // rows 4*(lane/16) .. +3 of the tile are contiguous in the column
+                        if constexpr (sizeof(typename M::Out) == 4) {
+                            *reinterpret_cast<float4 *>(dst + 4 * (lane >> 4)) =
+                                make_float4(acc[tm][tn][0], acc[tm][tn][1], acc[tm][tn][2], acc[tm][tn][3]);
+                        } else {
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) dst[4 * (lane >> 4) + i] = (typename M::Out)acc[tm][tn][i];
+                        }
+                    } else {
+                        const bool colok = (J * BS + cc) < m.out_cols;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int r = r0 + M::row_of(lane, i);
+                            const bool ok = colok && (I * BS + r) < m.out_rows;
+                            dst[M::row_of(lane, i)] = ok ? (typename M::Out)acc[tm][tn][i] : (typename M::Out)0;
+                        }
+                    }
+                }
+        }
+}
+
 // DENSE: the branch-free path (every tile multiplied, nil leaves copied as
 // zeros), valid when neither pack holds Inf or NaN (an infinite value times
 // the zero of a nil partner would give NaN where no product exists).
@@ -625,8 +718,7 @@ template <int MODE, int U, int BS, bool DENSE, bool NF = false>
 __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
-    constexpr int NT = 64 * G::NW;
-    constexpr int LPU = G::LPU, NSUB = G::NSUB, S = G::S, TPW = G::TPW;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB, TPW = G::TPW;
     const int tid = threadIdx.x;
     const int w = uni(tid >> 6);
     const int wr = w / G::WPS, wc = w % G::WPS;
@@ -656,25 +748,7 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
     for (int b0 = p0; b0 < p1; b0 += G::CAP) {
         const int nb = uni((p1 - b0) < G::CAP ? (p1 - b0) : G::CAP);
         __syncthreads();  // LDS (stages, metadata) of the previous batch or unit is free
-        for (int i = tid; i < nb; i += NT) {
-            const int p = b0 + i;
-            const int a = m.pl[p], b = m.pr[p];
-            mt.pm[i] = m.pmask[p];
-#pragma unroll
-            for (int kb = 0; kb < LPU; ++kb)
-#pragma unroll
-                for (int q = 0; q < LPU; ++q) {
-                    const int qa = m.transL ? morton_sub(kb, q, S) : morton_sub(q, kb, S);
-                    const int qb = m.transR ? morton_sub(q, kb, S) : morton_sub(kb, q, S);
-                    const int la = m.descL ? m.descL[(int64_t)a * NSUB + qa] : a;
-                    const int lb = m.descR ? m.descR[(int64_t)b * NSUB + qb] : b;
-                    uint64_t *d = mt.ad + (int64_t)i * 2 * NSUB + kb * 2 * LPU;
-                    d[q] = la < 0 ? 0 : reinterpret_cast<uint64_t>(static_cast<const uint8_t *>(m.packL) +
-                                                                   (int64_t)la * m.leafStrideL * (int64_t)sizeof(typename G::T));
-                    d[LPU + q] = lb < 0 ? 0 : reinterpret_cast<uint64_t>(static_cast<const uint8_t *>(m.packR) +
-                                                                         (int64_t)lb * m.leafStrideR * (int64_t)sizeof(typename G::T));
-                }
-        }
+        load_meta<MODE, U, BS>(m, mt, b0, nb);
         __syncthreads();
         Step st = first_step<LPU, NSUB>(mt, nb, 0);
         Advance nxa;
@@ -733,45 +807,7 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
         }
     }
 
-    // write the owned output blocks once (padding beyond the logical size = 0);
-    // a 16x16 tile lies inside one leaf, so its leaf index and edge test are
-    // wave-uniform
-    const int lane = tid & 63;
-    uint32_t ui, uj;
-    demorton(m.ukey[u], ui, uj);
-    typename M::Out *C = static_cast<typename M::Out *>(m.C);
-    constexpr int64_t N2 = (int64_t)BS * BS;
-#pragma unroll
-    for (int tm = 0; tm < TPW; ++tm)
-#pragma unroll
-        for (int tn = 0; tn < TPW; ++tn) {
-            const int row0 = G::WT * wr + 16 * tm, col0 = G::WT * wc + 16 * tn;
-            const int ib = row0 / BS, jb = col0 / BS;
-            const int32_t leaf = uni(m.cdesc[(int64_t)u * NSUB + ib * LPU + jb]);
-            if (leaf < 0) continue;
-            const int64_t I = (int64_t)ui * LPU + ib, J = (int64_t)uj * LPU + jb;
-            const bool interior = (I + 1) * BS <= m.out_rows && (J + 1) * BS <= m.out_cols;
-            const int cc = col0 - jb * BS + (lane & 15);
-            typename M::Out *dst = C + (int64_t)leaf * N2 + (int64_t)cc * BS + (row0 - ib * BS);
-            if (M::row_of(0, 1) == 1 && interior) {
-                // rows 4*(lane/16) .. +3 of the tile are contiguous in the column
-                if constexpr (sizeof(typename M::Out) == 4) {
-                    *reinterpret_cast<float4 *>(dst + 4 * (lane >> 4)) =
-                        make_float4(acc[tm][tn][0], acc[tm][tn][1], acc[tm][tn][2], acc[tm][tn][3]);
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) dst[4 * (lane >> 4) + i] = (typename M::Out)acc[tm][tn][i];
-                }
-            } else {
-                const bool colok = (J * BS + cc) < m.out_cols;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = row0 - ib * BS + M::row_of(lane, i);
-                    const bool ok = colok && (I * BS + r) < m.out_rows;
-                    dst[M::row_of(lane, i)] = ok ? (typename M::Out)acc[tm][tn][i] : (typename M::Out)0;
-                }
-            }
-        }
+    store_unit<MODE, U, BS>(m, u, acc, wr, wc);
 }
 
 // Unit 256 takes the branch-free path when both packs are finite; the
@@ -841,6 +877,144 @@ __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     }
 }
 
+#ifdef QB_K5_OZAKI_UNIT
+// The Ozaki mode at unit 128: 2 x 2 leaves of 64, four waves of one 64 x 64
+// output leaf each.  One step (the seven slices of two A leaves and two B
+// leaves, 112 KB) leaves no LDS for a second stage, so the step's fragments
+// are double-buffered in registers instead: every wave reads all of its
+// fragments of the step (column tile 0 first), multiplies column tile 0,
+// and once every wave's reads are complete (a barrier) the next step's copy
+// goes out into the same stage while the other column tiles run from
+// registers.  Against unit 64 every copied leaf serves two leaf products,
+// which halves the operand traffic.  A wave whose leaf product is absent in
+// a step reads nothing and multiplies nothing (its leaves may be nil), but
+// issues its share of the copy and meets both barriers.
+template <int BS, bool NF>
+__device__ void process_unit_oz128(const K5Member &m, int u, uint8_t *stage, uint8_t *meta) {
+    constexpr int MODE = QBSM_OZAKI_I8, U = 128;
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB, TPW = G::TPW, PARTS = M::PARTS;
+    static_assert(G::WT == BS && G::NCHUNK == 1 && G::NGROUPS == 1 && M::SUBS == 1,
+                  "one wave per output leaf, one K chunk per leaf, one read group");
+    const int w = uni((int)threadIdx.x >> 6);
+    const int wr = w / G::WPS, wc = w % G::WPS;
+    const int lane = threadIdx.x & 63, l16 = lane & 15, pc = lane >> 4;
+    const int bit = wr * LPU + wc;  // the wave's leaf product among a step's bits
+
+    typename M::Acc acc[TPW][TPW];
+#pragma unroll
+    for (int a = 0; a < TPW; ++a)
+#pragma unroll
+        for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
+    OzExp<TPW> ex{};
+
+    const int p0 = uni(m.ustart[u]), p1 = uni(m.ustart[u + 1]);
+    const Meta mt = meta_view(meta, G::CAP);
+    const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
+    const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
+    const uint8_t *Ab = stage, *Bb = stage + PARTS * G::ARRB;
+    auto tile = [&](typename M::Frag (&fa)[TPW][PARTS], typename M::Frag (&fb)[TPW][PARTS], int tm, int tn) {
+        typename M::Part pt;
+#pragma unroll
+        for (int k = 0; k < M::NSUMS; ++k) pt.s[k] = i4{0, 0, 0, 0};
+        M::mma_part(pt, fa[tm], fb[tn]);
+        M::template flush<NF>(acc[tm][tn], pt, ex.er[tm], ex.ec[tn]);
+    };
+    for (int b0 = p0; b0 < p1; b0 += G::CAP) {
+        const int nb = uni((p1 - b0) < G::CAP ? (p1 - b0) : G::CAP);
+        __syncthreads();  // LDS (stage, metadata) of the previous batch or unit is free
+        load_meta<MODE, U, BS>(m, mt, b0, nb);
+        __syncthreads();
+        Step st = first_step<LPU, NSUB>(mt, nb, 0);
+        Advance nxa;
+        nxa.nx = st;
+        nxa.addrs = 0;
+        if (st.i < nb) {
+            const uint64_t addrs = copy_addr<MODE, U, BS>(mt, st.i, st.kb, 0, cl, chunk_bytes);
+#pragma unroll
+            for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, stage, w);
+            // exponents only of leaves that exist (a nil leaf has no block)
+            if ((st.km >> bit) & 1u) oz_load_exp<MODE, U, BS>(mt, st.i, st.kb, wr, wc, ex);
+            nxa = advance<MODE, U, BS>(mt, nb, st, addrs, cl, chunk_bytes);
+        }
+        while (st.i < nb) {
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this step's copies and exponents
+            __syncthreads();
+            const bool mine = ((st.km >> bit) & 1u) != 0;
+            typename M::Frag fa[TPW][PARTS], fb[TPW][PARTS];
+            if (mine) {
+#pragma unroll
+                for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                    for (int part = 0; part < PARTS; ++part)
+                        fa[t][part].q[0] = lds_piece(Ab + part * G::ARRB, G::WT * wr + 16 * t + l16, G::LB, pc);
+#pragma unroll
+                for (int t = 0; t < TPW; ++t)
+#pragma unroll
+                    for (int part = 0; part < PARTS; ++part)
+                        fb[t][part].q[0] = lds_piece(Bb + part * G::ARRB, G::WT * wc + 16 * t + l16, G::LB, pc);
+#pragma unroll
+                for (int tm = 0; tm < TPW; ++tm) tile(fa, fb, tm, 0);
+            }
+            const bool more = nxa.nx.i < nb;
+            OzExp<TPW> exn = ex;
+            Advance nn = nxa;
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): every read of the stage is complete
+            __syncthreads();
+            if (more) {
+#pragma unroll
+                for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, stage, w);
+                if ((nxa.nx.km >> bit) & 1u) oz_load_exp<MODE, U, BS>(mt, nxa.nx.i, nxa.nx.kb, wr, wc, exn);
+                nn = advance<MODE, U, BS>(mt, nb, nxa.nx, nxa.addrs, cl, chunk_bytes);
+            }
+            if (mine) {
+#pragma unroll
+                for (int tn = 1; tn < TPW; ++tn)
+#pragma unroll
+                    for (int tm = 0; tm < TPW; ++tm) tile(fa, fb, tm, tn);
+            }
+            st = nxa.nx;
+            nxa = nn;
+            ex = exn;
+        }
+    }
+    store_unit<MODE, U, BS>(m, u, acc, wr, wc);
+}
+
+__device__ __forceinline__ void oz128_sel(const K5Member &m, int u, uint8_t *stage, uint8_t *meta) {
+    if ((*m.nfL | *m.nfR) != 0)
+        process_unit_oz128<64, true>(m, u, stage, meta);
+    else
+        process_unit_oz128<64, false>(m, u, stage, meta);
+}
+
+// BS = 64: one launch of one multiply; BS = 0: the persistent work-list form
+// (every member has 64 x 64 leaves).
+template <int BS>
+__global__ void __launch_bounds__(256, 1)
+    k5_oz128(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
+    __shared__ __attribute__((aligned(1024))) uint8_t stage[Geo<QBSM_OZAKI_I8, 128, 64>::STAGEB];
+    __shared__ __attribute__((aligned(16))) uint8_t meta[k5_meta_bytes<128>];
+    if constexpr (BS != 0) {
+        const int u = xcd_remap((int)blockIdx.x, single.nunits);
+        oz128_sel(single, u, stage, meta);
+    } else {
+        __shared__ int s_item;
+        for (;;) {
+            if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+            __syncthreads();
+            const int it = s_item;
+            __syncthreads();
+            if ((int64_t)it >= nitems) break;
+            const int2 wi = items[it];
+            const K5Member mm = members[wi.x];
+            oz128_sel(mm, wi.y, stage, meta);
+        }
+    }
+}
+#endif  // QB_K5_OZAKI_UNIT
+
 template <int MODE, int U>
 void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter, int grid,
               int persistent, const K5Member &single, hipStream_t s) {
@@ -876,9 +1050,17 @@ void launch_mode(int unit, int bs, const K5Member *members, const int2 *items, i
         case 128:
             if constexpr (MODE != QBSM_OZAKI_I8) {
                 launch_u<MODE, 128>(bs, members, items, nitems, counter, grid, persistent, single, s);
-                break;
+            } else {
+#ifdef QB_K5_OZAKI_UNIT
+                if (persistent)
+                    k5_oz128<0><<<grid, 256, 0, s>>>(single, members, items, nitems, counter);
+                else if (bs == 64)
+                    k5_oz128<64><<<grid, 256, 0, s>>>(single, members, items, nitems, counter);
+                else
+                    throw Error(QBSM_ERR_UNSUPPORTED, "leaf size for this unit side");
+#endif
             }
-            throw Error(QBSM_ERR_UNSUPPORTED, "unit side for this mode");
+            break;
         case 256:
             // the 128 x 128 part of a wave holds 64 KB of accumulators in FP32
             // but twice that in FP64, beyond the register file
@@ -901,9 +1083,10 @@ void k5_launch_ozaki(int unit, int bs, const K5Member *members, const int2 *item
 }
 
 const void *k5_kernel_ozaki(int unit, int bs) {
-    if (unit != 64) return nullptr;
-    if (bs == 0) return reinterpret_cast<const void *>(&k5<QBSM_OZAKI_I8, 64, 0>);
-    if (bs == 64) return reinterpret_cast<const void *>(&k5<QBSM_OZAKI_I8, 64, 64>);
+    if (unit == 64 && bs == 0) return reinterpret_cast<const void *>(&k5<QBSM_OZAKI_I8, 64, 0>);
+    if (unit == 64 && bs == 64) return reinterpret_cast<const void *>(&k5<QBSM_OZAKI_I8, 64, 64>);
+    if (unit == 128 && bs == 0) return reinterpret_cast<const void *>(&k5_oz128<0>);
+    if (unit == 128 && bs == 64) return reinterpret_cast<const void *>(&k5_oz128<64>);
     return nullptr;
 }
 #else
@@ -1012,8 +1195,8 @@ void numeric_check(const Plan &p, qbsm_mode mode) {
     plan_check_current(p);
     QB_CHECK(!(mode == QBSM_F64 && p.unit >= 256), QBSM_ERR_UNSUPPORTED,
              "unit 256 serves the FP32-accumulating modes only");
-    QB_CHECK(mode != QBSM_OZAKI_I8 || (p.unit == 64 && p.bs == 64), QBSM_ERR_UNSUPPORTED,
-             "the Ozaki mode needs 64 x 64 leaves and unit 64");
+    QB_CHECK(mode != QBSM_OZAKI_I8 || ((p.unit == 64 || p.unit == 128) && p.bs == 64), QBSM_ERR_UNSUPPORTED,
+             "the Ozaki mode needs 64 x 64 leaves and unit 64 or 128");
 }
 
 void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {

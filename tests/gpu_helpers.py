@@ -19,8 +19,8 @@ UNITS = {32: (64, 128), 64: (64, 128, 256), 128: (128, 256)}
 
 
 def units(bs, mode):
-    if mode == "ozaki":  # 64-wide integer MFMA: 64 x 64 leaves at unit 64
-        return (64,) if bs == 64 else ()
+    if mode == "ozaki":  # 64-wide integer MFMA: 64 x 64 leaves at unit 64 or 128
+        return (64, 128) if bs == 64 else ()
     return tuple(u for u in UNITS[bs] if not (u == 256 and mode == "f64"))
 
 

@@ -513,16 +513,28 @@ OZAKI_CASES = [
 
 
 @pytest.mark.parametrize("case", OZAKI_CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-bs{c[3]}")
-def test_ozaki_against_oracle_split(q, case):
+@pytest.mark.parametrize("unit", [64, 128])
+def test_ozaki_against_oracle_split(q, case, unit):
     """Ozaki mode: FP64 result within the stated tolerance of the FP64 oracle
-    and within rounding of the oracle's own Ozaki emulation."""
+    and within rounding of the oracle's own Ozaki emulation, at unit 64 (one
+    leaf per unit) and unit 128 (2 x 2 leaves, nil leaves inside a unit)."""
     m, k, n, bs, p, seed = case
     a, b = W.small_random(m, k, n, bs, p, seed)
-    C, ref, err, got = check_product(q, a, b, "ozaki", 64)
+    C, ref, err, got = check_product(q, a, b, "ozaki", unit)
     assert C.values().dtype == torch.float64
     oz = O.ozaki_multiply(O.from_workload(a), O.from_workload(b))
     assert O.rel_fro(got, oz.vals) <= TOL_OZAKI_EMULATED
     assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
+
+
+def test_ozaki_units_agree(q):
+    """Unit 64 and unit 128 add the same leaf products in the same order
+    (K ascending, one flush per leaf product), so their results are equal."""
+    a, b = W.small_random(900, 1000, 800, 64, 0.4, 90)
+    A, B = upload(q, a), upload(q, b)
+    g64 = values_np(q.Plan(A, B, unit=64).numeric("ozaki"))
+    g128 = values_np(q.Plan(A, B, unit=128).numeric("ozaki"))
+    assert np.array_equal(g64, g128)
 
 
 @pytest.mark.parametrize("decades", [40, 120, 280])
@@ -544,14 +556,15 @@ def test_ozaki_wide_dynamic_range(q, decades):
     qk = rng.uniform(-decades / 3, decades / 3, nb)
     a.vals *= 10.0 ** (p[a.brow] + qk[a.bcol])[:, None]
     b.vals *= 10.0 ** (r[b.bcol] - qk[b.brow])[:, None]
-    C, ref, err, got = check_product(q, a, b, "ozaki", 64)
-    assert np.all(np.isfinite(ref.vals)) and np.all(np.isfinite(got))
-    oz = O.ozaki_multiply(O.from_workload(a), O.from_workload(b))
-    assert O.rel_fro(got, oz.vals) <= TOL_OZAKI_EMULATED
-    # block by block, relative to each block's own norm
-    nrm = np.linalg.norm(ref.vals, axis=1)
-    rel = np.linalg.norm(got - ref.vals, axis=1) / np.where(nrm > 0, nrm, 1.0)
-    assert np.max(rel) <= 1e-10
+    for unit in (64, 128):
+        C, ref, err, got = check_product(q, a, b, "ozaki", unit)
+        assert np.all(np.isfinite(ref.vals)) and np.all(np.isfinite(got))
+        oz = O.ozaki_multiply(O.from_workload(a), O.from_workload(b))
+        assert O.rel_fro(got, oz.vals) <= TOL_OZAKI_EMULATED
+        # block by block, relative to each block's own norm
+        nrm = np.linalg.norm(ref.vals, axis=1)
+        rel = np.linalg.norm(got - ref.vals, axis=1) / np.where(nrm > 0, nrm, 1.0)
+        assert np.max(rel) <= 1e-10
 
 
 def test_ozaki_extreme_values_and_nonfinite(q):
@@ -570,18 +583,20 @@ def test_ozaki_extreme_values_and_nonfinite(q):
     a2.vals[0] *= 1e200
     b2.vals[0] *= 1e200
     r2 = O.multiply(O.from_workload(a2), O.from_workload(b2)).vals
-    g2 = values_np(q.matmul(upload(q, a2), upload(q, b2), "ozaki", unit=64))
-    assert np.array_equal(np.isfinite(g2), np.isfinite(r2)) and not np.all(np.isfinite(r2))
-    _finite_parts_close(g2, r2)
+    for unit in (64, 128):
+        g2 = values_np(q.matmul(upload(q, a2), upload(q, b2), "ozaki", unit=unit))
+        assert np.array_equal(np.isfinite(g2), np.isfinite(r2)) and not np.all(np.isfinite(r2))
+        _finite_parts_close(g2, r2)
     # Inf and NaN inputs
     a3, b3 = W.small_random(256, 256, 256, 64, 1.0, 13)
     a3.vals[5, 17] = np.nan
     a3.vals[9, 100] = np.inf
     b3.vals[2, 4000] = -np.inf
     ref3 = O.multiply(O.from_workload(a3), O.from_workload(b3)).vals
-    got3 = values_np(q.matmul(upload(q, a3), upload(q, b3), "ozaki", unit=64))
-    assert np.array_equal(np.isfinite(got3), np.isfinite(ref3))
-    _finite_parts_close(got3, ref3)
+    for unit in (64, 128):
+        got3 = values_np(q.matmul(upload(q, a3), upload(q, b3), "ozaki", unit=unit))
+        assert np.array_equal(np.isfinite(got3), np.isfinite(ref3))
+        _finite_parts_close(got3, ref3)
 
 
 def _finite_parts_close(got, ref, tol=1e-11):
@@ -604,8 +619,8 @@ def _finite_parts_close(got, ref, tol=1e-11):
 def test_ozaki_unit_and_backward(q):
     a, b = W.small_random(320, 256, 288, 64, 0.5, 86)
     A, B = upload(q, a), upload(q, b)
-    with pytest.raises(q.QbsmError, match="unit 64"):
-        q.Plan(A, B, unit=128).numeric("ozaki")
+    with pytest.raises(q.QbsmError, match="unit 64 or 128"):
+        q.Plan(A, B, unit=256).numeric("ozaki")
     a32, b32 = W.small_random(200, 150, 120, 32, 0.5, 87)
     with pytest.raises(q.QbsmError, match="64 x 64 leaves"):
         q.Plan(upload(q, a32), upload(q, b32), unit=64).numeric("ozaki")
@@ -619,20 +634,22 @@ def test_ozaki_unit_and_backward(q):
     dC = q.Matrix(320, 288, 64)
     dC.set_blocks(torch.from_numpy(ref.brow.astype(np.int32)).cuda(),
                   torch.from_numpy(ref.bcol.astype(np.int32)).cuda(), torch.from_numpy(dcv).cuda())
-    dA, dB = q.backward(A, B, dC, "ozaki", 64)
-    assert_backward(values_np(dA), values_np(dB), oa, ob, odc, ga, gb, "ozaki")
+    for unit in (64, 128):
+        dA, dB = q.backward(A, B, dC, "ozaki", unit)
+        assert_backward(values_np(dA), values_np(dB), oa, ob, odc, ga, gb, "ozaki")
 
 
 def test_ozaki_batched(q):
     rng = np.random.default_rng(87)
     members = [W.small_random(n, n, n, bs, 0.4, 300 + t) for t, (n, bs) in
                enumerate([(700, 64), (1000, 64), (513, 64)])]
-    plans = [q.Plan(upload(q, a), upload(q, b), unit=64) for a, b in members]
-    singles = [values_np(p.numeric("ozaki")) for p in plans]
-    batch = q.Batch(plans, "ozaki")
-    batch.run()
-    torch.cuda.synchronize()
-    for o, s_, (a, b) in zip(batch.outs, singles, members):
-        assert np.array_equal(values_np(o), s_)
-        oa, ob = O.from_workload(a), O.from_workload(b)
-        assert_product(s_, oa, ob, O.multiply(oa, ob).vals, "ozaki", what="ozaki batch member")
+    for unit in (64, 128):
+        plans = [q.Plan(upload(q, a), upload(q, b), unit=unit) for a, b in members]
+        singles = [values_np(p.numeric("ozaki")) for p in plans]
+        batch = q.Batch(plans, "ozaki")
+        batch.run()
+        torch.cuda.synchronize()
+        for o, s_, (a, b) in zip(batch.outs, singles, members):
+            assert np.array_equal(values_np(o), s_)
+            oa, ob = O.from_workload(a), O.from_workload(b)
+            assert_product(s_, oa, ob, O.multiply(oa, ob).vals, "ozaki", what=f"ozaki batch member (unit {unit})")
