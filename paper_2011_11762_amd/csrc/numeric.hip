@@ -167,6 +167,30 @@ struct MT<QBSM_OZAKI_I8> {
         }
         p.s[3] = group(a, b, 8, p.s[3]);
     }
+    // The same for NT tiles of one column tile at once, their MFMAs
+    // interleaved tile by tile: consecutive MFMAs on one accumulator are NT
+    // instructions apart, so the integer MFMA pipe never waits on a result,
+    // and a tile's shift between its two groups overlaps the others' MFMAs.
+    template <int NT>
+    __device__ static void mma_parts(Part (&p)[NT], const Frag (&a)[NT][OZ_SLICES], const Frag *b) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int h = 0; h < (k < 3 ? 2 : 1); ++h) {
+                const int g = k < 3 ? 2 * k + 2 + h : 8;
+                if (h == 1) {
+#pragma unroll
+                    for (int t = 0; t < NT; ++t) p[t].s[k] = p[t].s[k] * 128;  // S_g 2^7, below 2^30
+                }
+#pragma unroll
+                for (int ta = 1; ta < g; ++ta)
+                    if (ta <= OZ_SLICES && g - ta <= OZ_SLICES) {
+#pragma unroll
+                        for (int t = 0; t < NT; ++t) p[t].s[k] = mm(a[t], b, ta, g - ta, p[t].s[k]);
+                    }
+            }
+        }
+    }
     // c += 2^(er + ec) * (P1 2^-21 + P2 2^-35 + P3 2^-49 + P4 2^-56), element i
     // of a lane being row 4*(lane/16) + i (exponent er[i]) and column
     // lane % 16 (exponent ec).  NF: the operands hold non-finite lines,
@@ -914,12 +938,16 @@ __device__ void process_unit_oz128(const K5Member &m, int u, uint8_t *stage, uin
     const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
     const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
     const uint8_t *Ab = stage, *Bb = stage + PARTS * G::ARRB;
-    auto tile = [&](typename M::Frag (&fa)[TPW][PARTS], typename M::Frag (&fb)[TPW][PARTS], int tm, int tn) {
-        typename M::Part pt;
+    // the four row tiles of column tile tn: integer sums, then their flushes
+    auto column = [&](typename M::Frag (&fa)[TPW][PARTS], typename M::Frag (&fb)[TPW][PARTS], int tn) {
+        typename M::Part pt[TPW];
 #pragma unroll
-        for (int k = 0; k < M::NSUMS; ++k) pt.s[k] = i4{0, 0, 0, 0};
-        M::mma_part(pt, fa[tm], fb[tn]);
-        M::template flush<NF>(acc[tm][tn], pt, ex.er[tm], ex.ec[tn]);
+        for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int k = 0; k < M::NSUMS; ++k) pt[t].s[k] = i4{0, 0, 0, 0};
+        M::template mma_parts<TPW>(pt, fa, fb[tn]);
+#pragma unroll
+        for (int tm = 0; tm < TPW; ++tm) M::template flush<NF>(acc[tm][tn], pt[tm], ex.er[tm], ex.ec[tn]);
     };
     for (int b0 = p0; b0 < p1; b0 += G::CAP) {
         const int nb = uni((p1 - b0) < G::CAP ? (p1 - b0) : G::CAP);
@@ -954,8 +982,7 @@ __device__ void process_unit_oz128(const K5Member &m, int u, uint8_t *stage, uin
 #pragma unroll
                     for (int part = 0; part < PARTS; ++part)
                         fb[t][part].q[0] = lds_piece(Bb + part * G::ARRB, G::WT * wc + 16 * t + l16, G::LB, pc);
-#pragma unroll
-                for (int tm = 0; tm < TPW; ++tm) tile(fa, fb, tm, 0);
+                column(fa, fb, 0);
             }
             const bool more = nxa.nx.i < nb;
             OzExp<TPW> exn = ex;
@@ -970,9 +997,7 @@ __device__ void process_unit_oz128(const K5Member &m, int u, uint8_t *stage, uin
             }
             if (mine) {
 #pragma unroll
-                for (int tn = 1; tn < TPW; ++tn)
-#pragma unroll
-                    for (int tm = 0; tm < TPW; ++tm) tile(fa, fb, tm, tn);
+                for (int tn = 1; tn < TPW; ++tn) column(fa, fb, tn);
             }
             st = nxa.nx;
             nxa = nn;
