@@ -91,6 +91,42 @@ __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply(const Tin *in, Tout *
     }
 }
 
+// The apply pass for up to SCAN_SUM_MAX tiles: each workgroup sums the tile
+// totals before its own (at most SCAN_SUM_MAX values) instead of reading a
+// scanned partial array, so the scan takes two launches; the last workgroup
+// writes the total.
+constexpr int64_t SCAN_SUM_MAX = 1024;
+
+template <class Tin, class Tout, class Tacc>
+__global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply_sum(const Tin *in, Tout *out, int64_t n,
+                                                               const Tacc *partial, int64_t *total64) {
+    Tacc pre = 0;
+    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += SCAN_BLOCK) pre += partial[j];
+    Tacc before;
+    (void)block_exclusive_scan<Tacc>(pre, &before);
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    Tacc vals[SCAN_ITEMS];
+    Tacc s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = base + (int64_t)threadIdx.x * SCAN_ITEMS + i;
+        vals[i] = idx < n ? (Tacc)in[idx] : 0;
+        s += vals[i];
+    }
+    Tacc tot;
+    Tacc ex = block_exclusive_scan<Tacc>(s, &tot) + before;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t idx = base + (int64_t)threadIdx.x * SCAN_ITEMS + i;
+        if (idx < n) out[idx] = (Tout)ex;
+        ex += vals[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+        out[n] = (Tout)(before + tot);
+        if (total64) *total64 = (int64_t)(before + tot);
+    }
+}
+
 // The whole scan in one workgroup, for at most SCAN_TILE values (the small
 // levels of the symbolic walk): one launch and no scratch array.
 template <class Tin, class Tout>
@@ -128,11 +164,29 @@ void scan_impl(const Tin *in, Tout *out, int64_t n, int64_t *total64, hipStream_
     DArr<int64_t> partial(nb + 1, s);
     k_scan_reduce<Tin, int64_t><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, n, partial.p);
     QB_LAUNCH_CHECK();
+    if (nb <= SCAN_SUM_MAX) {
+        k_scan_apply_sum<Tin, Tout, int64_t><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, out, n, partial.p, total64);
+        QB_LAUNCH_CHECK();
+        return;
+    }
     k_scan_partials<int64_t><<<1, SCAN_BLOCK, 0, s>>>(partial.p, nb, partial.p + nb);
     QB_LAUNCH_CHECK();
     k_scan_apply<Tin, Tout, int64_t><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, out, n, partial.p,
                                                                          partial.p + nb, total64);
     QB_LAUNCH_CHECK();
+}
+
+// Zeroes `head` bytes at p, then n16 16-byte granules (p + head is aligned
+// to 16 bytes), then `tail` bytes.
+__global__ void k_zero(uint8_t *p, int head, int64_t n16, int tail) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint4 *q = reinterpret_cast<uint4 *>(p + head);
+    for (; i < n16; i += stride) q[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0) {
+        if ((int)threadIdx.x < head) p[threadIdx.x] = 0;
+        if ((int)threadIdx.x < tail) p[head + n16 * 16 + threadIdx.x] = 0;
+    }
 }
 
 template <class T>
@@ -192,18 +246,15 @@ void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 
 void fill_bytes_zero(void *p, size_t bytes, hipStream_t s) {
     if (!bytes) return;
-    // a plain fill kernel (graph-capture friendly); 16-byte granules + tail
-    size_t n16 = bytes / 16;
-    if (n16) {
-        k_fill<uint4><<<grid_for((int64_t)n16, 256) > 65536 ? 65536 : grid_for((int64_t)n16, 256), 256, 0, s>>>(
-            static_cast<uint4 *>(p), make_uint4(0, 0, 0, 0), (int64_t)n16);
-        QB_LAUNCH_CHECK();
-    }
-    size_t tail = bytes - n16 * 16;
-    if (tail) {
-        k_fill<uint8_t><<<1, 64, 0, s>>>(static_cast<uint8_t *>(p) + n16 * 16, (uint8_t)0, (int64_t)tail);
-        QB_LAUNCH_CHECK();
-    }
+    // a plain fill kernel (graph-capture friendly): 16-byte granules, the
+    // first workgroup also writes the unaligned head and the tail bytes
+    size_t head = (16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15;
+    if (head > bytes) head = bytes;
+    const int64_t n16 = (int64_t)((bytes - head) / 16);
+    const int tail = (int)(bytes - head - (size_t)n16 * 16);
+    const int64_t g = grid_for(n16 ? n16 : 1, 256);
+    k_zero<<<g > 65536 ? 65536 : g, 256, 0, s>>>(static_cast<uint8_t *>(p), (int)head, n16, tail);
+    QB_LAUNCH_CHECK();
 }
 
 void bitmap_rank(const uint32_t *keys, const uint8_t *active, int64_t n, uint64_t range, int32_t *rank,

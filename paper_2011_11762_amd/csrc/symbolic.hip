@@ -23,6 +23,11 @@ struct Pairs {
     int64_t n = 0;
     DArr<int32_t> pl, pr, gs, gm, pm;
     DArr<uint32_t> ck;
+    // set by the walk: a zero-initialised device block whose first int64 is
+    // the exact pair count (*count) followed by kWalkExtra int64 slots, also
+    // zero, for the caller's own counts
+    DArr<int64_t> book;
+    int64_t *count = nullptr;
     void alloc(int64_t cnt, hipStream_t s) {
         const int64_t c = cnt ? cnt : 1;
         n = cnt;
@@ -200,8 +205,11 @@ __global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t 
     }
 }
 
-__global__ void k_walk_root(int32_t *pl, int32_t *pr, int32_t *gs, int32_t *gm, int32_t *pm, uint32_t *ck) {
+// The root pair and its count.
+__global__ void k_walk_root(int32_t *pl, int32_t *pr, int32_t *gs, int32_t *gm, int32_t *pm, uint32_t *ck,
+                            int64_t *count) {
     pl[0] = 0; pr[0] = 0; gs[0] = 0; gm[0] = 1; pm[0] = 0; ck[0] = 0u;
+    *count = 1;
 }
 
 // Node keys of levels 1..target of both operand trees, for the level sizing.
@@ -250,28 +258,33 @@ __global__ void __launch_bounds__(256) k_level_dot(const int32_t *hist, LevelHis
 // be far above it, so a level whose bound exceeds kMaskedBoundPairs reads its
 // exact count back before its arrays are allocated.
 constexpr int64_t kMaskedBoundPairs = int64_t(1) << 20;
-Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int64_t *count, hipStream_t s,
+constexpr int kWalkExtra = 4;
+Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s,
            const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0, int upper = 0) {
     Pairs cur;
     const bool empty = tL.n[0] == 0 || tR.n[0] == 0 || (tM && tM->n[0] == 0);
     if (empty || target == 0) {
         cur.alloc(empty ? 0 : 1, s);
-        const int64_t c = empty ? 0 : 1;
-        QB_HIP(hipMemcpyAsync(count, &c, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        cur.book.alloc(1 + kWalkExtra, s);
+        fill_bytes_zero(cur.book.p, (1 + kWalkExtra) * sizeof(int64_t), s);
+        cur.count = cur.book.p;
         if (!empty) {
-            k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p);
+            k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p, cur.count);
             QB_LAUNCH_CHECK();
         }
         return cur;
     }
-    // capacities of levels 1..target
+    // one zeroed block: counts[0..target] (pairs per level), the caller's
+    // slots, the capacities of levels 1..target and the level histograms
     std::vector<int64_t> hoff(target + 1, 0);
     for (int l = 1; l <= target; ++l) hoff[l] = hoff[l - 1] + ((int64_t)1 << (l - 1));
     const int64_t hsize = hoff[target] + ((int64_t)1 << target);
-    DArr<int32_t> hist(2 * hsize, s);
-    DArr<unsigned long long> capd(target + 1, s);
-    fill_bytes_zero(hist.p, 2 * hsize * sizeof(int32_t), s);
-    fill_bytes_zero(capd.p, (target + 1) * sizeof(unsigned long long), s);
+    const int64_t nbook = (target + 1) + kWalkExtra + (target + 1) + (2 * hsize + 1) / 2;
+    DArr<int64_t> book(nbook, s);
+    fill_bytes_zero(book.p, nbook * sizeof(int64_t), s);
+    int64_t *counts = book.p;
+    unsigned long long *capd = reinterpret_cast<unsigned long long *>(book.p + (target + 1) + kWalkExtra);
+    int32_t *hist = reinterpret_cast<int32_t *>(capd + (target + 1));
     LevelHistArgs ha{};
     ha.use_col[0] = transL ? 0 : 1;
     ha.use_col[1] = transR ? 1 : 0;
@@ -285,22 +298,20 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
         ha.off[l] = hoff[l];
         nmax = std::max(nmax, std::max(tL.n[l], tR.n[l]));
     }
-    k_level_hist<<<dim3(grid_for(nmax, 256), (unsigned)target, 2), 256, 0, s>>>(ha, hist.p);
+    k_level_hist<<<dim3(grid_for(nmax, 256), (unsigned)target, 2), 256, 0, s>>>(ha, hist);
     QB_LAUNCH_CHECK();
-    k_level_dot<<<(unsigned)target, 256, 0, s>>>(hist.p, ha, capd.p);
+    k_level_dot<<<(unsigned)target, 256, 0, s>>>(hist, ha, capd);
     QB_LAUNCH_CHECK();
     std::vector<unsigned long long> cap(target + 1, 0);
-    QB_HIP(hipMemcpyAsync(cap.data(), capd.p, (target + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipMemcpyAsync(cap.data(), capd, (target + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
     QB_HIP(hipStreamSynchronize(s));
     for (int l = 1; l <= target; ++l)
         QB_CHECK(cap[l] <= (unsigned long long)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many node pairs at one level");
 
-    // counts[l]: pairs at level l (device), written by the scans
-    DArr<int64_t> counts(target + 1, s);
-    const int64_t one = 1;
-    QB_HIP(hipMemcpyAsync(counts.p, &one, sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // counts[l]: pairs at level l (device), written by the scans (a level
+    // without pairs keeps its zero)
     cur.alloc(1, s);
-    k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p);
+    k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p, counts);
     QB_LAUNCH_CHECK();
     auto level_in = [&](const Pairs &p, int l) {
         WalkLevel w{};
@@ -343,7 +354,7 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
                 tl.out[i] = level_out(outs[i]);
                 tl.ocap[i] = outs[i].n;
             }
-            k_walk_top<<<1, kTopThreads, 0, s>>>(tl, counts.p + l);
+            k_walk_top<<<1, kTopThreads, 0, s>>>(tl, counts + l);
             QB_LAUNCH_CHECK();
             capc = outs.back().n;
             cur = std::move(outs.back());
@@ -358,35 +369,35 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, int
             const unsigned g = grid_for(capc * 4, 256);
             const WalkLevel w = level_in(cur, l);
             const bool bounded = w.chM || w.nL || upper;
-            k_walk_count<<<g, 256, 0, s>>>(counts.p + l, capc * 4, w, X.p);
+            k_walk_count<<<g, 256, 0, s>>>(counts + l, capc * 4, w, X.p);
             QB_LAUNCH_CHECK();
-            exclusive_scan_i32(X.p, Y.p, capc * 4, counts.p + l + 1, s);
-            if (bounded && capn > kMaskedBoundPairs) capn = read_back(counts.p + l + 1, s);
+            exclusive_scan_i32(X.p, Y.p, capc * 4, counts + l + 1, s);
+            if (bounded && capn > kMaskedBoundPairs) capn = read_back(counts + l + 1, s);
             nxt.alloc(capn, s);
             if (capn) {
-                k_walk_fill<<<g, 256, 0, s>>>(counts.p + l, w, Y.p, capn, level_out(nxt));
+                k_walk_fill<<<g, 256, 0, s>>>(counts + l, w, Y.p, capn, level_out(nxt));
                 QB_LAUNCH_CHECK();
             }
         } else {
-            capn = 0;
+            capn = 0;  // counts[l + 1] stays zero
             nxt.alloc(0, s);
-            const int64_t zero = 0;
-            QB_HIP(hipMemcpyAsync(counts.p + l + 1, &zero, sizeof(int64_t), hipMemcpyHostToDevice, s));
         }
         cur = std::move(nxt);
         capc = capn;
     }
-    QB_HIP(hipMemcpyAsync(count, counts.p + target, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    // the caller's block: the level-`target` count and the slots after it
+    // (counts[target + 1 ..] are the zeroed extra slots)
     cur.n = capc;
+    cur.book = std::move(book);
+    cur.count = cur.book.p + target;
     return cur;
 }
 
 // The walk with its exact count read back.
 Pairs walk_exact(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hipStream_t s,
                  const double *nL = nullptr, const double *nR = nullptr, double tau = 0.0, int upper = 0) {
-    DArr<int64_t> cnt(1, s);
-    Pairs pr = walk(tL, transL, tR, transR, tM, target, cnt.p, s, nL, nR, tau, upper);
-    const int64_t n = read_back(cnt.p, s);
+    Pairs pr = walk(tL, transL, tR, transR, tM, target, s, nL, nR, tau, upper);
+    const int64_t n = read_back(pr.count, s);
     QB_CHECK(n <= pr.n, QBSM_ERR_STATE, "pair count above its bound");
     pr.n = n;
     return pr;
@@ -408,10 +419,13 @@ __global__ void k_unit_flags(const int64_t *npp, int64_t cap, const int32_t *gs,
 }
 
 // meta = {pairs, units} on the device; launches cover host-side bounds.
+// Also closes ustart (ustart[units] = pairs) and clears the units' output
+// leaf masks, which the pair-mask kernel then fills.
 __global__ void k_unit_fill(const int64_t *meta, const int32_t *gs, const int32_t *pm, const uint32_t *ck,
                             const int32_t *uscan, int32_t *ustart, uint32_t *ukey, int32_t *umask,
-                            int32_t *pu) {
+                            int32_t *pu, uint32_t *ucmask) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) ustart[meta[1]] = (int32_t)meta[0];
     if (p >= meta[0]) return;
     const bool start = gs[p] == (int32_t)p;
     const int32_t u = uscan[p] + (start ? 1 : 0) - 1;
@@ -420,10 +434,9 @@ __global__ void k_unit_fill(const int64_t *meta, const int32_t *gs, const int32_
         ustart[u] = (int32_t)p;
         ukey[u] = ck[p];
         umask[u] = pm[p];
+        ucmask[u] = 0u;
     }
 }
-
-__global__ void k_unit_end(int32_t *ustart, const int64_t *meta) { ustart[meta[1]] = (int32_t)meta[0]; }
 
 struct Dims {
     int64_t out_rows, inner, out_cols;
@@ -688,24 +701,26 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     Tree &tR = matrix_tree(*R, D, s);
     Tree *tM = M ? &matrix_tree(*M, D, s) : nullptr;
     const int Lw = D - sl;
-    // pair and unit counts come back together: meta = {pairs, units}
-    DArr<int64_t> meta(2, s);
     const double *nL = spamm_tol > 0.0 ? matrix_norms(*L, s) : nullptr;
     const double *nR = spamm_tol > 0.0 ? matrix_norms(*R, s) : nullptr;
     p->spamm_tol = spamm_tol;
     p->upper = upper;
-    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, meta.p, s, nL, nR, spamm_tol, upper);
+    Pairs pr = walk(tL, transL, tR, transR, tM, Lw, s, nL, nR, spamm_tol, upper);
     const int64_t cap = pr.n;
+    // the counts come back together, in the walk's zeroed block:
+    // meta = {pairs, units, leaf products, flops, output leaves}
+    int64_t *meta = pr.count;
+    static_assert(kWalkExtra >= 4, "units and the three totals follow the pair count");
+    struct Tot { unsigned long long nprod, flops; int64_t nout; };
+    Tot *totals = reinterpret_cast<Tot *>(meta + 2);
     const int nsub = p->lpu * p->lpu;
 
     // units = output groups at the unit level
     DArr<int32_t> flags(cap ? cap : 1, s), uscan((cap ? cap : 1) + 1, s), pu(cap ? cap : 1, s);
     if (cap) {
-        k_unit_flags<<<grid_for(cap, 256), 256, 0, s>>>(meta.p, cap, pr.gs.p, flags.p);
+        k_unit_flags<<<grid_for(cap, 256), 256, 0, s>>>(meta, cap, pr.gs.p, flags.p);
         QB_LAUNCH_CHECK();
-        exclusive_scan_i32(flags.p, uscan.p, cap, meta.p + 1, s);
-    } else {
-        fill_bytes_zero(meta.p + 1, sizeof(int64_t), s);
+        exclusive_scan_i32(flags.p, uscan.p, cap, meta + 1, s);
     }
     // Small plans size their unit arrays by the pair bound (units <= pairs)
     // and read the exact counts back with the totals, in one host read;
@@ -714,7 +729,7 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     const bool bound = cap <= kBoundedUnitPairs;
     if (!bound) {
         int64_t hm[2];
-        QB_HIP(hipMemcpyAsync(hm, meta.p, sizeof(hm), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipMemcpyAsync(hm, meta, sizeof(hm), hipMemcpyDeviceToHost, s));
         QB_HIP(hipStreamSynchronize(s));
         np = hm[0];
         nu = hm[1];
@@ -727,23 +742,17 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     p->pr = std::move(pr.pr);
     p->pmask.alloc(np ? np : 1, s);
     p->cdesc.alloc((nu ? nu : 1) * nsub, s);
-    struct Tot { unsigned long long nprod, flops; int64_t nout; };
-    DArr<Tot> totals(1, s);
-    fill_bytes_zero(totals.p, sizeof(Tot), s);
     DArr<uint32_t> ucmask(nu ? nu : 1, s);
-    fill_u32(ucmask.p, 0u, nu ? nu : 1, s);
     if (np) {
-        k_unit_fill<<<grid_for(np, 256), 256, 0, s>>>(meta.p, pr.gs.p, pr.pm.p, pr.ck.p, uscan.p, p->ustart.p,
-                                                     p->ukey.p, p->umask.p, pu.p);
-        QB_LAUNCH_CHECK();
-        k_unit_end<<<1, 1, 0, s>>>(p->ustart.p, meta.p);
+        k_unit_fill<<<grid_for(np, 256), 256, 0, s>>>(meta, pr.gs.p, pr.pm.p, pr.ck.p, uscan.p, p->ustart.p,
+                                                     p->ukey.p, p->umask.p, pu.p, ucmask.p);
         QB_LAUNCH_CHECK();
         Dims d{rows, inner, cols, bs, sl, p->lpu, transL, transR};
         const int32_t *dL = tree_desc(*L, tL, sl, s);
         const int32_t *dR = tree_desc(*R, tR, sl, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
 #define QB_PAIR_MASKS(S_)                                                                                   \
-    k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(meta.p, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p, \
+    k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(meta, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p,    \
                                                        dL, dR, dM, M ? 1 : 0, tL.key[Lw].p, d, nL, nR,     \
                                                        spamm_tol, upper, p->pmask.p, ucmask.p, part.p)
         const int64_t nblk = grid_for(np, 256);
@@ -753,7 +762,7 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
         else QB_PAIR_MASKS(2);
 #undef QB_PAIR_MASKS
         QB_LAUNCH_CHECK();
-        k_sum_parts<<<1, 256, 0, s>>>(part.p, nblk, &totals.p->nprod);
+        k_sum_parts<<<1, 256, 0, s>>>(part.p, nblk, &totals->nprod);
         QB_LAUNCH_CHECK();
     } else {
         int32_t zero = 0;
@@ -764,33 +773,35 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     DArr<uint32_t> okeys_b;
     if (nu) {
         DArr<int32_t> cnt(nu, s), cbase(nu + 1, s);
-        k_unit_count<<<grid_for(nu, 256), 256, 0, s>>>(meta.p, nu, ucmask.p, cnt.p);
+        k_unit_count<<<grid_for(nu, 256), 256, 0, s>>>(meta, nu, ucmask.p, cnt.p);
         QB_LAUNCH_CHECK();
-        exclusive_scan_i32(cnt.p, cbase.p, nu, &totals.p->nout, s);
+        exclusive_scan_i32(cnt.p, cbase.p, nu, &totals->nout, s);
         if (!M) okeys_b.alloc(nu * nsub, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
-        k_unit_cdesc<<<grid_for(nu, 256), 256, 0, s>>>(meta.p, ucmask.p, cbase.p, p->ukey.p, p->umask.p, dM,
+        k_unit_cdesc<<<grid_for(nu, 256), 256, 0, s>>>(meta, ucmask.p, cbase.p, p->ukey.p, p->umask.p, dM,
                                                       M ? 1 : 0, sl, p->lpu, p->cdesc.p,
                                                       M ? nullptr : okeys_b.p);
         QB_LAUNCH_CHECK();
     }
-    int64_t hm[2];
-    QB_HIP(hipMemcpyAsync(hm, meta.p, sizeof(hm), hipMemcpyDeviceToHost, s));
-    Tot h = read_back(totals.p, s);
+    int64_t hm[5];
+    QB_HIP(hipMemcpyAsync(hm, meta, sizeof(hm), hipMemcpyDeviceToHost, s));
+    QB_HIP(hipStreamSynchronize(s));
     QB_CHECK(hm[0] <= np && hm[1] <= hm[0], QBSM_ERR_STATE, "pair count above its bound");
     np = hm[0];
     nu = hm[1];
     p->npairs = np;
     p->nunits = nu;
-    const int64_t nout = nu ? h.nout : 0;
+    const int64_t nout = nu ? hm[4] : 0;
     QB_CHECK(nout <= nu * nsub, QBSM_ERR_STATE, "output leaf count above its bound");
+    // the output keys stay in their bounded array (nout of them are valid)
     if (!M) {
-        p->okeys.alloc(nout ? nout : 1, s);
-        if (nout)
-            QB_HIP(hipMemcpyAsync(p->okeys.p, okeys_b.p, nout * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+        if (okeys_b.p)
+            p->okeys = std::move(okeys_b);
+        else
+            p->okeys.alloc(1, s);
     }
-    p->nprod = (int64_t)h.nprod;
-    p->flops = (int64_t)h.flops;
+    p->nprod = (int64_t)hm[2];
+    p->flops = (int64_t)hm[3];
     p->nout = M ? M->nblk : nout;
     return p;
 }
