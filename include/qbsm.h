@@ -82,10 +82,12 @@ typedef QBSM_ENUM(qbsm_status_e) {
  *   QBSM_OZAKI_I8 Ozaki splitting (Ozaki, Ogita, Oishi and Rump 2012) on
  *               8-bit integer MFMA: each line of a leaf (a row of the left
  *               operand, a column of the right one) gets the exponent e of its
- *               largest magnitude m (m < 2^e), and each element is cut into 7
- *               signed 7-bit digits on the grid 2^(e - 7t), t = 1..7 (the 49
- *               leading bits of the element below e).  The 28 digit pairs with
- *               t + u <= 8 are multiplied; the products of one pair group
+ *               largest magnitude m (m < 2^e; one more when m lies within 0.4 %
+ *               below 2^e), each element x is truncated to the integer
+ *               M = sign(x) floor(|x| 2^(47 - e)) and M is written as 6
+ *               balanced base-256 digits in [-128, 127] on the grids
+ *               2^(e + 1 - 8t), t = 1..6.  The 21 digit pairs with
+ *               t + u <= 7 are multiplied; the products of one pair group
  *               (t + u fixed) over one leaf sum exactly in 32-bit integers, are
  *               combined in FP64, scaled by 2^(e_row + e_col) (so the whole FP64
  *               exponent range is covered) and accumulated in FP64; FP64 result.

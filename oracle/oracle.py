@@ -598,46 +598,64 @@ def split_bf16(x: np.ndarray):
 # of matrix multiplication by using fast routines of matrix multiplication
 # and its applications", Numer. Algorithms 59, 2012): an addition to the
 # paper's FP64-only leaves.  Reading taken here: one exponent per leaf row of
-# the left operand and per leaf column of the right operand; OZ_SLICES slices
-# of OZ_BITS-bit digits, so that a signed digit is an 8-bit integer (|d| <=
-# 127) and a slice is that integer on the line's exponent grid; the slice
-# pairs with t + u <= OZ_SLICES + 1 are kept.
-OZ_SLICES, OZ_BITS = 7, 7
+# the left operand and per leaf column of the right operand; each element is
+# truncated to an integer M of OZ_MANT bits on the line's grid and M is
+# written in OZ_SLICES balanced base-2^OZ_BITS digits (every digit in
+# [-128, 127], an 8-bit integer); the slice pairs with t + u <= OZ_SLICES + 1
+# are kept.
+OZ_SLICES, OZ_BITS, OZ_MANT = 6, 8, 47
+# the largest M whose balanced digits all fit in [-128, 127]: 127 (2^48 - 1) / 255
+OZ_MAXM = 127 * ((1 << (OZ_SLICES * OZ_BITS)) - 1) // ((1 << OZ_BITS) - 1)
 
 
-def ozaki_split(vals: np.ndarray, bs: int, line: str, slices: int = OZ_SLICES, bits: int = OZ_BITS) -> np.ndarray:
+def ozaki_exponent(m: np.ndarray) -> np.ndarray:
+    """Line exponents for line maxima m (finite, >= 0): the e of m = f 2^e,
+    0.5 <= f < 1 (0 for m = 0), raised by one where floor(m 2^(OZ_MANT - e))
+    would exceed OZ_MAXM (m within 0.4 % below 2^e), so that every element of
+    the line has a digit expansion."""
+    _, e = np.frexp(m)
+    mmax = np.floor(np.ldexp(m, OZ_MANT - e))
+    return np.where(mmax > OZ_MAXM, e + 1, e)
+
+
+def ozaki_split(vals: np.ndarray, bs: int, line: str, slices: int = OZ_SLICES) -> np.ndarray:
     """Exponent-aligned slices of leaf blocks: returns [slices, nblk, bs*bs].
 
     line = "row" (left operand: one exponent per leaf row) or "col" (right
-    operand: one per leaf column).  With m the largest finite magnitude of a
-    line and e the exponent with m < 2^e, every finite element x of the line
-    is cut into N = floor(|x| 2^(slices*bits - e)) < 2^(slices*bits) and
-    slice t (t = 1 .. slices) is sign(x) * digit_t(N) * 2^(e - t*bits), digit
-    t being bits [(slices-t)*bits, (slices-t+1)*bits) of N.  An Inf or NaN
-    element is its own first slice (the rest zero).
+    operand: one per leaf column).  With e the line's exponent
+    (ozaki_exponent of its largest finite magnitude), every finite element x
+    becomes M = sign(x) floor(|x| 2^(OZ_MANT - e)), |M| <= OZ_MAXM, written
+    from the lowest digit up as M = sum_t d_t 2^(OZ_BITS (OZ_SLICES - t)) with
+    d_t = ((M + 128) mod 256) - 128; slice t (t = 1 .. slices, the highest
+    digits) is d_t 2^(e + 1 - OZ_BITS t).  An Inf or NaN element is its own
+    first slice (the rest zero).
     """
     v = np.asarray(vals, dtype=np.float64).reshape(-1, bs, bs)   # [block, column, row]
     fin = np.isfinite(v)
     a = np.where(fin, np.abs(v), 0.0)
     m = a.max(axis=1, keepdims=True) if line == "row" else a.max(axis=2, keepdims=True)
-    _, e = np.frexp(m)                     # m = f 2^e with 0.5 <= f < 1, so m < 2^e (0 for m = 0)
-    total = slices * bits
-    n = np.floor(np.ldexp(a, total - e))   # exact: a 2^(total-e) < 2^total <= 2^53
-    sign = np.sign(v)
+    e = ozaki_exponent(m)
+    big = np.sign(v) * np.floor(np.ldexp(a, OZ_MANT - e))   # exact integers, |M| < 2^47
+    half = 2.0 ** (OZ_BITS - 1)
+    digits = np.zeros((OZ_SLICES,) + v.shape)
+    for t in range(OZ_SLICES, 0, -1):
+        d = np.mod(big + half, 2.0 ** OZ_BITS) - half
+        digits[t - 1] = d
+        big = (big - d) / 2.0 ** OZ_BITS
+    assert not np.any(big[fin]), "balanced digits do not cover an element"
     out = np.zeros((slices,) + v.shape)
     for t in range(1, slices + 1):
-        digit = np.mod(np.floor(np.ldexp(n, -(total - bits * t))), 2.0 ** bits)
-        out[t - 1] = np.where(fin, sign * np.ldexp(digit, e - bits * t), 0.0)
+        out[t - 1] = np.where(fin, np.ldexp(digits[t - 1], e + 1 - OZ_BITS * t), 0.0)
     out[0] = np.where(fin, out[0], v)
     return out.reshape(slices, -1, bs * bs)
 
 
-def ozaki_multiply(a: OMatrix, b: OMatrix, slices: int = OZ_SLICES, bits: int = OZ_BITS) -> OProduct:
-    """C = sum over t + u <= slices + 1 of A_t B_u, every slice product in FP64
-    through the plain multiply (the slice products are exact; only their
-    accumulation rounds)."""
-    sa = ozaki_split(a.vals, a.bs, "row", slices, bits)
-    sb = ozaki_split(b.vals, b.bs, "col", slices, bits)
+def ozaki_multiply(a: OMatrix, b: OMatrix, slices: int = OZ_SLICES) -> OProduct:
+    """C = sum over t + u <= slices + 1 of A_t B_u (the first `slices`
+    slices of each operand), every slice product in FP64 through the plain
+    multiply (the slice products are exact; only their accumulation rounds)."""
+    sa = ozaki_split(a.vals, a.bs, "row", slices)
+    sb = ozaki_split(b.vals, b.bs, "col", slices)
     total = None
     for t in range(1, slices + 1):
         for u in range(1, slices + 2 - t):

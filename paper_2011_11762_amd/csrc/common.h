@@ -117,11 +117,14 @@ void bitmap_rank(const uint32_t *keys, const uint8_t *active, int64_t n, uint64_
 // ----------------------------------------------------------------- handles
 enum Storage { ST_NONE = 0, ST_F64 = 1, ST_F32 = 2 };
 
-// Ozaki mode: OZ_SLICES signed digits of OZ_BITS bits per element (each an
-// 8-bit integer); a packed leaf holds the slices [slice][chunk][line][bytes]
-// followed by one int32 exponent per line.  OZ_NONFINITE marks a line that
-// holds an Inf or NaN.
-constexpr int OZ_SLICES = 7, OZ_BITS = 7;
+// Ozaki mode: each element is truncated to an integer M of OZ_MANT bits on
+// its line's exponent grid and stored as OZ_SLICES balanced digits of OZ_BITS
+// bits (each in [-128, 127], an 8-bit integer); a packed leaf holds the
+// slices [slice][chunk][line][bytes] followed by one int32 exponent per
+// line.  OZ_MAXM is the largest M the digits reach.  OZ_NONFINITE marks a
+// line that holds an Inf or NaN.
+constexpr int OZ_SLICES = 6, OZ_BITS = 8, OZ_MANT = 47;
+constexpr int64_t OZ_MAXM = 127 * (((int64_t)1 << (OZ_SLICES * OZ_BITS)) - 1) / ((1 << OZ_BITS) - 1);
 constexpr int32_t OZ_NONFINITE = 0x10000000;  // twice it still fits an int32
 __host__ __device__ constexpr int64_t oz_leaf_bytes(int bs) {
     return (int64_t)OZ_SLICES * bs * bs + 4 * (int64_t)bs;

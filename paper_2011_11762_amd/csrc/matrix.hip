@@ -415,13 +415,23 @@ __global__ void __launch_bounds__(256) k_pack2(const Src *src, int32_t bk, uint8
 }
 
 // Ozaki splitting on 8-bit integers (Ozaki, Ogita, Oishi and Rump 2012):
-// every element of a packed line is cut into OZ_SLICES signed digits of
-// OZ_BITS bits on the exponent grid of that line; the line exponents are
-// stored after the slices of each leaf (OZ_* in common.h).
+// every element of a packed line is truncated to an integer on the exponent
+// grid of that line and written as OZ_SLICES balanced digits of OZ_BITS bits;
+// the line exponents are stored after the slices of each leaf (OZ_* in
+// common.h).
 
-// Exponent e of every packed line (a row of a leaf for the left operand):
-// the largest magnitude m of the line satisfies m < 2^e (e = 0 for an
-// all-zero line); a line holding an Inf or NaN gets OZ_NONFINITE.
+// The exponent of a line with largest finite magnitude m: e with
+// m = f 2^e, 0.5 <= f < 1 (0 for m = 0), one more where floor(m 2^(OZ_MANT - e))
+// exceeds OZ_MAXM, so that every element's integer has a digit expansion.
+__device__ __forceinline__ int oz_line_exponent(double m) {
+    int e = 0;
+    if (m > 0.0) (void)frexp(m, &e);
+    if (m > 0.0 && floor(ldexp(m, OZ_MANT - e)) > (double)OZ_MAXM) ++e;
+    return e;
+}
+
+// Exponent e of every packed line (a row of a leaf for the left operand);
+// a line holding an Inf or NaN gets OZ_NONFINITE.
 template <class Src>
 __global__ void __launch_bounds__(256) k_oz_exp_row(const Src *src, int64_t nblk, int32_t bs, uint8_t *dst,
                                                     int32_t *nonfinite) {
@@ -437,9 +447,7 @@ __global__ void __launch_bounds__(256) k_oz_exp_row(const Src *src, int64_t nblk
         bad |= !isfinite(v);
         m = v > m ? v : m;
     }
-    int e = 0;
-    if (m > 0.0) (void)frexp(m, &e);
-    oz_exponents(dst, leaf, bs)[l] = bad ? OZ_NONFINITE : e;
+    oz_exponents(dst, leaf, bs)[l] = bad ? OZ_NONFINITE : oz_line_exponent(m);
     if (bad) *nonfinite = 1;
 }
 
@@ -467,20 +475,18 @@ __global__ void __launch_bounds__(256) k_oz_exp_col(const Src *src, int64_t nblk
         bad |= __shfl_xor(bad, o, 64);
     }
     if (r == 0) {
-        int e = 0;
-        if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
-        oz_exponents(dst, leaf, bs)[c] = bad ? OZ_NONFINITE : e;
+        oz_exponents(dst, leaf, bs)[c] = bad ? OZ_NONFINITE : oz_line_exponent(m);
         if (bad) *nonfinite = 1;
     }
 }
 
 // One 16-byte piece (16 elements) of one packed line, all slices: element x
-// of a line with exponent e becomes N = floor(|x| 2^(B - e)) < 2^B, with
-// B = OZ_SLICES * OZ_BITS, and slice t = 1..OZ_SLICES holds the signed digit
-// sign(x) * bits [B - t OZ_BITS, B - (t - 1) OZ_BITS) of N, so that
-// x = sum_t digit_t 2^(e - t OZ_BITS) + (less than 2^(e - B)).  A line with
-// an Inf or NaN gets zero digits (its products are set to NaN from its
-// exponent).
+// of a line with exponent e becomes M = sign(x) floor(|x| 2^(OZ_MANT - e)),
+// |M| <= OZ_MAXM, whose balanced digits are taken from the lowest up:
+// d = ((M + 128) mod 256) - 128, M = (M - d) / 256; slice t = 1..OZ_SLICES
+// holds the t-th highest digit, so that x = sum_t d_t 2^(e + 1 - 8t) + (less
+// than 2^(e - OZ_MANT) in magnitude, toward zero).  A line with an Inf or NaN
+// gets zero digits (its products are set to NaN from its exponent).
 template <class Src>
 __global__ void __launch_bounds__(256) k_pack_oz(const Src *src, int64_t nblk, int32_t bs, int32_t bk, int role,
                                                  uint8_t *dst) {
@@ -513,12 +519,13 @@ __global__ void __launch_bounds__(256) k_pack_oz(const Src *src, int64_t nblk, i
 #pragma unroll
         for (int k = 0; k < EPP; ++k) {
             const double v = role == ROLE_COL ? (double)x[(k0 + k) + l * bs] : (double)x[l + (k0 + k) * bs];
-            const uint64_t n = (uint64_t)floor(ldexp(fabs(v), OZ_SLICES * OZ_BITS - e));
+            const int64_t n = (int64_t)floor(ldexp(fabs(v), OZ_MANT - e));
+            int64_t big = v < 0.0 ? -n : n;
 #pragma unroll
-            for (int q = 0; q < OZ_SLICES; ++q) {
-                const int d = (int)((n >> (OZ_BITS * (OZ_SLICES - 1 - q))) & ((1u << OZ_BITS) - 1u));
-                const uint32_t b = (uint32_t)(uint8_t)(int8_t)(v < 0.0 ? -d : d);
-                w[q][k >> 2] |= b << (8 * (k & 3));
+            for (int q = OZ_SLICES - 1; q >= 0; --q) {
+                const int64_t d = ((big + 128) & 255) - 128;  // two's complement: the floor modulus
+                big = (big - d) >> 8;                         // exact: big - d is a multiple of 256
+                w[q][k >> 2] |= (uint32_t)(uint8_t)(int8_t)d << (8 * (k & 3));
             }
         }
     }

@@ -124,16 +124,17 @@ struct MT<QBSM_BF16X3> {
 // then hold zeros, so the products of a nil leaf add exact zeros.
 __device__ __attribute__((aligned(1024))) uint8_t g_zero_page[1024] = {};
 
-// Ozaki slices: OZ_SLICES = 7 signed 7-bit digits per element, as 8-bit
-// integers.  The products of digit pairs (t, u) of one pair group g = t + u
-// (2..8; the pairs with t + u > 8 are dropped) lie on one exponent grid
-// 2^(e_row + e_col - 7g) per leaf, and over one 64-wide leaf each group's
-// integer MFMA sum S_g is exact (|S_g| <= 7 * 64 * 127^2 < 2^23).  Groups
-// share four int32 accumulators: P1 = S_2 2^7 + S_3, P2 = S_4 2^7 + S_5,
-// P3 = S_6 2^7 + S_7 (each below 2^31: the accumulator is shifted by 7 bits
-// between its two groups) and P4 = S_8.  At the end of every leaf the four
-// are converted to FP64, scaled by 2^(e_row + e_col) and added to the FP64
-// accumulator, so the whole FP64 exponent range is covered.
+// Ozaki slices: OZ_SLICES = 6 balanced 8-bit digits per element (each in
+// [-128, 127]), digit t on the grid 2^(e + 1 - 8t) of its line's exponent e.
+// The products of digit pairs (t, u) of one pair group g = t + u (2..7; the
+// pairs with t + u > 7 are dropped) lie on one grid 2^(e_row + e_col + 2 - 8g)
+// per leaf, and over one 64-wide leaf each group's integer MFMA sum S_g is
+// exact (|S_g| <= 6 * 64 * 128^2 < 2^23).  The six groups share three int32
+// accumulators: P1 = S_2 2^8 + S_3, P2 = S_4 2^8 + S_5, P3 = S_6 2^8 + S_7
+// (|P3| <= 5 2^28 + 6 2^20 < 2^31: the accumulator is shifted by 8 bits
+// between its two groups).  At the end of every leaf the three are converted
+// to FP64, scaled by 2^(e_row + e_col) and added to the FP64 accumulator, so
+// the whole FP64 exponent range is covered.
 typedef __attribute__((ext_vector_type(4))) int i4;
 
 template <>
@@ -143,8 +144,8 @@ struct MT<QBSM_OZAKI_I8> {
     using Out = double;
     static constexpr int BK = 64, PARTS = OZ_SLICES, LBMAX = 64, KPG = 64, PPG = 4, SUBS = 1;
     static constexpr bool LEAF_SUMS = true;
-    static constexpr int NSUMS = 4;
-    static_assert(OZ_SLICES == 7 && OZ_BITS == 7, "the accumulators below combine seven 7-bit pair groups");
+    static constexpr int NSUMS = 3;
+    static_assert(OZ_SLICES == 6 && OZ_BITS == 8, "the accumulators below combine six 8-bit pair groups");
     struct Part { i4 s[NSUMS]; };
     struct Frag { uint4 q[1]; };
     __device__ static i4 mm(const Frag *a, const Frag *b, int ta, int tb, i4 c) {
@@ -160,12 +161,11 @@ struct MT<QBSM_OZAKI_I8> {
     }
     __device__ static void mma_part(Part &p, const Frag *a, const Frag *b) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < NSUMS; ++k) {
             p.s[k] = group(a, b, 2 * k + 2, p.s[k]);
-            p.s[k] = p.s[k] * 128;  // S_g 2^7, below 2^30
+            p.s[k] = p.s[k] * 256;  // S_g 2^8, below 2^31
             p.s[k] = group(a, b, 2 * k + 3, p.s[k]);
         }
-        p.s[3] = group(a, b, 8, p.s[3]);
     }
     // The same for NT tiles of one column tile at once, their MFMAs
     // interleaved tile by tile: consecutive MFMAs on one accumulator are NT
@@ -174,13 +174,13 @@ struct MT<QBSM_OZAKI_I8> {
     template <int NT>
     __device__ static void mma_parts(Part (&p)[NT], const Frag (&a)[NT][OZ_SLICES], const Frag *b) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < NSUMS; ++k) {
 #pragma unroll
-            for (int h = 0; h < (k < 3 ? 2 : 1); ++h) {
-                const int g = k < 3 ? 2 * k + 2 + h : 8;
+            for (int h = 0; h < 2; ++h) {
+                const int g = 2 * k + 2 + h;
                 if (h == 1) {
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) p[t].s[k] = p[t].s[k] * 128;  // S_g 2^7, below 2^30
+                    for (int t = 0; t < NT; ++t) p[t].s[k] = p[t].s[k] * 256;  // S_g 2^8, below 2^31
                 }
 #pragma unroll
                 for (int ta = 1; ta < g; ++ta)
@@ -191,17 +191,16 @@ struct MT<QBSM_OZAKI_I8> {
             }
         }
     }
-    // c += 2^(er + ec) * (P1 2^-21 + P2 2^-35 + P3 2^-49 + P4 2^-56), element i
-    // of a lane being row 4*(lane/16) + i (exponent er[i]) and column
-    // lane % 16 (exponent ec).  NF: the operands hold non-finite lines,
-    // whose products become NaN.
+    // c += 2^(er + ec - 22) (P1 + P2 2^-16 + P3 2^-32), element i of a lane
+    // being row 4*(lane/16) + i (exponent er[i]) and column lane % 16
+    // (exponent ec).  NF: the operands hold non-finite lines, whose products
+    // become NaN.
     template <bool NF>
     __device__ static void flush(Acc &c, Part &p, const i4 &er, int ec) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const double x = fma((double)p.s[3][i], 0x1p-35,
-                                 fma((double)p.s[2][i], 0x1p-28, fma((double)p.s[1][i], 0x1p-14, (double)p.s[0][i])));
-            const double v = c[i] + ldexp(x, er[i] + ec - 21);
+            const double x = fma((double)p.s[2][i], 0x1p-32, fma((double)p.s[1][i], 0x1p-16, (double)p.s[0][i]));
+            const double v = c[i] + ldexp(x, er[i] + ec - 22);
             if constexpr (NF)
                 c[i] = (er[i] == OZ_NONFINITE || ec == OZ_NONFINITE) ? __builtin_nan("") : v;
             else
@@ -903,8 +902,8 @@ __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
 
 #ifdef QB_K5_OZAKI_UNIT
 // The Ozaki mode at unit 128: 2 x 2 leaves of 64, four waves of one 64 x 64
-// output leaf each.  One step (the seven slices of two A leaves and two B
-// leaves, 112 KB) leaves no LDS for a second stage, so the step's fragments
+// output leaf each.  One step (the six slices of two A leaves and two B
+// leaves, 96 KB) leaves no LDS for a second stage, so the step's fragments
 // are double-buffered in registers instead: every wave reads all of its
 // fragments of the step (column tile 0 first), multiplies column tile 0,
 // and once every wave's reads are complete (a barrier) the next step's copy

@@ -25,17 +25,20 @@ products exact or rounded once):
 * BF16X3: 3 n u32 + 4 * 2^-16 + u32: a = hi + lo + d with |d| <= 2^-16 |a|;
           the three kept terms hi hi + hi lo + lo hi miss lo lo and the d
           terms (below 3.1 * 2^-16 |a||b|), and 3 n products are summed in FP32.
-* OZAKI:  n u64 + (14 bs + 4) 2^-48: an element a of a line with maximum m
-          (2^(e-1) <= m < 2^e) is cut to the 49 bits below e, a = sum of
-          seven slices + d with |d| < 2^(e-49) <= 2^-48 m, each slice a
-          digit of at most 127 on the grid 2^(e-7t); the kept pairs
-          t + u <= 8 are summed exactly in integers, the dropped pairs
-          (t + u = 9..14, 21 of them) add below 127^2 (6 2^-63 + 5 2^-70 + ...)
-          2^(e+f) <= 11.9 2^-48 m m' per element product, the truncations
-          2 2^-48 m m'; over bs terms and with m <= ||A_IK row||,
-          m' <= ||B_KJ column|| this is below 14 bs 2^-48 ||A_IK||_F ||B_KJ||_F
-          per leaf product, plus a few FP64 roundings of the per-leaf
-          conversion (the 4) and the FP64 accumulation.
+* OZAKI:  n u64 + (29 bs + 4) 2^-48: an element a of a line with maximum m
+          gets the line exponent e with 2^e < 2.01 m (the frexp exponent, or
+          one more for a maximum within 0.4 % below a power of two); a is cut
+          to M = floor(|a| 2^(47-e)) on the grid 2^(e-47), a = sum of six
+          slices + d with |d| < 2^(e-47) < 4.02 2^-48 m, slice t a balanced
+          digit of at most 128 on the grid 2^(e+1-8t); the kept pairs
+          t + u <= 7 are summed exactly in integers, the dropped pairs
+          (t + u = 8..12, 15 of them) add below 128^2 2^(e+f+2)
+          (5 2^-64 + 4 2^-72 + ...) <= 20.3 2^-48 m m' per element product,
+          the truncations 8.04 2^-48 m m'; over bs terms and with
+          m <= ||A_IK row||, m' <= ||B_KJ column|| this is below
+          29 bs 2^-48 ||A_IK||_F ||B_KJ||_F per leaf product, plus a few FP64
+          roundings of the per-leaf conversion (the 4) and the FP64
+          accumulation.
 """
 from __future__ import annotations
 
@@ -57,7 +60,7 @@ def rel_bound(mode: str, nprod, bs: int):
     if mode == "bf16x3":
         return 3 * n * U32 + 4 * 2.0 ** -16 + U32
     if mode == "ozaki":
-        return n * U64 + (14 * bs + 4) * 2.0 ** -48
+        return n * U64 + (29 * bs + 4) * 2.0 ** -48
     raise ValueError(mode)
 
 

@@ -385,36 +385,61 @@ def test_multiply_blocks_matches_full():
     assert np.array_equal(got, C.vals[pick])
 
 
+def _balanced_digits(m_int: int, n: int, bits: int):
+    """Digits d_1 .. d_n (highest first) of the integer m_int in balanced base
+    2^bits, each in [-2^(bits-1), 2^(bits-1)), by plain integer arithmetic;
+    None if n digits do not reach m_int."""
+    half, base = 1 << (bits - 1), 1 << bits
+    out = []
+    for _ in range(n):
+        d = (m_int + half) % base - half
+        out.append(d)
+        m_int = (m_int - d) // base
+    return None if m_int else out[::-1]
+
+
 def test_ozaki_split_exact_slices_and_reconstruction():
-    """Slices are signed 7-bit digits (8-bit integers) on the line's exponent
-    grid, and their sum is the element truncated to 49 bits below the line
-    exponent."""
+    """Slices are 8-bit integers (balanced digits in [-128, 127]) on the
+    grid 2^(e + 1 - 8 t) of the line's exponent, they are the balanced base-256
+    digits of the element truncated to 47 bits below the line exponent (checked
+    against Python integer arithmetic element by element), and a line whose
+    maximum lies within 0.4 % below a power of two takes the next exponent."""
     rng = np.random.default_rng(5)
     bs = 16
     vals = rng.standard_normal((7, bs * bs)) * np.exp(rng.uniform(-20, 20, (7, 1)))
     vals[2, :] = 0.0                        # an all-zero block
     vals[3, 5] = 2.0 ** 10                  # an exact power of two as a line maximum
     vals[4, 0:bs] *= -1.0
+    vals[5, 3] = (2.0 ** 47 - 5) * 2.0 ** -40          # just below 2^7: its line is raised
+    vals[6, 7 * bs + 2] = -(2.0 ** 47 - 5) * 2.0 ** -60
+    assert O.OZ_SLICES * O.OZ_BITS == 48 and O.OZ_MANT == 47 and O.OZ_MAXM == 127 * (2 ** 48 - 1) // 255
     for line in ("row", "col"):
         sl = O.ozaki_split(vals, bs, line)
         assert sl.shape == (O.OZ_SLICES, 7, bs * bs)
-        assert O.OZ_SLICES * O.OZ_BITS == 49 and 2 ** O.OZ_BITS - 1 <= 127  # 49 bits, int8 digits
         v = vals.reshape(-1, bs, bs)
         m = np.abs(v).max(axis=1 if line == "row" else 2, keepdims=True)
-        _, e = np.frexp(m)
+        _, e0 = np.frexp(m)
+        e = O.ozaki_exponent(m)
+        assert np.all((e == e0) | (e == e0 + 1))
+        raised = e != e0
+        assert np.all(m[raised] >= 0.996 * np.ldexp(1.0, e0[raised])) and raised.any()
         e = np.broadcast_to(e, v.shape).reshape(-1, bs * bs)
-        for t in range(1, O.OZ_SLICES + 1):
-            q = np.ldexp(sl[t - 1], -(e - O.OZ_BITS * t))        # digit times sign
-            assert np.array_equal(q, np.rint(q)) and np.all(np.abs(q) < 2 ** O.OZ_BITS)
-            assert np.all(np.sign(sl[t - 1]) * np.sign(vals) >= 0)
+        q = np.stack([np.ldexp(sl[t - 1], -(e + 1 - O.OZ_BITS * t)) for t in range(1, O.OZ_SLICES + 1)])
+        assert np.array_equal(q, np.rint(q)) and q.min() >= -128 and q.max() <= 127
+        # element by element against integer arithmetic
+        for blk, idx in [(0, 0), (0, 17), (1, 100), (3, 5), (4, 3), (5, 3), (6, 7 * bs + 2), (6, 200)]:
+            x = vals[blk, idx]
+            mint = int(np.sign(x)) * int(np.floor(np.ldexp(abs(x), O.OZ_MANT - int(e[blk, idx]))))
+            want = _balanced_digits(mint, O.OZ_SLICES, O.OZ_BITS)
+            assert want is not None and [int(d) for d in q[:, blk, idx]] == want
         rec = sl.sum(axis=0)
         err = np.abs(vals - rec)
-        assert np.all(err < np.ldexp(1.0, e - O.OZ_SLICES * O.OZ_BITS))
+        assert np.all(err < np.ldexp(1.0, e - O.OZ_MANT))
         assert np.all(np.abs(rec) <= np.abs(vals))           # truncation toward zero
         assert np.all(sl[:, 2] == 0)
-    # values with at most 49 bits below the line exponent split exactly
-    ints = rng.integers(-(2 ** 48), 2 ** 48, (3, bs * bs)).astype(np.float64)
-    ints[:, 0] = 2.0 ** 48 - 1                                # line maxima just below 2^48
+    # values with at most 46 bits below the line exponent split exactly
+    ints = rng.integers(-(2 ** 46), 2 ** 46, (3, bs * bs)).astype(np.float64)
+    ints[:, 0] = 2.0 ** 46 - 1                                # line maxima just below 2^46
     x = np.ldexp(ints, -30)
     for line in ("row", "col"):
         assert np.array_equal(O.ozaki_split(x, bs, line).sum(axis=0), x)
@@ -433,24 +458,32 @@ def test_ozaki_split_nonfinite_and_sign():
 
 
 def test_ozaki_multiply_against_fp64():
-    """Slice products are exact, so inputs with at most 24 bits below their
-    line exponents (four 7-bit slices, all of whose pairs are kept) give the
-    FP64 product; general inputs differ from it by the 49-bit truncation and
+    """Slice products are exact, so inputs on the grid 2^(e - 22) of their
+    line exponents (their expansions end at the third digit, and every pair of
+    the first three slices is kept) give the FP64 product up to the FP64
+    accumulation; general inputs differ from it by the 47-bit truncation and
     the dropped pairs only."""
-    rng = np.random.default_rng(6)
     a, b = W.small_random(150, 130, 170, 32, 0.6, 7)
     oa, ob = O.from_workload(a), O.from_workload(b)
     ref = O.multiply(oa, ob)
     oz = O.ozaki_multiply(oa, ob)
     assert np.array_equal(oz.brow, ref.brow) and np.array_equal(oz.bcol, ref.bcol)
     assert O.rel_fro(oz.vals, ref.vals) < 1e-13
-    # 24-bit inputs (four slices each): every needed slice pair is present
-    a24 = O.OMatrix(oa.nrows, oa.ncols, oa.bs, oa.brow, oa.bcol, O.round_to_f32(oa.vals))
-    b24 = O.OMatrix(ob.nrows, ob.ncols, ob.bs, ob.brow, ob.bcol, O.round_to_f32(ob.vals))
-    r24, z24 = O.multiply(a24, b24), O.ozaki_multiply(a24, b24)
-    scale = np.abs(r24.vals).max()
-    assert np.max(np.abs(z24.vals - r24.vals)) <= 64 * 2.0 ** -52 * scale
-    # a dropped term is visible: with 2 slices of 7 bits the error is ~2^-13
+
+    def on_grid(m, line):
+        v = m.vals.reshape(-1, m.bs, m.bs)
+        mx = np.abs(v).max(axis=1 if line == "row" else 2, keepdims=True)
+        _, e0 = np.frexp(mx)
+        g = np.ldexp(np.rint(np.ldexp(v, 22 - e0)), e0 - 22)
+        return O.OMatrix(m.nrows, m.ncols, m.bs, m.brow, m.bcol, g.reshape(m.vals.shape))
+
+    ag, bg = on_grid(oa, "row"), on_grid(ob, "col")
+    for sl in (O.ozaki_split(ag.vals, ag.bs, "row"), O.ozaki_split(bg.vals, bg.bs, "col")):
+        assert not np.any(sl[3:])                            # three digits carry them
+    rg, zg = O.multiply(ag, bg), O.ozaki_multiply(ag, bg)
+    scale = np.abs(rg.vals).max()
+    assert np.max(np.abs(zg.vals - rg.vals)) <= 64 * 2.0 ** -52 * scale
+    # a dropped term is visible: with 2 slices of 8 bits the error is ~2^-15
     r2 = O.ozaki_multiply(oa, ob, slices=2)
     assert 1e-7 < O.rel_fro(r2.vals, ref.vals) < 1e-3
 
