@@ -91,7 +91,7 @@ typedef QBSM_ENUM(qbsm_status_e) {
  *               (t + u fixed) over one leaf sum exactly in 32-bit integers, are
  *               combined in FP64, scaled by 2^(e_row + e_col) (so the whole FP64
  *               exponent range is covered) and accumulated in FP64; FP64 result.
- *               Needs 64 x 64 leaves and a plan with unit 64 (see
+ *               Needs 64 x 64 leaves and a plan with unit 64 or 128 (see
  *               qbsm_plan_opts).  A line holding an Inf or NaN makes every
  *               element its leaf products reach NaN.
  * In every mode a product exists only where both leaf blocks are stored: an

@@ -142,7 +142,10 @@ __global__ void k_walk_fill(const int64_t *npp, WalkLevel w, const int32_t *Y, i
 // The small top levels of the walk in one workgroup: for each level, counts
 // into LDS, a workgroup scan, then the fill, with the level's count kept in
 // counts[l + 1] as the separate launches do.  Every level's input holds at
-// most kTopItems / 4 pairs.
+// most kTopItems / 4 pairs, so the pairs passed from one level to the next
+// stay in LDS (two alternating buffers); only the last level's pairs go to
+// device memory (out[n - 1]), and a level waits on no global read but its
+// tree lookups.
 constexpr int kTopThreads = 1024, kTopItems = 4096;
 struct TopLevels {
     int n;                    // levels processed: l0 .. l0 + n - 1
@@ -154,10 +157,25 @@ struct TopLevels {
 __global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t *counts) {
     __shared__ int32_t X[kTopItems + 1];
     __shared__ int32_t wsum[kTopThreads / 64];
+    constexpr int PMAX = kTopItems / 4;                  // pairs of a level's input
+    __shared__ int32_t pbuf[2][5][PMAX];                 // pl, pr, gs, gm, pm
+    __shared__ uint32_t kbuf[2][PMAX];                   // ck
     const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int IPT = kTopItems / kTopThreads;  // items per thread
     for (int i = 0; i < tl.n; ++i) {
-        const WalkLevel &w = tl.lv[i];
+        WalkLevel w = tl.lv[i];
+        if (i > 0) {  // the previous level's pairs, in LDS
+            const int b = (i - 1) & 1;
+            w.pl = pbuf[b][0]; w.pr = pbuf[b][1]; w.gs = pbuf[b][2]; w.gm = pbuf[b][3]; w.pm = pbuf[b][4];
+            w.ck = kbuf[b];
+        }
+        WalkOut o = tl.out[i];
+        int64_t ocap = tl.ocap[i];
+        if (i + 1 < tl.n) {
+            const int b = i & 1;
+            o = WalkOut{pbuf[b][0], pbuf[b][1], pbuf[b][2], pbuf[b][3], pbuf[b][4], kbuf[b]};
+            ocap = ocap < PMAX ? ocap : PMAX;
+        }
         const int64_t n4 = counts[i] * 4;  // this level's pairs (written by the previous round)
         // counts: thread tid owns items tid*IPT .. +IPT-1
 #pragma unroll
@@ -197,7 +215,7 @@ __global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t 
         __syncthreads();
         for (int k = 0; k < IPT; ++k) {
             const int t = tid * IPT + k;
-            if (t < n4) walk_fill_item(w, t, X, tl.ocap[i], tl.out[i]);
+            if (t < n4) walk_fill_item(w, t, X, ocap, o);
         }
         if (tid == 0) counts[i + 1] = tot;
         __syncthreads();  // the next level reads this level's output and count
