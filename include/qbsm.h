@@ -252,8 +252,8 @@ qbsm_status qbsm_matrix_extract_blocks(qbsm_matrix m, int64_t n, const int32_t *
  * 4-byte-accumulator modes (F32, BF16, BF16X3); its FP64 numeric phase
  * returns QBSM_ERR_UNSUPPORTED (a 256 x 256 FP64 accumulator exceeds the
  * register file of one compute unit).  QBSM_OZAKI_I8 runs on plans with
- * unit 64 only (its seven slices per operand fill the LDS) and returns
- * QBSM_ERR_UNSUPPORTED otherwise. */
+ * unit 64 or 128 and 64 x 64 leaves (its six slices per operand leave no
+ * LDS for a 256-wide unit) and returns QBSM_ERR_UNSUPPORTED otherwise. */
 typedef struct {
     int32_t unit;
     /* 1: only the output blocks with I <= J are formed (the symmetric square
@@ -447,7 +447,7 @@ qbsm_status qbsm_batch_autotune(int32_t n, const qbsm_matrix *L, const qbsm_matr
  * + numeric, `reps` timed repetitions after one warm-up) and reports the
  * fastest.  times_ms (host, may be NULL) receives 3 entries in the order
  * unit = 64, 128, 256 (negative when not applicable to the leaf size or the
- * mode; QBSM_OZAKI_I8 has unit 64 only). */
+ * mode; QBSM_OZAKI_I8 has units 64 and 128). */
 qbsm_status qbsm_autotune_unit(qbsm_matrix A, qbsm_matrix B, qbsm_mode mode, int32_t reps,
                                void *stream, int32_t *best_unit, double *times_ms);
 
