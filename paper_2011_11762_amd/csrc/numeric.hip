@@ -833,6 +833,13 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
     store_unit<MODE, U, BS>(m, u, acc, wr, wc);
 }
 
+// The unit of this workgroup in a single-multiply launch (XCD-aware).
+__device__ __forceinline__ int launch_unit(const K5Member &m) { return xcd_remap((int)blockIdx.x, m.nunits); }
+
+// Whether a member takes the branch-free unit-256 path (read from its
+// packs' device flags).
+__device__ __forceinline__ bool dense_ok(const K5Member &m) { return (*m.nfL | *m.nfR) == 0 && !m.select; }
+
 // Unit 256 takes the branch-free path when both packs are finite; the
 // smaller units (two workgroups per compute unit) keep the skipping path.
 template <int MODE, int U, int BS>
@@ -840,7 +847,7 @@ __device__ __forceinline__ void process_sel(const K5Member &m, int u, uint8_t *s
     if constexpr (U >= 256) {
         // the branch-free path multiplies every pair of stored leaves of a
         // step, so it serves only plans whose products are all such pairs
-        if ((*m.nfL | *m.nfR) == 0 && !m.select) {
+        if (dense_ok(m)) {
             process_unit<MODE, U, BS, true>(m, u, st0, st1, meta);
             return;
         }
@@ -876,15 +883,25 @@ constexpr int k5_min_blocks = (MODE == QBSM_F64 || MODE == QBSM_OZAKI_I8 || U >=
 // BS > 0: one launch of one multiply with that leaf size, one workgroup per
 // unit.  BS == 0: persistent launch over a work list of (member, unit) items
 // of members with any leaf size, pulled from a device counter.
-template <int MODE, int U, int BS>
+// PATH (unit 256, BS > 0): 1 = the branch-free path only, 2 = the
+// tile-skipping path only; each workgroup leaves at once when its path does
+// not apply, and the host launches both (or only 2 where the plan selects
+// products), so neither kernel carries the other path.  0 = both paths in one
+// kernel, chosen per unit.
+template <int MODE, int U, int BS, int PATH = 0>
 __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     k5(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
     __shared__ __attribute__((aligned(1024))) uint8_t st0[k5_stage_bytes<MODE, U>];
     __shared__ __attribute__((aligned(1024))) uint8_t st1[k5_stage_bytes<MODE, U>];
     __shared__ __attribute__((aligned(16))) uint8_t meta[k5_meta_bytes<U>];
-    if constexpr (BS != 0) {
-        const int u = xcd_remap((int)blockIdx.x, single.nunits);
-        process_sel<MODE, U, BS>(single, u, st0, st1, meta);
+    if constexpr (BS != 0 && PATH == 1) {
+        if (!dense_ok(single)) return;
+        process_unit<MODE, U, BS, true>(single, launch_unit(single), st0, st1, meta);
+    } else if constexpr (BS != 0 && PATH == 2) {
+        if (dense_ok(single)) return;
+        process_unit<MODE, U, BS, false>(single, launch_unit(single), st0, st1, meta);
+    } else if constexpr (BS != 0) {
+        process_sel<MODE, U, BS>(single, launch_unit(single), st0, st1, meta);
     } else {
         __shared__ int s_item;
         for (;;) {
@@ -1021,8 +1038,7 @@ __global__ void __launch_bounds__(256, 1)
     __shared__ __attribute__((aligned(1024))) uint8_t stage[Geo<QBSM_OZAKI_I8, 128, 64>::STAGEB];
     __shared__ __attribute__((aligned(16))) uint8_t meta[k5_meta_bytes<128>];
     if constexpr (BS != 0) {
-        const int u = xcd_remap((int)blockIdx.x, single.nunits);
-        oz128_sel(single, u, stage, meta);
+        oz128_sel(single, launch_unit(single), stage, meta);
     } else {
         __shared__ int s_item;
         for (;;) {
@@ -1053,14 +1069,28 @@ void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems
             return;
         }
     }
-    if (bs == 64) {
-        k5<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
-        return;
-    }
-    if constexpr (U >= 128) {
-        if (bs == 128) {
-            k5<MODE, U, 128><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+    if constexpr (U >= 256) {
+        // the two paths as two kernels (the plan's selection is known here;
+        // the packs' finiteness is read by each workgroup)
+        if (bs == 64 || bs == 128) {
+            if (!single.select) {
+                if (bs == 64) k5<MODE, U, 64, 1><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                else k5<MODE, U, 128, 1><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+            }
+            if (bs == 64) k5<MODE, U, 64, 2><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+            else k5<MODE, U, 128, 2><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
             return;
+        }
+    } else {
+        if (bs == 64) {
+            k5<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+            return;
+        }
+        if constexpr (U >= 128) {
+            if (bs == 128) {
+                k5<MODE, U, 128><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                return;
+            }
         }
     }
     throw Error(QBSM_ERR_UNSUPPORTED, "leaf size for this unit side");
@@ -1147,10 +1177,13 @@ int k5_occupancy(qbsm_mode mode, int unit, int bs) {
 #define QB_OCC_M(MD)                                                                               \
     QB_OCC(MD, 64, 0) QB_OCC(MD, 64, 32) QB_OCC(MD, 64, 64) QB_OCC(MD, 128, 0) QB_OCC(MD, 128, 32) \
     QB_OCC(MD, 128, 64) QB_OCC(MD, 128, 128)
-#define QB_OCC_256(MD) QB_OCC(MD, 256, 0) QB_OCC(MD, 256, 64) QB_OCC(MD, 256, 128)
+#define QB_OCC2(MD, UU, BB) \
+    if (mode == MD && unit == UU && bs == BB) fn = reinterpret_cast<const void *>(&k5<MD, UU, BB, 1>);
+#define QB_OCC_256(MD) QB_OCC(MD, 256, 0) QB_OCC2(MD, 256, 64) QB_OCC2(MD, 256, 128)
     QB_OCC_M(QBSM_F64) QB_OCC_M(QBSM_F32) QB_OCC_M(QBSM_BF16) QB_OCC_M(QBSM_BF16X3)
     QB_OCC_256(QBSM_F32) QB_OCC_256(QBSM_BF16) QB_OCC_256(QBSM_BF16X3)
 #undef QB_OCC_256
+#undef QB_OCC2
 #undef QB_OCC_M
 #undef QB_OCC
     if (mode == QBSM_OZAKI_I8) fn = k5_kernel_ozaki(unit, bs);
