@@ -45,21 +45,25 @@ KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # HBM bytes of one numeric-kernel launch on the default workload, per
 # "mode@unit", from two rocprofv3 --pmc passes (FETCH_SIZE, WRITE_SIZE in KiB
 # per dispatch), scaled by what the same counters read for a 1 GiB
-# device-to-device copy in the same runs (FETCH_SIZE x2.0, WRITE_SIZE x1.0).
+# device-to-device copy in the same runs (FETCH_SIZE x2.0, WRITE_SIZE x1.0);
+# at unit 256 the two kernels of one launch (branch-free and tile-skipping
+# paths) are summed.
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "bac98c7bb5542313",
+    "sources_sha256_16": "58c215d8e00d3b5b",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 121539910955,
-        "bf16x3@256": 50052018725,
-        "bf16x3@64": 330812222613,
-        "f32@128": 208178071189,
-        "f32@256": 68106300517,
-        "f32@64": 337558545301,
-        "f64@128": 285042906898,
-        "f64@64": 715585925632,
+        "bf16x3@128": 117781486891,
+        "bf16x3@256": 53227742491,
+        "bf16x3@64": 329439401685,
+        "f32@128": 204145957065,
+        "f32@256": 67991648384,
+        "f32@64": 338163386901,
+        "f64@128": 270714323237,
+        "f64@64": 711755487360,
+        "ozaki@128": 117525422592,
+        "ozaki@64": 534310602155,
     },
 }
 

@@ -55,7 +55,7 @@ def test_config2_decay_full(q):
     del gI, gJ, gK
     S, npr = O.block_bound_terms(oa, oa)
     for mode, unit in (("f64", 128), ("f32", 256), ("bf16x3", 256), ("bf16x3", 128), ("bf16", 256),
-                       ("ozaki", 64)):
+                       ("ozaki", 64), ("ozaki", 128)):
         Pm = P if unit == 128 else q.Plan(A, A, unit=unit)
         C = Pm.numeric(mode)
         cr, cc = pattern_np(C)
