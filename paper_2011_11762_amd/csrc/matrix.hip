@@ -480,6 +480,28 @@ __global__ void __launch_bounds__(256) k_oz_exp_col(const Src *src, int64_t nblk
     }
 }
 
+// The digits of 16 elements of one line with exponent e, written as one
+// 16-byte piece per slice at o + slice * n2 (zeros for a non-finite line).
+__device__ __forceinline__ void oz_store_piece(const double (&v)[16], int e, uint8_t *o, int64_t n2) {
+    uint32_t w[OZ_SLICES][4] = {};
+    if (e != OZ_NONFINITE) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int64_t n = (int64_t)floor(ldexp(fabs(v[k]), OZ_MANT - e));
+            int64_t big = v[k] < 0.0 ? -n : n;
+#pragma unroll
+            for (int q = OZ_SLICES - 1; q >= 0; --q) {
+                const int64_t d = ((big + 128) & 255) - 128;  // two's complement: the floor modulus
+                big = (big - d) >> 8;                         // exact: big - d is a multiple of 256
+                w[q][k >> 2] |= (uint32_t)(uint8_t)(int8_t)d << (8 * (k & 3));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < OZ_SLICES; ++q)
+        *reinterpret_cast<uint4 *>(o + q * n2) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
+}
+
 // One 16-byte piece (16 elements) of one packed line, all slices: element x
 // of a line with exponent e becomes M = sign(x) floor(|x| 2^(OZ_MANT - e)),
 // |M| <= OZ_MAXM, whose balanced digits are taken from the lowest up:
@@ -514,25 +536,67 @@ __global__ void __launch_bounds__(256) k_pack_oz(const Src *src, int64_t nblk, i
     const int64_t k0 = c * bk + piece * EPP;
     uint8_t *base = dst + leaf * oz_leaf_bytes(bs);
     const int e = oz_exponents(dst, leaf, bs)[l];
-    uint32_t w[OZ_SLICES][4] = {};
-    if (e != OZ_NONFINITE) {
+    double v[EPP];
 #pragma unroll
-        for (int k = 0; k < EPP; ++k) {
-            const double v = role == ROLE_COL ? (double)x[(k0 + k) + l * bs] : (double)x[l + (k0 + k) * bs];
-            const int64_t n = (int64_t)floor(ldexp(fabs(v), OZ_MANT - e));
-            int64_t big = v < 0.0 ? -n : n;
+    for (int k = 0; k < EPP; ++k) v[k] = role == ROLE_COL ? (double)x[(k0 + k) + l * bs] : (double)x[l + (k0 + k) * bs];
+    oz_store_piece(v, e, base + c * (int64_t)bs * LB + l * LB + ((piece ^ piece_swizzle((int)l, LB)) << 4), n2);
+}
+
+// Both roles of one matrix of 64 x 64 leaves in one pass (the left and the
+// right operand of A * A in the Ozaki mode): one workgroup per leaf reads the
+// leaf once into LDS, takes the row and the column maxima, and writes the
+// exponents and the digits of the row-line and the column-line packs.
+template <class Src>
+__global__ void __launch_bounds__(256) k_pack_oz2(const Src *src, uint8_t *dst_row, uint8_t *dst_col,
+                                                  int32_t *nf_row, int32_t *nf_col) {
+    constexpr int BS = 64, LB = 64, PPL = LB / 16;
+    constexpr int64_t n2 = (int64_t)BS * BS;
+    constexpr int ld = BS + 1;  // column stride in LDS (rows and columns both read without conflicts)
+    __shared__ double x[ld * BS];
+    __shared__ int32_t ex[2][BS];  // row, column exponents
+    const int64_t leaf = blockIdx.x;
+    const int tid = (int)threadIdx.x;
+    using Src2 = typename std::conditional<std::is_same<Src, double>::value, double2, float2>::type;
+    const Src2 *g = reinterpret_cast<const Src2 *>(src + leaf * n2);
+    Src2 t[n2 / 512];
 #pragma unroll
-            for (int q = OZ_SLICES - 1; q >= 0; --q) {
-                const int64_t d = ((big + 128) & 255) - 128;  // two's complement: the floor modulus
-                big = (big - d) >> 8;                         // exact: big - d is a multiple of 256
-                w[q][k >> 2] |= (uint32_t)(uint8_t)(int8_t)d << (8 * (k & 3));
-            }
-        }
+    for (int q = 0; q < n2 / 512; ++q) t[q] = g[tid + 256 * q];
+#pragma unroll
+    for (int q = 0; q < n2 / 512; ++q) {
+        const int i = 2 * (tid + 256 * q);
+        x[(i % BS) + (i / BS) * ld] = (double)t[q].x;
+        x[(i % BS) + 1 + (i / BS) * ld] = (double)t[q].y;
     }
-    uint8_t *o = base + c * (int64_t)bs * LB + l * LB + ((piece ^ piece_swizzle((int)l, LB)) << 4);
+    __syncthreads();
+    // threads 0..63: row tid; 64..127: column tid - 64
+    if (tid < 2 * BS) {
+        const bool col = tid >= BS;
+        const int l = col ? tid - BS : tid;
+        double m = 0.0;
+        bool bad = false;
+        for (int k = 0; k < BS; ++k) {
+            const double v = fabs(col ? x[k + l * ld] : x[l + k * ld]);
+            bad |= !isfinite(v);
+            m = isfinite(v) && v > m ? v : m;
+        }
+        const int e = bad ? OZ_NONFINITE : oz_line_exponent(m);
+        ex[col ? 1 : 0][l] = e;
+        oz_exponents(col ? dst_col : dst_row, leaf, BS)[l] = e;
+        if (bad) *(col ? nf_col : nf_row) = 1;
+    }
+    __syncthreads();
+    // 2 roles x 64 lines x 4 pieces of 16 elements, two per thread
+    for (int r = tid; r < 2 * BS * PPL; r += 256) {
+        const bool col = r >= BS * PPL;
+        const int rem = col ? r - BS * PPL : r;
+        const int piece = rem % PPL, l = rem / PPL;
+        const int k0 = piece * 16;
+        double v[16];
 #pragma unroll
-    for (int q = 0; q < OZ_SLICES; ++q)
-        *reinterpret_cast<uint4 *>(o + q * n2) = make_uint4(w[q][0], w[q][1], w[q][2], w[q][3]);
+        for (int k = 0; k < 16; ++k) v[k] = col ? x[(k0 + k) + l * ld] : x[l + (k0 + k) * ld];
+        uint8_t *base = (col ? dst_col : dst_row) + leaf * oz_leaf_bytes(BS);
+        oz_store_piece(v, ex[col ? 1 : 0][l], base + l * LB + ((piece ^ piece_swizzle(l, LB)) << 4), n2);
+    }
 }
 
 size_t mode_elem_bytes(qbsm_mode mode) {
@@ -855,7 +919,10 @@ void pack2_launch(Matrix &m, qbsm_mode mode, Pack &pr, Pack &pc, hipStream_t ks)
             case QBSM_F32: QB_PACK2(double, m.v64.p, QBSM_F32); break;
             case QBSM_BF16: QB_PACK2(double, m.v64.p, QBSM_BF16); break;
             case QBSM_BF16X3: QB_PACK2(double, m.v64.p, QBSM_BF16X3); break;
-            default: break;  // Ozaki: one pack per role
+            case QBSM_OZAKI_I8:
+                k_pack_oz2<double><<<g, 256, 0, ks>>>(m.v64.p, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p);
+                break;
+            default: break;
         }
     } else {
         switch (mode) {
@@ -863,7 +930,10 @@ void pack2_launch(Matrix &m, qbsm_mode mode, Pack &pr, Pack &pc, hipStream_t ks)
             case QBSM_F32: QB_PACK2(float, m.v32.p, QBSM_F32); break;
             case QBSM_BF16: QB_PACK2(float, m.v32.p, QBSM_BF16); break;
             case QBSM_BF16X3: QB_PACK2(float, m.v32.p, QBSM_BF16X3); break;
-            default: break;  // Ozaki: one pack per role
+            case QBSM_OZAKI_I8:
+                k_pack_oz2<float><<<g, 256, 0, ks>>>(m.v32.p, pr.buf.p, pc.buf.p, pr.nonfinite.p, pc.nonfinite.p);
+                break;
+            default: break;
         }
     }
 #undef QB_PACK2
@@ -894,7 +964,7 @@ bool pack_stale(const Matrix &m, qbsm_mode mode, const Pack &pk) {
     return pk.buf.n != pack_bytes(m, mode) || pk.version != m.version || !pk.buf.p;
 }
 bool pair_ok(const Matrix &m, qbsm_mode mode) {
-    return (m.bs == 32 || m.bs == 64) && m.nblk > 0 && mode != QBSM_OZAKI_I8;
+    return (m.bs == 32 || m.bs == 64) && m.nblk > 0 && (mode != QBSM_OZAKI_I8 || m.bs == 64);
 }
 // Sizes the buffers of a stale pack (memory taken on s).
 void pack_size(const Matrix &m, qbsm_mode mode, Pack &pk, hipStream_t s) {

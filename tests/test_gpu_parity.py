@@ -527,6 +527,27 @@ def test_ozaki_against_oracle_split(q, case, unit):
     assert padding_is_zero(got, ref.brow, ref.bcol, m, n, bs)
 
 
+def test_ozaki_square_pack_pair_matches_single_packs(q):
+    """A * A packs both roles of A in one pass (one read per leaf, row and
+    column exponents together); a separate copy of A as the right operand
+    is packed role by role.  Both give the same digits, so the products are
+    bit-identical, also with an infinite entry (its row and column are
+    marked in the respective packs) and in FP32 storage."""
+    a, _ = W.small_random(900, 900, 900, 64, 0.5, 91)
+    a.vals[3, 77] = np.inf
+    for f32 in (False, True):
+        A, A2 = upload(q, a), upload(q, a)
+        if f32:
+            A.store_f32()
+            A2.store_f32()
+        for unit in (64, 128):
+            g_pair = values_np(q.Plan(A, A, unit=unit).numeric("ozaki"))
+            g_single = values_np(q.Plan(A, A2, unit=unit).numeric("ozaki"))
+            assert np.array_equal(np.isfinite(g_pair), np.isfinite(g_single))
+            fin = np.isfinite(g_pair)
+            assert np.array_equal(g_pair[fin], g_single[fin]), (f32, unit)
+
+
 def test_ozaki_units_agree(q):
     """Unit 64 and unit 128 add the same leaf products in the same order
     (K ascending, one flush per leaf product), so their results are equal."""
