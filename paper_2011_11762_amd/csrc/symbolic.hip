@@ -61,55 +61,67 @@ struct WalkOut {
     uint32_t *ck;
 };
 
-// Child pairs of item t (0..2), written to its slot of the count layout
-// 4 g + q m + (p - g) (g the first pair of p's group, m the group size), so
-// that the exclusive scan of the counts gives every child its position with
-// groups kept together, quadrants in order and pairs in order inside them.
-// A nL test keeps a leaf pair only when not nL[l] * nR[r] < tau.
-__device__ __forceinline__ void walk_count_item(const WalkLevel &w, int64_t t, int32_t *X) {
-    const int64_t p = t >> 2;
-    const int q = (int)(t & 3);
-    const int ib = q >> 1, jb = q & 1;
-    int cnt = 0;
-    if ((!w.chM || w.chM[(int64_t)w.pm[p] * 4 + q] >= 0) && !(w.upper && ib > jb && on_diagonal(w.ck[p]))) {
-        const int64_t a = (int64_t)w.pl[p] * 4, b = (int64_t)w.pr[p] * 4;
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb) {
-            const int32_t cl = w.chL[a + slot_of(ib, kb, w.transL)];
-            const int32_t cr = w.chR[b + slot_of(kb, jb, w.transR)];
-            cnt += (cl >= 0 && cr >= 0 && (!w.nL || !(w.nL[cl] * w.nR[cr] < w.tau))) ? 1 : 0;
-        }
-    }
-    const int64_t g = w.gs[p];
-    X[4 * g + (int64_t)q * w.gm[p] + (p - g)] = cnt;
+// The fields of one pair, read once per item (or once per pair in the
+// top-level kernel).
+struct PairRec {
+    int32_t pl, pr, gs, gm, pm;
+    uint32_t ck;
+};
+
+__device__ __forceinline__ PairRec pair_at(const WalkLevel &w, int64_t p) {
+    return PairRec{w.pl[p], w.pr[p], w.gs[p], w.gm[p], w.chM ? w.pm[p] : -1, w.ck[p]};
 }
 
-// Writes the child pairs of item t at their scanned positions Y.
-__device__ __forceinline__ void walk_fill_item(const WalkLevel &w, int64_t t, const int32_t *Y, int64_t ocap,
-                                               const WalkOut &o) {
-    const int64_t p = t >> 2;
-    const int q = (int)(t & 3);
+// The live child pairs of output quadrant q of pair r: bit kb of the result
+// is set when both children at contraction index kb exist (and pass the nL
+// test on the step into the leaves), with their nodes in cl[kb], cr[kb];
+// mchild is the mask tree's child (-1 without a mask).  A quadrant outside
+// the mask, or below the diagonal of a diagonal node under `upper`, has none.
+// A nL test keeps a leaf pair only when not nL[l] * nR[r] < tau.
+__device__ __forceinline__ int quadrant_children(const WalkLevel &w, const PairRec &r, int q, int32_t (&cl)[2],
+                                                 int32_t (&cr)[2], int32_t &mchild) {
     const int ib = q >> 1, jb = q & 1;
-    int32_t mchild = -1;
+    mchild = -1;
     if (w.chM) {
-        mchild = w.chM[(int64_t)w.pm[p] * 4 + q];
-        if (mchild < 0) return;
+        mchild = w.chM[(int64_t)r.pm * 4 + q];
+        if (mchild < 0) return 0;
     }
-    if (w.upper && ib > jb && on_diagonal(w.ck[p])) return;
-    const int64_t g = w.gs[p], m = w.gm[p];
-    const int64_t base = 4 * g + (int64_t)q * m;
-    int32_t pos = Y[base + (p - g)];
-    const int32_t ngs = Y[base];
-    const int32_t nge = Y[base + m];
-    const int64_t a = (int64_t)w.pl[p] * 4, b = (int64_t)w.pr[p] * 4;
-    const uint32_t key = w.ck[p] * 4u + (uint32_t)q;
+    if (w.upper && ib > jb && on_diagonal(r.ck)) return 0;
+    const int64_t a = (int64_t)r.pl * 4, b = (int64_t)r.pr * 4;
+    int live = 0;
 #pragma unroll
     for (int kb = 0; kb < 2; ++kb) {
-        const int32_t cl = w.chL[a + slot_of(ib, kb, w.transL)];
-        const int32_t cr = w.chR[b + slot_of(kb, jb, w.transR)];
-        if (cl >= 0 && cr >= 0 && (!w.nL || !(w.nL[cl] * w.nR[cr] < w.tau)) && pos < ocap) {  // pos < ocap always
-            o.pl[pos] = cl;
-            o.pr[pos] = cr;
+        cl[kb] = w.chL[a + slot_of(ib, kb, w.transL)];
+        cr[kb] = w.chR[b + slot_of(kb, jb, w.transR)];
+        if (cl[kb] >= 0 && cr[kb] >= 0 && (!w.nL || !(w.nL[cl[kb]] * w.nR[cr[kb]] < w.tau))) live |= 1 << kb;
+    }
+    return live;
+}
+
+// Slot of item (pair p, quadrant q) in the count layout 4 g + q m + (p - g)
+// (g the first pair of p's group, m the group size): the exclusive scan of
+// the counts gives every child its position with groups kept together,
+// quadrants in order and pairs in order inside them.
+__device__ __forceinline__ int64_t item_slot(const PairRec &r, int64_t p, int q) {
+    return 4 * (int64_t)r.gs + (int64_t)q * r.gm + (p - r.gs);
+}
+
+// Writes the live children of quadrant q of pair r from position pos on
+// (Y the scanned counts, for the children's group bounds).
+template <class Out>
+__device__ __forceinline__ void emit_children(const PairRec &r, int64_t p, int q, int live, const int32_t (&cl)[2],
+                                              const int32_t (&cr)[2], int32_t mchild, const int32_t *Y,
+                                              int64_t ocap, const Out &o) {
+    const int64_t base = 4 * (int64_t)r.gs + (int64_t)q * r.gm;
+    int32_t pos = Y[base + (p - r.gs)];
+    const int32_t ngs = Y[base];
+    const int32_t nge = Y[base + r.gm];
+    const uint32_t key = r.ck * 4u + (uint32_t)q;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+        if (((live >> kb) & 1) && pos < ocap) {  // pos < ocap always
+            o.pl[pos] = cl[kb];
+            o.pr[pos] = cr[kb];
             o.gs[pos] = ngs;
             o.gm[pos] = nge - ngs;
             o.pm[pos] = mchild;
@@ -117,6 +129,27 @@ __device__ __forceinline__ void walk_fill_item(const WalkLevel &w, int64_t t, co
             ++pos;
         }
     }
+}
+
+// Child pair count of item t = 4 p + q (0..2), written to its slot.
+__device__ __forceinline__ void walk_count_item(const WalkLevel &w, int64_t t, int32_t *X) {
+    const int64_t p = t >> 2;
+    const int q = (int)(t & 3);
+    const PairRec r = pair_at(w, p);
+    int32_t cl[2], cr[2], mchild;
+    const int live = quadrant_children(w, r, q, cl, cr, mchild);
+    X[item_slot(r, p, q)] = __popc(live);
+}
+
+// Writes the child pairs of item t at their scanned positions Y.
+__device__ __forceinline__ void walk_fill_item(const WalkLevel &w, int64_t t, const int32_t *Y, int64_t ocap,
+                                               const WalkOut &o) {
+    const int64_t p = t >> 2;
+    const int q = (int)(t & 3);
+    const PairRec r = pair_at(w, p);
+    int32_t cl[2], cr[2], mchild;
+    const int live = quadrant_children(w, r, q, cl, cr, mchild);
+    if (live) emit_children(r, p, q, live, cl, cr, mchild, Y, ocap, o);
 }
 
 // The pair count np of the level is read from device memory (the previous
@@ -142,11 +175,14 @@ __global__ void k_walk_fill(const int64_t *npp, WalkLevel w, const int32_t *Y, i
 // The small top levels of the walk in one workgroup: for each level, counts
 // into LDS, a workgroup scan, then the fill, with the level's count kept in
 // counts[l + 1] as the separate launches do.  Every level's input holds at
-// most kTopItems / 4 pairs, so the pairs passed from one level to the next
-// stay in LDS (two alternating buffers); only the last level's pairs go to
-// device memory (out[n - 1]), and a level waits on no global read but its
-// tree lookups.
-constexpr int kTopThreads = 1024, kTopItems = 4096;
+// most kTopPairs pairs, one per thread: a thread reads its pair and its
+// children's nodes once, before the level's first barrier, so the level's
+// output may overwrite its input in place (one LDS copy of the pairs); only
+// the last level's pairs go to device memory (out[n - 1]).  The LDS stays
+// near 20 KB so that the kernel finds room on a compute unit beside four
+// operand-packing workgroups (33 KB each), which the side stream runs at the
+// same time.
+constexpr int kTopPairs = 512, kTopThreads = kTopPairs, kTopItems = 4 * kTopPairs;
 struct TopLevels {
     int n;                    // levels processed: l0 .. l0 + n - 1
     WalkLevel lv[8];          // level inputs (the first one's pair arrays given; the rest filled here)
@@ -157,39 +193,41 @@ struct TopLevels {
 __global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t *counts) {
     __shared__ int32_t X[kTopItems + 1];
     __shared__ int32_t wsum[kTopThreads / 64];
-    constexpr int PMAX = kTopItems / 4;                  // pairs of a level's input
-    __shared__ int32_t pbuf[2][5][PMAX];                 // pl, pr, gs, gm, pm
-    __shared__ uint32_t kbuf[2][PMAX];                   // ck
+    __shared__ int32_t pbuf[5][kTopPairs];  // pl, pr, gs, gm, pm
+    __shared__ uint32_t kbuf[kTopPairs];    // ck
     const int tid = (int)threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    constexpr int IPT = kTopItems / kTopThreads;  // items per thread
+    const WalkOut lds{pbuf[0], pbuf[1], pbuf[2], pbuf[3], pbuf[4], kbuf};
     for (int i = 0; i < tl.n; ++i) {
         WalkLevel w = tl.lv[i];
         if (i > 0) {  // the previous level's pairs, in LDS
-            const int b = (i - 1) & 1;
-            w.pl = pbuf[b][0]; w.pr = pbuf[b][1]; w.gs = pbuf[b][2]; w.gm = pbuf[b][3]; w.pm = pbuf[b][4];
-            w.ck = kbuf[b];
+            w.pl = pbuf[0]; w.pr = pbuf[1]; w.gs = pbuf[2]; w.gm = pbuf[3]; w.pm = pbuf[4];
+            w.ck = kbuf;
         }
-        WalkOut o = tl.out[i];
-        int64_t ocap = tl.ocap[i];
-        if (i + 1 < tl.n) {
-            const int b = i & 1;
-            o = WalkOut{pbuf[b][0], pbuf[b][1], pbuf[b][2], pbuf[b][3], pbuf[b][4], kbuf[b]};
-            ocap = ocap < PMAX ? ocap : PMAX;
-        }
-        const int64_t n4 = counts[i] * 4;  // this level's pairs (written by the previous round)
-        // counts: thread tid owns items tid*IPT .. +IPT-1
+        const bool last = i + 1 == tl.n;
+        const WalkOut o = last ? tl.out[i] : lds;
+        const int64_t ocap = last ? tl.ocap[i] : (tl.ocap[i] < kTopPairs ? tl.ocap[i] : kTopPairs);
+        const int np = (int)counts[i];  // this level's pairs (written by the previous round)
+        const bool mine = tid < np;
+        PairRec r{};
+        int live[4] = {0, 0, 0, 0};
+        int32_t cl[4][2], cr[4][2], mch[4];
+        if (mine) {
+            r = pair_at(w, tid);
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            const int t = tid * IPT + k;
-            if (t < n4) walk_count_item(w, t, X);
-            else X[t] = 0;
+            for (int q = 0; q < 4; ++q) live[q] = quadrant_children(w, r, q, cl[q], cr[q], mch[q]);
+        }
+        // counts: the pair's four items go to their slots of [0, 4 np); the rest stay zero
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (mine) X[item_slot(r, tid, q)] = __popc(live[q]);
+            else X[4 * tid + q] = 0;
         }
         __syncthreads();
-        // exclusive scan of X[0 .. kTopItems)
-        int32_t v[IPT], s = 0;
+        // exclusive scan of X[0 .. kTopItems), four items per thread
+        int32_t v[4], s = 0;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            v[k] = X[tid * IPT + k];
+        for (int k = 0; k < 4; ++k) {
+            v[k] = X[tid * 4 + k];
             s += v[k];
         }
         int32_t x = s;
@@ -207,15 +245,16 @@ __global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t 
         }
         int32_t e = base + x - s;
 #pragma unroll
-        for (int k = 0; k < IPT; ++k) {
-            X[tid * IPT + k] = e;
+        for (int k = 0; k < 4; ++k) {
+            X[tid * 4 + k] = e;
             e += v[k];
         }
         if (tid == 0) X[kTopItems] = tot;
-        __syncthreads();
-        for (int k = 0; k < IPT; ++k) {
-            const int t = tid * IPT + k;
-            if (t < n4) walk_fill_item(w, t, X, ocap, o);
+        __syncthreads();  // every pair has been read: the output may overwrite it
+        if (mine) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (live[q]) emit_children(r, tid, q, live[q], cl[q], cr[q], mch[q], X, ocap, o);
         }
         if (tid == 0) counts[i + 1] = tot;
         __syncthreads();  // the next level reads this level's output and count
