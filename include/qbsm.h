@@ -271,7 +271,19 @@ typedef struct {
      * The norms are taken from the values current at the symbolic phase.
      * 0 = the regular multiply.  Ignored by qbsm_multiply_backward. */
     double spamm_tol;
-    int32_t reserved[4];
+    /* Schedule of the numeric phase (the order in which workgroups take the
+     * plan's units; results are the same bit for bit).  0 = automatic (one
+     * workgroup per unit, the faster of the two where they were measured).
+     * 1 = one workgroup per unit.  2 = streamed where the mode and unit
+     * allow it: resident workgroups each run every G-th unit, reading the
+     * next unit's metadata and issuing its first operand copies before
+     * storing the current unit's output (units 64 and 128, all modes but
+     * QBSM_OZAKI_I8; elsewhere one workgroup per unit).  Used by
+     * qbsm_multiply_numeric, qbsm_multiply_backward and (from the forward
+     * plan) qbsm_multiply_backward_plan; the batched and no-allocation entry
+     * points keep their own schedules.  QBSM_ERR_ARG for another value. */
+    int32_t schedule;
+    int32_t reserved[3];
 } qbsm_plan_opts;
 
 /* Symbolic phase of C = A * B (Sec. 2 and 2.1: the recursive multiply over

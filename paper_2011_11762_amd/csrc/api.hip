@@ -455,6 +455,8 @@ qbsm_status qbsm_multiply_symbolic_ex(qbsm_matrix L, int32_t trans_l, qbsm_matri
         QB_CHECK(tau >= 0.0 && std::isfinite(tau), QBSM_ERR_ARG, "spamm_tol must be finite and >= 0");
         const int upper = opts ? opts->upper : 0;
         QB_CHECK(upper == 0 || upper == 1, QBSM_ERR_ARG, "upper must be 0 or 1");
+        const int sched = opts ? opts->schedule : 0;
+        QB_CHECK(sched >= 0 && sched <= 2, QBSM_ERR_ARG, "schedule must be 0, 1 or 2");
         if (upper) {
             const int64_t rows = trans_l ? L->m.ncols : L->m.nrows, cols = trans_r ? R->m.nrows : R->m.ncols;
             QB_CHECK(rows == cols, QBSM_ERR_SHAPE, "the upper triangle needs a square product");
@@ -462,6 +464,7 @@ qbsm_status qbsm_multiply_symbolic_ex(qbsm_matrix L, int32_t trans_l, qbsm_matri
         }
         auto p = plan_build(&L->m, trans_l ? 1 : 0, &R->m, trans_r ? 1 : 0, mask ? &mask->m : nullptr, unit, tau,
                             upper, as_stream(stream));
+        p->sched = sched;
         if (nblk_out) *nblk_out = p->nout;
         if (nprod) *nprod = p->nprod;
         auto h = std::make_unique<qbsm_plan_>();
@@ -517,9 +520,12 @@ qbsm_status qbsm_multiply_backward(qbsm_matrix A, qbsm_matrix B, qbsm_matrix dC,
         QB_CHECK(dC->m.nrows == A->m.nrows && dC->m.ncols == B->m.ncols, QBSM_ERR_SHAPE,
                  "dC shape differs from A*B");
         const int unit = opts ? opts->unit : 0;
+        const int sched = opts ? opts->schedule : 0;
+        QB_CHECK(sched >= 0 && sched <= 2, QBSM_ERR_ARG, "schedule must be 0, 1 or 2");
         hipStream_t s = as_stream(stream);
         // one symbolic walk for the forward product list, regrouped for both adjoints
         auto f = plan_build(&A->m, 0, &B->m, 0, nullptr, unit, 0.0, 0, s);
+        f->sched = sched;
         backward_from(*f, dC->m, mode, dA ? &dA->m : nullptr, dB ? &dB->m : nullptr, s);
     });
 }

@@ -133,6 +133,7 @@ std::unique_ptr<Plan> plan_backward(const Plan &f, Matrix *dC, int which, hipStr
     static uint64_t next_id = 0;
     auto p = std::make_unique<Plan>();
     p->id = (uint64_t(1) << 62) | ++next_id;
+    p->sched = f.sched;  // the forward plan's numeric schedule
     if (which == 0) {
         p->L = dC; p->transL = 0; p->R = f.R; p->transR = 1;
     } else {

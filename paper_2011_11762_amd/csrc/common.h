@@ -192,6 +192,7 @@ struct Plan {
     int64_t nunits = 0, npairs = 0, nprod = 0, nout = 0, flops = 0;
     double spamm_tol = 0.0;  // > 0: leaf products selected by the norm-product test
     int upper = 0;           // 1: output blocks with I <= J only
+    int sched = 0;           // numeric schedule: 0 automatic, 1 one workgroup per unit, 2 streamed
     DArr<int32_t> ustart;   // [nunits + 1] pair range of each unit
     DArr<uint32_t> ukey;    // [nunits] Morton key of the unit node
     DArr<int32_t> umask;    // [nunits] mask-tree node of the unit (masked plans)
@@ -285,6 +286,9 @@ void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s)
 // Checks that a plan is still current and runs at unit p.unit in `mode`.
 void numeric_check(const Plan &p, qbsm_mode mode);
 void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s);
+// Grid of the streamed numeric schedule for this plan and mode (resident
+// workgroups, each running every G-th unit), or 0 for one workgroup per unit.
+int numeric_stream_grid(const Plan &p, qbsm_mode mode);
 
 // Kernel-side member description (also used by the batched launch).
 struct K5Member {

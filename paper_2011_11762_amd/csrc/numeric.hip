@@ -17,6 +17,11 @@
 // with lines of LB = 64 or 128 bytes whose 16-byte pieces are XOR-swizzled
 // by the line index, so the LDS copy is a contiguous 1 KB per instruction
 // and the MFMA fragment reads of 16 consecutive lines hit distinct banks.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "common.h"
 #include "device_math.h"
 
@@ -669,38 +674,53 @@ __device__ __forceinline__ void load_meta(const K5Member &m, const Meta &mt, int
     }
 }
 
+// Where a unit's output goes: its node coordinates and, for each leaf of
+// the wave's part, the output leaf index (-1: no output block there).
+template <int NLW>
+struct UnitOut {
+    uint32_t ui, uj;
+    int32_t leaves[NLW][NLW];
+};
+
+template <int MODE, int U, int BS>
+__device__ __forceinline__ UnitOut<Geo<MODE, U, BS>::NLW> unit_out_load(const K5Member &m, int u, int wr, int wc) {
+    using G = Geo<MODE, U, BS>;
+    constexpr int LPU = G::LPU, NSUB = G::NSUB, NLW = G::NLW;
+    UnitOut<NLW> o;
+    demorton(m.ukey[u], o.ui, o.uj);
+    const int ib0 = (G::WT * wr) / BS, jb0 = (G::WT * wc) / BS;
+#pragma unroll
+    for (int a = 0; a < NLW; ++a)
+#pragma unroll
+        for (int b = 0; b < NLW; ++b) o.leaves[a][b] = uni(m.cdesc[(int64_t)u * NSUB + (ib0 + a) * LPU + jb0 + b]);
+    return o;
+}
+
 // Writes a unit's owned output blocks once (padding beyond the logical size
 // = 0) from the wave's accumulators.
 template <int MODE, int U, int BS>
-__device__ __forceinline__ void store_unit(const K5Member &m, int u,
-                                           const typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
-                                           int wr, int wc) {
+__device__ __forceinline__ void store_unit_out(const K5Member &m, const UnitOut<Geo<MODE, U, BS>::NLW> &o,
+                                               const typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                               int wr, int wc) {
     using G = Geo<MODE, U, BS>;
     using M = MT<MODE>;
-    constexpr int LPU = G::LPU, NSUB = G::NSUB;
+    constexpr int LPU = G::LPU;
     const int tid = threadIdx.x;
-    // leaf by leaf: the wave's NLW x NLW leaves have their output indices
-    // looked up together, then each stored leaf writes its TPL x TPL tiles
+    // leaf by leaf: each stored leaf of the wave's NLW x NLW writes its
+    // TPL x TPL tiles
     const int lane = tid & 63;
-    uint32_t ui, uj;
-    demorton(m.ukey[u], ui, uj);
     typename M::Out *C = static_cast<typename M::Out *>(m.C);
     constexpr int64_t N2 = (int64_t)BS * BS;
     constexpr int NLW = G::NLW, TPL = G::TPL;
     const int ib0 = (G::WT * wr) / BS, jb0 = (G::WT * wc) / BS;
-    int32_t leaves[NLW][NLW];
-#pragma unroll
-    for (int a = 0; a < NLW; ++a)
-#pragma unroll
-        for (int b = 0; b < NLW; ++b) leaves[a][b] = uni(m.cdesc[(int64_t)u * NSUB + (ib0 + a) * LPU + jb0 + b]);
 #pragma unroll
     for (int a = 0; a < NLW; ++a)
 #pragma unroll
         for (int b = 0; b < NLW; ++b) {
-            const int32_t leaf = leaves[a][b];
+            const int32_t leaf = o.leaves[a][b];
             if (leaf < 0) continue;
             const int ib = ib0 + a, jb = jb0 + b;
-            const int64_t I = (int64_t)ui * LPU + ib, J = (int64_t)uj * LPU + jb;
+            const int64_t I = (int64_t)o.ui * LPU + ib, J = (int64_t)o.uj * LPU + jb;
             const bool interior = (I + 1) * BS <= m.out_rows && (J + 1) * BS <= m.out_cols;
             typename M::Out *Cl = C + (int64_t)leaf * N2;
 #pragma unroll
@@ -734,24 +754,111 @@ __device__ __forceinline__ void store_unit(const K5Member &m, int u,
         }
 }
 
-// DENSE: the branch-free path (every tile multiplied, nil leaves copied as
-// zeros), valid when neither pack holds Inf or NaN (an infinite value times
-// the zero of a nil partner would give NaN where no product exists).
-template <int MODE, int U, int BS, bool DENSE, bool NF = false>
-__device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
-    using G = Geo<MODE, U, BS>;
-    using M = MT<MODE>;
-    constexpr int LPU = G::LPU, NSUB = G::NSUB, TPW = G::TPW;
-    const int tid = threadIdx.x;
-    const int w = uni(tid >> 6);
-    const int wr = w / G::WPS, wc = w % G::WPS;
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void store_unit(const K5Member &m, int u,
+                                           const typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                           int wr, int wc) {
+    store_unit_out<MODE, U, BS>(m, unit_out_load<MODE, U, BS>(m, u, wr, wc), acc, wr, wc);
+}
 
-    typename M::Acc acc[TPW][TPW];
+// A batch of a unit's pairs whose metadata is in LDS and whose first copies
+// are in flight: its first step, the next step with its copy addresses, and
+// whether that next step's copy went out with the first (pre).
+struct BatchGo {
+    Step st;
+    Advance nxa;
+    int nb;
+    bool pre;
+};
+
+// Reads the metadata of pairs b0 .. min(b0 + CAP, p1) - 1 into LDS and
+// issues the copy of the batch's first step and, below unit 256, of its
+// second: a unit of two steps (one leaf product of two K chunks) waits for
+// one copy latency instead of two.  Only below unit 256: those units are
+// short on sparse inputs, while the 256-wide kernels run long units and have
+// no registers to spare for a third copy of the step body.
+template <int MODE, int U, int BS>
+__device__ __forceinline__ BatchGo batch_begin(const K5Member &m, const Meta &mt, int b0, int p1, const CopyLane &cl,
+                                               uint32_t chunk_bytes, int w, int wr, int wc, uint8_t *st0,
+                                               uint8_t *st1, OzExp<Geo<MODE, U, BS>::TPW> &ex) {
+    using G = Geo<MODE, U, BS>;
+    BatchGo g;
+    g.nb = uni((p1 - b0) < G::CAP ? (p1 - b0) : G::CAP);
+    __syncthreads();  // LDS (stages, metadata) of the previous batch or unit is free
+    load_meta<MODE, U, BS>(m, mt, b0, g.nb);
+    __syncthreads();
+    g.st = first_step<G::LPU, G::NSUB>(mt, g.nb, 0);
+    g.nxa.nx = g.st;
+    g.nxa.addrs = 0;
+    constexpr bool PRE2 = U <= 128;
+    g.pre = false;
+    if (g.st.i < g.nb) {
+        const uint64_t addrs = copy_addr<MODE, U, BS>(mt, g.st.i, g.st.kb, 0, cl, chunk_bytes);
+#pragma unroll
+        for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
+        oz_load_exp<MODE, U, BS>(mt, g.st.i, g.st.kb, wr, wc, ex);
+        g.nxa = advance<MODE, U, BS>(mt, g.nb, g.st, addrs, cl, chunk_bytes);
+        g.pre = PRE2 && g.nxa.nx.i < g.nb;
+        if (g.pre) {
+#pragma unroll
+            for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(g.nxa.addrs, k, st1, w);
+        }
+    }
+    return g;
+}
+
+// Runs the steps of a begun batch, from the wait for its first copy on.
+// WAIT_ALL: the first wait is for every outstanding memory operation (other
+// loads and stores were issued after the batch's copies).
+template <int MODE, int U, int BS, bool DENSE, bool NF, bool WAIT_ALL = false>
+__device__ __forceinline__ void batch_run(const K5Member &m, const Meta &mt, BatchGo &g, uint8_t *st0, uint8_t *st1,
+                                          typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                          typename MT<MODE>::Part (&part)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                          const CopyLane &cl, uint32_t chunk_bytes, int w, int wr, int wc,
+                                          OzExp<Geo<MODE, U, BS>::TPW> &ex) {
+    using G = Geo<MODE, U, BS>;
+    constexpr bool PRE2 = U <= 128;
+    const int nb = g.nb;
+    Step &st = g.st;
+    Advance &nxa = g.nxa;
+    if (g.pre && !WAIT_ALL)
+        __builtin_amdgcn_s_waitcnt(k5_vmcnt<G::PER_WAVE>);  // the first step's copies (and exponents)
+    else
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    // steps alternate between the two stages; unrolled by two so that
+    // every access names its stage array at compile time
+    if constexpr (PRE2) {
+        if (st.i < nb) {
+            if (g.pre)
+                run_step<MODE, U, BS, DENSE, NF, true>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w,
+                                                       wr, wc, ex);
+            else
+                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
+                                                 ex);
+        }
+        while (st.i < nb) {
+            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
+            if (st.i >= nb) break;
+            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
+        }
+    } else {
+        while (st.i < nb) {
+            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
+            if (st.i >= nb) break;
+            run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc, ex);
+        }
+    }
+}
+
+template <int MODE, int TPW>
+__device__ __forceinline__ void clear_acc(typename MT<MODE>::Acc (&acc)[TPW][TPW],
+                                          typename MT<MODE>::Part (&part)[TPW][TPW], OzExp<TPW> &ex) {
+    using M = MT<MODE>;
 #pragma unroll
     for (int a = 0; a < TPW; ++a)
 #pragma unroll
         for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
-    typename M::Part part[TPW][TPW];
     if constexpr (M::LEAF_SUMS) {
 #pragma unroll
         for (int a = 0; a < TPW; ++a)
@@ -760,7 +867,25 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
 #pragma unroll
                 for (int k = 0; k < M::NSUMS; ++k) part[a][b].s[k] = i4{0, 0, 0, 0};
     }
-    OzExp<TPW> ex{};
+    ex = OzExp<TPW>{};
+}
+
+// DENSE: the branch-free path (every tile multiplied, nil leaves copied as
+// zeros), valid when neither pack holds Inf or NaN (an infinite value times
+// the zero of a nil partner would give NaN where no product exists).
+template <int MODE, int U, int BS, bool DENSE, bool NF = false>
+__device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    constexpr int TPW = G::TPW;
+    const int tid = threadIdx.x;
+    const int w = uni(tid >> 6);
+    const int wr = w / G::WPS, wc = w % G::WPS;
+
+    typename M::Acc acc[TPW][TPW];
+    typename M::Part part[TPW][TPW];
+    OzExp<TPW> ex;
+    clear_acc<MODE, TPW>(acc, part, ex);
 
     // (loaded values are not known to be wave-uniform: say so, or every
     // comparison with the batch size makes the step iterator divergent)
@@ -769,68 +894,80 @@ __device__ void process_unit(const K5Member &m, int u, uint8_t *st0, uint8_t *st
     const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
     const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
     for (int b0 = p0; b0 < p1; b0 += G::CAP) {
-        const int nb = uni((p1 - b0) < G::CAP ? (p1 - b0) : G::CAP);
-        __syncthreads();  // LDS (stages, metadata) of the previous batch or unit is free
-        load_meta<MODE, U, BS>(m, mt, b0, nb);
-        __syncthreads();
-        Step st = first_step<LPU, NSUB>(mt, nb, 0);
-        Advance nxa;
-        nxa.nx = st;
-        nxa.addrs = 0;
-        // the first step's copy and, right behind it, the second step's: a
-        // unit of two steps (one leaf product of two K chunks) waits for one
-        // copy latency instead of two.  Only below unit 256: those units are
-        // short on sparse inputs, while the 256-wide kernels run long units
-        // and have no registers to spare for a third copy of the step body.
-        constexpr bool PRE2 = U <= 128;
-        bool pre = false;
-        if (st.i < nb) {
-            const uint64_t addrs = copy_addr<MODE, U, BS>(mt, st.i, st.kb, 0, cl, chunk_bytes);
-#pragma unroll
-            for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
-            oz_load_exp<MODE, U, BS>(mt, st.i, st.kb, wr, wc, ex);
-            nxa = advance<MODE, U, BS>(mt, nb, st, addrs, cl, chunk_bytes);
-            pre = PRE2 && nxa.nx.i < nb;
-            if (pre) {
-#pragma unroll
-                for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(nxa.addrs, k, st1, w);
-            }
-        }
-        if (pre)
-            __builtin_amdgcn_s_waitcnt(k5_vmcnt<G::PER_WAVE>);  // the first step's copies (and exponents)
-        else
-            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-        __syncthreads();
-        // steps alternate between the two stages; unrolled by two so that
-        // every access names its stage array at compile time
-        if constexpr (PRE2) {
-            if (st.i < nb) {
-                if (pre)
-                    run_step<MODE, U, BS, DENSE, NF, true>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes,
-                                                           w, wr, wc, ex);
-                else
-                    run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr,
-                                                     wc, ex);
-            }
-            while (st.i < nb) {
-                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
-                                                 ex);
-                if (st.i >= nb) break;
-                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
-                                                 ex);
-            }
-        } else {
-            while (st.i < nb) {
-                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st0, st1, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
-                                                 ex);
-                if (st.i >= nb) break;
-                run_step<MODE, U, BS, DENSE, NF>(m, mt, nb, st1, st0, acc, part, st, nxa, cl, chunk_bytes, w, wr, wc,
-                                                 ex);
-            }
-        }
+        BatchGo g = batch_begin<MODE, U, BS>(m, mt, b0, p1, cl, chunk_bytes, w, wr, wc, st0, st1, ex);
+        batch_run<MODE, U, BS, DENSE, NF>(m, mt, g, st0, st1, acc, part, cl, chunk_bytes, w, wr, wc, ex);
     }
 
     store_unit<MODE, U, BS>(m, u, acc, wr, wc);
+}
+
+// Streamed schedule for plans of few leaf products per unit, where a unit
+// is a metadata read, a copy, a short MFMA burst and a store, each waiting
+// on the one before: one persistent workgroup runs units it, it + G, ...
+// (G workgroups; unit xcd_remap(it) as in the one-unit-per-workgroup
+// launch).  The next unit's metadata is read and its first copies are issued
+// before this unit's output is stored, so the stores drain while those
+// copies land, and the next unit's pair range and output leaves are looked
+// up while this one runs.  The tile-skipping path only (units below 256).
+template <int MODE, int U, int BS>
+__device__ void process_stream(const K5Member &m, uint8_t *st0, uint8_t *st1, uint8_t *meta) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    constexpr int TPW = G::TPW, NLW = G::NLW;
+    const int n = m.nunits, gsz = (int)gridDim.x;
+    int it = (int)blockIdx.x;
+    if (it >= n) return;
+    const int tid = threadIdx.x;
+    const int w = uni(tid >> 6);
+    const int wr = w / G::WPS, wc = w % G::WPS;
+    const Meta mt = meta_view(meta, G::CAP);
+    const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
+    const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
+
+    typename M::Acc acc[TPW][TPW];
+    typename M::Part part[TPW][TPW];
+    OzExp<TPW> ex;
+    clear_acc<MODE, TPW>(acc, part, ex);
+
+    int u = xcd_remap(it, n);
+    int p0 = uni(m.ustart[u]), p1 = uni(m.ustart[u + 1]);
+    UnitOut<NLW> o = unit_out_load<MODE, U, BS>(m, u, wr, wc);
+    BatchGo g{};
+    if (p0 < p1) g = batch_begin<MODE, U, BS>(m, mt, p0, p1, cl, chunk_bytes, w, wr, wc, st0, st1, ex);
+    for (;;) {
+        // the next unit's pair range and output leaves, read under this unit
+        const int itn = it + gsz;
+        const int un = itn < n ? xcd_remap(itn, n) : 0;
+        int q0 = 0, q1 = 0;
+        UnitOut<NLW> on = o;
+        if (itn < n) {
+            q0 = uni(m.ustart[un]);
+            q1 = uni(m.ustart[un + 1]);
+            on = unit_out_load<MODE, U, BS>(m, un, wr, wc);
+        }
+        if (p0 < p1) {
+            // (the previous unit's stores went out after this batch's copies)
+            batch_run<MODE, U, BS, false, false, true>(m, mt, g, st0, st1, acc, part, cl, chunk_bytes, w, wr, wc, ex);
+            for (int b0 = p0 + G::CAP; b0 < p1; b0 += G::CAP) {
+                g = batch_begin<MODE, U, BS>(m, mt, b0, p1, cl, chunk_bytes, w, wr, wc, st0, st1, ex);
+                batch_run<MODE, U, BS, false, false>(m, mt, g, st0, st1, acc, part, cl, chunk_bytes, w, wr, wc, ex);
+            }
+        }
+        // every step of this unit has passed its closing barrier: the stages
+        // and the metadata may take the next unit's
+        OzExp<TPW> exn{};
+        if (itn < n && q0 < q1)
+            g = batch_begin<MODE, U, BS>(m, mt, q0, q1, cl, chunk_bytes, w, wr, wc, st0, st1, exn);
+        store_unit_out<MODE, U, BS>(m, o, acc, wr, wc);
+        if (itn >= n) break;
+        clear_acc<MODE, TPW>(acc, part, ex);
+        ex = exn;
+        it = itn;
+        u = un;
+        p0 = q0;
+        p1 = q1;
+        o = on;
+    }
 }
 
 // The unit of this workgroup in a single-multiply launch (XCD-aware).
@@ -887,7 +1024,8 @@ constexpr int k5_min_blocks = (MODE == QBSM_F64 || MODE == QBSM_OZAKI_I8 || U >=
 // tile-skipping path only; each workgroup leaves at once when its path does
 // not apply, and the host launches both (or only 2 where the plan selects
 // products), so neither kernel carries the other path.  0 = both paths in one
-// kernel, chosen per unit.
+// kernel, chosen per unit.  3 (units below 256, BS > 0): the streamed
+// schedule, a grid of resident workgroups that each run every G-th unit.
 template <int MODE, int U, int BS, int PATH = 0>
 __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     k5(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
@@ -900,6 +1038,9 @@ __global__ void __launch_bounds__((k5_nt<MODE, U>), (k5_min_blocks<MODE, U>))
     } else if constexpr (BS != 0 && PATH == 2) {
         if (dense_ok(single)) return;
         process_unit<MODE, U, BS, false>(single, launch_unit(single), st0, st1, meta);
+    } else if constexpr (BS != 0 && PATH == 3) {
+        static_assert(U <= 128 && MODE != QBSM_OZAKI_I8, "streamed schedule: tile-skipping units below 256");
+        process_stream<MODE, U, BS>(single, st0, st1, meta);
     } else if constexpr (BS != 0) {
         process_sel<MODE, U, BS>(single, launch_unit(single), st0, st1, meta);
     } else {
@@ -1059,9 +1200,28 @@ template <int MODE, int U>
 void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter, int grid,
               int persistent, const K5Member &single, hipStream_t s) {
     constexpr int NT = k5_nt<MODE, U>;
-    if (persistent) {
+    if (persistent == 1) {
         k5<MODE, U, 0><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
         return;
+    }
+    if (persistent == 2) {
+        if constexpr (U <= 128 && MODE != QBSM_OZAKI_I8) {
+            if (bs == 32) {
+                k5<MODE, U, 32, 3><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                return;
+            }
+            if (bs == 64) {
+                k5<MODE, U, 64, 3><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                return;
+            }
+            if constexpr (U >= 128) {
+                if (bs == 128) {
+                    k5<MODE, U, 128, 3><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                    return;
+                }
+            }
+        }
+        throw Error(QBSM_ERR_UNSUPPORTED, "streamed schedule for this mode, unit and leaf size");
     }
     if constexpr (U <= 128 && MODE != QBSM_OZAKI_I8) {
         if (bs == 32) {
@@ -1296,11 +1456,58 @@ void numeric_prepare_output(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s)
     out.stream = s;
 }
 
+// Resident workgroups per CU of the streamed kernel for (mode, unit, leaf
+// size), and the device's CU count, looked up once per device.
+static int stream_slots(qbsm_mode mode, int unit, int bs) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
+    int dev = 0;
+    QB_HIP(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, (int)mode, unit, bs);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const void *fn = nullptr;
+#define QB_ST(MD, UU, BB) \
+    if (mode == MD && unit == UU && bs == BB) fn = reinterpret_cast<const void *>(&k5<MD, UU, BB, 3>);
+#define QB_ST_M(MD) QB_ST(MD, 64, 32) QB_ST(MD, 64, 64) QB_ST(MD, 128, 32) QB_ST(MD, 128, 64) QB_ST(MD, 128, 128)
+    QB_ST_M(QBSM_F64) QB_ST_M(QBSM_F32) QB_ST_M(QBSM_BF16) QB_ST_M(QBSM_BF16X3)
+#undef QB_ST_M
+#undef QB_ST
+    int nb = 0;
+    if (fn) {
+        const int NT = 64 * (unit / 64) * (unit / 64);
+        QB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, NT, 0));
+        nb = std::max(nb, 1) * device_cu_count();
+        // a multiple of the XCD count keeps every workgroup's units on its XCD
+        if (nb >= 8) nb -= nb % 8;
+    }
+    cache[key] = nb;
+    return nb;
+}
+
+// Measured on the random-block multiply (N = 65536, 128-wide leaves, about
+// one leaf product per unit, where it was meant to pay): the streamed
+// schedule is 1% faster in FP64 and 0.5-3.5% slower in FP32, BF16X3 and BF16
+// (that kernel moves its L2-side traffic at the rate of a device copy), so
+// the automatic choice is one workgroup per unit and the streamed schedule
+// is taken only on request.
+int numeric_stream_grid(const Plan &p, qbsm_mode mode) {
+    if (p.sched != 2 || p.unit > 128 || mode == QBSM_OZAKI_I8 || p.nunits <= 0) return 0;
+    const int64_t g = stream_slots(mode, p.unit, p.bs);
+    if (g <= 0) return 0;
+    return (int)std::min<int64_t>(g, p.nunits);
+}
+
 void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     if (!p.nunits) return;
     K5Member m = make_member(p, mode, out, s);
     ProfScope prof(PROF_NUMERIC, s);
-    k5_launch(mode, p.unit, nullptr, 1, nullptr, 0, nullptr, (int)p.nunits, 0, m, s);
+    const int sg = numeric_stream_grid(p, mode);
+    if (sg > 0)
+        k5_launch(mode, p.unit, nullptr, 1, nullptr, 0, nullptr, sg, 2, m, s);
+    else
+        k5_launch(mode, p.unit, nullptr, 1, nullptr, 0, nullptr, (int)p.nunits, 0, m, s);
 }
 
 // ------------------------------------------------------------------ batched

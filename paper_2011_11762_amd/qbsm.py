@@ -38,7 +38,8 @@ class BatchTuning(ctypes.Structure):
 
 
 class PlanOpts(ctypes.Structure):
-    _fields_ = [("unit", c_int32), ("upper", c_int32), ("spamm_tol", c_double), ("reserved", c_int32 * 4)]
+    _fields_ = [("unit", c_int32), ("upper", c_int32), ("spamm_tol", c_double), ("schedule", c_int32),
+                ("reserved", c_int32 * 3)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p, c_void_p)
@@ -256,14 +257,17 @@ class Plan:
     """Symbolic phase result (work list + output pattern) of op(L) op(R) [masked]."""
 
     def __init__(self, L: Matrix, R: Matrix, trans_l=False, trans_r=False, mask: Matrix | None = None,
-                 unit: int = 0, spamm_tol: float = 0.0, upper: bool = False):
+                 unit: int = 0, spamm_tol: float = 0.0, upper: bool = False, schedule: int = 0):
         """spamm_tol > 0: sparse approximate multiply (leaf products with
         ||L_leaf|| * ||R_leaf|| < spamm_tol are left out).  upper: only the
-        output blocks with I <= J (symmetric square of a symmetric matrix)."""
+        output blocks with I <= J (symmetric square of a symmetric matrix).
+        schedule: numeric-phase schedule, 0 automatic, 1 one workgroup per
+        unit, 2 streamed (same results)."""
         load()
         h = c_void_p()
         nout, nprod = c_int64(), c_int64()
-        opts = PlanOpts(unit=int(unit), spamm_tol=float(spamm_tol), upper=int(bool(upper)))
+        opts = PlanOpts(unit=int(unit), spamm_tol=float(spamm_tol), upper=int(bool(upper)),
+                        schedule=int(schedule))
         _check(_lib.qbsm_multiply_symbolic_ex(L.handle, int(trans_l), R.handle, int(trans_r),
                                               mask.handle if mask is not None else None, ctypes.byref(opts),
                                               _stream(), ctypes.byref(h), ctypes.byref(nout),
