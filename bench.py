@@ -51,19 +51,19 @@ KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "58c215d8e00d3b5b",
+    "sources_sha256_16": "9a6044a51807d76e",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 117781486891,
-        "bf16x3@256": 53227742491,
-        "bf16x3@64": 329439401685,
-        "f32@128": 204145957065,
-        "f32@256": 67991648384,
-        "f32@64": 338163386901,
-        "f64@128": 270714323237,
-        "f64@64": 711755487360,
-        "ozaki@128": 117525422592,
-        "ozaki@64": 534310602155,
+        "bf16x3@128": 124052490176,
+        "bf16x3@256": 49934640046,
+        "bf16x3@64": 327954186219,
+        "f32@128": 203937924599,
+        "f32@256": 67834635179,
+        "f32@64": 337774274304,
+        "f64@128": 269286343552,
+        "f64@64": 733774161259,
+        "ozaki@128": 116221679616,
+        "ozaki@64": 533811299712,
     },
 }
 
