@@ -80,6 +80,15 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *tot
                         hipStream_t s);
 // Same for int64 values (no overflow concerns at these sizes).
 void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+// Tiles of the scans: kScanThreads threads of kScanItems consecutive values.
+constexpr int kScanThreads = 256, kScanItems = 8;
+constexpr int64_t kScanTile = (int64_t)kScanThreads * kScanItems;
+// exclusive_scan_i32 for values whose producer kernel already wrote their
+// sums by parts: partial[t] is the sum of [t * kScanTile / sub, (t + 1) *
+// kScanTile / sub), sub = 1 or 8 parts per tile; partial holds
+// ceil(n * sub / kScanTile) + 1 entries and may be overwritten.  n > 0.
+void exclusive_scan_i32_partials(const int32_t *in, int32_t *out, int64_t n, int64_t *partial, int sub,
+                                 int64_t *total64, hipStream_t s);
 
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
 void fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

@@ -5,8 +5,8 @@ namespace qbsm {
 
 namespace {
 
-constexpr int SCAN_BLOCK = 256;
-constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_BLOCK = kScanThreads;
+constexpr int SCAN_ITEMS = kScanItems;
 constexpr int SCAN_TILE = SCAN_BLOCK * SCAN_ITEMS;
 
 // Exclusive scan of one value per thread over a 256-thread block (4 waves of
@@ -99,9 +99,11 @@ constexpr int64_t SCAN_SUM_MAX = 1024;
 
 template <class Tin, class Tout, class Tacc>
 __global__ void __launch_bounds__(SCAN_BLOCK) k_scan_apply_sum(const Tin *in, Tout *out, int64_t n,
-                                                               const Tacc *partial, int64_t *total64) {
+                                                               const Tacc *partial, int64_t *total64,
+                                                               int sub = 1) {
+    // partial holds `sub` sums per tile (of consecutive parts of it)
     Tacc pre = 0;
-    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x; j += SCAN_BLOCK) pre += partial[j];
+    for (int64_t j = threadIdx.x; j < (int64_t)blockIdx.x * sub; j += SCAN_BLOCK) pre += partial[j];
     Tacc before;
     (void)block_exclusive_scan<Tacc>(pre, &before);
     const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
@@ -230,6 +232,26 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int64_t *tot
 
 void exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
     scan_impl<int64_t, int64_t>(in, out, n, nullptr, s);
+}
+
+void exclusive_scan_i32_partials(const int32_t *in, int32_t *out, int64_t n, int64_t *partial, int sub,
+                                 int64_t *total64, hipStream_t s) {
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb <= SCAN_SUM_MAX) {
+        k_scan_apply_sum<int32_t, int32_t, int64_t><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, out, n, partial, total64,
+                                                                                     sub);
+        QB_LAUNCH_CHECK();
+        return;
+    }
+    if (sub != 1) {  // a long scan: its own tile sums
+        scan_impl<int32_t, int32_t>(in, out, n, total64, s);
+        return;
+    }
+    k_scan_partials<int64_t><<<1, SCAN_BLOCK, 0, s>>>(partial, nb, partial + nb);
+    QB_LAUNCH_CHECK();
+    k_scan_apply<int32_t, int32_t, int64_t><<<(unsigned)nb, SCAN_BLOCK, 0, s>>>(in, out, n, partial, partial + nb,
+                                                                                 total64);
+    QB_LAUNCH_CHECK();
 }
 
 void fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {

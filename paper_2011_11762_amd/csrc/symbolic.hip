@@ -131,16 +131,6 @@ __device__ __forceinline__ void emit_children(const PairRec &r, int64_t p, int q
     }
 }
 
-// Child pair count of item t = 4 p + q (0..2), written to its slot.
-__device__ __forceinline__ void walk_count_item(const WalkLevel &w, int64_t t, int32_t *X) {
-    const int64_t p = t >> 2;
-    const int q = (int)(t & 3);
-    const PairRec r = pair_at(w, p);
-    int32_t cl[2], cr[2], mchild;
-    const int live = quadrant_children(w, r, q, cl, cr, mchild);
-    X[item_slot(r, p, q)] = __popc(live);
-}
-
 // Writes the child pairs of item t at their scanned positions Y.
 __device__ __forceinline__ void walk_fill_item(const WalkLevel &w, int64_t t, const int32_t *Y, int64_t ocap,
                                                const WalkOut &o) {
@@ -152,24 +142,52 @@ __device__ __forceinline__ void walk_fill_item(const WalkLevel &w, int64_t t, co
     if (live) emit_children(r, p, q, live, cl, cr, mchild, Y, ocap, o);
 }
 
-// The pair count np of the level is read from device memory (the previous
-// level's scan total); the launch covers the level's capacity and the slots
-// beyond 4*np are zeroed, so that the scan over the whole capacity gives the
-// next level's count without a host round trip.
-__global__ void k_walk_count(const int64_t *npp, int64_t cap4, WalkLevel w, int32_t *X) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= cap4) return;
-    if (t >= *npp * 4) {
-        X[t] = 0;  // the layout covers exactly [0, 4*np)
-        return;
-    }
-    walk_count_item(w, t, X);
-}
-
+// The pair count np of a level is read from device memory (the previous
+// level's scan total); the launches cover the level's capacity, so that the
+// next level's count needs no host round trip.
 __global__ void k_walk_fill(const int64_t *npp, WalkLevel w, const int32_t *Y, int64_t ocap, WalkOut o) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= *npp * 4) return;
     walk_fill_item(w, t, Y, ocap, o);
+}
+
+// Sum of one value per thread over a kScanThreads-thread workgroup (the
+// result in every thread).
+__device__ __forceinline__ int64_t block_sum(int64_t v) {
+    __shared__ int64_t red[kScanThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; ++k) t += red[k];
+    __syncthreads();  // red may be written again by the next call
+    return t;
+}
+
+// The counts of one walk level by slot of the count layout, one slot per
+// thread, each workgroup's sum written to partial[block] for the scan (which
+// then needs no reduction pass of its own).  Slot s lies in [4g, 4g + 4m),
+// the slots of the group of pair s / 4 (g its first pair, m its size), so
+// its item is quadrant (s - 4g) / m of pair g + (s - 4g) % m.  Slots from
+// 4 np up to the capacity are zero.
+__global__ void __launch_bounds__(kScanThreads) k_walk_count_tile(const int64_t *npp, int64_t cap4, WalkLevel w,
+                                                                  int32_t *X, int64_t *partial) {
+    const int64_t n4 = *npp * 4;
+    const int64_t s = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+    int32_t c = 0;
+    if (s < n4) {
+        const int64_t pp = s >> 2;
+        const int64_t g = w.gs[pp];
+        // a group holds at most 2^16 pairs (one per contraction index)
+        const uint32_t m = (uint32_t)w.gm[pp], off = (uint32_t)(s - 4 * g);
+        const PairRec r = pair_at(w, g + off % m);
+        int32_t cl[2], cr[2], mchild;
+        c = __popc(quadrant_children(w, r, (int)(off / m), cl, cr, mchild));
+    }
+    if (s < cap4) X[s] = c;
+    const int64_t tot = block_sum(c);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
 // The small top levels of the walk in one workgroup: for each level, counts
@@ -185,6 +203,7 @@ __global__ void k_walk_fill(const int64_t *npp, WalkLevel w, const int32_t *Y, i
 constexpr int kTopPairs = 512, kTopThreads = kTopPairs, kTopItems = 4 * kTopPairs;
 struct TopLevels {
     int n;                    // levels processed: l0 .. l0 + n - 1
+    int root;                 // 1: level l0 is the root level (its one pair made here, counts[0] = 1)
     WalkLevel lv[8];          // level inputs (the first one's pair arrays given; the rest filled here)
     WalkOut out[8];           // level outputs (out[i] is the input pairs of lv[i + 1])
     int64_t ocap[8];          // output capacities
@@ -206,13 +225,17 @@ __global__ void __launch_bounds__(kTopThreads) k_walk_top(TopLevels tl, int64_t 
         const bool last = i + 1 == tl.n;
         const WalkOut o = last ? tl.out[i] : lds;
         const int64_t ocap = last ? tl.ocap[i] : (tl.ocap[i] < kTopPairs ? tl.ocap[i] : kTopPairs);
-        const int np = (int)counts[i];  // this level's pairs (written by the previous round)
+        const bool root = i == 0 && tl.root;
+        // this level's pairs (written by the previous round)
+        const int np = root ? 1 : (int)counts[i];
+        if (root && tid == 0) counts[0] = 1;
         const bool mine = tid < np;
         PairRec r{};
         int live[4] = {0, 0, 0, 0};
         int32_t cl[4][2], cr[4][2], mch[4];
         if (mine) {
-            r = pair_at(w, tid);
+            // the root pair: both trees' (and the mask's) root nodes, one group
+            r = root ? PairRec{0, 0, 0, 1, w.chM ? 0 : -1, 0u} : pair_at(w, tid);
 #pragma unroll
             for (int q = 0; q < 4; ++q) live[q] = quadrant_children(w, r, q, cl[q], cr[q], mch[q]);
         }
@@ -368,8 +391,6 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hip
     // counts[l]: pairs at level l (device), written by the scans (a level
     // without pairs keeps its zero)
     cur.alloc(1, s);
-    k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p, counts);
-    QB_LAUNCH_CHECK();
     auto level_in = [&](const Pairs &p, int l) {
         WalkLevel w{};
         w.pl = p.pl.p; w.pr = p.pr.p; w.gs = p.gs.p; w.gm = p.gm.p; w.pm = p.pm.p; w.ck = p.ck.p;
@@ -411,11 +432,15 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hip
                 tl.out[i] = level_out(outs[i]);
                 tl.ocap[i] = outs[i].n;
             }
+            tl.root = 1;  // the kernel makes the root pair itself
             k_walk_top<<<1, kTopThreads, 0, s>>>(tl, counts + l);
             QB_LAUNCH_CHECK();
             capc = outs.back().n;
             cur = std::move(outs.back());
             l += tl.n;
+        } else {
+            k_walk_root<<<1, 1, 0, s>>>(cur.pl.p, cur.pr.p, cur.gs.p, cur.gm.p, cur.pm.p, cur.ck.p, counts);
+            QB_LAUNCH_CHECK();
         }
     }
     for (; l < target; ++l) {
@@ -426,9 +451,13 @@ Pairs walk(Tree &tL, int transL, Tree &tR, int transR, Tree *tM, int target, hip
             const unsigned g = grid_for(capc * 4, 256);
             const WalkLevel w = level_in(cur, l);
             const bool bounded = w.chM || w.nL || upper;
-            k_walk_count<<<g, 256, 0, s>>>(counts + l, capc * 4, w, X.p);
+            // counts with their workgroup sums, then the scan's apply pass
+            constexpr int sub = (int)(kScanTile / kScanThreads);
+            const int64_t nt = (capc * 4 + kScanTile - 1) / kScanTile;
+            DArr<int64_t> part(nt * sub + 1, s);
+            k_walk_count_tile<<<(unsigned)(nt * sub), kScanThreads, 0, s>>>(counts + l, capc * 4, w, X.p, part.p);
             QB_LAUNCH_CHECK();
-            exclusive_scan_i32(X.p, Y.p, capc * 4, counts + l + 1, s);
+            exclusive_scan_i32_partials(X.p, Y.p, capc * 4, part.p, sub, counts + l + 1, s);
             if (bounded && capn > kMaskedBoundPairs) capn = read_back(counts + l + 1, s);
             nxt.alloc(capn, s);
             if (capn) {
@@ -470,9 +499,24 @@ __device__ __forceinline__ void demorton_u32(uint32_t k, uint32_t &i, uint32_t &
 }
 
 // First pair of every unit (output group) among the *npp pairs; 0 beyond.
-__global__ void k_unit_flags(const int64_t *npp, int64_t cap, const int32_t *gs, int32_t *flags) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < cap) flags[p] = (p < *npp && gs[p] == (int32_t)p) ? 1 : 0;
+// kScanItems pairs per thread, each workgroup's flag count to partial[block]
+// for the scan.
+__global__ void __launch_bounds__(kScanThreads) k_unit_flags(const int64_t *npp, int64_t cap, const int32_t *gs,
+                                                             int32_t *flags, int64_t *partial) {
+    const int64_t np = *npp;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t p = base + i;
+        if (p < cap) {
+            const int32_t f = (p < np && gs[p] == (int32_t)p) ? 1 : 0;
+            flags[p] = f;
+            sum += f;
+        }
+    }
+    const int64_t tot = block_sum(sum);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
 // meta = {pairs, units} on the device; launches cover host-side bounds.
@@ -586,7 +630,7 @@ __global__ void k_pair_masks(const int64_t *meta, const int32_t *pl, const int32
     // The output mask takes one atomic per unit run inside a wave: the pairs
     // of a unit are contiguous, so a run of lanes with the same unit is
     // OR-reduced onto its first lane.  The product and flop totals go to one
-    // slot per block (summed by k_sum_parts) rather than to a single address.
+    // slot per block (summed by k_unit_count) rather than to a single address.
     unsigned long long cnt = (unsigned long long)__popcll(bits);
     const int lane = (int)(threadIdx.x & 63);
     for (int o = 1; o < 64; o <<= 1) {
@@ -611,32 +655,43 @@ __global__ void k_pair_masks(const int64_t *meta, const int32_t *pl, const int32
             red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
 }
 
-// Sums the per-block (products, flops) pairs into out[0..1].
-__global__ void __launch_bounds__(256) k_sum_parts(const unsigned long long *part, int64_t nblk,
-                                                   unsigned long long *out) {
-    unsigned long long c = 0, f = 0;
-    for (int64_t i = threadIdx.x; i < nblk; i += 256) {
-        c += part[2 * i];
-        f += part[2 * i + 1];
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        c += __shfl_down(c, o);
-        f += __shfl_down(f, o);
-    }
-    __shared__ unsigned long long red[2][4];
-    if ((threadIdx.x & 63) == 0) {
-        red[0][threadIdx.x >> 6] = c;
-        red[1][threadIdx.x >> 6] = f;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2)
-        out[threadIdx.x] = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
-}
 
 // Output leaves per unit; zero beyond the units (the scan covers the bound).
-__global__ void k_unit_count(const int64_t *meta, int64_t cap, const uint32_t *ucmask, int32_t *cnt) {
-    int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (u < cap) cnt[u] = u < meta[1] ? __popc(ucmask[u]) : 0;
+// Output leaves of every unit (0 beyond the unit count), kScanItems units
+// per thread with each workgroup's sum to partial[block] for the scan; the
+// first workgroup also adds up the pair-mask kernel's per-block (products,
+// flops) into tot[0..1].
+__global__ void __launch_bounds__(kScanThreads) k_unit_count(const int64_t *meta, int64_t cap, const uint32_t *ucmask,
+                                                             int32_t *cnt, int64_t *partial,
+                                                             const unsigned long long *part, int64_t nblk,
+                                                             unsigned long long *tot) {
+    const int64_t nu = meta[1];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t u = base + i;
+        if (u < cap) {
+            const int32_t c = u < nu ? __popc(ucmask[u]) : 0;
+            cnt[u] = c;
+            sum += c;
+        }
+    }
+    const int64_t t = block_sum(sum);
+    if (threadIdx.x == 0) partial[blockIdx.x] = t;
+    if (blockIdx.x == 0) {
+        unsigned long long c = 0, f = 0;
+        for (int64_t i = threadIdx.x; i < nblk; i += kScanThreads) {
+            c += part[2 * i];
+            f += part[2 * i + 1];
+        }
+        const int64_t cs = block_sum((int64_t)c);
+        const int64_t fs = block_sum((int64_t)f);
+        if (threadIdx.x == 0) {
+            tot[0] = (unsigned long long)cs;
+            tot[1] = (unsigned long long)fs;
+        }
+    }
 }
 
 // Output leaves of each unit: numbered in Morton order inside the unit
@@ -775,9 +830,11 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     // units = output groups at the unit level
     DArr<int32_t> flags(cap ? cap : 1, s), uscan((cap ? cap : 1) + 1, s), pu(cap ? cap : 1, s);
     if (cap) {
-        k_unit_flags<<<grid_for(cap, 256), 256, 0, s>>>(meta, cap, pr.gs.p, flags.p);
+        const int64_t nt = (cap + kScanTile - 1) / kScanTile;
+        DArr<int64_t> tsum(nt + 1, s);
+        k_unit_flags<<<(unsigned)nt, kScanThreads, 0, s>>>(meta, cap, pr.gs.p, flags.p, tsum.p);
         QB_LAUNCH_CHECK();
-        exclusive_scan_i32(flags.p, uscan.p, cap, meta + 1, s);
+        exclusive_scan_i32_partials(flags.p, uscan.p, cap, tsum.p, 1, meta + 1, s);
     }
     // Small plans size their unit arrays by the pair bound (units <= pairs)
     // and read the exact counts back with the totals, in one host read;
@@ -800,6 +857,8 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     p->pmask.alloc(np ? np : 1, s);
     p->cdesc.alloc((nu ? nu : 1) * nsub, s);
     DArr<uint32_t> ucmask(nu ? nu : 1, s);
+    DArr<unsigned long long> part;  // per-block (products, flops) of the pair-mask kernel
+    int64_t nblk = 0;
     if (np) {
         k_unit_fill<<<grid_for(np, 256), 256, 0, s>>>(meta, pr.gs.p, pr.pm.p, pr.ck.p, uscan.p, p->ustart.p,
                                                      p->ukey.p, p->umask.p, pu.p, ucmask.p);
@@ -812,14 +871,12 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     k_pair_masks<S_><<<grid_for(np, 256), 256, 0, s>>>(meta, p->pl.p, p->pr.p, pu.p, p->ukey.p, p->umask.p,    \
                                                        dL, dR, dM, M ? 1 : 0, tL.key[Lw].p, d, nL, nR,     \
                                                        spamm_tol, upper, p->pmask.p, ucmask.p, part.p)
-        const int64_t nblk = grid_for(np, 256);
-        DArr<unsigned long long> part(2 * nblk, s);
+        nblk = grid_for(np, 256);
+        part.alloc(2 * nblk, s);
         if (sl == 0) QB_PAIR_MASKS(0);
         else if (sl == 1) QB_PAIR_MASKS(1);
         else QB_PAIR_MASKS(2);
 #undef QB_PAIR_MASKS
-        QB_LAUNCH_CHECK();
-        k_sum_parts<<<1, 256, 0, s>>>(part.p, nblk, &totals->nprod);
         QB_LAUNCH_CHECK();
     } else {
         int32_t zero = 0;
@@ -830,9 +887,13 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     DArr<uint32_t> okeys_b;
     if (nu) {
         DArr<int32_t> cnt(nu, s), cbase(nu + 1, s);
-        k_unit_count<<<grid_for(nu, 256), 256, 0, s>>>(meta, nu, ucmask.p, cnt.p);
+        const int64_t nt = (nu + kScanTile - 1) / kScanTile;
+        DArr<int64_t> tsum(nt + 1, s);
+        // (with the product and flop totals of the pair-mask kernel's blocks)
+        k_unit_count<<<(unsigned)nt, kScanThreads, 0, s>>>(meta, nu, ucmask.p, cnt.p, tsum.p, part.p, nblk,
+                                                            &totals->nprod);
         QB_LAUNCH_CHECK();
-        exclusive_scan_i32(cnt.p, cbase.p, nu, &totals->nout, s);
+        exclusive_scan_i32_partials(cnt.p, cbase.p, nu, tsum.p, 1, &totals->nout, s);
         if (!M) okeys_b.alloc(nu * nsub, s);
         const int32_t *dM = M ? tree_desc(*M, *tM, sl, s) : nullptr;
         k_unit_cdesc<<<grid_for(nu, 256), 256, 0, s>>>(meta, ucmask.p, cbase.p, p->ukey.p, p->umask.p, dM,
