@@ -43,22 +43,27 @@ struct SetStatus {
 };
 
 // Keys + range check for every input block.
+// (also clears ksort, the kept flags by key rank that the norm pass sets)
 __global__ void k_keys(const int32_t *brow, const int32_t *bcol, int64_t n, int64_t nbr, int64_t nbc,
-                       uint32_t *keys, uint8_t *valid, SetStatus *st) {
+                       uint32_t *keys, uint8_t *valid, SetStatus *st, int32_t *ksort) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     int32_t i = brow[t], j = bcol[t];
     bool ok = i >= 0 && j >= 0 && i < nbr && j < nbc;
     valid[t] = ok ? 1 : 0;
     keys[t] = ok ? morton2((uint32_t)i, (uint32_t)j) : 0u;
+    ksort[t] = 0;
     if (!ok) st->range_err = 1;
 }
 
 // FP64 Frobenius norm of the logical part of each block; keep iff not (norm < tol).
+// A kept block also sets ksort[rank] at its key's rank among the distinct
+// input keys, so that a scan of ksort ranks the kept keys.
 __global__ void __launch_bounds__(256) k_norm_keep(const double *__restrict__ vals, const int32_t *brow,
                                                    const int32_t *bcol, const uint8_t *valid,
                                                    int64_t n, int32_t bs, int64_t nrows,
-                                                   int64_t ncols, double tol, uint8_t *keep) {
+                                                   int64_t ncols, double tol, uint8_t *keep,
+                                                   const int32_t *rank, int32_t *ksort) {
     const int64_t t = blockIdx.x;
     if (t >= n) return;
     __shared__ double red[4];
@@ -95,25 +100,31 @@ __global__ void __launch_bounds__(256) k_norm_keep(const double *__restrict__ va
     __syncthreads();
     if (threadIdx.x == 0) {
         const double nrm = sqrt((red[0] + red[1]) + (red[2] + red[3]));
-        keep[t] = (ok && !(nrm < tol)) ? 1 : 0;
+        const bool kp = ok && !(nrm < tol);
+        keep[t] = kp ? 1 : 0;
+        if (kp && rank[t] >= 0) ksort[rank[t]] = 1;
     }
 }
 
-__global__ void k_copy_flags(const uint8_t *valid, int64_t n, uint8_t *keep) {
+__global__ void k_copy_flags(const uint8_t *valid, int64_t n, uint8_t *keep, const int32_t *rank, int32_t *ksort) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) keep[t] = valid[t];
+    if (t >= n) return;
+    keep[t] = valid[t];
+    if (valid[t] && rank[t] >= 0) ksort[rank[t]] = 1;
 }
 
-// Scatter kept blocks into Morton order, zeroing the padding.
+// Scatter kept blocks into Morton order, zeroing the padding: a kept block
+// goes to the rank of its key among the kept keys, kscan[rank among all keys].
 __global__ void __launch_bounds__(256) k_store_blocks(const double *__restrict__ vals, const int32_t *brow,
                                                       const int32_t *bcol, const uint32_t *keys,
-                                                      const int32_t *rank, int64_t n, int32_t bs,
+                                                      const uint8_t *keep, const int32_t *rank,
+                                                      const int32_t *kscan, int64_t n, int32_t bs,
                                                       int64_t nrows, int64_t ncols, double *__restrict__ pool,
                                                       uint32_t *okeys) {
     int64_t t = blockIdx.x;
     if (t >= n) return;
-    int32_t r = rank[t];
-    if (r < 0) return;
+    if (!keep[t]) return;
+    const int32_t r = kscan[rank[t]];
     const int64_t mr = min((int64_t)bs, nrows - (int64_t)brow[t] * bs);
     const int64_t nc = min((int64_t)bs, ncols - (int64_t)bcol[t] * bs);
     const int64_t n2 = (int64_t)bs * bs;
@@ -629,25 +640,26 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     QB_HIP(hipMemsetAsync(st.p, 0, sizeof(SetStatus), s));
     DArr<uint32_t> keys(n ? n : 1, s);
     DArr<uint8_t> valid(n ? n : 1, s), keep(n ? n : 1, s);
-    DArr<int32_t> rank(n ? n : 1, s), rank2(n ? n : 1, s);
+    // rank: of each in-range block's key among the distinct input keys;
+    // ksort: kept flags by that rank, whose scan kscan ranks the kept keys
+    DArr<int32_t> rank(n ? n : 1, s), ksort(n ? n : 1, s), kscan(n + 1, s);
     const uint64_t range = (uint64_t)1 << (2 * ceil_log2(m.nbr > m.nbc ? m.nbr : m.nbc));
     if (n) {
-        k_keys<<<grid_for(n, 256), 256, 0, s>>>(brow, bcol, n, m.nbr, m.nbc, keys.p, valid.p, st.p);
+        k_keys<<<grid_for(n, 256), 256, 0, s>>>(brow, bcol, n, m.nbr, m.nbc, keys.p, valid.p, st.p, ksort.p);
         QB_LAUNCH_CHECK();
     }
     // duplicates among all in-range input blocks
-    bitmap_rank(keys.p, valid.p, n, range, rank2.p, &st.p->dup, &st.p->ndistinct, s);
+    bitmap_rank(keys.p, valid.p, n, range, rank.p, &st.p->dup, &st.p->ndistinct, s);
     if (n) {
         if (drop_tol > 0.0) {
             k_norm_keep<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, valid.p, n, m.bs, m.nrows, m.ncols,
-                                                    drop_tol, keep.p);
+                                                    drop_tol, keep.p, rank.p, ksort.p);
         } else {
-            k_copy_flags<<<grid_for(n, 256), 256, 0, s>>>(valid.p, n, keep.p);
+            k_copy_flags<<<grid_for(n, 256), 256, 0, s>>>(valid.p, n, keep.p, rank.p, ksort.p);
         }
         QB_LAUNCH_CHECK();
+        exclusive_scan_i32(ksort.p, kscan.p, n, &st.p->nkept, s);
     }
-    DArr<int32_t> dummy(1, s);
-    bitmap_rank(keys.p, keep.p, n, range, rank.p, dummy.p, &st.p->nkept, s);
     SetStatus h = read_back(st.p, s);
     QB_CHECK(!h.range_err, QBSM_ERR_PATTERN, "block coordinate outside the block grid");
     QB_CHECK(!h.dup, QBSM_ERR_PATTERN, "repeated block coordinate");
@@ -655,8 +667,8 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     DArr<double> pool(nk * (int64_t)m.bs * m.bs, s);
     DArr<uint32_t> okeys(nk, s);
     if (n && nk) {
-        k_store_blocks<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, keys.p, rank.p, n, m.bs, m.nrows,
-                                                   m.ncols, pool.p, okeys.p);
+        k_store_blocks<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, keys.p, keep.p, rank.p, kscan.p, n, m.bs,
+                                                   m.nrows, m.ncols, pool.p, okeys.p);
         QB_LAUNCH_CHECK();
     }
     m.v64 = std::move(pool);
