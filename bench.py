@@ -51,19 +51,19 @@ KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "9a6044a51807d76e",
+    "sources_sha256_16": "d3f7389e96850f78",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 124052490176,
-        "bf16x3@256": 49934640046,
-        "bf16x3@64": 327954186219,
-        "f32@128": 203937924599,
-        "f32@256": 67834635179,
-        "f32@64": 337774274304,
-        "f64@128": 269286343552,
-        "f64@64": 733774161259,
-        "ozaki@128": 116221679616,
-        "ozaki@64": 533811299712,
+        "bf16x3@128": 126210763093,
+        "bf16x3@256": 52165246327,
+        "bf16x3@64": 323983764864,
+        "f32@128": 204035100407,
+        "f32@256": 67761737600,
+        "f32@64": 337903877845,
+        "f64@128": 274845496709,
+        "f64@64": 726393625856,
+        "ozaki@128": 116678126373,
+        "ozaki@64": 558198889941,
     },
 }
 
