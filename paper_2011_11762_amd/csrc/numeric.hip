@@ -970,6 +970,108 @@ __device__ void process_stream(const K5Member &m, uint8_t *st0, uint8_t *st1, ui
     }
 }
 
+// Single-stage schedule for plans of about one leaf product per unit (the
+// HBM-bound random-block multiply): a unit is a metadata read, one or two
+// copies, a short MFMA burst and a store, each waiting on the one before, so
+// throughput comes from workgroups in flight rather than from overlap inside
+// one.  With one 32 KB LDS stage, a small metadata area and at most 128
+// vector registers (a 64 x 64 FP32 accumulator per wave), four workgroups fit
+// on a compute unit instead of two.  Each step copies, waits, computes and
+// leaves the stage with a barrier before the next copy; the MFMA order of
+// every accumulator is that of the double-buffered kernel, so the results are
+// the same bit for bit.  BF16 and BF16X3 at unit 128 (their 64-byte packed
+// lines make two steps of a 128-wide leaf).
+constexpr int kMetaSmall = 2048;
+
+template <int MODE, int U, int BS>
+__device__ __forceinline__ void compute_step(const uint8_t *cur,
+                                             typename MT<MODE>::Acc (&acc)[Geo<MODE, U, BS>::TPW][Geo<MODE, U, BS>::TPW],
+                                             const Step &st, int wr, int wc) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    constexpr int PARTS = M::PARTS, TPW = G::TPW, TPL = G::TPL, NLW = G::NLW;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wl = wave_leaves<MODE, U, BS>(st.km, wr, wc);
+    if (!wl) return;
+    const uint8_t *Ab = cur;
+    const uint8_t *Bb = cur + PARTS * G::ARRB;
+#pragma unroll
+    for (int rg = 0; rg < G::NGROUPS; ++rg) {
+        const int pbase = rg * M::PPG + (lane >> 4) * M::SUBS;
+        typename M::Frag fa[TPW][PARTS];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) {
+            const int la_ = G::WT * wr + 16 * t + (lane & 15);
+#pragma unroll
+            for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                for (int q = 0; q < M::SUBS; ++q)
+                    fa[t][part].q[q] = lds_piece(Ab + part * G::ARRB, la_, G::LB, pbase + q);
+        }
+#pragma unroll
+        for (int tn = 0; tn < TPW; ++tn) {
+            typename M::Frag fb[PARTS];
+            const int lb_ = G::WT * wc + 16 * tn + (lane & 15);
+#pragma unroll
+            for (int part = 0; part < PARTS; ++part)
+#pragma unroll
+                for (int q = 0; q < M::SUBS; ++q)
+                    fb[part].q[q] = lds_piece(Bb + part * G::ARRB, lb_, G::LB, pbase + q);
+#pragma unroll
+            for (int tm = 0; tm < TPW; ++tm)
+                if ((wl >> ((tm / TPL) * NLW + tn / TPL)) & 1u) M::mma(acc[tm][tn], fa[tm], fb);
+        }
+    }
+}
+
+template <int MODE, int U, int BS>
+__device__ void process_unit_serial(const K5Member &m, int u, uint8_t *st0, uint8_t *meta) {
+    using G = Geo<MODE, U, BS>;
+    using M = MT<MODE>;
+    static_assert(!M::LEAF_SUMS, "the integer-digit mode has its own kernels");
+    constexpr int TPW = G::TPW, LPU = G::LPU, NSUB = G::NSUB;
+    constexpr int CAPS = kMetaSmall / (8 + 16 * NSUB);
+    const int w = uni((int)threadIdx.x >> 6);
+    const int wr = w / G::WPS, wc = w % G::WPS;
+    typename M::Acc acc[TPW][TPW];
+#pragma unroll
+    for (int a = 0; a < TPW; ++a)
+#pragma unroll
+        for (int b = 0; b < TPW; ++b) acc[a][b] = typename M::Acc{};
+    const int p0 = uni(m.ustart[u]), p1 = uni(m.ustart[u + 1]);
+    const Meta mt = meta_view(meta, CAPS);
+    const CopyLane cl = copy_lane<MODE, U, BS>(m, w);
+    const uint32_t chunk_bytes = (uint32_t)((int64_t)m.chunkStrideL * (int64_t)sizeof(typename G::T));
+    for (int b0 = p0; b0 < p1; b0 += CAPS) {
+        const int nb = uni((p1 - b0) < CAPS ? (p1 - b0) : CAPS);
+        __syncthreads();  // the metadata of the previous batch is no longer read
+        load_meta<MODE, U, BS>(m, mt, b0, nb);
+        __syncthreads();
+        Step st = first_step<LPU, NSUB>(mt, nb, 0);
+        while (st.i < nb) {
+            const uint64_t addrs = copy_addr<MODE, U, BS>(mt, st.i, st.kb, st.c, cl, chunk_bytes);
+#pragma unroll
+            for (int k = 0; k < G::PER_WAVE; ++k) issue_one<MODE, U, BS>(addrs, k, st0, w);
+            __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's copies have landed
+            __syncthreads();
+            compute_step<MODE, U, BS>(st0, acc, st, wr, wc);
+            __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): this wave's reads of the stage are done
+            __syncthreads();
+            st = next_step<LPU, NSUB, G::NCHUNK>(mt, nb, st);
+        }
+    }
+    store_unit<MODE, U, BS>(m, u, acc, wr, wc);
+}
+
+template <int MODE, int U, int BS>
+__global__ void __launch_bounds__((k5_nt<MODE, U>), 4)
+    k5s(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
+    static_assert(U == 128 && (MODE == QBSM_BF16 || MODE == QBSM_BF16X3), "single-stage kernel: BF16 modes, unit 128");
+    __shared__ __attribute__((aligned(1024))) uint8_t st0[k5_stage_bytes<MODE, U>];
+    __shared__ __attribute__((aligned(16))) uint8_t meta[kMetaSmall];
+    process_unit_serial<MODE, U, BS>(single, xcd_remap((int)blockIdx.x, single.nunits), st0, meta);
+}
+
 // The unit of this workgroup in a single-multiply launch (XCD-aware).
 __device__ __forceinline__ int launch_unit(const K5Member &m) { return xcd_remap((int)blockIdx.x, m.nunits); }
 
@@ -1203,6 +1305,19 @@ void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems
     if (persistent == 1) {
         k5<MODE, U, 0><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
         return;
+    }
+    if (persistent == 3) {
+        if constexpr (U == 128 && (MODE == QBSM_BF16 || MODE == QBSM_BF16X3)) {
+            if (bs == 64) {
+                k5s<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                return;
+            }
+            if (bs == 128) {
+                k5s<MODE, U, 128><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
+                return;
+            }
+        }
+        throw Error(QBSM_ERR_UNSUPPORTED, "single-stage schedule for this mode, unit and leaf size");
     }
     if (persistent == 2) {
         if constexpr (U <= 128 && MODE != QBSM_OZAKI_I8) {
@@ -1499,6 +1614,15 @@ int numeric_stream_grid(const Plan &p, qbsm_mode mode) {
     return (int)std::min<int64_t>(g, p.nunits);
 }
 
+// The automatic schedule takes the single-stage kernel for BF16 and BF16X3
+// plans at unit 128 with at most 1.25 unit-level pairs per unit (on the
+// random-block multiply: BF16 0.284 -> 0.256 ms, BF16X3 0.371 -> 0.348 ms;
+// FP32, whose 128-wide leaves take four steps, was 1% slower).
+bool numeric_single_stage(const Plan &p, qbsm_mode mode) {
+    return p.sched == 0 && p.unit == 128 && (p.bs == 64 || p.bs == 128) &&
+           (mode == QBSM_BF16 || mode == QBSM_BF16X3) && p.nunits > 0 && 4 * p.npairs <= 5 * p.nunits;
+}
+
 void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     if (!p.nunits) return;
     K5Member m = make_member(p, mode, out, s);
@@ -1506,6 +1630,8 @@ void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {
     const int sg = numeric_stream_grid(p, mode);
     if (sg > 0)
         k5_launch(mode, p.unit, nullptr, 1, nullptr, 0, nullptr, sg, 2, m, s);
+    else if (numeric_single_stage(p, mode))
+        k5_launch(mode, p.unit, nullptr, 1, nullptr, 0, nullptr, (int)p.nunits, 3, m, s);
     else
         k5_launch(mode, p.unit, nullptr, 1, nullptr, 0, nullptr, (int)p.nunits, 0, m, s);
 }

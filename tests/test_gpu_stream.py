@@ -155,3 +155,45 @@ def test_schedule_option_checked(q):
     _bitwise(values_np(q.Plan(A, B, unit=256, schedule=2).numeric("f32")), ref, "unit 256")
     ref = values_np(q.Plan(A, B, unit=64, schedule=1).numeric("ozaki"))
     _bitwise(values_np(q.Plan(A, B, unit=64, schedule=2).numeric("ozaki")), ref, "ozaki")
+
+
+def _from_mask(mask, bs, rng):
+    """Block matrix (U[-1,1] values) with the leaves of a boolean mask."""
+    ii, jj = np.nonzero(mask)
+    n = mask.shape[0] * bs
+    return W.BlockMatrix(n, n, bs, ii.astype(np.int32), jj.astype(np.int32),
+                         rng.uniform(-1.0, 1.0, size=(ii.size, bs * bs)), {"kind": "test"})
+
+
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+def test_single_stage_schedule(q, mode):
+    """The automatic schedule's single-stage kernel (BF16 modes at unit 128,
+    about one unit-level pair per unit) against the double-buffered kernel,
+    bit for bit, and against the oracle.  One unit holds 50 pairs, more than
+    one metadata batch (28 pairs of 2 x 2 leaves), among about 5500 units of
+    about one pair each."""
+    bs, nb = 64, 400
+    rng = np.random.default_rng(31)
+    ma = np.zeros((nb, nb), dtype=bool)
+    mb = np.zeros((nb, nb), dtype=bool)
+    ma[0, :100] = True      # C block (0, 0): 100 leaf products over K < 100
+    mb[:100, 0] = True
+    ma[2:, 200:] = rng.random((nb - 2, nb - 200)) < 0.01
+    mb[200:, 2:] = rng.random((nb - 200, nb - 2)) < 0.01
+    a, b = _from_mask(ma, bs, rng), _from_mask(mb, bs, rng)
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    ref = O.multiply(oa, ob)
+    A, B = upload(q, a), upload(q, b)
+    vals = {}
+    for sched in (0, 1):
+        P = q.Plan(A, B, unit=128, schedule=sched)
+        info = P.info()
+        C = P.numeric(mode)
+        torch.cuda.synchronize()
+        cr, cc = pattern_np(C)
+        assert np.array_equal(cr, ref.brow) and np.array_equal(cc, ref.bcol)
+        vals[sched] = values_np(C)
+    # the automatic schedule's condition for the single-stage kernel holds
+    assert 4 * info["npairs"] <= 5 * info["nunits"] and info["nunits"] > 1000
+    _bitwise(vals[0], vals[1], mode)
+    assert_product(vals[0], oa, ob, ref.vals, mode, what="single-stage")
