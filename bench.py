@@ -51,19 +51,19 @@ KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "d3f7389e96850f78",
+    "sources_sha256_16": "65f2b83b8444b89f",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 126210763093,
-        "bf16x3@256": 52165246327,
-        "bf16x3@64": 323983764864,
-        "f32@128": 204035100407,
-        "f32@256": 67761737600,
-        "f32@64": 337903877845,
-        "f64@128": 274845496709,
-        "f64@64": 726393625856,
-        "ozaki@128": 116678126373,
-        "ozaki@64": 558198889941,
+        "bf16x3@128": 131017451157,
+        "bf16x3@256": 53592299099,
+        "bf16x3@64": 324127315947,
+        "f32@128": 203972867840,
+        "f32@256": 67807421294,
+        "f32@64": 337976368085,
+        "f64@128": 272759314542,
+        "f64@64": 715494862763,
+        "ozaki@128": 120544873673,
+        "ozaki@64": 565436851499,
     },
 }
 
