@@ -51,19 +51,19 @@ KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "65f2b83b8444b89f",
+    "sources_sha256_16": "53ecf422ddbd942b",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 131017451157,
-        "bf16x3@256": 53592299099,
-        "bf16x3@64": 324127315947,
-        "f32@128": 203972867840,
-        "f32@256": 67807421294,
-        "f32@64": 337976368085,
-        "f64@128": 272759314542,
-        "f64@64": 715494862763,
-        "ozaki@128": 120544873673,
-        "ozaki@64": 565436851499,
+        "bf16x3@128": 121428061077,
+        "bf16x3@256": 49991038098,
+        "bf16x3@64": 324854373035,
+        "f32@128": 203712157019,
+        "f32@256": 67803449003,
+        "f32@64": 337808887211,
+        "f64@128": 430339324617,
+        "f64@64": 719756246773,
+        "ozaki@128": 116095875493,
+        "ozaki@64": 547641706453,
     },
 }
 

@@ -273,11 +273,12 @@ typedef struct {
     double spamm_tol;
     /* Schedule of the numeric phase (how workgroups take the plan's units;
      * results are the same bit for bit).  0 = automatic: one workgroup per
-     * unit, on a single-LDS-stage kernel that fits four workgroups per
-     * compute unit for QBSM_BF16 and QBSM_BF16X3 plans at unit 128 with at
-     * most 1.25 unit-level pairs per unit (about one leaf product per unit,
-     * where the multiply is bound by memory), else on the double-buffered
-     * kernel.  1 = one workgroup per unit, double-buffered kernel.
+     * unit, on a single-LDS-stage kernel that fits more workgroups per
+     * compute unit for QBSM_F64 plans at unit 128 and for QBSM_BF16 and
+     * QBSM_BF16X3 plans at unit 128 with at most 1.25 unit-level pairs per
+     * unit (about one leaf product per unit, where the multiply is bound by
+     * memory), else on the double-buffered kernel.  1 = one workgroup per
+     * unit, double-buffered kernel.
      * 2 = streamed where the mode and unit
      * allow it: resident workgroups each run every G-th unit, reading the
      * next unit's metadata and issuing its first operand copies before

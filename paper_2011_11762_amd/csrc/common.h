@@ -362,7 +362,7 @@ void pack_launch(Matrix &m, qbsm_mode mode, Role role, Pack &pk, hipStream_t s);
 // persistent: 0 = one workgroup per unit of `single` (grid = its units);
 // 1 = the work list of `members` / `items`; 2 = the streamed schedule of
 // `single` (grid = resident workgroups); 3 = one workgroup per unit on the
-// single-stage kernel (BF16 modes at unit 128).
+// single-stage kernel (BF16 modes and FP64 at unit 128).
 void k5_launch(qbsm_mode mode, int unit, const K5Member *members, int32_t nmembers_host_unused,
                const int2 *items, int64_t nitems, int32_t *counter, int grid, int persistent,
                const K5Member &single, hipStream_t s);

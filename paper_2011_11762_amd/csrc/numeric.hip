@@ -970,17 +970,19 @@ __device__ void process_stream(const K5Member &m, uint8_t *st0, uint8_t *st1, ui
     }
 }
 
-// Single-stage schedule for plans of about one leaf product per unit (the
-// HBM-bound random-block multiply): a unit is a metadata read, one or two
-// copies, a short MFMA burst and a store, each waiting on the one before, so
-// throughput comes from workgroups in flight rather than from overlap inside
-// one.  With one 32 KB LDS stage, a small metadata area and at most 128
-// vector registers (a 64 x 64 FP32 accumulator per wave), four workgroups fit
-// on a compute unit instead of two.  Each step copies, waits, computes and
-// leaves the stage with a barrier before the next copy; the MFMA order of
-// every accumulator is that of the double-buffered kernel, so the results are
-// the same bit for bit.  BF16 and BF16X3 at unit 128 (their 64-byte packed
-// lines make two steps of a 128-wide leaf).
+// Single-stage kernel: one 32 KB LDS stage and a small metadata area, so
+// that more workgroups share a compute unit and cover each other's waits.
+// Each step copies, waits, computes and leaves the stage with a barrier
+// before the next copy; the MFMA order of every accumulator is that of the
+// double-buffered kernel, so the results are the same bit for bit.
+// - BF16 and BF16X3 at unit 128, for plans of about one leaf product per
+//   unit (the HBM-bound random-block multiply, where a unit is a metadata
+//   read, one or two copies, a short MFMA burst and a store, each waiting on
+//   the one before): at most 128 vector registers, four workgroups per
+//   compute unit instead of two.
+// - FP64 at unit 128, for every plan: the double-buffered FP64 kernel keeps
+//   its accumulators and fragments in 256 + 143 registers and runs one
+//   workgroup per compute unit; this one needs 168 and runs three.
 constexpr int kMetaSmall = 2048;
 
 template <int MODE, int U, int BS>
@@ -1064,9 +1066,10 @@ __device__ void process_unit_serial(const K5Member &m, int u, uint8_t *st0, uint
 }
 
 template <int MODE, int U, int BS>
-__global__ void __launch_bounds__((k5_nt<MODE, U>), 4)
+__global__ void __launch_bounds__((k5_nt<MODE, U>), (MODE == QBSM_F64 ? 2 : 4))
     k5s(K5Member single, const K5Member *members, const int2 *items, int64_t nitems, int32_t *counter) {
-    static_assert(U == 128 && (MODE == QBSM_BF16 || MODE == QBSM_BF16X3), "single-stage kernel: BF16 modes, unit 128");
+    static_assert(U == 128 && (MODE == QBSM_BF16 || MODE == QBSM_BF16X3 || MODE == QBSM_F64),
+                  "single-stage kernel: BF16 modes and FP64, unit 128");
     __shared__ __attribute__((aligned(1024))) uint8_t st0[k5_stage_bytes<MODE, U>];
     __shared__ __attribute__((aligned(16))) uint8_t meta[kMetaSmall];
     process_unit_serial<MODE, U, BS>(single, xcd_remap((int)blockIdx.x, single.nunits), st0, meta);
@@ -1307,7 +1310,7 @@ void launch_u(int bs, const K5Member *members, const int2 *items, int64_t nitems
         return;
     }
     if (persistent == 3) {
-        if constexpr (U == 128 && (MODE == QBSM_BF16 || MODE == QBSM_BF16X3)) {
+        if constexpr (U == 128 && (MODE == QBSM_BF16 || MODE == QBSM_BF16X3 || MODE == QBSM_F64)) {
             if (bs == 64) {
                 k5s<MODE, U, 64><<<grid, NT, 0, s>>>(single, members, items, nitems, counter);
                 return;
@@ -1614,13 +1617,17 @@ int numeric_stream_grid(const Plan &p, qbsm_mode mode) {
     return (int)std::min<int64_t>(g, p.nunits);
 }
 
-// The automatic schedule takes the single-stage kernel for BF16 and BF16X3
-// plans at unit 128 with at most 1.25 unit-level pairs per unit (on the
-// random-block multiply: BF16 0.284 -> 0.256 ms, BF16X3 0.371 -> 0.348 ms;
-// FP32, whose 128-wide leaves take four steps, was 1% slower).
+// The automatic schedule takes the single-stage kernel for FP64 plans at
+// unit 128 (decay workload 142.8 -> 136.7 ms, banded N = 1e5 128.2 ->
+// 116.2 ms) and for BF16 and BF16X3 plans at unit 128 with at most 1.25
+// unit-level pairs per unit (random-block multiply: BF16 0.284 -> 0.256 ms,
+// BF16X3 0.371 -> 0.348 ms).  Measured slower, so not taken: FP32 (whose
+// 128-wide leaves take four steps) and BF16X3 on dense units (21.1 -> 30.7
+// ms on the decay workload).
 bool numeric_single_stage(const Plan &p, qbsm_mode mode) {
-    return p.sched == 0 && p.unit == 128 && (p.bs == 64 || p.bs == 128) &&
-           (mode == QBSM_BF16 || mode == QBSM_BF16X3) && p.nunits > 0 && 4 * p.npairs <= 5 * p.nunits;
+    if (p.sched != 0 || p.unit != 128 || (p.bs != 64 && p.bs != 128) || p.nunits <= 0) return false;
+    if (mode == QBSM_F64) return true;
+    return (mode == QBSM_BF16 || mode == QBSM_BF16X3) && 4 * p.npairs <= 5 * p.nunits;
 }
 
 void numeric_launch(Plan &p, qbsm_mode mode, Matrix &out, hipStream_t s) {

@@ -165,7 +165,7 @@ def _from_mask(mask, bs, rng):
                          rng.uniform(-1.0, 1.0, size=(ii.size, bs * bs)), {"kind": "test"})
 
 
-@pytest.mark.parametrize("mode", ["bf16", "bf16x3"])
+@pytest.mark.parametrize("mode", ["bf16", "bf16x3", "f64"])
 def test_single_stage_schedule(q, mode):
     """The automatic schedule's single-stage kernel (BF16 modes at unit 128,
     about one unit-level pair per unit) against the double-buffered kernel,
@@ -197,3 +197,25 @@ def test_single_stage_schedule(q, mode):
     assert 4 * info["npairs"] <= 5 * info["nunits"] and info["nunits"] > 1000
     _bitwise(vals[0], vals[1], mode)
     assert_product(vals[0], oa, ob, ref.vals, mode, what="single-stage")
+
+
+@pytest.mark.parametrize("case", [(300, 260, 200, 64, 0.5, 1), (400, 300, 520, 128, 0.6, 3),
+                                  (64 * 9 + 5, 64 * 7, 64 * 11 + 63, 64, 0.3, 5)],
+                         ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-bs{c[3]}")
+def test_single_stage_f64_dense(q, case):
+    """FP64 at unit 128 takes the single-stage kernel under the automatic
+    schedule on every plan: against the double-buffered kernel (bit for bit)
+    and the oracle, on ragged rectangular products with several pairs per
+    unit."""
+    m, k, n, bs, p, seed = case
+    a, b = W.small_random(m, k, n, bs, p, seed)
+    oa, ob = O.from_workload(a), O.from_workload(b)
+    ref = O.multiply(oa, ob)
+    A, B = upload(q, a), upload(q, b)
+    vals = {}
+    for sched in (0, 1):
+        C = q.Plan(A, B, unit=128, schedule=sched).numeric("f64")
+        torch.cuda.synchronize()
+        vals[sched] = values_np(C)
+    _bitwise(vals[0], vals[1], "f64")
+    assert_product(vals[0], oa, ob, ref.vals, "f64", what="single-stage f64")
