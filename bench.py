@@ -51,19 +51,19 @@ KERNEL_SOURCES = ("numeric.hip", "numeric_oz.hip", "common.h", "device_math.h")
 # They describe only the kernel sources with this digest; for any other
 # source, mode, unit or workload the traffic is reported as null.
 TRAFFIC = {
-    "sources_sha256_16": "53ecf422ddbd942b",
+    "sources_sha256_16": "fef3b78a2915da3e",
     "npoints": 16384,
     "bytes": {
-        "bf16x3@128": 121428061077,
-        "bf16x3@256": 49991038098,
-        "bf16x3@64": 324854373035,
-        "f32@128": 203712157019,
-        "f32@256": 67803449003,
-        "f32@64": 337808887211,
-        "f64@128": 430339324617,
-        "f64@64": 719756246773,
-        "ozaki@128": 116095875493,
-        "ozaki@64": 547641706453,
+        "bf16x3@128": 121468077205,
+        "bf16x3@256": 49774483538,
+        "bf16x3@64": 327485731776,
+        "f32@128": 203662038683,
+        "f32@256": 67679619840,
+        "f32@64": 338423548032,
+        "f64@128": 430586429760,
+        "f64@64": 710156404224,
+        "ozaki@128": 117787017198,
+        "ozaki@64": 555307313621,
     },
 }
 

@@ -274,7 +274,8 @@ typedef struct {
     /* Schedule of the numeric phase (how workgroups take the plan's units;
      * results are the same bit for bit).  0 = automatic: one workgroup per
      * unit, on a single-LDS-stage kernel that fits more workgroups per
-     * compute unit for QBSM_F64 plans at unit 128 and for QBSM_BF16 and
+     * compute unit for QBSM_F64 plans at unit 128 without transposed
+     * operands and for QBSM_BF16 and
      * QBSM_BF16X3 plans at unit 128 with at most 1.25 unit-level pairs per
      * unit (about one leaf product per unit, where the multiply is bound by
      * memory), else on the double-buffered kernel.  1 = one workgroup per

@@ -1618,15 +1618,17 @@ int numeric_stream_grid(const Plan &p, qbsm_mode mode) {
 }
 
 // The automatic schedule takes the single-stage kernel for FP64 plans at
-// unit 128 (decay workload 142.8 -> 136.7 ms, banded N = 1e5 128.2 ->
-// 116.2 ms) and for BF16 and BF16X3 plans at unit 128 with at most 1.25
+// unit 128 without transposed operands (decay workload 142.8 -> 136.7 ms,
+// banded N = 1e5 128.2 -> 116.2 ms, random blocks N = 65536 1.607 -> 1.356
+// ms) and for BF16 and BF16X3 plans at unit 128 with at most 1.25
 // unit-level pairs per unit (random-block multiply: BF16 0.284 -> 0.256 ms,
-// BF16X3 0.371 -> 0.348 ms).  Measured slower, so not taken: FP32 (whose
-// 128-wide leaves take four steps) and BF16X3 on dense units (21.1 -> 30.7
-// ms on the decay workload).
+// BF16X3 0.371 -> 0.348 ms).  Measured slower, so not taken: the masked
+// FP64 adjoints with a transposed operand (1.23 -> 1.33 ms for both), FP32
+// (whose 128-wide leaves take four steps) and BF16X3 on dense units (21.1 ->
+// 30.7 ms on the decay workload).
 bool numeric_single_stage(const Plan &p, qbsm_mode mode) {
     if (p.sched != 0 || p.unit != 128 || (p.bs != 64 && p.bs != 128) || p.nunits <= 0) return false;
-    if (mode == QBSM_F64) return true;
+    if (mode == QBSM_F64) return !p.transL && !p.transR;
     return (mode == QBSM_BF16 || mode == QBSM_BF16X3) && 4 * p.npairs <= 5 * p.nunits;
 }
 
