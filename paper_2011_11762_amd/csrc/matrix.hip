@@ -52,8 +52,86 @@ __global__ void k_keys(const int32_t *brow, const int32_t *bcol, int64_t n, int6
     bool ok = i >= 0 && j >= 0 && i < nbr && j < nbc;
     valid[t] = ok ? 1 : 0;
     keys[t] = ok ? morton2((uint32_t)i, (uint32_t)j) : 0u;
-    ksort[t] = 0;
+    if (ksort) ksort[t] = 0;
     if (!ok) st->range_err = 1;
+}
+
+// Small inputs in one workgroup: the keys, the range check, the duplicate
+// check and the rank of every in-range key among the distinct keys (a
+// bitmap over the key range and the scan of its words' bit counts, both in
+// LDS), in place of the clearing, key, bitmap and scan launches of larger
+// inputs.  Writes the whole status; nkept is the distinct count, which is
+// the kept count when no block is dropped.
+constexpr int kSetSmallThreads = 1024;
+constexpr int kSetSmallWords = 8192;            // key range up to 2^18 (block grid side up to 512)
+constexpr int64_t kSetSmallBlocks = 16384;
+
+__global__ void __launch_bounds__(kSetSmallThreads) k_set_small(const int32_t *brow, const int32_t *bcol, int64_t n,
+                                                                int64_t nbr, int64_t nbc, int nw, uint32_t *keys,
+                                                                uint8_t *valid, int32_t *rank, int32_t *ksort,
+                                                                SetStatus *st) {
+    __shared__ uint32_t bm[kSetSmallWords];
+    __shared__ int32_t ws[kSetSmallWords];
+    __shared__ int32_t wsum[kSetSmallThreads / 64];
+    __shared__ int32_t bad[2];
+    for (int w = threadIdx.x; w < nw; w += kSetSmallThreads) bm[w] = 0u;
+    if (threadIdx.x < 2) bad[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < n; t += kSetSmallThreads) {
+        const int32_t i = brow[t], j = bcol[t];
+        const bool ok = i >= 0 && j >= 0 && i < nbr && j < nbc;
+        const uint32_t k = ok ? morton2((uint32_t)i, (uint32_t)j) : 0u;
+        valid[t] = ok ? 1 : 0;
+        keys[t] = k;
+        if (ksort) ksort[t] = 0;
+        if (ok) {
+            const uint32_t bit = 1u << (k & 31u);
+            if (atomicOr(&bm[k >> 5], bit) & bit) bad[1] = 1;
+        } else {
+            bad[0] = 1;
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the words' bit counts: `per` consecutive words a thread
+    const int per = (nw + kSetSmallThreads - 1) / kSetSmallThreads;
+    const int w0 = (int)threadIdx.x * per;
+    int32_t own = 0;
+    for (int q = 0; q < per; ++q)
+        if (w0 + q < nw) own += __popc(bm[w0 + q]);
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    int32_t inc = own;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t v = __shfl_up(inc, o);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int q = 0; q < kSetSmallThreads / 64; ++q) {
+            const int32_t v = wsum[q];
+            wsum[q] = acc;
+            acc += v;
+        }
+        st->range_err = bad[0];
+        st->dup = bad[1];
+        st->ndistinct = acc;
+        st->nkept = acc;
+    }
+    __syncthreads();
+    int32_t run = wsum[wave] + inc - own;
+    for (int q = 0; q < per; ++q) {
+        if (w0 + q < nw) {
+            ws[w0 + q] = run;
+            run += __popc(bm[w0 + q]);
+        }
+    }
+    __syncthreads();
+    // each thread reads back the keys and flags it wrote itself
+    for (int64_t t = threadIdx.x; t < n; t += kSetSmallThreads) {
+        const uint32_t k = keys[t];
+        rank[t] = valid[t] ? ws[k >> 5] + __popc(bm[k >> 5] & ((1u << (k & 31u)) - 1u)) : -1;
+    }
 }
 
 // FP64 Frobenius norm of the logical part of each block; keep iff not (norm < tol).
@@ -106,15 +184,9 @@ __global__ void __launch_bounds__(256) k_norm_keep(const double *__restrict__ va
     }
 }
 
-__global__ void k_copy_flags(const uint8_t *valid, int64_t n, uint8_t *keep, const int32_t *rank, int32_t *ksort) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    keep[t] = valid[t];
-    if (valid[t] && rank[t] >= 0) ksort[rank[t]] = 1;
-}
-
 // Scatter kept blocks into Morton order, zeroing the padding: a kept block
-// goes to the rank of its key among the kept keys, kscan[rank among all keys].
+// goes to the rank of its key among the kept keys, kscan[rank among all keys]
+// (the rank itself when kscan is null: no block dropped).
 __global__ void __launch_bounds__(256) k_store_blocks(const double *__restrict__ vals, const int32_t *brow,
                                                       const int32_t *bcol, const uint32_t *keys,
                                                       const uint8_t *keep, const int32_t *rank,
@@ -124,7 +196,7 @@ __global__ void __launch_bounds__(256) k_store_blocks(const double *__restrict__
     int64_t t = blockIdx.x;
     if (t >= n) return;
     if (!keep[t]) return;
-    const int32_t r = kscan[rank[t]];
+    const int32_t r = kscan ? kscan[rank[t]] : rank[t];
     const int64_t mr = min((int64_t)bs, nrows - (int64_t)brow[t] * bs);
     const int64_t nc = min((int64_t)bs, ncols - (int64_t)bcol[t] * bs);
     const int64_t n2 = (int64_t)bs * bs;
@@ -636,39 +708,52 @@ int64_t matrix_set_blocks(Matrix &m, int64_t n, const int32_t *brow, const int32
     QB_CHECK(!(drop_tol < 0.0) && !std::isnan(drop_tol), QBSM_ERR_ARG, "drop_tol must be >= 0");
     QB_CHECK(n <= (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many blocks");
     matrix_settle(m, s);  // a pack made ahead may still read the old values
+    // Without a drop tolerance every in-range block is kept (a repeated or
+    // out-of-range one fails the call), so the kept rank is the rank among
+    // the distinct keys: no keep flags, no scan of them.
+    const bool drop = drop_tol > 0.0;
     DArr<SetStatus> st(1, s);
-    QB_HIP(hipMemsetAsync(st.p, 0, sizeof(SetStatus), s));
     DArr<uint32_t> keys(n ? n : 1, s);
-    DArr<uint8_t> valid(n ? n : 1, s), keep(n ? n : 1, s);
+    DArr<uint8_t> valid(n ? n : 1, s), keep;
     // rank: of each in-range block's key among the distinct input keys;
     // ksort: kept flags by that rank, whose scan kscan ranks the kept keys
-    DArr<int32_t> rank(n ? n : 1, s), ksort(n ? n : 1, s), kscan(n + 1, s);
-    const uint64_t range = (uint64_t)1 << (2 * ceil_log2(m.nbr > m.nbc ? m.nbr : m.nbc));
-    if (n) {
-        k_keys<<<grid_for(n, 256), 256, 0, s>>>(brow, bcol, n, m.nbr, m.nbc, keys.p, valid.p, st.p, ksort.p);
-        QB_LAUNCH_CHECK();
+    DArr<int32_t> rank(n ? n : 1, s), ksort, kscan;
+    if (drop) {
+        keep.alloc(n ? n : 1, s);
+        ksort.alloc(n ? n : 1, s);
+        kscan.alloc(n + 1, s);
     }
-    // duplicates among all in-range input blocks
-    bitmap_rank(keys.p, valid.p, n, range, rank.p, &st.p->dup, &st.p->ndistinct, s);
-    if (n) {
-        if (drop_tol > 0.0) {
-            k_norm_keep<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, valid.p, n, m.bs, m.nrows, m.ncols,
-                                                    drop_tol, keep.p, rank.p, ksort.p);
-        } else {
-            k_copy_flags<<<grid_for(n, 256), 256, 0, s>>>(valid.p, n, keep.p, rank.p, ksort.p);
+    const uint64_t range = (uint64_t)1 << (2 * ceil_log2(m.nbr > m.nbc ? m.nbr : m.nbc));
+    const uint64_t nw = (range + 31) / 32;
+    if (n <= kSetSmallBlocks && nw <= (uint64_t)kSetSmallWords) {
+        k_set_small<<<1, kSetSmallThreads, 0, s>>>(brow, bcol, n, m.nbr, m.nbc, (int)nw, keys.p, valid.p, rank.p,
+                                                   ksort.p, st.p);
+        QB_LAUNCH_CHECK();
+    } else {
+        QB_HIP(hipMemsetAsync(st.p, 0, sizeof(SetStatus), s));
+        if (n) {
+            k_keys<<<grid_for(n, 256), 256, 0, s>>>(brow, bcol, n, m.nbr, m.nbc, keys.p, valid.p, st.p, ksort.p);
+            QB_LAUNCH_CHECK();
         }
+        // duplicates among all in-range input blocks
+        bitmap_rank(keys.p, valid.p, n, range, rank.p, &st.p->dup, &st.p->ndistinct, s);
+    }
+    if (n && drop) {
+        k_norm_keep<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, valid.p, n, m.bs, m.nrows, m.ncols, drop_tol,
+                                                keep.p, rank.p, ksort.p);
         QB_LAUNCH_CHECK();
         exclusive_scan_i32(ksort.p, kscan.p, n, &st.p->nkept, s);
     }
     SetStatus h = read_back(st.p, s);
     QB_CHECK(!h.range_err, QBSM_ERR_PATTERN, "block coordinate outside the block grid");
     QB_CHECK(!h.dup, QBSM_ERR_PATTERN, "repeated block coordinate");
-    const int64_t nk = h.nkept;
+    const int64_t nk = drop ? h.nkept : h.ndistinct;
     DArr<double> pool(nk * (int64_t)m.bs * m.bs, s);
     DArr<uint32_t> okeys(nk, s);
     if (n && nk) {
-        k_store_blocks<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, keys.p, keep.p, rank.p, kscan.p, n, m.bs,
-                                                   m.nrows, m.ncols, pool.p, okeys.p);
+        k_store_blocks<<<(unsigned)n, 256, 0, s>>>(vals, brow, bcol, keys.p, drop ? keep.p : valid.p, rank.p,
+                                                   drop ? kscan.p : nullptr, n, m.bs, m.nrows, m.ncols, pool.p,
+                                                   okeys.p);
         QB_LAUNCH_CHECK();
     }
     m.v64 = std::move(pool);
