@@ -94,7 +94,8 @@ def parse():
     ap.add_argument("--no-legs", action="store_true",
                     help="decay workload only: leave out the compact legs of the other workloads (N 2048 "
                          "banded FP64, random blocks, batched, forward + backward)")
-    ap.add_argument("--leg-steps", type=int, default=3, help="timed steps of each compact leg")
+    ap.add_argument("--leg-steps", type=int, default=3,
+                    help="timed steps of the batched leg (the millisecond-scale legs time 20 times as many)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of MIB MiB (reference for HBM byte counters)")
@@ -966,9 +967,12 @@ def main():
         torch.cuda.empty_cache()
         legs = {}
         ls, lw = max(args.leg_steps, 1), 1
-        for name, fn in (("banded-n2048-f64", lambda: leg_config1(torch, qbsm, W, ls, lw)),
-                         ("random-blocks-n65536", lambda: leg_config3(torch, qbsm, W, ls, lw)),
-                         ("forward-backward-n16384-f32", lambda: leg_config5(torch, qbsm, W, ls, lw)),
+        # the millisecond-scale legs time 20 times as many steps (a few tens of
+        # ms each), after a few warmup steps
+        ms_s, ms_w = 20 * ls, 5
+        for name, fn in (("banded-n2048-f64", lambda: leg_config1(torch, qbsm, W, ms_s, ms_w)),
+                         ("random-blocks-n65536", lambda: leg_config3(torch, qbsm, W, ms_s, ms_w)),
+                         ("forward-backward-n16384-f32", lambda: leg_config5(torch, qbsm, W, ms_s, ms_w)),
                          ("batched-256-f32", lambda: leg_config4(torch, qbsm, W, ls, lw))):
             t_leg = time.perf_counter()
             legs[name] = fn()

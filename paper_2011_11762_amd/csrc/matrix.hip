@@ -35,6 +35,11 @@ __device__ __forceinline__ void demorton2(uint32_t k, uint32_t &i, uint32_t &j) 
     }
 }
 
+// Key of the level-`sh / 2`-up ancestor: the key shifted right by sh bits
+// (sh = 32 at the root of a depth-16 tree, where a plain shift of a 32-bit
+// value is undefined).
+__device__ __forceinline__ uint32_t key_above(uint32_t k, int sh) { return sh < 32 ? k >> sh : 0u; }
+
 struct SetStatus {
     int32_t range_err;
     int32_t dup;
@@ -252,7 +257,7 @@ __global__ void k_tree_flags_all(const uint32_t *lkeys, int64_t n, int D, LevelP
     const uint32_t kp = i ? lkeys[i - 1] : 0u;
     for (int l = 0; l < D; ++l) {
         const int sh = 2 * (D - l);
-        flags[(int64_t)l * n + i] = (i == 0 || (k >> sh) != (kp >> sh)) ? 1 : 0;
+        flags[(int64_t)l * n + i] = (i == 0 || key_above(k, sh) != key_above(kp, sh)) ? 1 : 0;
         // every slot starts nil; the link pass (a later launch) fills the live ones
         reinterpret_cast<int4 *>(lp.child[l])[i] = make_int4(-1, -1, -1, -1);
     }
@@ -271,7 +276,7 @@ __global__ void k_tree_link_all(const uint32_t *lkeys, int64_t n, int D, LevelPt
         const int32_t start = flags[f];
         const int32_t node = scan[f] - scan[(int64_t)l * n] + start - 1;
         const int sh = 2 * (D - l);
-        if (start) lp.key[l][node] = k >> sh;
+        if (start) lp.key[l][node] = key_above(k, sh);
         const bool child_start = l + 1 == D || flags[f + n];
         if (child_start) lp.child[l][(int64_t)node * 4 + ((k >> (sh - 2)) & 3u)] = below;
         below = node;
@@ -279,6 +284,78 @@ __global__ void k_tree_link_all(const uint32_t *lkeys, int64_t n, int D, LevelPt
     if (i == 0) {
         for (int l = 0; l < D; ++l) counts[l] = scan[(int64_t)(l + 1) * n] - scan[(int64_t)l * n];
         counts[D] = n;
+    }
+}
+
+// Small trees in one workgroup, in place of the flag, scan and link
+// launches of larger ones.  A thread takes `per` consecutive leaves; level by
+// level from the leaves up, a node starts at a leaf whose key above that
+// level differs from the previous leaf's, the workgroup scan of the starts
+// numbers the nodes, and `below` (LDS) holds each leaf's node one level
+// down, whose slot in its parent is linked where that node starts.
+constexpr int kTreeSmallThreads = 1024;
+constexpr int64_t kTreeSmallLeaves = 16384;
+
+__global__ void __launch_bounds__(kTreeSmallThreads) k_tree_small(const uint32_t *lkeys, int n, int D, LevelPtrs lp,
+                                                                  int64_t *counts) {
+    __shared__ int32_t below[kTreeSmallLeaves];
+    __shared__ int32_t wsum[kTreeSmallThreads / 64];
+    const int per = (n + kTreeSmallThreads - 1) / kTreeSmallThreads;
+    const int i0 = (int)threadIdx.x * per;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    for (int q = 0; q < per; ++q) {
+        const int i = i0 + q;
+        if (i < n) {
+            lp.key[D][i] = lkeys[i];
+            below[i] = i;  // the leaf itself at level D
+        }
+    }
+    // every slot starts nil (no level has more nodes than leaves)
+    for (int l = 0; l < D; ++l)
+        for (int e = (int)threadIdx.x; e < n; e += kTreeSmallThreads)
+            reinterpret_cast<int4 *>(lp.child[l])[e] = make_int4(-1, -1, -1, -1);
+    if (threadIdx.x == 0) counts[D] = n;
+    __syncthreads();
+    for (int l = D - 1; l >= 0; --l) {
+        const int sh = 2 * (D - l);
+        int own = 0;
+        for (int q = 0; q < per; ++q) {
+            const int i = i0 + q;
+            if (i < n && (i == 0 || key_above(lkeys[i], sh) != key_above(lkeys[i - 1], sh))) ++own;
+        }
+        int inc = own;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o);
+            if (lane >= o) inc += v;
+        }
+        if (lane == 63) wsum[wave] = inc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int acc = 0;
+            for (int w = 0; w < kTreeSmallThreads / 64; ++w) {
+                const int v = wsum[w];
+                wsum[w] = acc;
+                acc += v;
+            }
+            counts[l] = acc;
+        }
+        __syncthreads();
+        int node = wsum[wave] + inc - own - 1;  // the last node started before leaf i0
+        for (int q = 0; q < per; ++q) {
+            const int i = i0 + q;
+            if (i >= n) break;
+            const uint32_t k = lkeys[i];
+            const uint32_t kp = i ? lkeys[i - 1] : 0u;
+            if (i == 0 || key_above(k, sh) != key_above(kp, sh)) {
+                ++node;
+                lp.key[l][node] = key_above(k, sh);
+            }
+            // leaf i starts its node one level down: link that node
+            if (l + 1 == D || i == 0 || (k >> (sh - 2)) != (kp >> (sh - 2)))
+                lp.child[l][node * 4 + ((k >> (sh - 2)) & 3u)] = below[i];
+            below[i] = node;  // only this thread reads or writes leaf i's entry
+        }
+        __syncthreads();  // wsum is reused by the next level
     }
 }
 
@@ -847,7 +924,13 @@ Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
             lp.child[l] = t->child[l].p;
         }
     }
-    if (cap && D > 0) {
+    if (cap && D > 0 && cap <= kTreeSmallLeaves) {
+        DArr<int64_t> counts(D + 1, s);
+        k_tree_small<<<1, kTreeSmallThreads, 0, s>>>(m.keys.p, (int)cap, D, lp, counts.p);
+        QB_LAUNCH_CHECK();
+        QB_HIP(hipMemcpyAsync(t->n.data(), counts.p, (D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+    } else if (cap && D > 0) {
         DArr<int64_t> counts(D + 1, s);
         DArr<int32_t> flags(D * cap, s), scan(D * cap + 1, s);
         k_tree_flags_all<<<grid_for(cap, 256), 256, 0, s>>>(m.keys.p, cap, D, lp, flags.p);

@@ -116,3 +116,43 @@ def test_set_blocks_many_with_repeat(q):
     with pytest.raises(q.QbsmError) as e:
         M.set_blocks(_dev(brow), _dev(bcol), _dev(vals))
     assert e.value.status == 3
+
+
+@pytest.mark.parametrize("nblk", [6, 20000], ids=["one-workgroup-tree", "multi-launch-tree"])
+def test_depth16_grid_against_oracle(q, nblk):
+    """A block grid of side 65536 (quadtree depth 16, the largest): the root
+    level's keys shift by all 32 bits of a key.  Blocks include the grid's
+    corners; the product's pattern and values against the oracle."""
+    from oracle import oracle as O
+
+    bs, side = 32, 65536
+    n = side * bs
+    rng = np.random.default_rng(17)
+    if nblk == 6:
+        ar = np.array([0, 0, side - 1, 40000, side - 1, 123], dtype=np.int32)
+        ac = np.array([0, side - 1, side - 1, 123, 0, 40000], dtype=np.int32)
+    else:
+        cells = rng.choice(side * side, size=nblk, replace=False)
+        ar, ac = (cells // side).astype(np.int32), (cells % side).astype(np.int32)
+    # B's rows are A's columns (so every A block meets B blocks), columns random
+    br = np.concatenate([ac, rng.integers(0, side, size=nblk // 2).astype(np.int32)])
+    bc = np.concatenate([ar[::-1], rng.integers(0, side, size=nblk // 2).astype(np.int32)])
+    keyb = np.unique(br.astype(np.int64) * side + bc, return_index=True)[1]
+    br, bc = br[keyb], bc[keyb]
+    av = rng.uniform(-1, 1, size=(ar.size, bs * bs))
+    bv = rng.uniform(-1, 1, size=(br.size, bs * bs))
+    A, B = q.Matrix(n, n, bs), q.Matrix(n, n, bs)
+    assert A.set_blocks(_dev(ar), _dev(ac), _dev(av)) == ar.size
+    assert B.set_blocks(_dev(br), _dev(bc), _dev(bv)) == br.size
+    oa = O.canonical(n, n, bs, ar, ac, av, 0.0)
+    ob = O.canonical(n, n, bs, br, bc, bv, 0.0)
+    ref = O.multiply(oa, ob)
+    P = q.Plan(A, B)
+    assert P.info()["nprod"] == ref.I.size
+    C = P.numeric("f64")
+    torch.cuda.synchronize()
+    r, c = C.pattern()
+    assert np.array_equal(r.cpu().numpy(), ref.brow) and np.array_equal(c.cpu().numpy(), ref.bcol)
+    got = C.values().cpu().numpy()
+    err = np.linalg.norm(got - ref.vals) / max(np.linalg.norm(ref.vals), 1e-300)
+    assert err < 1e-12
