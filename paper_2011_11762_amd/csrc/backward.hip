@@ -17,6 +17,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "common.h"
+#include "trees.h"
 
 namespace qbsm {
 
@@ -128,6 +129,8 @@ std::unique_ptr<Plan> plan_backward(const Plan &f, Matrix *dC, int which, hipStr
              "dC shape or leaf size differs from the product");
     Matrix *X = which == 0 ? f.L : f.R;  // the operand whose adjoint is formed (its pattern is the mask)
     const int Lw = f.D - f.s;
+    Matrix *const ops[2] = {X, dC};
+    matrix_trees(ops, 2, f.D, s);
     Tree &tX = matrix_tree(*X, f.D, s);
     Tree &tC = matrix_tree(*dC, f.D, s);
     static uint64_t next_id = 0;

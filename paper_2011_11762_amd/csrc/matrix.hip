@@ -1,5 +1,6 @@
 // Matrix handles: construction from leaf blocks, block truncation, the
 // sparse quadtree (Morton-ordered node tables), readback and operand packing.
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -7,6 +8,7 @@
 
 #include "common.h"
 #include "device_math.h"
+#include "trees.h"
 
 namespace qbsm {
 
@@ -904,14 +906,16 @@ void matrix_store_f32(Matrix &m, hipStream_t s) {
     m.packs.clear();
 }
 
-Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
-    auto it = m.trees.find(D);
-    if (it != m.trees.end()) return *it->second;
+namespace {
+// Queues the build of m's depth-D tree.  Level sizes that only the device
+// knows are written to counts[0..D] (dev_counts set) for the caller's read.
+std::unique_ptr<Tree> tree_queue(Matrix &m, int D, int64_t *counts, hipStream_t s, bool &dev_counts) {
     auto t = std::make_unique<Tree>();
     t->D = D;
     t->n.assign(D + 1, 0);
     t->child.resize(D);
     t->key.resize(D + 1);
+    dev_counts = false;
     const int64_t cap = m.nblk;  // nodes of any level <= leaves
     QB_CHECK(D <= 16, QBSM_ERR_UNSUPPORTED, "block grid side above 65536");
     QB_CHECK((int64_t)D * cap < (int64_t)INT32_MAX, QBSM_ERR_UNSUPPORTED, "too many leaves for the tree build");
@@ -925,28 +929,58 @@ Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
         }
     }
     if (cap && D > 0 && cap <= kTreeSmallLeaves) {
-        DArr<int64_t> counts(D + 1, s);
-        k_tree_small<<<1, kTreeSmallThreads, 0, s>>>(m.keys.p, (int)cap, D, lp, counts.p);
+        k_tree_small<<<1, kTreeSmallThreads, 0, s>>>(m.keys.p, (int)cap, D, lp, counts);
         QB_LAUNCH_CHECK();
-        QB_HIP(hipMemcpyAsync(t->n.data(), counts.p, (D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        QB_HIP(hipStreamSynchronize(s));
+        dev_counts = true;
     } else if (cap && D > 0) {
-        DArr<int64_t> counts(D + 1, s);
         DArr<int32_t> flags(D * cap, s), scan(D * cap + 1, s);
         k_tree_flags_all<<<grid_for(cap, 256), 256, 0, s>>>(m.keys.p, cap, D, lp, flags.p);
         QB_LAUNCH_CHECK();
         exclusive_scan_i32(flags.p, scan.p, D * cap, nullptr, s);
-        k_tree_link_all<<<grid_for(cap, 256), 256, 0, s>>>(m.keys.p, cap, D, lp, flags.p, scan.p, counts.p);
+        k_tree_link_all<<<grid_for(cap, 256), 256, 0, s>>>(m.keys.p, cap, D, lp, flags.p, scan.p, counts);
         QB_LAUNCH_CHECK();
-        QB_HIP(hipMemcpyAsync(t->n.data(), counts.p, (D + 1) * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        QB_HIP(hipStreamSynchronize(s));
+        dev_counts = true;
     } else if (cap) {  // D == 0: a single leaf is the root
         QB_HIP(hipMemcpyAsync(t->key[0].p, m.keys.p, sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
         t->n[0] = cap;
     }
-    Tree &ref = *t;
-    m.trees[D] = std::move(t);
-    return ref;
+    return t;
+}
+}  // namespace
+
+void matrix_trees(Matrix *const *ms, int nm, int D, hipStream_t s) {
+    std::vector<Matrix *> todo;
+    for (int i = 0; i < nm; ++i) {
+        Matrix *m = ms[i];
+        if (m && m->trees.find(D) == m->trees.end() && std::find(todo.begin(), todo.end(), m) == todo.end())
+            todo.push_back(m);
+    }
+    if (todo.empty()) return;
+    const size_t nt = todo.size(), stride = (size_t)D + 1;
+    DArr<int64_t> counts(nt * stride, s);
+    std::vector<std::unique_ptr<Tree>> built(nt);
+    std::vector<char> dev(nt, 0);
+    bool any = false;
+    for (size_t k = 0; k < nt; ++k) {
+        bool d = false;
+        built[k] = tree_queue(*todo[k], D, counts.p + k * stride, s, d);
+        dev[k] = d;
+        any = any || d;
+    }
+    if (any) {  // one host read for every tree's level sizes
+        std::vector<int64_t> h(nt * stride);
+        QB_HIP(hipMemcpyAsync(h.data(), counts.p, h.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        QB_HIP(hipStreamSynchronize(s));
+        for (size_t k = 0; k < nt; ++k)
+            if (dev[k]) std::copy(h.begin() + k * stride, h.begin() + (k + 1) * stride, built[k]->n.begin());
+    }
+    for (size_t k = 0; k < nt; ++k) todo[k]->trees[D] = std::move(built[k]);
+}
+
+Tree &matrix_tree(Matrix &m, int D, hipStream_t s) {
+    Matrix *one = &m;
+    matrix_trees(&one, 1, D, s);
+    return *m.trees.find(D)->second;
 }
 
 const int32_t *tree_desc(Matrix &m, Tree &t, int s_lvl, hipStream_t st) {

@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "trees.h"
 
 namespace qbsm {
 
@@ -809,6 +810,8 @@ std::unique_ptr<Plan> plan_build(Matrix *L, int transL, Matrix *R, int transR, M
     p->out_rows = rows; p->out_cols = cols;
     p->stream = s;
 
+    Matrix *const ops[3] = {L, R, M};
+    matrix_trees(ops, 3, D, s);  // the operands' trees behind one host read
     Tree &tL = matrix_tree(*L, D, s);
     Tree &tR = matrix_tree(*R, D, s);
     Tree *tM = M ? &matrix_tree(*M, D, s) : nullptr;
