@@ -601,6 +601,12 @@ def backward_main(args, torch, qbsm, W):
               file=sys.stderr, flush=True)
     ch = results[args.mode]
     achieved = MFMA_TERMS[args.mode] * bwd_flops / (ch["backward_ms"] * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        oa, ob, odc = O.from_workload(c["A"]), O.from_workload(c["B"]), O.from_workload(c["dC"])
+        cpu, _ = _oracle_timed(lambda: O.backward(oa, ob, odc), bwd_flops,
+                               "the whole masked backward (dA and dB), FP64 oracle")
     out = {
         "metric": METRIC,
         "value": ch["backward_gflops"],
@@ -632,7 +638,7 @@ def backward_main(args, torch, qbsm, W):
             "kernel": "whole backward (regrouping included): a small, launch-bound workload",
         },
         "modes": results,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -676,6 +682,11 @@ def sparse_main(args, torch, qbsm, W):
         print(f"[bench] {mode}: {ms:.3f} ms/step, kernel {kern:.3f} ms, {results[mode]['kernel_gbps']} GB/s "
               f"(unit {unit})", file=sys.stderr, flush=True)
     ch = results[args.mode]
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        oa, ob = O.from_workload(c["A"]), O.from_workload(c["B"])
+        cpu, _ = _oracle_timed(lambda: O.multiply(oa, ob), info["flops"], "the whole product, FP64 oracle")
     out = {
         "metric": METRIC,
         "value": ch["effective_gflops"],
@@ -708,7 +719,7 @@ def sparse_main(args, torch, qbsm, W):
             "kernel": f"numeric leaf-product kernel, mode {args.mode}, unit {ch['unit']}",
         },
         "modes": results,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
