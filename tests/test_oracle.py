@@ -900,3 +900,78 @@ def test_add_identity_against_dense():
     dense[np.arange(90), np.arange(90)] += 3.5
     got = W.BlockMatrix(100, 90, 16, c.brow.astype(np.int32), c.bcol.astype(np.int32), c.vals).to_dense()
     assert np.array_equal(got[:100, :90], dense) and not np.any(got[100:, :]) and not np.any(got[:, 90:])
+
+
+def _brute_pairs(a, b, i, j, tau):
+    """Every stored pair (A_iK, B_Kj), K ascending, enumerated over all pairs
+    of stored blocks; for tau > 0 only pairs whose norm product (each norm a
+    plain sum of squares) is not below tau."""
+    na = np.sqrt(np.einsum("ij,ij->i", a.vals, a.vals))
+    nb = np.sqrt(np.einsum("ij,ij->i", b.vals, b.vals))
+    out = []
+    for l in range(a.brow.size):
+        if a.brow[l] != i:
+            continue
+        for r in range(b.brow.size):
+            if b.bcol[r] == j and b.brow[r] == a.bcol[l] and not (tau > 0 and na[l] * nb[r] < tau):
+                out.append((int(a.bcol[l]), l, r))
+    return [(l, r) for _, l, r in sorted(out)]
+
+
+@pytest.mark.parametrize("case", ["sparse-exact", "decay-approx"])
+def test_sampled_products_brute_force(case):
+    """sampled_products (the product lists behind multiply_blocks) lists, for
+    every selected C block, exactly the pairs of stored blocks with a shared
+    contraction index, K ascending, and for tau > 0 only those whose norm
+    product is not below tau (Sec. 2.2 regular multiply; Sec. 1 and 2.2
+    sparse approximate multiply): brute-force enumeration over all pairs of
+    stored blocks of two different, ragged operands, on every (I, J) of the
+    grid, empty blocks included."""
+    bs = 16
+    if case == "sparse-exact":
+        wa, wb = W.small_random(150, 120, 170, bs, 0.3, 31)
+        a, b, tau = om(wa), om(wb), 0.0
+    else:
+        a = _decay_rect(200, 120, bs, 0.30, 21, shift=40)
+        b = _decay_rect(120, 168, bs, 0.08, 22, shift=-25)
+        tau = 0.5
+        # no norm product sits so close to tau that the summation order of a
+        # norm could decide it
+        na = np.sqrt(np.einsum("ij,ij->i", a.vals, a.vals))
+        nb = np.sqrt(np.einsum("ij,ij->i", b.vals, b.vals))
+        assert np.min(np.abs(np.outer(na, nb) / tau - 1.0)) > 1e-9
+    nbr, nbc = -(-a.nrows // bs), -(-b.ncols // bs)
+    si, sj = (g.ravel() for g in np.meshgrid(np.arange(nbr), np.arange(nbc), indexing="ij"))
+    seg, lidx, ridx = O.sampled_products(a, b, si, sj, tau)
+    assert seg.size == si.size + 1
+    kept = dropped = 0
+    empty = 0
+    for q, (i, j) in enumerate(zip(si.tolist(), sj.tolist())):
+        got = list(zip(np.asarray(lidx[seg[q]:seg[q + 1]]).tolist(), np.asarray(ridx[seg[q]:seg[q + 1]]).tolist()))
+        exp = _brute_pairs(a, b, i, j, tau)
+        assert got == exp, (i, j)
+        kept += len(exp)
+        empty += not exp
+        if tau > 0:
+            dropped += len(_brute_pairs(a, b, i, j, 0.0)) - len(exp)
+    assert kept > 0 and empty > 0
+    if tau > 0:
+        assert dropped > 0
+
+
+def test_truncate_borderline_closed_form():
+    """truncate_borderline counts the partial sums of the ascending squared
+    leaf norms that lie within rel of eps^2 (where the truncation's cut could
+    depend on summation order).  Blocks with one entry each, 1, -1 and 2:
+    squared norms 1, 1, 4, partial sums 1, 2, 6 exactly."""
+    bs = 4
+    vals = np.zeros((3, bs * bs))
+    vals[0, 0], vals[1, 5], vals[2, 10] = 1.0, -1.0, 2.0
+    a = O.canonical(12, 4, bs, [0, 1, 2], [0, 0, 0], vals)
+    assert O.truncate_borderline(a, np.sqrt(2.0)) == 1
+    assert O.truncate_borderline(a, np.sqrt(6.0)) == 1
+    assert O.truncate_borderline(a, 1.0) == 1
+    assert O.truncate_borderline(a, 2.0) == 0
+    assert O.truncate_borderline(a, np.sqrt(3.0)) == 0
+    assert O.truncate_borderline(a, 0.0) == 0
+    assert O.truncate_borderline(O.canonical(12, 4, bs, [], [], np.zeros((0, bs * bs))), 1.0) == 0
